@@ -1,0 +1,370 @@
+"""Pins of the FP64 CPU oracle against values fixed by mathematics, textbook
+constants and the paper -- never against the oracle itself.
+
+Each pin is chosen so that a plausible slip (dropped k=0 constant, wrong
+self term, wrong sign in the real-space kernel, transposed field, wrong
+energy) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+from oracle import ewald, freespace, saddle, se
+from paper_2401_04865_amd import inputs
+
+# Self-potential of a unit point charge in a periodic simple-cubic cell with a
+# neutralising background, in units of 1/(4 pi eps L) (Wigner / Ewald lattice
+# constant of the sc lattice).
+WIGNER_SC = -2.837297479480620
+# Madelung constants referred to the nearest-neighbour distance.
+MADELUNG_NACL = 1.747564594633182
+MADELUNG_CSCL = 1.762674773070988
+
+
+# ----------------------------------------------------------------- the kernel
+
+
+@pytest.mark.parametrize("sigma,L", [(0.2, 20.0), (0.3, 7.0), (0.05, 3.0)])
+@pytest.mark.parametrize("xi", [0.8, 1.9])
+def test_wigner_self_potential(sigma, L, xi):
+    """M_aa of one Gaussian charge = Gaussian self-energy + lattice constant
+    + sigma^2/V (the k=0 term the definition drops): exact, xi-free."""
+    M = ewald.potential_matrix(np.array([[0.3, 1.1, 2.0]]), np.array([sigma]),
+                               np.full(3, L), xi)
+    want = 1 / (4 * math.pi ** 1.5 * sigma) + WIGNER_SC / (4 * math.pi * L) + sigma ** 2 / L ** 3
+    assert abs(M[0, 0] - want) <= 1e-13 * want
+
+
+def _lattice(kind, a, ncell):
+    pts, q = [], []
+    for i in range(ncell):
+        for j in range(ncell):
+            for k in range(ncell):
+                o = np.array([i, j, k], float) * a
+                if kind == "nacl":
+                    for b in np.ndindex(2, 2, 2):
+                        pts.append(o + np.array(b) * a / 2)
+                        q.append((-1) ** sum(b))
+                else:  # cscl
+                    pts.append(o)
+                    q.append(1.0)
+                    pts.append(o + a / 2)
+                    q.append(-1.0)
+    return np.array(pts) + 0.37, np.array(q, float)
+
+
+@pytest.mark.parametrize("kind,const,dnn", [("nacl", MADELUNG_NACL, 0.5),
+                                            ("cscl", MADELUNG_CSCL, math.sqrt(3) / 2)])
+def test_madelung_point_limit(kind, const, dnn):
+    """Narrow Gaussians reproduce point-charge lattice sums: the potential at
+    an ion from all others is -A q / (4 pi eps d_nn)."""
+    a = 1.7
+    pts, q = _lattice(kind, a, 2)
+    sig = np.full(len(q), 1e-3)
+    phi, _ = ewald.potential_field(pts[:3], sig[:3], pts, sig, q, np.full(3, 2 * a), xi=2.5,
+                                   want_field=False)
+    own = q[:3] / (4 * math.pi ** 1.5 * sig[0])   # the narrow charge's own self potential
+    got = -(phi - own) * 4 * math.pi * dnn * a / q[:3]
+    np.testing.assert_allclose(got, const, rtol=1e-9)
+
+
+def test_ewald_equals_plain_fourier_sum():
+    """The Ewald split (real-space kernel, self value, k=0 constant) equals
+    the defining Fourier sum, in a non-cubic box with unequal widths."""
+    rng = np.random.default_rng(7)
+    pos = rng.random((7, 3)) * np.array([4.0, 4.5, 5.0])
+    sig = 0.33 + 0.15 * rng.random(7)
+    box = np.array([4.0, 4.5, 5.0])
+    Mk = ewald.potential_matrix_ksum(pos, sig, box)
+    for xi in (0.9, 1.7):
+        Me = ewald.potential_matrix(pos, sig, box, xi)
+        assert np.abs(Mk - Me).max() <= 1e-13 * np.abs(Mk).max()
+
+
+def test_split_independence_shell_and_field():
+    """Both profiles: M and the field do not depend on the split xi."""
+    rng = np.random.default_rng(3)
+    box = np.array([5.0, 5.0, 6.0])
+    pos = rng.random((9, 3)) * box
+    sig = np.full(9, 0.2)
+    q = rng.standard_normal(9)
+    for prof in (ewald.Gaussian(), ewald.Shell(0.25)):
+        p1, e1 = ewald.potential_field(pos, sig, pos, sig, q, box, 1.1, profile=prof)
+        p2, e2 = ewald.potential_field(pos, sig, pos, sig, q, box, 2.3, profile=prof)
+        assert np.abs(p1 - p2).max() <= 1e-12 * np.abs(p1).max()
+        assert np.abs(e1 - e2).max() <= 1e-11 * np.abs(e1).max()
+
+
+def _radial_inverse(fk, r):
+    """(1/2pi^2) int_0^inf f(k) k^2 sin(kr)/(kr) dk for a radial f."""
+    val, _ = quad(lambda k: fk(k) * k * math.sin(k * r) / r, 0, np.inf, limit=2000)
+    return val / (2 * math.pi ** 2)
+
+
+@pytest.mark.parametrize("r", [0.13, 0.4, 0.71])
+def test_gaussian_free_kernel_is_inverse_transform(r):
+    s2 = 0.2 ** 2 + 0.15 ** 2
+    want = _radial_inverse(lambda k: math.exp(-0.5 * s2 * k * k) / (k * k) if k > 0 else 0.0, r)
+    got = ewald.Gaussian.free(np.array([r]), s2)[0]
+    assert abs(got - want) <= 1e-9 * abs(want)
+
+
+@pytest.mark.parametrize("r", [0.05, 0.3, 0.49, 0.8, 1.7])
+def test_shell_free_kernel_is_inverse_transform(r):
+    """The shell-shell kernel (printed real-space form with the stray factors
+    of a removed) is the inverse transform of j0(ka)^2/k^2."""
+    a = 0.25
+    sh = ewald.Shell(a)
+    # int_0^inf j0(ka)^2 sin(kr)/(k r) dk / (2 pi^2), split at the oscillation scale
+    f = lambda k: (math.sin(k * a) / (k * a)) ** 2 * math.sin(k * r) / (k * r) if k > 0 else 1.0
+    val = 0.0
+    edges = np.linspace(0, 4000, 4001)
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        val += quad(f, lo, hi, limit=200)[0]
+    want = val / (2 * math.pi ** 2)
+    got = sh.free(np.array([r]))[0]
+    assert abs(got - want) <= 2e-6 * abs(want)
+
+
+def test_point_charge_limit_of_real_kernel():
+    """sigma -> 0: the real-space kernel becomes erfc(xi r)/(4 pi eps r)
+    (the point-charge limit stated for the real-space sum)."""
+    from scipy.special import erfc
+    r = np.linspace(0.05, 3.0, 40)
+    xi = 1.3
+    got = ewald.Gaussian.real(r, 2 * 1e-4 ** 2, xi)
+    np.testing.assert_allclose(got, erfc(xi * r) / (4 * math.pi * r), rtol=1e-12)
+
+
+def test_real_kernel_derivative_matches_finite_difference():
+    for prof, s2 in ((ewald.Gaussian(), 0.05), (ewald.Shell(0.3), 0.0)):
+        r = np.array([0.2, 0.45, 0.7, 1.3])
+        h = 1e-6
+        fd = (prof.real(r + h, s2, 1.4) - prof.real(r - h, s2, 1.4)) / (2 * h)
+        np.testing.assert_allclose(prof.real_deriv(r, s2, 1.4), fd, rtol=1e-6, atol=1e-9)
+
+
+# -------------------------------------------------- geometry (paper numbers)
+
+
+@pytest.mark.parametrize("level,n,ratio", [(3, 642, 14.5), (4, 2562, 29.0)])
+def test_icosphere_bead_radius_ratio(level, n, ratio):
+    """Beads as large as possible without overlap: a = d_min/2; the paper
+    quotes a_b ~ 14.5 a for 642 beads and ~ 29 a for 2562."""
+    p = inputs.icosphere(level, 1.0)
+    assert len(p) == n
+    if level == 3:
+        d = inputs.min_bead_spacing(p)
+    else:
+        from scipy.spatial import cKDTree
+        d = cKDTree(p).query(p, k=2)[0][:, 1].min()
+    assert abs(2.0 / d - ratio) / ratio < 0.01
+
+
+# ------------------------------------------------------ conductor solutions
+
+
+def _continuum_sphere_dipole(R, sigma):
+    """Continuum conductor of radius R covered by Gaussian-smeared charge:
+    S/E0 = 4 pi eps R^4 / (3 K1), K1 = (2R^2/pi) int exp(-sigma^2 k^2) j1(kR)^2 dk
+    (-> 4 pi eps R^3 as sigma -> 0, the isolated conducting-sphere dipole)."""
+    def j1(x):
+        return math.sin(x) / x ** 2 - math.cos(x) / x if x > 1e-6 else x / 3
+    kmax = 9.0 / sigma
+    edges = np.arange(0.0, kmax + 2.0, 2.0)
+    I = sum(quad(lambda k: math.exp(-sigma ** 2 * k ** 2) * j1(k * R) ** 2, lo, hi)[0]
+            for lo, hi in zip(edges[:-1], edges[1:]))
+    K1 = 2 * R ** 2 / math.pi * I
+    return 4 * math.pi * R ** 4 / (3 * K1)
+
+
+def test_continuum_sphere_dipole_reduces_to_paper_closed_form():
+    """sigma -> 0 recovers the isolated conducting sphere, S = 4 pi eps a^3 E0;
+    the first correction is O(sigma)."""
+    for sig in (4e-3, 2e-3):
+        assert abs(_continuum_sphere_dipole(1.0, sig) / (4 * math.pi) - 1.0) < 2 * sig
+
+
+def test_cfg1_dipole_matches_periodic_conductor():
+    """One 162-bead conductor, sigma 0.2, L = 20: the dipole equals the
+    continuum value corrected by the Lorentz field of the periodic images,
+    S = a E0 / (1 - a/(3 eps V)); transverse components vanish."""
+    s = inputs.config(1)
+    q, dpsi, M, b = saddle.solve(s, xi=0.6)
+    S = saddle.dipoles(s, q)[0]
+    alpha = _continuum_sphere_dipole(1.0, 0.2)
+    want = alpha / (1 - alpha / (3 * 20.0 ** 3))
+    assert abs(S[2] - want) / want < 1e-6
+    assert abs(S[0]) < 1e-12 and abs(S[1]) < 1e-12
+    assert abs(q.sum()) < 1e-12
+    # the bare 4 pi a^3 is far off at this width: guard against testing that
+    assert abs(S[2] / (4 * math.pi) - 1.0) > 0.4
+
+
+def test_free_sphere_dipole_and_torque_free():
+    s = inputs.config(1)
+    q, dpsi, _ = freespace.solve(s.body_offsets, s.bead_pos, s.bead_sigma, s.body_center,
+                                 s.body_charge, s.E0)
+    out = freespace.forces_torques(s.body_offsets, s.bead_pos, s.bead_sigma, s.body_center, q, s.E0)
+    alpha = _continuum_sphere_dipole(1.0, 0.2)
+    assert abs(out["dipole"][0, 2] - alpha) / alpha < 1e-6
+    assert np.abs(out["body_force"]).max() < 1e-12
+    assert np.abs(out["body_torque"]).max() < 1e-12
+
+
+def test_isolated_anisotropic_body_torque_is_S_cross_E():
+    """For an isolated neutral body internal forces are central, so F = 0
+    and L = S x E0 (the fibre torque relation)."""
+    p = inputs.icosphere(2, 1.0) * np.array([1.8, 1.0, 0.7])
+    rng = np.random.default_rng(11)
+    R = inputs.quat_to_matrix(inputs.random_quaternions(rng, 1))[0]
+    p = p @ R.T
+    off = np.array([0, len(p)])
+    E0 = np.array([0.3, -0.5, 0.8])
+    sig = np.full(len(p), 0.12)
+    c = p.mean(0, keepdims=True)
+    q, dpsi, _ = freespace.solve(off, p, sig, c, np.zeros(1), E0)
+    out = freespace.forces_torques(off, p, sig, c, q, E0)
+    S = out["dipole"][0]
+    assert np.linalg.norm(np.cross(S, E0)) > 0.1
+    np.testing.assert_allclose(out["body_torque"][0], np.cross(S, E0), atol=1e-12)
+    assert np.abs(out["body_force"]).max() < 1e-12
+
+
+def _small(seed=5, **kw):
+    return inputs.small_random_system(seed, n_body=2, level=1, n_ion=6, L=6.0, sigma=0.18,
+                                      charges=kw.pop("charges", [0.7, -0.3]), **kw)
+
+
+def test_saddle_invariants():
+    s = _small()
+    q, dpsi, M, b = saddle.solve(s, xi=1.2)
+    assert np.allclose(M, M.T, atol=1e-15 * np.abs(M).max())
+    assert np.linalg.eigvalsh(M).min() > 0
+    bi = saddle.body_index(s.body_offsets)
+    np.testing.assert_allclose(np.bincount(bi, q), s.body_charge, atol=1e-13)
+    # equipotential: (Mq - phi_ion - r.E0) is dPsi on every bead of a body
+    r = saddle.relative_positions(s.bead_pos, s.body_center, s.body_offsets)
+    phi_ion = saddle.ion_potential_at_beads(s, 1.2)
+    lhs = M @ q + phi_ion - r @ s.E0
+    np.testing.assert_allclose(lhs, dpsi[bi], atol=1e-12)
+
+
+def _energy(s, xi):
+    q, dpsi, M, b = saddle.solve(s, xi=xi)
+    return saddle.forces_torques(s, q, xi)["total_energy"], q
+
+
+def _moved(s, body, shift=None, rot=None):
+    s2 = inputs.System(**{k: getattr(s, k) for k in s.__dataclass_fields__})
+    off = s.body_offsets
+    sl = slice(off[body], off[body + 1])
+    bp = s.bead_pos.copy()
+    cen = s.body_center.copy()
+    if shift is not None:
+        bp[sl] += shift
+        cen[body] += shift
+    if rot is not None:
+        bp[sl] = cen[body] + (bp[sl] - cen[body]) @ rot.T
+    s2.bead_pos = bp
+    s2.body_center = cen
+    return s2
+
+
+def test_body_force_and_torque_are_energy_gradients():
+    """Finite differences of U = 1/2 q.Mq - q x.E0 under a rigid translation
+    and rotation of one body, re-solving at each displaced configuration."""
+    xi = 1.2
+    s = _small()
+    q, dpsi, M, b = saddle.solve(s, xi=xi)
+    out = saddle.forces_torques(s, q, xi)
+    h = 1e-5
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = h
+        up, _ = _energy(_moved(s, 0, shift=e), xi)
+        dn, _ = _energy(_moved(s, 0, shift=-e), xi)
+        assert abs(-(up - dn) / (2 * h) - out["body_force"][0, ax]) < 2e-7
+        th = h
+        K = np.zeros((3, 3))
+        K[(ax + 1) % 3, (ax + 2) % 3] = -1
+        K[(ax + 2) % 3, (ax + 1) % 3] = 1
+        Rp = np.eye(3) + math.sin(th) * K + (1 - math.cos(th)) * K @ K
+        Rm = np.eye(3) - math.sin(th) * K + (1 - math.cos(th)) * K @ K
+        up, _ = _energy(_moved(s, 1, rot=Rp), xi)
+        dn, _ = _energy(_moved(s, 1, rot=Rm), xi)
+        assert abs(-(up - dn) / (2 * th) - out["body_torque"][1, ax]) < 2e-7
+
+
+def test_total_momentum_balance():
+    """Internal forces cancel: sum of body and ion forces = Q_tot E0."""
+    s = _small(charges=[1.0, 0.5])
+    q, dpsi, M, b = saddle.solve(s, xi=1.2)
+    out = saddle.forces_torques(s, q, 1.2)
+    tot = out["body_force"].sum(0) + out["ion_force"].sum(0)
+    Qt = s.body_charge.sum() + s.ion_charge.sum()
+    np.testing.assert_allclose(tot, Qt * s.E0, atol=1e-12)
+
+
+def test_bead_field_matches_potential_gradient():
+    """Oracle field is minus the gradient of the potential in the target
+    position (sources fixed), by central differences."""
+    s = _small()
+    pos, sig, chg = saddle.all_particles(s, np.linspace(-1, 1, s.n_bead))
+    t = np.array([3, 17])
+    _, E = ewald.potential_field(pos[t], sig[t], pos, sig, chg, s.box, 1.3)
+    h = 1e-5
+    for ax in range(3):
+        d = np.zeros(3)
+        d[ax] = h
+        pp, _ = ewald.potential_field(pos[t] + d, sig[t], pos, sig, chg, s.box, 1.3, want_field=False)
+        pm, _ = ewald.potential_field(pos[t] - d, sig[t], pos, sig, chg, s.box, 1.3, want_field=False)
+        np.testing.assert_allclose(E[:, ax], -(pp - pm) / (2 * h), rtol=1e-6, atol=1e-8)
+
+
+# ----------------------------------------------------------------- mode B
+
+
+def test_modeB_dft_is_numpy_fft():
+    rng = np.random.default_rng(0)
+    H = rng.standard_normal((6, 8, 5))
+    Fx, Fy, Fz = (se.dft_matrix(N, -1) for N in H.shape)
+    D = np.einsum("ai,bj,ck,ijk->abc", Fx, Fy, Fz, H)
+    np.testing.assert_allclose(D, np.fft.fftn(H), atol=1e-12)
+
+
+def test_modeB_converges_to_ewald_with_support():
+    """The discrete spectral-Ewald operator approaches the exact one as the
+    support P grows (truncation/quadrature errors exp(-pi P / 2))."""
+    rng = np.random.default_rng(2)
+    L = 6.0
+    box = np.full(3, L)
+    pos = rng.random((12, 3)) * L
+    sig = np.full(12, 0.25)
+    q = rng.standard_normal(12)
+    q -= q.mean()
+    N = 24
+    h = L / N
+    xi = math.pi * (N - 1) / L / (2 * math.sqrt(math.log(1e10)))
+    r_c = math.sqrt(math.log(1e14)) * max(1 / xi, 2 * 0.25)
+    r_c = min(r_c, L / 2)
+    exact, Ee = ewald.potential_field(pos, sig, pos, sig, q, box, 1.0)
+    errs = []
+    for P in (4, 8, 12):
+        eta = se.eta_of(h, xi, P)
+        phi, E = se.apply(pos, sig, pos, sig, q, box, (N, N, N), P, xi, eta, r_c, want_field=True,
+                          same=True)
+        errs.append(np.abs(phi - exact).max() / np.abs(exact).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] < 1e-4 and errs[2] < 1e-6
+
+
+def test_modeB_operator_symmetric():
+    rng = np.random.default_rng(4)
+    L = 5.0
+    pos = rng.random((10, 3)) * L
+    sig = np.full(10, 0.2)
+    M = se.matrix(pos, sig, np.full(3, L), (16, 16, 16), 6, 1.3, se.eta_of(L / 16, 1.3, 6), 2.4)
+    assert np.abs(M - M.T).max() <= 1e-14 * np.abs(M).max()
