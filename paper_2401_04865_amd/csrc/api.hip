@@ -1,0 +1,814 @@
+// C ABI entry points, configuration setup, the saddle-point operator, the
+// GMRES driver (plain double and mixed-precision refinement), the
+// right-hand side and the force pass.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "pe_internal.hpp"
+#include "vector.hpp"
+#include "guess.hpp"
+
+using namespace pe;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+using Clock = std::chrono::steady_clock;
+inline double secs(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double>(b - a).count();
+}
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void rel_kernel(const double* __restrict__ x, const double* __restrict__ X,
+                           const int* __restrict__ body_of, int64_t n, double* __restrict__ rel) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = body_of[i];
+  rel[3 * i] = x[3 * i] - X[3 * b];
+  rel[3 * i + 1] = x[3 * i + 1] - X[3 * b + 1];
+  rel[3 * i + 2] = x[3 * i + 2] - X[3 * b + 2];
+}
+
+// b_top[i] = -r_i.E0 + phi_ion[i] - (ck[0] - ck[1] sigma_i^2)
+__global__ void rhs_top_kernel(int64_t n, const double* __restrict__ rel, double ex, double ey, double ez,
+                               const double* __restrict__ phi_ion, const double* __restrict__ sig,
+                               const double* __restrict__ ck, double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = -(rel[3 * i] * ex + rel[3 * i + 1] * ey + rel[3 * i + 2] * ez);
+  if (phi_ion) v += phi_ion[i] - (ck[0] - ck[1] * sig[i] * sig[i]);
+  b[i] = v;
+}
+
+// phi[i] -= ck_total(sigma_i); then f = q (E0 + E), u = q phi / 2 - q x.E0
+__global__ void finish_particles_kernel(int64_t n, const double* __restrict__ chg, const double* __restrict__ pos,
+                                        const double* __restrict__ sig, double ex, double ey, double ez,
+                                        const double* __restrict__ ckA, const double* __restrict__ ckB,
+                                        double* __restrict__ phi, const double* __restrict__ E,
+                                        double* __restrict__ f, double* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s2 = sig[i] * sig[i];
+  double c0 = 0, c1 = 0;
+  if (ckA) { c0 += ckA[0]; c1 += ckA[1]; }
+  if (ckB) { c0 += ckB[0]; c1 += ckB[1]; }
+  const double ph = phi[i] - (c0 - c1 * s2);
+  phi[i] = ph;
+  if (f) {
+    const double q = chg[i];
+    f[3 * i] = q * (ex + E[3 * i]);
+    f[3 * i + 1] = q * (ey + E[3 * i + 1]);
+    f[3 * i + 2] = q * (ez + E[3 * i + 2]);
+    u[i] = 0.5 * q * ph - q * (pos[3 * i] * ex + pos[3 * i + 1] * ey + pos[3 * i + 2] * ez);
+  }
+}
+
+// stats[0] += non-finite count, stats[1] = max, stats[2] = min (per block partials)
+__global__ void stats_kernel(const double* __restrict__ a, int64_t n, int stride, int col, double* __restrict__ part) {
+  double bad = 0, mx = -INFINITY, mn = INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = a[i * stride + col];
+    if (!isfinite(v)) bad += 1;
+    else {
+      mx = fmax(mx, v);
+      mn = fmin(mn, v);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    bad += __shfl_xor(bad, o, 64);
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+  }
+  __shared__ double sh[3][4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sh[0][w] = bad; sh[1][w] = mx; sh[2][w] = mn; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b2 = 0, m2 = -INFINITY, n2 = INFINITY;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      b2 += sh[0][k]; m2 = fmax(m2, sh[1][k]); n2 = fmin(n2, sh[2][k]);
+    }
+    part[3 * blockIdx.x] = b2;
+    part[3 * blockIdx.x + 1] = m2;
+    part[3 * blockIdx.x + 2] = n2;
+  }
+}
+
+__global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void sum_kernel(const double* __restrict__ a, int64_t n, double* __restrict__ out) {
+  // single block, fixed order
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += a[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __shared__ double sh[16];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+    *out = t;
+  }
+}
+
+// --------------------------------------------------------------- helpers
+
+struct Stats {
+  double bad, mx, mn;
+};
+
+Stats array_stats(pe_context* c, const double* a, int64_t n, int stride, int col) {
+  Stats st{0, -INFINITY, INFINITY};
+  if (n == 0 || !a) return st;
+  unsigned nb = nblk(n, 256);
+  if (nb > 256) nb = 256;
+  hipLaunchKernelGGL(stats_kernel, dim3(nb), dim3(256), 0, c->stream, a, n, stride, col, c->red.get());
+  PE_CHECK_LAUNCH();
+  std::vector<double> h(3 * nb);
+  PE_HIP(hipMemcpyAsync(h.data(), c->red.get(), sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, c->stream));
+  PE_HIP(hipStreamSynchronize(c->stream));
+  for (unsigned b = 0; b < nb; ++b) {
+    st.bad += h[3 * b];
+    st.mx = std::max(st.mx, h[3 * b + 1]);
+    st.mn = std::min(st.mn, h[3 * b + 2]);
+  }
+  return st;
+}
+
+void dcopy(hipStream_t s, const double* a, double* b, int64_t n) {
+  if (n == 0) return;
+  PE_HIP(hipMemcpyAsync(b, a, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+}
+
+CkCoef ck_coef(const pe_context* c) {
+  CkCoef cc;
+  cc.reg = c->p.reg;
+  cc.inv_epsV = 1.0 / (c->p.eps * c->V);
+  cc.inv4xi2 = 1.0 / (4.0 * c->xi * c->xi);
+  cc.a = c->p.shell_radius;
+  return cc;
+}
+
+// Scratch layout in c->sums: [ck_bead(2), ck_ion(2), tot(2), tmp(...)]
+double* ck_bead(pe_context* c) { return c->sums.get(); }
+double* ck_ion(pe_context* c) { return c->sums.get() + 2; }
+double* tot2(pe_context* c) { return c->sums.get() + 4; }
+double* scal(pe_context* c) { return c->sums.get() + 8; }   // misc device scalars (32)
+
+template <typename T>
+T* grid_real(pe::DevBuf<double>& g) { return reinterpret_cast<T*>(g.get()); }
+
+// M q for the beads with bead charges q (caller order), assembled into the
+// saddle operator: y[0:nb] = -(M q) + Sigma^T dpsi, y[nb:] = Sigma q.
+template <typename T>
+void apply_saddle(pe_context* c, const double* x, double* y) {
+  hipStream_t s = c->stream;
+  const int64_t nb = c->n_bead;
+  const double* q = x;
+  const double* dpsi = x + nb;
+  launch_moments(s, q, c->bead_sig.get(), 0.0, nb, ck_coef(c), c->red.get(), ck_bead(c), nullptr);
+  launch_seg_sum(s, c->off.get(), c->n_body, q, y + nb);
+  T* gA = grid_real<T>(c->gridA);
+  T* gB = grid_real<T>(c->gridB);
+  launch_spread<T>(s, c->B, q, gA, c->gg);
+  launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
+  launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false);
+  launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), ck_bead(c), y);
+}
+
+void apply_saddle_prec(pe_context* c, int prec, const double* x, double* y) {
+  if (prec == PE_MIXED) apply_saddle<float>(c, x, y);
+  else apply_saddle<double>(c, x, y);
+}
+
+// Potential (and field) of all particles for bead charges qb and ion charges qi.
+// phi (n_all), E (3 n_all or null).  Includes the self terms and removes
+// the k = 0 constant; optionally forms forces/energies.
+template <typename T>
+void all_potential(pe_context* c, const double* qb, const double* qi, double* phi, double* E,
+                   double* f, double* u, const double* chg_all) {
+  hipStream_t s = c->stream;
+  const int64_t nb = c->n_bead, ni = c->n_ion, na = nb + ni;
+  PE_HIP(hipMemsetAsync(phi, 0, sizeof(double) * na, s));
+  if (E) PE_HIP(hipMemsetAsync(E, 0, sizeof(double) * 3 * na, s));
+  launch_moments(s, qb, c->bead_sig.get(), 0.0, nb, ck_coef(c), c->red.get(), ck_bead(c), nullptr);
+  if (ni) launch_moments(s, qi, c->ion_sig.get(), 0.0, ni, ck_coef(c), c->red.get(), ck_ion(c), nullptr);
+  T* gA = grid_real<T>(c->gridA);
+  T* gB = grid_real<T>(c->gridB);
+  launch_spread<T>(s, c->B, qb, gA, c->gg);
+  if (ni) launch_spread<T>(s, c->I, qi, gA, c->gg);
+  launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
+  launch_gather<T>(s, c->B, gB, c->gg, phi, E, true);
+  if (ni) launch_gather<T>(s, c->I, gB, c->gg, phi + nb, E ? E + 3 * nb : nullptr, true);
+  launch_pair_onfly<T>(s, c->B, c->B, qb, c->rg, phi, E);
+  if (ni) {
+    launch_pair_onfly<T>(s, c->B, c->I, qi, c->rg, phi, E);
+    launch_pair_onfly<T>(s, c->I, c->B, qb, c->rg, phi + nb, E ? E + 3 * nb : nullptr);
+    launch_pair_onfly<T>(s, c->I, c->I, qi, c->rg, phi + nb, E ? E + 3 * nb : nullptr);
+  }
+  // k = 0 constant, then forces and energies
+  if (nb)
+    hipLaunchKernelGGL(finish_particles_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, chg_all,
+                       c->bead_x.get(), c->bead_sig.get(), c->E0[0], c->E0[1], c->E0[2], ck_bead(c),
+                       ni ? ck_ion(c) : (const double*)nullptr, phi, E, f, u);
+  if (ni)
+    hipLaunchKernelGGL(finish_particles_kernel, dim3(nblk(ni, 256)), dim3(256), 0, s, ni,
+                       chg_all ? chg_all + nb : nullptr, c->ion_x.get(), c->ion_sig.get(), c->E0[0],
+                       c->E0[1], c->E0[2], ck_bead(c), ck_ion(c), phi + nb, E ? E + 3 * nb : nullptr,
+                       f ? f + 3 * nb : nullptr, u ? u + nb : nullptr);
+  PE_CHECK_LAUNCH();
+}
+
+// Right-hand side b = [-r.E0 + phi_ion(beads); Q] in double.
+void build_rhs(pe_context* c, double* b) {
+  hipStream_t s = c->stream;
+  const int64_t nb = c->n_bead, ni = c->n_ion;
+  double* phi_ion = nullptr;
+  if (ni) {
+    phi_ion = c->phi_w.get();
+    launch_moments(s, c->ion_q.get(), c->ion_sig.get(), 0.0, ni, ck_coef(c), c->red.get(), ck_ion(c), nullptr);
+    double* gA = c->gridA.get();
+    double* gB = c->gridB.get();
+    launch_spread<double>(s, c->I, c->ion_q.get(), gA, c->gg);
+    launch_wave_pipeline<double>(s, c, gA, gB, c->gridC.get());
+    launch_gather<double>(s, c->B, gB, c->gg, phi_ion, nullptr, false);
+    launch_pair_onfly<double>(s, c->B, c->I, c->ion_q.get(), c->rg, phi_ion, nullptr);
+  }
+  if (nb)
+    hipLaunchKernelGGL(rhs_top_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, c->rel.get(), c->E0[0],
+                       c->E0[1], c->E0[2], phi_ion, c->bead_sig.get(), ck_ion(c), b);
+  PE_CHECK_LAUNCH();
+  dcopy(s, c->body_Q.get(), b + nb, c->n_body);
+}
+
+// --------------------------------------------------------------- GMRES
+
+struct KWork {
+  double* V;      // (m+1) x n
+  double* w;      // n
+  double* r;      // n
+  double* tmp;    // n
+  double* st;     // Hessenberg etc.
+  double* h1;     // m+1
+  double* h2;     // m+1
+  double* nrm;    // 1
+  double* res;    // 1
+  double* y;      // m
+};
+
+KWork kwork(pe_context* c, int64_t n, int m) {
+  KWork k;
+  c->Vb.ensure((size_t)(m + 1) * n);
+  c->kvec.ensure((size_t)3 * n);
+  const size_t nst = (size_t)(m + 1) * m + 2 * m + (m + 1);
+  c->hs.ensure(nst + 3 * (m + 1) + 4 + m);
+  k.V = c->Vb.get();
+  k.w = c->kvec.get();
+  k.r = k.w + n;
+  k.tmp = k.r + n;
+  k.st = c->hs.get();
+  k.h1 = k.st + nst;
+  k.h2 = k.h1 + (m + 1);
+  k.nrm = k.h2 + (m + 1);
+  k.res = k.nrm + 1;
+  k.y = k.res + 2;
+  return k;
+}
+
+double fetch(pe_context* c, const double* d) {
+  double h;
+  PE_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  PE_HIP(hipStreamSynchronize(c->stream));
+  return h;
+}
+
+struct GmresOut {
+  int iters = 0;
+  bool converged = false;
+  double rel = 0;  // last true (or estimated) relative residual w.r.t. bnorm
+};
+
+// Restarted GMRES on A x = b with operator precision `prec`; x is updated in
+// place.  Convergence: ||b - A x|| <= tol * bnorm, checked with the true
+// residual of the operator at every restart.
+GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero, double bnorm, double tol,
+               int max_iters, pe_solve_info* info, int* mv64, int* mv32) {
+  hipStream_t s = c->stream;
+  const int64_t n = c->n_bead + c->n_body;
+  const int m = std::max(1, std::min(c->p.gmres_restart, kMaxK - 1));
+  KWork k = kwork(c, n, m);
+  GmresOut out;
+  double* partial = c->red.get();
+  bool first = true;
+  for (;;) {
+    // r = b - A x
+    if (first && x_zero) {
+      dcopy(s, b, k.r, n);
+    } else {
+      apply_saddle_prec(c, prec, x, k.tmp);
+      (prec == PE_MIXED ? *mv32 : *mv64) += 1;
+      launch_sub(s, b, k.tmp, k.r, n);
+    }
+    first = false;
+    launch_mdot(s, k.r, n, 1, k.r, n, partial, k.nrm, true);
+    const double beta = fetch(c, k.nrm);
+    if (!std::isfinite(beta)) throw Error(PE_ERR_NUMERIC, "non-finite residual in GMRES");
+    out.rel = beta / bnorm;
+    if (beta <= tol * bnorm) {
+      out.converged = true;
+      return out;
+    }
+    if (out.iters >= max_iters) return out;
+    launch_scale(s, k.r, k.nrm, k.V, n);
+    launch_init_g(s, k.st, m, k.nrm);
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = k.V + (size_t)j * n;
+      apply_saddle_prec(c, prec, vj, k.w);
+      (prec == PE_MIXED ? *mv32 : *mv64) += 1;
+      launch_mdot(s, k.V, n, j + 1, k.w, n, partial, k.h1, false);
+      launch_maxpy(s, k.V, n, j + 1, k.h1, k.w, n, 1.0);
+      launch_mdot(s, k.V, n, j + 1, k.w, n, partial, k.h2, false);
+      launch_maxpy(s, k.V, n, j + 1, k.h2, k.w, n, 1.0);
+      launch_mdot(s, k.w, n, 1, k.w, n, partial, k.nrm, true);
+      launch_scale(s, k.w, k.nrm, k.V + (size_t)(j + 1) * n, n);
+      launch_givens(s, k.h1, k.h2, k.nrm, k.st, m, j, k.res);
+      const double est = fetch(c, k.res);
+      out.iters += 1;
+      if (info && info->n_hist < 1024) info->hist[info->n_hist++] = est / bnorm;
+      jend = j + 1;
+      if (!std::isfinite(est)) throw Error(PE_ERR_NUMERIC, "non-finite residual estimate in GMRES");
+      if (est <= tol * bnorm || out.iters >= max_iters) break;
+    }
+    launch_backsolve(s, k.st, m, jend, k.y);
+    launch_maxpy(s, k.V, n, jend, k.y, x, n, -1.0);  // x += V y
+  }
+}
+
+void compute_params(pe_context* c) {
+  const pe_params& p = c->p;
+  double hmax = 0;
+  for (int d = 0; d < 3; ++d) hmax = std::max(hmax, p.box[d] / p.mesh[d]);
+  c->hmax = hmax;
+  c->V = p.box[0] * p.box[1] * p.box[2];
+  const double lt = std::sqrt(std::log(1.0 / p.split_tol));
+  if (p.xi > 0) c->xi = p.xi;
+  else {
+    double kc = 1e300;
+    for (int d = 0; d < 3; ++d) kc = std::min(kc, M_PI * (p.mesh[d] - 1) / p.box[d]);
+    c->xi = kc / (2.0 * lt);
+  }
+  c->eta = (hmax * c->xi) * (hmax * c->xi) * p.P / (M_PI * p.eta_c * p.eta_c);
+  GridGeom& g = c->gg;
+  for (int d = 0; d < 3; ++d) {
+    g.N[d] = p.mesh[d];
+    g.h[d] = p.box[d] / p.mesh[d];
+    g.inv_h[d] = p.mesh[d] / p.box[d];
+    g.L[d] = p.box[d];
+  }
+  g.Nzc = p.mesh[2] / 2 + 1;
+  g.P = p.P;
+  g.wexp = 2.0 * c->xi * c->xi / c->eta;
+  g.wnorm = std::sqrt(2.0 * c->xi * c->xi / (M_PI * c->eta));
+  g.h3 = g.h[0] * g.h[1] * g.h[2];
+  g.eps = p.eps;
+  g.fcoef = -4.0 * c->xi * c->xi * g.h3 / (p.eps * c->eta);
+}
+
+void build_twiddles(pe_context* c) {
+  for (int d = 0; d < 3; ++d) {
+    const int n = c->p.mesh[d];
+    make_fft_plan(n, c->plan[d]);
+    std::vector<double2> t64(n);
+    std::vector<float2> t32(n);
+    for (int j = 0; j < n; ++j) {
+      // exp(-2 pi i j / n), evaluated in long double
+      const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)j / (long double)n;
+      t64[j] = make_double2((double)cosl(a), (double)sinl(a));
+      t32[j] = make_float2((float)t64[j].x, (float)t64[j].y);
+    }
+    c->tw64[d].ensure(n);
+    c->tw32[d].ensure(n);
+    PE_HIP(hipMemcpy(c->tw64[d].get(), t64.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
+    PE_HIP(hipMemcpy(c->tw32[d].get(), t32.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
+  }
+}
+
+void ensure_grids(pe_context* c) {
+  const int64_t G = (int64_t)c->p.mesh[0] * c->p.mesh[1] * c->p.mesh[2];
+  const int64_t Gc = (int64_t)c->p.mesh[0] * c->p.mesh[1] * (c->p.mesh[2] / 2 + 1);
+  const bool fresh = c->gridA.cap < (size_t)G;
+  c->gridA.ensure(G);
+  c->gridB.ensure(G);
+  c->gridC.ensure(Gc);
+  if (fresh) PE_HIP(hipMemsetAsync(c->gridA.get(), 0, sizeof(double) * G, c->stream));
+}
+
+// The spread accumulates into grid A and the first FFT pass zeroes it after
+// reading; clear it at every entry point in case an earlier call stopped
+// between the two.
+void clean_grid(pe_context* c) {
+  const int64_t G = (int64_t)c->p.mesh[0] * c->p.mesh[1] * c->p.mesh[2];
+  PE_HIP(hipMemsetAsync(c->gridA.get(), 0, sizeof(double) * G, c->stream));
+}
+
+}  // namespace
+
+// =============================================================== C ABI
+
+#define PE_API_BEGIN try {
+#define PE_API_END(ctx)                                   \
+  }                                                       \
+  catch (const pe::Error& e) {                            \
+    if (ctx) (ctx)->err = e.what();                       \
+    else g_create_error = e.what();                       \
+    return e.code;                                        \
+  }                                                       \
+  catch (const std::exception& e) {                       \
+    if (ctx) (ctx)->err = e.what();                       \
+    else g_create_error = e.what();                       \
+    return PE_ERR_DEVICE;                                 \
+  }                                                       \
+  return PE_OK;
+
+extern "C" {
+
+pe_status pe_default_params(pe_params* p) {
+  if (!p) return PE_ERR_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->P = 8;
+  p->eta_c = 1.0;
+  p->xi = 0.0;
+  p->r_cut = 0.0;
+  p->split_tol = 1e-8;
+  p->eps = 1.0;
+  p->precision = PE_FP64;
+  p->reg = PE_REG_GAUSSIAN;
+  p->shell_radius = 0.0;
+  p->gmres_restart = 30;
+  p->max_iters = 1000;
+  p->rel_tol = 1e-6;
+  p->inner_tol = 1e-4;
+  p->max_refine = 8;
+  p->use_learned_guess = 0;
+  return PE_OK;
+}
+
+const char* pe_last_error(const pe_context* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out) {
+  pe_context* c = nullptr;
+  PE_API_BEGIN
+  require(params != nullptr && out != nullptr, "null argument");
+  const pe_params& p = *params;
+  for (int d = 0; d < 3; ++d) {
+    require(std::isfinite(p.box[d]) && p.box[d] > 0, "box lengths must be positive");
+    require(p.mesh[d] >= 2, "mesh must have at least 2 points per axis");
+  }
+  require(p.mesh[2] % 2 == 0, "mesh[2] must be even (real-to-complex transform)");
+  require(p.P >= 2 && p.P <= 16, "P must be in [2, 16]");
+  require(p.P <= p.mesh[0] && p.P <= p.mesh[1] && p.P <= p.mesh[2], "P must not exceed the mesh");
+  require(p.eps > 0 && std::isfinite(p.eps), "eps must be positive");
+  require(p.eta_c > 0, "eta_c must be positive");
+  require(p.split_tol > 0 && p.split_tol < 1, "split_tol must be in (0,1)");
+  require(p.precision == PE_FP64 || p.precision == PE_MIXED, "unknown precision");
+  require(p.reg == PE_REG_GAUSSIAN || p.reg == PE_REG_SHELL, "unknown regularization");
+  if (p.reg == PE_REG_SHELL) require(p.shell_radius > 0, "shell_radius must be positive");
+  require(p.gmres_restart >= 1, "gmres_restart must be >= 1");
+  require(p.max_iters >= 1, "max_iters must be >= 1");
+  require(p.rel_tol > 0, "rel_tol must be positive");
+  c = new pe_context();
+  c->p = p;
+  if (c->p.inner_tol <= 0) c->p.inner_tol = 1e-4;
+  if (c->p.max_refine <= 0) c->p.max_refine = 8;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  pe::FFTPlan1D tmp;
+  for (int d = 0; d < 3; ++d) make_fft_plan(p.mesh[d], tmp);
+  compute_params(c);
+  require(c->eta > 0 && c->eta < 1, "eta = (h xi)^2 P/(pi c^2) must lie in (0, 1); refine the mesh or lower xi");
+  build_twiddles(c);
+  c->sums.ensure(64);
+  c->red.ensure((size_t)kMaxK * 1024 + 4096);
+  *out = c;
+  c = nullptr;
+  PE_API_END(c)
+}
+
+pe_status pe_destroy(pe_context* ctx) {
+  if (!ctx) return PE_OK;
+  if (ctx->guess) guess_destroy(ctx);
+  delete ctx;
+  return PE_OK;
+}
+
+pe_status pe_get_derived(const pe_context* ctx, double out[6]) {
+  if (!ctx || !out) return PE_ERR_ARG;
+  out[0] = ctx->xi;
+  out[1] = ctx->rc;
+  out[2] = ctx->eta;
+  out[3] = ctx->hmax;
+  out[4] = (double)ctx->nnz;
+  out[5] = (double)ctx->rg.nc[0];
+  return PE_OK;
+}
+
+pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offsets, const double* bead_pos,
+                        const double* bead_sigma, const double* body_center, const double* body_quat,
+                        const double* body_charge, int64_t n_ion, const double* ion_pos, const double* ion_charge,
+                        const double* ion_sigma, const double E0[3]) {
+  if (!c) return PE_ERR_ARG;
+  PE_API_BEGIN
+  c->have_system = false;
+  c->have_solution = false;
+  c->have_forces = false;
+  require(n_body >= 0 && n_ion >= 0, "negative sizes");
+  require(n_body == 0 || body_offsets != nullptr, "body_offsets is null");
+  require(E0 != nullptr, "E0 is null");
+  for (int d = 0; d < 3; ++d) require(std::isfinite(E0[d]), "E0 must be finite");
+  std::vector<int64_t> off(n_body + 1, 0);
+  if (n_body) std::copy(body_offsets, body_offsets + n_body + 1, off.begin());
+  require(off[0] == 0, "body_offsets[0] must be 0");
+  for (int64_t i = 0; i < n_body; ++i) require(off[i + 1] >= off[i], "body_offsets must be nondecreasing");
+  const int64_t nb = off[n_body];
+  require(nb < ((int64_t)1 << 31) && n_ion < ((int64_t)1 << 31), "too many particles");
+  require(nb == 0 || (bead_pos && bead_sigma), "bead arrays are null");
+  require(n_body == 0 || (body_center && body_charge), "body arrays are null");
+  require(n_ion == 0 || (ion_pos && ion_charge && ion_sigma), "ion arrays are null");
+  hipStream_t s = c->stream;
+  c->n_body = n_body;
+  c->n_bead = nb;
+  c->n_ion = n_ion;
+  c->h_off = off;
+  for (int d = 0; d < 3; ++d) c->E0[d] = E0[d];
+  // copies
+  c->off.ensure(n_body + 1);
+  PE_HIP(hipMemcpyAsync(c->off.get(), off.data(), sizeof(int64_t) * (n_body + 1), hipMemcpyHostToDevice, s));
+  std::vector<int> bof(nb);
+  for (int64_t i = 0; i < n_body; ++i)
+    for (int64_t j = off[i]; j < off[i + 1]; ++j) bof[j] = (int)i;
+  c->body_of.ensure(nb);
+  if (nb) PE_HIP(hipMemcpyAsync(c->body_of.get(), bof.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+  c->bead_x.ensure(3 * nb);
+  c->bead_sig.ensure(nb);
+  c->rel.ensure(3 * nb);
+  c->ion_x.ensure(3 * n_ion);
+  c->ion_q.ensure(n_ion);
+  c->ion_sig.ensure(n_ion);
+  c->body_Q.ensure(n_body);
+  c->quat.ensure(4 * n_body);
+  dcopy(s, bead_pos, c->bead_x.get(), 3 * nb);
+  dcopy(s, bead_sigma, c->bead_sig.get(), nb);
+  dcopy(s, ion_pos, c->ion_x.get(), 3 * n_ion);
+  dcopy(s, ion_charge, c->ion_q.get(), n_ion);
+  dcopy(s, ion_sigma, c->ion_sig.get(), n_ion);
+  dcopy(s, body_charge, c->body_Q.get(), n_body);
+  if (body_quat) dcopy(s, body_quat, c->quat.get(), 4 * n_body);
+  else {
+    std::vector<double> qi(4 * n_body, 0.0);
+    for (int64_t i = 0; i < n_body; ++i) qi[4 * i] = 1.0;
+    if (n_body) PE_HIP(hipMemcpyAsync(c->quat.get(), qi.data(), sizeof(double) * 4 * n_body, hipMemcpyHostToDevice, s));
+    PE_HIP(hipStreamSynchronize(s));
+  }
+  // validation on the device
+  double sig_max = 0, sig_min = INFINITY;
+  for (int d = 0; d < 3; ++d) {
+    Stats a = array_stats(c, c->bead_x.get(), nb, 3, d);
+    require(a.bad == 0, "bead positions must be finite");
+    Stats b = array_stats(c, c->ion_x.get(), n_ion, 3, d);
+    require(b.bad == 0, "ion positions must be finite");
+  }
+  {
+    Stats a = array_stats(c, c->bead_sig.get(), nb, 1, 0);
+    Stats b = array_stats(c, c->ion_sig.get(), n_ion, 1, 0);
+    Stats q1 = array_stats(c, c->ion_q.get(), n_ion, 1, 0);
+    Stats q2 = array_stats(c, c->body_Q.get(), n_body, 1, 0);
+    require(a.bad == 0 && b.bad == 0 && q1.bad == 0 && q2.bad == 0, "charges and widths must be finite");
+    if (c->p.reg == PE_REG_GAUSSIAN) {
+      require(nb == 0 || a.mn > 0, "bead widths must be positive");
+      require(n_ion == 0 || b.mn > 0, "ion widths must be positive");
+    }
+    if (nb) { sig_max = std::max(sig_max, a.mx); sig_min = std::min(sig_min, a.mn); }
+    if (n_ion) { sig_max = std::max(sig_max, b.mx); }
+    c->bead_sig_uniform = (nb && a.mx == a.mn) ? a.mx : -1.0;
+  }
+  // cutoff and cells
+  const double lt = std::sqrt(std::log(1.0 / c->p.split_tol));
+  if (c->p.r_cut > 0) c->rc = c->p.r_cut;
+  else if (c->p.reg == PE_REG_GAUSSIAN) c->rc = lt * std::max(1.0 / c->xi, 2.0 * sig_max);
+  else c->rc = std::max(lt / c->xi, 2.0 * c->p.shell_radius);
+  const double Lmin = std::min(c->p.box[0], std::min(c->p.box[1], c->p.box[2]));
+  require(c->rc <= 0.5 * Lmin * (1 + 1e-12),
+          "real-space cutoff " + std::to_string(c->rc) + " exceeds half the box; use a finer mesh or a larger box");
+  RealGeom& rg = c->rg;
+  for (int d = 0; d < 3; ++d) {
+    rg.L[d] = c->p.box[d];
+    rg.inv_L[d] = 1.0 / c->p.box[d];
+    int nc = (int)std::floor(c->p.box[d] / c->rc);
+    if (nc < 3) nc = 1;
+    if (nc > 512) nc = 512;
+    rg.nc[d] = nc;
+    rg.cell_inv[d] = nc / c->p.box[d];
+  }
+  rg.rc2 = c->rc * c->rc;
+  rg.xi = c->xi;
+  rg.eps = c->p.eps;
+  rg.reg = c->p.reg;
+  rg.a = c->p.shell_radius;
+  // relative positions, cells, bead operator, grids
+  if (nb)
+    hipLaunchKernelGGL(rel_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, c->bead_x.get(), body_center,
+                       c->body_of.get(), nb, c->rel.get());
+  PE_CHECK_LAUNCH();
+  build_cells(s, c->B, c->bead_x.get(), c->bead_sig.get(), 0.0, nb, rg);
+  build_cells(s, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, n_ion, rg);
+  build_bead_matrix(c);
+  ensure_grids(c);
+  c->phi_w.ensure(nb + n_ion + 1);
+  c->phi_all.ensure(nb + n_ion + 1);
+  c->E_all.ensure(3 * (nb + n_ion) + 1);
+  c->forces.ensure(3 * (nb + n_ion) + 1);
+  c->xsol.ensure(nb + n_body + 1);
+  c->rhs_b.ensure(nb + n_body + 1);
+  c->have_system = true;
+  if (c->guess) guess_on_system(c);
+  PE_HIP(hipStreamSynchronize(s));
+  PE_API_END(c)
+}
+
+pe_status pe_apply_potential(pe_context* c, const double* charges, double* psi_out, double* field_out,
+                             int32_t precision) {
+  if (!c) return PE_ERR_ARG;
+  PE_API_BEGIN
+  if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
+  require(charges && psi_out, "null charges or output");
+  require(precision == PE_FP64 || precision == PE_MIXED, "unknown precision");
+  clean_grid(c);
+  const int64_t nb = c->n_bead;
+  if (precision == PE_MIXED)
+    all_potential<float>(c, charges, charges + nb, psi_out, field_out, nullptr, nullptr, nullptr);
+  else
+    all_potential<double>(c, charges, charges + nb, psi_out, field_out, nullptr, nullptr, nullptr);
+  PE_HIP(hipStreamSynchronize(c->stream));
+  PE_API_END(c)
+}
+
+pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_out, double* dpsi_out,
+                                double* dipole_out, pe_solve_info* info) {
+  if (!c) return PE_ERR_ARG;
+  pe_status status = PE_OK;
+  PE_API_BEGIN
+  if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
+  require(q_out && dpsi_out, "null output");
+  pe_solve_info local;
+  pe_solve_info* inf = info ? info : &local;
+  std::memset(inf, 0, sizeof(*inf));
+  hipStream_t s = c->stream;
+  const auto t0 = Clock::now();
+  clean_grid(c);
+  const int64_t nb = c->n_bead, nbody = c->n_body, n = nb + nbody;
+  double* b = c->rhs_b.get();
+  double* x = c->xsol.get();
+  build_rhs(c, b);
+  // ||b||
+  KWork k = kwork(c, n, std::max(1, std::min(c->p.gmres_restart, kMaxK - 1)));
+  launch_mdot(s, b, n, 1, b, n, c->red.get(), k.nrm, true);
+  const double bnorm = fetch(c, k.nrm);
+  const auto t1 = Clock::now();
+  // initial guess
+  bool x_zero = true;
+  PE_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+  if (q_init) {
+    dcopy(s, q_init, x, nb);
+    x_zero = false;
+  } else if (c->p.use_learned_guess) {
+    require(c->guess != nullptr && guess_ready(c), "use_learned_guess set but no model is loaded");
+    guess_predict(c, x);
+    x_zero = false;
+  }
+  const auto t2 = Clock::now();
+  int mv64 = 0, mv32 = 0;
+  if (bnorm == 0.0) {
+    inf->rel_residual = 0;
+  } else {
+    // residual at the guess (double operator)
+    if (!x_zero) {
+      apply_saddle_prec(c, PE_FP64, x, k.tmp);
+      mv64++;
+      launch_sub(s, b, k.tmp, k.r, n);
+      launch_mdot(s, k.r, n, 1, k.r, n, c->red.get(), k.nrm, true);
+      inf->rel_residual_guess = fetch(c, k.nrm) / bnorm;
+    } else {
+      inf->rel_residual_guess = 1.0;
+    }
+    const double tol = c->p.rel_tol;
+    if (c->p.precision == PE_FP64) {
+      GmresOut o = gmres(c, PE_FP64, b, x, x_zero, bnorm, tol, c->p.max_iters, inf, &mv64, &mv32);
+      inf->iters = o.iters;
+      inf->rel_residual = o.rel;
+      if (!o.converged) status = PE_ERR_NOT_CONVERGED;
+    } else {
+      // double iterative refinement around float-operator GMRES solves
+      double* r = c->phi_all.get();  // reuse as residual vector storage (size >= n needed)
+      c->phi_all.ensure(std::max<int64_t>(n, nb + c->n_ion) + 1);
+      r = c->phi_all.get();
+      double* d = c->E_all.get();
+      c->E_all.ensure(std::max<int64_t>(n, 3 * (nb + c->n_ion)) + 1);
+      d = c->E_all.get();
+      int total = 0;
+      bool conv = false;
+      double rel = 1.0;
+      for (int outer = 0; outer <= c->p.max_refine; ++outer) {
+        // r = b - A64 x
+        if (x_zero && outer == 0) {
+          dcopy(s, b, r, n);
+        } else {
+          apply_saddle_prec(c, PE_FP64, x, k.tmp);
+          mv64++;
+          launch_sub(s, b, k.tmp, r, n);
+        }
+        launch_mdot(s, r, n, 1, r, n, c->red.get(), k.nrm, true);
+        const double rn = fetch(c, k.nrm);
+        if (!std::isfinite(rn)) throw Error(PE_ERR_NUMERIC, "non-finite residual in refinement");
+        rel = rn / bnorm;
+        if (rel <= tol) { conv = true; break; }
+        if (outer == c->p.max_refine || total >= c->p.max_iters) break;
+        inf->outer_refinements++;
+        PE_HIP(hipMemsetAsync(d, 0, sizeof(double) * n, s));
+        const double itol = std::max(c->p.inner_tol, 0.5 * tol / std::max(rel, 1e-300));
+        GmresOut o = gmres(c, PE_MIXED, r, d, true, rn, std::min(itol, 0.5), c->p.max_iters - total, inf,
+                           &mv64, &mv32);
+        total += o.iters;
+        launch_axpby(s, 1.0, d, 1.0, x, n);
+      }
+      inf->iters = total;
+      inf->rel_residual = rel;
+      if (!conv) status = PE_ERR_NOT_CONVERGED;
+    }
+  }
+  inf->matvecs_fp64 = mv64;
+  inf->matvecs_fp32 = mv32;
+  // outputs
+  dcopy(s, x, q_out, nb);
+  dcopy(s, x + nb, dpsi_out, nbody);
+  if (dipole_out) launch_body_outputs(s, c->off.get(), nbody, c->rel.get(), x, nullptr, nullptr, dipole_out,
+                                      nullptr, nullptr, nullptr);
+  PE_HIP(hipStreamSynchronize(s));
+  const auto t3 = Clock::now();
+  inf->t_rhs = secs(t0, t1);
+  inf->t_guess = secs(t1, t2);
+  inf->t_solve = secs(t2, t3);
+  inf->t_total = secs(t0, t3);
+  c->have_solution = true;
+  if (status != PE_OK) {
+    c->err = status == PE_ERR_NOT_CONVERGED ? "GMRES did not reach rel_tol within max_iters" : "solve failed";
+    return status;
+  }
+  PE_API_END(c)
+}
+
+pe_status pe_forces_torques(pe_context* c, double* body_force, double* body_torque, double* body_energy,
+                            double* ion_force, double* bead_force, double* total_energy) {
+  if (!c) return PE_ERR_ARG;
+  PE_API_BEGIN
+  if (!c->have_solution) throw Error(PE_ERR_STATE, "pe_solve_polarization has not been called");
+  require(total_energy != nullptr, "total_energy is null");
+  hipStream_t s = c->stream;
+  clean_grid(c);
+  const int64_t nb = c->n_bead, ni = c->n_ion, na = nb + ni;
+  c->phi_all.ensure(na + 1);
+  c->E_all.ensure(3 * na + 1);
+  c->forces.ensure(3 * na + 1);
+  c->kvec.ensure(2 * na + 2);
+  double* chg = c->kvec.get();     // all charges
+  double* u = chg + na;            // energies
+  dcopy(s, c->xsol.get(), chg, nb);
+  dcopy(s, c->ion_q.get(), chg + nb, ni);
+  double* f = c->forces.get();
+  if (c->p.precision == PE_MIXED)
+    all_potential<float>(c, chg, chg + nb, c->phi_all.get(), c->E_all.get(), f, u, chg);
+  else
+    all_potential<double>(c, chg, chg + nb, c->phi_all.get(), c->E_all.get(), f, u, chg);
+  launch_body_outputs(s, c->off.get(), c->n_body, c->rel.get(), chg, f, u, nullptr, body_force, body_torque,
+                      body_energy);
+  if (ion_force) dcopy(s, f + 3 * nb, ion_force, 3 * ni);
+  if (bead_force) dcopy(s, f, bead_force, 3 * nb);
+  double* tot = scal(c);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, s, u, na, tot);
+  PE_CHECK_LAUNCH();
+  *total_energy = fetch(c, tot);
+  c->have_forces = true;
+  PE_API_END(c)
+}
+
+}  // extern "C"

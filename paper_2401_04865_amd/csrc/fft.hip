@@ -1,0 +1,401 @@
+// Hand-written 3-D FFT with the Green's-function scaling fused in (section
+// "Spectral Ewald implementation", steps 3-5).
+//
+// Layout: real grids [Nx][Ny][Nz] (z fastest); the half spectrum
+// [Nx][Ny][Nzc], Nzc = Nz/2 + 1.  Five passes, each one read and one write of
+// the grid through LDS:
+//   1. z, real -> complex: two real lines packed into one complex line, one
+//      complex FFT, then split (X_a = (Z_k + conj Z_{N-k})/2,
+//      X_b = (Z_k - conj Z_{N-k})/2i); the real input is zeroed after it is
+//      read, so the next spread starts from a clean grid.
+//   2. y, complex, forward.
+//   3. x forward, multiply by G_k / (Nx Ny Nz), x inverse: the whole x line
+//      stays in LDS, so scaling and both x transforms cost one pass.
+//   4. y, complex, inverse.
+//   5. z, complex -> real (mirror of 1).
+// Each 1-D transform is a Stockham autosort FFT in LDS (ping-pong buffers)
+// with radices 8, 4, 2, 3, 5 and a twiddle table computed on the host in
+// double.  A block transforms several lines at once; lines of the strided
+// passes are taken along the contiguous kz / (y,kz) index so global loads
+// and stores are coalesced.
+#include <cmath>
+
+#include "pe_internal.hpp"
+
+namespace pe {
+
+template <typename T> struct C2;
+template <> struct C2<float> { using type = float2; };
+template <> struct C2<double> { using type = double2; };
+
+namespace {
+
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { return {a.x + b.x, a.y + b.y}; }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { return {a.x - b.x, a.y - b.y}; }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// multiply by -i*s (s = +1 forward: -i; s = -1 inverse: +i)
+template <typename C>
+__device__ __forceinline__ C mul_mi(C a, int s) { return s > 0 ? C{a.y, -a.x} : C{-a.y, a.x}; }
+
+// In-register DFT of size R; fwd = +1 for exp(-2 pi i ...), -1 for inverse.
+template <typename T, typename C>
+__device__ __forceinline__ void dft2(C& a, C& b) {
+  C t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <typename T, typename C>
+__device__ __forceinline__ void dft4(C& v0, C& v1, C& v2, C& v3, int fwd) {
+  C t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = mul_mi(csub(v1, v3), fwd);
+  v0 = cadd(t0, t2);
+  v2 = csub(t0, t2);
+  v1 = cadd(t1, t3);
+  v3 = csub(t1, t3);
+}
+
+template <typename T, typename C>
+__device__ __forceinline__ void butterfly(int R, C* v, int fwd) {
+  const T r2 = (T)0.70710678118654752440;
+  if (R == 2) {
+    dft2<T, C>(v[0], v[1]);
+  } else if (R == 4) {
+    dft4<T, C>(v[0], v[1], v[2], v[3], fwd);
+  } else if (R == 8) {
+    // even / odd halves, then combine with W8^k
+    dft4<T, C>(v[0], v[2], v[4], v[6], fwd);
+    dft4<T, C>(v[1], v[3], v[5], v[7], fwd);
+    // W8^1 = (1 - i fwd)/sqrt2, W8^2 = -i fwd, W8^3 = (-1 - i fwd)/sqrt2
+    C o1 = v[3], o2 = v[5], o3 = v[7];
+    C w1 = {r2, -r2 * (T)fwd};
+    C w3 = {-r2, -r2 * (T)fwd};
+    o1 = cmul(o1, w1);
+    o2 = mul_mi(o2, fwd);
+    o3 = cmul(o3, w3);
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1];
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+  } else if (R == 3) {
+    const T s3 = (T)0.86602540378443864676 * (T)fwd;
+    C t = cadd(v[1], v[2]);
+    C u = csub(v[1], v[2]);
+    C a = {v[0].x - (T)0.5 * t.x, v[0].y - (T)0.5 * t.y};
+    // X1 = a - i s3 u, X2 = a + i s3 u
+    C iu = {-s3 * u.y, s3 * u.x};  // i*s3*u
+    v[0] = cadd(v[0], t);
+    v[1] = csub(a, iu);
+    v[2] = cadd(a, iu);
+  } else if (R == 5) {
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = (T)0.95105651629515357212 * (T)fwd, s2 = (T)0.58778525229247312917 * (T)fwd;
+    C a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    C a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    C x0 = cadd(v[0], cadd(a1, a2));
+    C p1 = {v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y};
+    C p2 = {v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y};
+    // -i * (s1 b1 + s2 b2) and -i * (s2 b1 - s1 b2)
+    C q1 = {s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y};
+    C q2 = {s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y};
+    C mq1 = {q1.y, -q1.x}, mq2 = {q2.y, -q2.x};
+    v[0] = x0;
+    v[1] = cadd(p1, mq1);
+    v[4] = csub(p1, mq1);
+    v[2] = cadd(p2, mq2);
+    v[3] = csub(p2, mq2);
+  }
+}
+
+// Transform `nl` lines of length n held in LDS (`in`, line stride ls).
+// Returns the buffer that holds the result (in or out).
+template <typename T, typename C>
+__device__ C* lds_fft(C* in, C* out, int n, int nl, int ls, const FFTPlan1D& plan,
+                      const C* __restrict__ tw, int fwd) {
+  int Ns = 1;
+  for (int s = 0; s < plan.nstage; ++s) {
+    const int R = plan.radix[s];
+    const int nb = n / R;
+    const int tws = n / (Ns * R);
+    for (int t = threadIdx.x; t < nl * nb; t += blockDim.x) {
+      const int line = t / nb;
+      const int j = t - line * nb;
+      const int k = j % Ns;
+      C v[8];
+      const C* src = in + line * ls;
+      for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+      if (Ns > 1) {
+        for (int r = 1; r < R; ++r) {
+          C w = tw[r * k * tws];
+          if (fwd < 0) w.y = -w.y;
+          v[r] = cmul(v[r], w);
+        }
+      }
+      butterfly<T, C>(R, v, fwd);
+      C* dst = out + line * ls;
+      const int base = (j / Ns) * Ns * R + k;
+      for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+    }
+    __syncthreads();
+    C* tmp = in;
+    in = out;
+    out = tmp;
+    Ns *= R;
+  }
+  return in;
+}
+
+// Green's function of the wave-space part, with the inverse-DFT normalization.
+struct ScaleArgs {
+  int Nx, Ny, Nz, Nzc;
+  double kfx, kfy, kfz;   // 2 pi / L
+  double gexp;            // (1 - eta) / (4 xi^2)
+  double norm;            // 1 / (Nx Ny Nz)
+};
+
+__device__ __forceinline__ int signed_idx(int m, int N) { return (m < (N + 1) / 2) ? m : m - N; }
+
+// Lines along a strided axis: line L (0..nlines-1), element j at
+// base(L) + j*stride, base(L) = (L / inner) * outer + (L % inner).
+template <typename T, bool SCALE>
+__global__ void __launch_bounds__(256) fft_lines_kernel(typename C2<T>::type* __restrict__ data, int n,
+                                                        int64_t nlines, int64_t inner, int64_t outer,
+                                                        int64_t stride, int lpb, FFTPlan1D plan,
+                                                        const typename C2<T>::type* __restrict__ tw,
+                                                        int fwd, ScaleArgs sa) {
+  using C = typename C2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* b0 = reinterpret_cast<C*>(smem_raw);
+  const int ls = n + 1;
+  C* b1 = b0 + lpb * ls;
+  const int64_t L0 = (int64_t)blockIdx.x * lpb;
+  for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
+    const int j = t / lpb;
+    const int c = t - j * lpb;
+    const int64_t L = L0 + c;
+    C v = {0, 0};
+    if (L < nlines) v = data[(L / inner) * outer + (L % inner) + (int64_t)j * stride];
+    b0[c * ls + j] = v;
+  }
+  __syncthreads();
+  C* res = lds_fft<T, C>(b0, b1, n, lpb, ls, plan, tw, fwd);
+  if (SCALE) {
+    // x lines: j = x index, L = y * Nzc + kz
+    for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
+      const int c = t / n;
+      const int j = t - c * n;
+      const int64_t L = L0 + c;
+      if (L >= nlines) continue;
+      const int y = (int)(L / sa.Nzc);
+      const int kz = (int)(L - (int64_t)y * sa.Nzc);
+      const double kx = sa.kfx * signed_idx(j, sa.Nx);
+      const double ky = sa.kfy * signed_idx(y, sa.Ny);
+      const double kzz = sa.kfz * kz;
+      const double k2 = kx * kx + ky * ky + kzz * kzz;
+      const T gk = k2 > 0 ? (T)(exp(-sa.gexp * k2) / k2 * sa.norm) : (T)0;
+      C v = res[c * ls + j];
+      res[c * ls + j] = {v.x * gk, v.y * gk};
+    }
+    __syncthreads();
+    C* other = (res == b0) ? b1 : b0;
+    res = lds_fft<T, C>(res, other, n, lpb, ls, plan, tw, -fwd);
+  }
+  for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
+    const int j = t / lpb;
+    const int c = t - j * lpb;
+    const int64_t L = L0 + c;
+    if (L < nlines) data[(L / inner) * outer + (L % inner) + (int64_t)j * stride] = res[c * ls + j];
+  }
+}
+
+// z pass, real -> half complex, two real lines per complex transform.
+template <typename T>
+__global__ void __launch_bounds__(256) fft_z_r2c_kernel(T* __restrict__ real,
+                                                        typename C2<T>::type* __restrict__ cplx,
+                                                        int Nz, int64_t nlines, int ppb, FFTPlan1D plan,
+                                                        const typename C2<T>::type* __restrict__ tw) {
+  using C = typename C2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* b0 = reinterpret_cast<C*>(smem_raw);
+  const int ls = Nz + 1;
+  C* b1 = b0 + ppb * ls;
+  const int Nzc = Nz / 2 + 1;
+  const int64_t p0 = (int64_t)blockIdx.x * ppb;
+  for (int t = threadIdx.x; t < Nz * ppb; t += blockDim.x) {
+    const int c = t / Nz;
+    const int j = t - c * Nz;
+    const int64_t la = 2 * (p0 + c), lb = la + 1;
+    T a = 0, b = 0;
+    if (la < nlines) {
+      a = real[la * Nz + j];
+      real[la * Nz + j] = 0;
+    }
+    if (lb < nlines) {
+      b = real[lb * Nz + j];
+      real[lb * Nz + j] = 0;
+    }
+    b0[c * ls + j] = {a, b};
+  }
+  __syncthreads();
+  C* res = lds_fft<T, C>(b0, b1, Nz, ppb, ls, plan, tw, 1);
+  for (int t = threadIdx.x; t < Nzc * ppb; t += blockDim.x) {
+    const int c = t / Nzc;
+    const int k = t - c * Nzc;
+    const int64_t la = 2 * (p0 + c), lb = la + 1;
+    const C zk = res[c * ls + k];
+    const C zn = res[c * ls + ((Nz - k) % Nz)];
+    // A = (Z_k + conj Z_{N-k}) / 2 ; B = (Z_k - conj Z_{N-k}) / (2i)
+    const C A = {(T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y - zn.y)};
+    const T dr = zk.x - zn.x, di = zk.y + zn.y;
+    const C Bv = {(T)0.5 * di, (T)-0.5 * dr};
+    if (la < nlines) cplx[la * Nzc + k] = A;
+    if (lb < nlines) cplx[lb * Nzc + k] = Bv;
+  }
+}
+
+// z pass, half complex -> real (unnormalized inverse), two lines at once.
+template <typename T>
+__global__ void __launch_bounds__(256) fft_z_c2r_kernel(const typename C2<T>::type* __restrict__ cplx,
+                                                        T* __restrict__ real, int Nz, int64_t nlines,
+                                                        int ppb, FFTPlan1D plan,
+                                                        const typename C2<T>::type* __restrict__ tw) {
+  using C = typename C2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* b0 = reinterpret_cast<C*>(smem_raw);
+  const int ls = Nz + 1;
+  C* b1 = b0 + ppb * ls;
+  const int Nzc = Nz / 2 + 1;
+  const int64_t p0 = (int64_t)blockIdx.x * ppb;
+  for (int t = threadIdx.x; t < Nz * ppb; t += blockDim.x) {
+    const int c = t / Nz;
+    const int k = t - c * Nz;
+    const int64_t la = 2 * (p0 + c), lb = la + 1;
+    C A = {0, 0}, Bv = {0, 0};
+    if (k < Nzc) {
+      if (la < nlines) A = cplx[la * Nzc + k];
+      if (lb < nlines) Bv = cplx[lb * Nzc + k];
+    } else {
+      if (la < nlines) { A = cplx[la * Nzc + (Nz - k)]; A.y = -A.y; }
+      if (lb < nlines) { Bv = cplx[lb * Nzc + (Nz - k)]; Bv.y = -Bv.y; }
+    }
+    b0[c * ls + k] = {A.x - Bv.y, A.y + Bv.x};  // A + i B
+  }
+  __syncthreads();
+  C* res = lds_fft<T, C>(b0, b1, Nz, ppb, ls, plan, tw, -1);
+  for (int t = threadIdx.x; t < Nz * ppb; t += blockDim.x) {
+    const int c = t / Nz;
+    const int j = t - c * Nz;
+    const int64_t la = 2 * (p0 + c), lb = la + 1;
+    const C z = res[c * ls + j];
+    if (la < nlines) real[la * Nz + j] = z.x;
+    if (lb < nlines) real[lb * Nz + j] = z.y;
+  }
+}
+
+inline int lines_per_block(int n, size_t elem, size_t lds_budget) {
+  // two ping-pong buffers of (n+1) complex per line
+  int l = (int)(lds_budget / (2 * (size_t)(n + 1) * elem));
+  if (l < 1) l = 1;
+  if (l > 64) l = 64;
+  return l;
+}
+
+}  // namespace
+
+void make_fft_plan(int n, FFTPlan1D& plan) {
+  require(n >= 1 && n <= 1024, "FFT length must be in [1, 1024]");
+  plan.n = n;
+  plan.nstage = 0;
+  int m = n;
+  while (m > 1) {
+    int r;
+    if (m % 8 == 0) r = 8;
+    else if (m % 4 == 0) r = 4;
+    else if (m % 2 == 0) r = 2;
+    else if (m % 3 == 0) r = 3;
+    else if (m % 5 == 0) r = 5;
+    else throw Error(PE_ERR_ARG, "mesh size " + std::to_string(n) + " has a prime factor other than 2, 3, 5");
+    require(plan.nstage < 16, "FFT length has too many factors");
+    plan.radix[plan.nstage++] = r;
+    m /= r;
+  }
+}
+
+template <typename T>
+void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv) {
+  using C = typename C2<T>::type;
+  C* gC = reinterpret_cast<C*>(gCv);
+  const GridGeom& g = c->gg;
+  const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2], Nzc = g.Nzc;
+  const C* twx;
+  const C* twy;
+  const C* twz;
+  if constexpr (sizeof(T) == 8) {
+    twx = c->tw64[0].get(); twy = c->tw64[1].get(); twz = c->tw64[2].get();
+  } else {
+    twx = c->tw32[0].get(); twy = c->tw32[1].get(); twz = c->tw32[2].get();
+  }
+  const size_t budget = 64 * 1024;
+  // 1. z, r2c
+  {
+    const int64_t nlines = (int64_t)Nx * Ny;
+    const int ppb = lines_per_block(Nz, sizeof(C), budget);
+    const int64_t npairs = (nlines + 1) / 2;
+    const unsigned nb = (unsigned)((npairs + ppb - 1) / ppb);
+    const size_t sh = 2 * (size_t)ppb * (Nz + 1) * sizeof(C);
+    hipLaunchKernelGGL(fft_z_r2c_kernel<T>, dim3(nb), dim3(256), sh, s, gA, gC, Nz, nlines, ppb,
+                       c->plan[2], twz);
+    PE_CHECK_LAUNCH();
+  }
+  ScaleArgs sa{};
+  sa.Nx = Nx; sa.Ny = Ny; sa.Nz = Nz; sa.Nzc = Nzc;
+  sa.kfx = 2 * M_PI / g.L[0]; sa.kfy = 2 * M_PI / g.L[1]; sa.kfz = 2 * M_PI / g.L[2];
+  sa.gexp = (1.0 - c->eta) / (4.0 * c->xi * c->xi);
+  sa.norm = 1.0 / ((double)Nx * Ny * Nz);
+  // 2. y forward: lines (x, kz), element y
+  auto ypass = [&](int fwd) {
+    const int64_t nlines = (int64_t)Nx * Nzc;
+    const int lpb = lines_per_block(Ny, sizeof(C), budget);
+    const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
+    const size_t sh = 2 * (size_t)lpb * (Ny + 1) * sizeof(C);
+    hipLaunchKernelGGL((fft_lines_kernel<T, false>), dim3(nb), dim3(256), sh, s, gC, Ny, nlines,
+                       (int64_t)Nzc, (int64_t)Ny * Nzc, (int64_t)Nzc, lpb, c->plan[1], twy, fwd, sa);
+    PE_CHECK_LAUNCH();
+  };
+  ypass(1);
+  // 3. x forward + scale + x inverse: lines (y, kz), element x
+  {
+    const int64_t nlines = (int64_t)Ny * Nzc;
+    const int lpb = lines_per_block(Nx, sizeof(C), budget);
+    const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
+    const size_t sh = 2 * (size_t)lpb * (Nx + 1) * sizeof(C);
+    hipLaunchKernelGGL((fft_lines_kernel<T, true>), dim3(nb), dim3(256), sh, s, gC, Nx, nlines,
+                       nlines, (int64_t)0, (int64_t)Ny * Nzc, lpb, c->plan[0], twx, 1, sa);
+    PE_CHECK_LAUNCH();
+  }
+  // 4. y inverse
+  ypass(-1);
+  // 5. z, c2r into grid B
+  {
+    const int64_t nlines = (int64_t)Nx * Ny;
+    const int ppb = lines_per_block(Nz, sizeof(C), budget);
+    const int64_t npairs = (nlines + 1) / 2;
+    const unsigned nb = (unsigned)((npairs + ppb - 1) / ppb);
+    const size_t sh = 2 * (size_t)ppb * (Nz + 1) * sizeof(C);
+    hipLaunchKernelGGL(fft_z_c2r_kernel<T>, dim3(nb), dim3(256), sh, s, gC, gB, Nz, nlines, ppb,
+                       c->plan[2], twz);
+    PE_CHECK_LAUNCH();
+  }
+}
+
+template void launch_wave_pipeline<float>(hipStream_t, pe_context*, float*, float*, void*);
+template void launch_wave_pipeline<double>(hipStream_t, pe_context*, double*, double*, void*);
+
+}  // namespace pe

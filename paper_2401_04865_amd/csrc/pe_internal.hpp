@@ -1,0 +1,219 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pe.h"
+
+namespace pe {
+
+// ----------------------------------------------------------------- errors
+
+struct Error : std::runtime_error {
+  pe_status code;
+  Error(pe_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define PE_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::pe::Error(PE_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define PE_CHECK_LAUNCH() PE_HIP(hipGetLastError())
+
+inline void require(bool ok, const std::string& msg) {
+  if (!ok) throw Error(PE_ERR_ARG, msg);
+}
+
+// ----------------------------------------------------------- device buffer
+
+// Device allocation owned by the context; grows on demand, never shrinks.
+template <typename T>
+struct DevBuf {
+  T* ptr = nullptr;
+  size_t cap = 0;  // elements
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+  }
+  T* ensure(size_t n) {
+    if (n <= cap && ptr) return ptr;
+    release();
+    size_t bytes = (n ? n : 1) * sizeof(T);
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      throw Error(PE_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    cap = n ? n : 1;
+    return ptr;
+  }
+  T* get() const { return ptr; }
+  operator T*() const { return ptr; }
+};
+
+// ---------------------------------------------------------------- geometry
+
+// Spectral-Ewald grid geometry and window constants (passed by value).
+struct GridGeom {
+  int N[3];         // mesh
+  int Nzc;          // N[2]/2 + 1
+  double h[3];      // spacing
+  double inv_h[3];
+  double L[3];
+  int P;            // support per axis
+  double wexp;      // 2 xi^2 / eta   (w = wnorm * exp(-wexp d^2) per axis)
+  double wnorm;     // sqrt(2 xi^2 / (pi eta))
+  double h3;        // h_x h_y h_z
+  double eps;
+  double fcoef;     // -4 xi^2 h3 / (eps eta)  (field prefactor)
+};
+
+// Real-space geometry.
+struct RealGeom {
+  double L[3];
+  double inv_L[3];
+  int nc[3];        // cells per axis (1 or >= 3)
+  double cell_inv[3];
+  double rc2;
+  double xi;
+  double eps;
+  int reg;          // pe_reg
+  double a;         // shell radius
+};
+
+// A particle set sorted by real-space cell.
+struct ParticleSet {
+  int64_t n = 0;
+  DevBuf<double4> pos;      // sorted: wrapped x,y,z and sigma in w
+  DevBuf<int> idx;          // sorted slot -> caller index within the set
+  DevBuf<int> cell_start;   // ncell + 1
+  DevBuf<int> cell_count;   // ncell (scratch)
+  DevBuf<int> cell_of;      // caller order (scratch)
+  DevBuf<double4> tmp;      // caller order wrapped positions (scratch)
+};
+
+// 1-D FFT factorization (radices 8, 4, 2, 3, 5).
+struct FFTPlan1D {
+  int n;
+  int nstage;
+  int radix[16];
+};
+
+// ----------------------------------------------------------------- context
+
+struct LearnedGuess;  // defined in the guess translation unit
+
+}  // namespace pe
+
+struct pe_context {
+  pe_params p;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // derived parameters
+  double xi = 0, rc = 0, eta = 0, hmax = 0, V = 0;
+  pe::GridGeom gg{};
+  pe::RealGeom rg{};
+  pe::FFTPlan1D plan[3]{};
+  pe::DevBuf<double2> tw64[3];
+  pe::DevBuf<float2> tw32[3];
+
+  // system
+  bool have_system = false;
+  bool have_solution = false;
+  bool have_forces = false;
+  int64_t n_body = 0, n_bead = 0, n_ion = 0;
+  std::vector<int64_t> h_off;
+  double E0[3] = {0, 0, 0};
+  pe::DevBuf<int64_t> off;
+  pe::DevBuf<int> body_of;
+  pe::DevBuf<double> rel;          // n_bead x 3, r_ij
+  pe::DevBuf<double> bead_x;       // n_bead x 3 unwrapped copy
+  pe::DevBuf<double> ion_x;        // n_ion x 3 unwrapped copy
+  pe::DevBuf<double> bead_sig, ion_sig, ion_q, body_Q, quat;
+  pe::DevBuf<int> body_type;
+  pe::ParticleSet B, I;
+  double bead_sig_uniform = -1.0;  // >0 if all bead widths are equal
+
+  // bead-bead real-space operator, sliced ELLPACK with 64-row slices
+  int64_t nslice = 0, nnz = 0;
+  pe::DevBuf<int64_t> slice_ptr;
+  pe::DevBuf<int> cnt;
+  pe::DevBuf<int> col;
+  pe::DevBuf<double> val64;
+  pe::DevBuf<float> val32;
+  bool have_val32 = false;
+
+  // grids (sized for double; float reuses the same memory)
+  pe::DevBuf<double> gridA, gridB;
+  pe::DevBuf<double2> gridC;
+
+  // per-particle scratch in caller order
+  pe::DevBuf<double> phi_w, phi_all, E_all;   // (n_bead+n_ion), (n_bead+n_ion)x3
+  pe::DevBuf<double> sums;                     // body sums / totals scratch
+  pe::DevBuf<double> red;                      // reduction partials
+
+  // Krylov
+  pe::DevBuf<double> Vb;       // (m+1) x n basis
+  pe::DevBuf<double> kvec;     // x, b, r, w, ... (several n-vectors)
+  pe::DevBuf<double> hs;       // Hessenberg, rotations, g, y, scalars
+  pe::DevBuf<double> rhs_b;    // right-hand side
+  pe::DevBuf<double> xsol;     // last solution [q; dpsi]
+  pe::DevBuf<double> forces;   // f per particle (n_bead+n_ion) x 3
+  pe::DevBuf<double> host_pin; // unused placeholder
+
+  // learned guess
+  pe::LearnedGuess* guess = nullptr;
+};
+
+namespace pe {
+
+// ------------------------------------------------------------ launchers
+// (each enqueues on the given stream; geometry passed by value)
+
+// grid: spread charges q (indexed by caller index through idx) into grid (accumulate)
+template <typename T>
+void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* grid, const GridGeom& g);
+// grid: gather potential (and optionally field) at the particles of ps;
+// writes (or adds, if accumulate) phi[idx] and E[idx*3+d]
+template <typename T>
+void launch_gather(hipStream_t s, const ParticleSet& ps, const T* grid, const GridGeom& g,
+                   double* phi, double* E, bool accumulate);
+
+// FFT pipeline: real grid A (zeroed on read) -> complex -> scaled -> real grid B
+template <typename T>
+void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gridA, T* gridB, void* gridC);
+void make_fft_plan(int n, FFTPlan1D& plan);
+
+// real space
+void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
+                 double sig_const, int64_t n, const RealGeom& rg);
+void build_bead_matrix(pe_context* c);
+template <typename T>
+void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const double* dpsi,
+                          const double* phi_wave, const double* ck0, double* y_top);
+template <typename T>
+void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet& src,
+                       const double* q_src, const RealGeom& rg, double* phi, double* E);
+
+// body / vector kernels
+void launch_body_sums(hipStream_t s, pe_context* c, const double* q, double* out_sum, double* out_sig2);
+void launch_seg_totals(hipStream_t s, int64_t n_body, const double* body_sum, const double* body_sig2,
+                       double* totals);
+void launch_zero(hipStream_t s, double* p, int64_t n);
+
+}  // namespace pe

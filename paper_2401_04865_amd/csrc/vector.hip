@@ -1,0 +1,349 @@
+// Double-precision reductions and vector kernels: charge moments for the k=0
+// constant of the split, per-body segmented sums (the summation tensor
+// Sigma and its transpose, appendix "Summation Tensors"), body outputs
+// (dipole, force, torque, energy), and the GMRES building blocks (multi-dot
+// and multi-axpy for classical Gram-Schmidt, Givens rotations, back
+// substitution).  Every reduction is two-stage with a fixed order, so
+// results are bitwise reproducible run to run.
+#include "pe_internal.hpp"
+#include "vector.hpp"
+
+namespace pe {
+
+namespace {
+
+constexpr int kBS = 256;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of K values per thread; result valid in thread 0 (out[k]).
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* out) {
+  __shared__ double sh[kBS / 64][K > 0 ? K : 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wsum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[w][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// partial[blk*2 + {0,1}] = sum q, sum sigma^2 q over this block's range
+__global__ void __launch_bounds__(kBS) moments_partial_kernel(const double* __restrict__ q,
+                                                              const double* __restrict__ sig,
+                                                              double sig_const, int64_t n,
+                                                              double* __restrict__ partial) {
+  double v[2] = {0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double s = sig ? sig[i] : sig_const;
+    v[0] += q[i];
+    v[1] += s * s * q[i];
+  }
+  __shared__ double o[2];
+  block_sum<2>(v, o);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = o[0];
+    partial[2 * blockIdx.x + 1] = o[1];
+  }
+}
+
+// ck[0], ck[1]: the k=0 constant at a target of width sigma_t is
+// ck[0] - ck[1] sigma_t^2 (see the split in the real-space unit).
+__global__ void moments_final_kernel(const double* __restrict__ partial, int nb, CkCoef cc,
+                                     double* __restrict__ ck, double* __restrict__ tot) {
+  double v[2] = {0, 0};
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    v[0] += partial[2 * i];
+    v[1] += partial[2 * i + 1];
+  }
+  __shared__ double o[2];
+  block_sum<2>(v, o);
+  if (threadIdx.x == 0) {
+    const double Sq = o[0], Ssq = o[1];
+    if (cc.reg == PE_REG_GAUSSIAN) {
+      ck[0] = cc.inv_epsV * (Sq * cc.inv4xi2 - 0.5 * Ssq);
+      ck[1] = cc.inv_epsV * 0.5 * Sq;
+    } else {
+      ck[0] = cc.inv_epsV * (cc.inv4xi2 - cc.a * cc.a / 3.0) * Sq;
+      ck[1] = 0.0;
+    }
+    if (tot) {
+      tot[0] = Sq;
+      tot[1] = Ssq;
+    }
+  }
+}
+
+// out[b] = sum of x over the beads of body b (one block per body)
+__global__ void __launch_bounds__(kBS) seg_sum_kernel(const int64_t* __restrict__ off,
+                                                      const double* __restrict__ x,
+                                                      double* __restrict__ out) {
+  const int b = blockIdx.x;
+  double v[1] = {0};
+  for (int64_t i = off[b] + threadIdx.x; i < off[b + 1]; i += blockDim.x) v[0] += x[i];
+  __shared__ double o[1];
+  block_sum<1>(v, o);
+  if (threadIdx.x == 0) out[b] = o[0];
+}
+
+// Body outputs from bead data: S = sum r q, F = sum f, L = sum r x f, U = sum u.
+__global__ void __launch_bounds__(kBS) body_outputs_kernel(
+    const int64_t* __restrict__ off, const double* __restrict__ rel, const double* __restrict__ q,
+    const double* __restrict__ f, const double* __restrict__ u, double* __restrict__ S,
+    double* __restrict__ F, double* __restrict__ L, double* __restrict__ U) {
+  const int b = blockIdx.x;
+  double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = off[b] + threadIdx.x; i < off[b + 1]; i += blockDim.x) {
+    const double rx = rel[3 * i], ry = rel[3 * i + 1], rz = rel[3 * i + 2];
+    const double qi = q[i];
+    v[0] += rx * qi;
+    v[1] += ry * qi;
+    v[2] += rz * qi;
+    if (f) {
+      const double fx = f[3 * i], fy = f[3 * i + 1], fz = f[3 * i + 2];
+      v[3] += fx;
+      v[4] += fy;
+      v[5] += fz;
+      v[6] += ry * fz - rz * fy;
+      v[7] += rz * fx - rx * fz;
+      v[8] += rx * fy - ry * fx;
+      v[9] += u[i];
+    }
+  }
+  __shared__ double o[10];
+  block_sum<10>(v, o);
+  if (threadIdx.x == 0) {
+    if (S) { S[3 * b] = o[0]; S[3 * b + 1] = o[1]; S[3 * b + 2] = o[2]; }
+    if (F) { F[3 * b] = o[3]; F[3 * b + 1] = o[4]; F[3 * b + 2] = o[5]; }
+    if (L) { L[3 * b] = o[6]; L[3 * b + 1] = o[7]; L[3 * b + 2] = o[8]; }
+    if (U) U[b] = o[9];
+  }
+}
+
+// out[i] = (sum over vectors k of) V_k . w, partial per block, K <= kMaxK
+__global__ void __launch_bounds__(kBS) mdot_partial_kernel(const double* __restrict__ V, int64_t ldv, int K,
+                                                           const double* __restrict__ w, int64_t n,
+                                                           double* __restrict__ partial) {
+  double acc[kMaxK];
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) acc[k] = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K) acc[k] += V[k * ldv + i] * wi;
+  }
+  __shared__ double sh[kBS / 64][kMaxK];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    if (k < K) {
+      const double s = wsum(acc[k]);
+      if (lane == 0) sh[wv][k] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i][threadIdx.x];
+    partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__global__ void mdot_final_kernel(const double* __restrict__ partial, int nb, int K, double* __restrict__ out,
+                                  int sqrt_flag) {
+  // one wavefront per output
+  const int k = blockIdx.x;
+  double s = 0;
+  for (int i = threadIdx.x; i < nb; i += 64) s += partial[(int64_t)k * nb + i];
+  s = wsum(s);
+  if (threadIdx.x == 0) out[k] = sqrt_flag ? sqrt(s) : s;
+}
+
+// w -= sum_k h[k] V_k   (h on the device)
+__global__ void __launch_bounds__(kBS) maxpy_kernel(const double* __restrict__ V, int64_t ldv, int K,
+                                                    const double* __restrict__ h, double* __restrict__ w,
+                                                    int64_t n, double sign) {
+  __shared__ double hs[kMaxK];
+  if (threadIdx.x < K) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int k = 0; k < K; ++k) s += hs[k] * V[k * ldv + i];
+    w[i] -= sign * s;
+  }
+}
+
+// vout = w / *nrm  (guarding a zero norm)
+__global__ void scale_kernel(const double* __restrict__ w, const double* __restrict__ nrm,
+                             double* __restrict__ vout, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = *nrm;
+  vout[i] = d > 0 ? w[i] / d : 0.0;
+}
+
+// y = a*x + b*y
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] = a * x[i] + b * y[i];
+}
+
+// z = x - y
+__global__ void sub_kernel(const double* __restrict__ x, const double* __restrict__ y, double* __restrict__ z,
+                           int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  z[i] = x[i] - y[i];
+}
+
+// Arnoldi column j: h = h1 + h2 (two Gram-Schmidt passes), subdiagonal = norm.
+// Apply the previous rotations, form the new one, update g; store |g[j+1]|.
+// Layout of st (double): H[(m+1) x m] column-major at 0, cs[m], sn[m], g[m+1].
+__global__ void givens_kernel(const double* __restrict__ h1, const double* __restrict__ h2,
+                              const double* __restrict__ nrm, double* __restrict__ st, int m, int j,
+                              double* __restrict__ res) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* H = st;
+  double* cs = st + (m + 1) * m;
+  double* sn = cs + m;
+  double* g = sn + m;
+  double* col = H + (int64_t)j * (m + 1);
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  col[j + 1] = *nrm;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * b;
+    col[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double r = hypot(a, b);
+  const double c = r > 0 ? a / r : 1.0;
+  const double s = r > 0 ? b / r : 0.0;
+  cs[j] = c;
+  sn[j] = s;
+  col[j] = r;
+  col[j + 1] = 0.0;
+  const double gj = g[j];
+  g[j] = c * gj;
+  g[j + 1] = -s * gj;
+  *res = fabs(g[j + 1]);
+}
+
+// g = [beta, 0, ...]
+__global__ void init_g_kernel(double* __restrict__ st, int m, const double* __restrict__ beta) {
+  double* g = st + (m + 1) * m + 2 * m;
+  for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = (i == 0) ? *beta : 0.0;
+}
+
+// Back substitution R y = g for the first k columns; y -> ybuf.
+__global__ void backsolve_kernel(const double* __restrict__ st, int m, int k, double* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double* H = st;
+  const double* g = st + (m + 1) * m + 2 * m;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int l = i + 1; l < k; ++l) s -= H[(int64_t)l * (m + 1) + i] * y[l];
+    const double d = H[(int64_t)i * (m + 1) + i];
+    y[i] = d != 0 ? s / d : 0.0;
+  }
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+inline unsigned nred(int64_t n) {
+  int64_t b = (n + kBS * 4 - 1) / (kBS * 4);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+void launch_moments(hipStream_t s, const double* q, const double* sig, double sig_const, int64_t n,
+                    const CkCoef& cc, double* partial, double* ck, double* tot) {
+  const unsigned nb = nred(n);
+  hipLaunchKernelGGL(moments_partial_kernel, dim3(nb), dim3(kBS), 0, s, q, sig, sig_const, n, partial);
+  PE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(kBS), 0, s, partial, (int)nb, cc, ck, tot);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_seg_sum(hipStream_t s, const int64_t* off, int64_t n_body, const double* x, double* out) {
+  if (n_body == 0) return;
+  hipLaunchKernelGGL(seg_sum_kernel, dim3((unsigned)n_body), dim3(kBS), 0, s, off, x, out);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_body_outputs(hipStream_t s, const int64_t* off, int64_t n_body, const double* rel, const double* q,
+                         const double* f, const double* u, double* S, double* F, double* L, double* U) {
+  if (n_body == 0) return;
+  hipLaunchKernelGGL(body_outputs_kernel, dim3((unsigned)n_body), dim3(kBS), 0, s, off, rel, q, f, u, S, F, L, U);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_mdot(hipStream_t s, const double* V, int64_t ldv, int K, const double* w, int64_t n,
+                 double* partial, double* out, bool take_sqrt) {
+  require(K >= 1 && K <= kMaxK, "mdot: too many vectors");
+  const unsigned nb = nred(n);
+  hipLaunchKernelGGL(mdot_partial_kernel, dim3(nb), dim3(kBS), 0, s, V, ldv, K, w, n, partial);
+  PE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(mdot_final_kernel, dim3(K), dim3(64), 0, s, partial, (int)nb, K, out, take_sqrt ? 1 : 0);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_maxpy(hipStream_t s, const double* V, int64_t ldv, int K, const double* h, double* w, int64_t n,
+                  double sign) {
+  require(K >= 1 && K <= kMaxK, "maxpy: too many vectors");
+  unsigned nb = nblk(n, kBS);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(maxpy_kernel, dim3(nb), dim3(kBS), 0, s, V, ldv, K, h, w, n, sign);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_scale(hipStream_t s, const double* w, const double* nrm, double* vout, int64_t n) {
+  hipLaunchKernelGGL(scale_kernel, dim3(nblk(n, kBS)), dim3(kBS), 0, s, w, nrm, vout, n);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y, int64_t n) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(axpby_kernel, dim3(nblk(n, kBS)), dim3(kBS), 0, s, a, x, b, y, n);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_sub(hipStream_t s, const double* x, const double* y, double* z, int64_t n) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(sub_kernel, dim3(nblk(n, kBS)), dim3(kBS), 0, s, x, y, z, n);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_givens(hipStream_t s, const double* h1, const double* h2, const double* nrm, double* st, int m,
+                   int j, double* res) {
+  hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, s, h1, h2, nrm, st, m, j, res);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_init_g(hipStream_t s, double* st, int m, const double* beta) {
+  hipLaunchKernelGGL(init_g_kernel, dim3(1), dim3(64), 0, s, st, m, beta);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_backsolve(hipStream_t s, const double* st, int m, int k, double* y) {
+  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, s, st, m, k, y);
+  PE_CHECK_LAUNCH();
+}
+
+}  // namespace pe

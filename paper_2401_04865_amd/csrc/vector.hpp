@@ -1,0 +1,41 @@
+// Declarations of the double-precision vector and reduction launchers.
+#pragma once
+
+#include "pe_internal.hpp"
+
+namespace pe {
+
+constexpr int kMaxK = 32;  // max Krylov vectors in one multi-dot (restart + 1)
+
+// Coefficients of the k = 0 constant of the split.
+struct CkCoef {
+  int reg;
+  double inv_epsV;  // 1 / (eps V)
+  double inv4xi2;   // 1 / (4 xi^2)
+  double a;         // shell radius
+};
+
+void launch_moments(hipStream_t s, const double* q, const double* sig, double sig_const, int64_t n,
+                    const CkCoef& cc, double* partial, double* ck, double* tot);
+void launch_seg_sum(hipStream_t s, const int64_t* off, int64_t n_body, const double* x, double* out);
+void launch_body_outputs(hipStream_t s, const int64_t* off, int64_t n_body, const double* rel, const double* q,
+                         const double* f, const double* u, double* S, double* F, double* L, double* U);
+void launch_mdot(hipStream_t s, const double* V, int64_t ldv, int K, const double* w, int64_t n,
+                 double* partial, double* out, bool take_sqrt);
+void launch_maxpy(hipStream_t s, const double* V, int64_t ldv, int K, const double* h, double* w, int64_t n,
+                  double sign);
+void launch_scale(hipStream_t s, const double* w, const double* nrm, double* vout, int64_t n);
+void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y, int64_t n);
+void launch_sub(hipStream_t s, const double* x, const double* y, double* z, int64_t n);
+void launch_givens(hipStream_t s, const double* h1, const double* h2, const double* nrm, double* st, int m,
+                   int j, double* res);
+void launch_init_g(hipStream_t s, double* st, int m, const double* beta);
+void launch_backsolve(hipStream_t s, const double* st, int m, int k, double* y);
+
+// per-particle kernels of the solve / force passes (solver unit)
+void launch_rhs_top(hipStream_t s, int64_t n, const double* rel, const double* E0, const double* phi_ion,
+                    double* b);
+void launch_forces_energy(hipStream_t s, int64_t n, const double* chg, const double* pos, const double* E0v,
+                          const double* phi, const double* E, double* f, double* u);
+
+}  // namespace pe
