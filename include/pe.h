@@ -108,6 +108,7 @@ typedef struct pe_solve_info {
   int32_t matvecs_fp32;       /* float operator applications */
   double rel_residual;        /* final ||b - A x||/||b||, double operator */
   double rel_residual_guess;  /* same, at the initial guess */
+  double rhs_norm;            /* ||b||, so ||b - A x|| = rel_residual * rhs_norm */
   double t_rhs, t_guess, t_solve, t_total; /* seconds */
   int32_t n_hist;             /* residual estimates recorded in hist */
   double hist[1024];
@@ -195,6 +196,40 @@ pe_status pe_solve_polarization(pe_context* ctx, const double* q_init, double* q
 pe_status pe_forces_torques(pe_context* ctx, double* body_force, double* body_torque,
                             double* body_energy, double* ion_force, double* bead_force,
                             double* total_energy);
+
+/*
+ * The saddle-point operator itself (the matrix of eq. "saddle", ions
+ * eliminated): y = [-M q + Sigma^T dPsi ; Sigma q] for x = [q ; dPsi].  This is
+ * the product every Krylov iteration evaluates: one bead-only spectral-Ewald
+ * pass (spread, FFT, scale, inverse FFT, gather) plus the stored bead-bead
+ * real-space operator, plus the per-body sums.
+ *   x, y  dev n_bead + n_body;  precision PE_FP64 or PE_MIXED (float kernels)
+ */
+pe_status pe_apply_saddle(pe_context* ctx, const double* x, double* y, int32_t precision);
+
+/*
+ * Kernel timing with HIP events recorded around every launch on the
+ * context's stream, accumulated per kernel class and precision.
+ * pe_profile_enable(ctx, 1) resets and starts; pe_profile_read fills
+ * out[4*PE_PROF_NCLASS] with (launch count, total milliseconds) per class in
+ * enum order, first for the float kernels, then for the double kernels (the
+ * Krylov vector kernels are always double).
+ */
+typedef enum {
+  PE_PROF_SPREAD = 0,
+  PE_PROF_FFT_Z_R2C,
+  PE_PROF_FFT_Y_FWD,
+  PE_PROF_FFT_X_SCALE,
+  PE_PROF_FFT_Y_INV,
+  PE_PROF_FFT_Z_C2R,
+  PE_PROF_GATHER,
+  PE_PROF_SPMV,
+  PE_PROF_PAIR,
+  PE_PROF_KRYLOV,
+  PE_PROF_NCLASS
+} pe_prof_class;
+pe_status pe_profile_enable(pe_context* ctx, int32_t on);
+pe_status pe_profile_read(pe_context* ctx, double* out);
 
 /*
  * Learned initial guess (a per-bead network, not in the paper).  Features of

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libpe.so")
 PE_OK, PE_ERR_ARG, PE_ERR_STATE, PE_ERR_DEVICE, PE_ERR_NOMEM, PE_ERR_NOT_CONVERGED, PE_ERR_NUMERIC = range(7)
 PE_FP64, PE_MIXED = 0, 1
 PE_REG_GAUSSIAN, PE_REG_SHELL = 0, 1
+PROF_CLASSES = ["spread", "fft_z_r2c", "fft_y_fwd", "fft_x_scale", "fft_y_inv", "fft_z_c2r", "gather",
+                "spmv", "pair", "krylov"]
 STATUS_NAMES = {0: "PE_OK", 1: "PE_ERR_ARG", 2: "PE_ERR_STATE", 3: "PE_ERR_DEVICE", 4: "PE_ERR_NOMEM",
                 5: "PE_ERR_NOT_CONVERGED", 6: "PE_ERR_NUMERIC"}
 
@@ -52,6 +54,7 @@ class pe_solve_info(ctypes.Structure):
         ("matvecs_fp32", ctypes.c_int32),
         ("rel_residual", ctypes.c_double),
         ("rel_residual_guess", ctypes.c_double),
+        ("rhs_norm", ctypes.c_double),
         ("t_rhs", ctypes.c_double),
         ("t_guess", ctypes.c_double),
         ("t_solve", ctypes.c_double),
@@ -89,6 +92,9 @@ SIGNATURES = {
     "pe_apply_potential": [_vp, _vp, _vp, _vp, _i32],
     "pe_solve_polarization": [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(pe_solve_info)],
     "pe_forces_torques": [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_dbl)],
+    "pe_apply_saddle": [_vp, _vp, _vp, _i32],
+    "pe_profile_enable": [_vp, _i32],
+    "pe_profile_read": [_vp, ctypes.POINTER(_dbl)],
     "pe_guess_init": [_vp, _u64],
     "pe_guess_set_types": [_vp, ctypes.POINTER(_i32)],
     "pe_guess_record": [_vp, _vp],
@@ -213,6 +219,22 @@ class Context:
 
     def pe_apply_potential(self, charges, psi_out, field_out=None, precision=PE_FP64):
         self._chk(_lib.pe_apply_potential(self.h, _ptr(charges), _ptr(psi_out), _ptr(field_out), int(precision)))
+
+    def pe_apply_saddle(self, x, y, precision=PE_FP64):
+        self._chk(_lib.pe_apply_saddle(self.h, _ptr(x), _ptr(y), int(precision)))
+
+    def pe_profile_enable(self, on=True):
+        self._chk(_lib.pe_profile_enable(self.h, 1 if on else 0))
+
+    def pe_profile_read(self):
+        """{class: (launches, total ms)} for float kernels, {class + '_f64': ...} for double."""
+        nc = len(PROF_CLASSES)
+        out = (ctypes.c_double * (4 * nc))()
+        self._chk(_lib.pe_profile_read(self.h, out))
+        res = {n: (int(out[2 * i]), float(out[2 * i + 1])) for i, n in enumerate(PROF_CLASSES)}
+        res.update({n + "_f64": (int(out[2 * (nc + i)]), float(out[2 * (nc + i) + 1]))
+                    for i, n in enumerate(PROF_CLASSES)})
+        return res
 
     def pe_solve_polarization(self, q_init, q_out, dpsi_out, dipole_out=None, check=True):
         info = pe_solve_info()

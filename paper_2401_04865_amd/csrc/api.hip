@@ -179,10 +179,10 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
   launch_seg_sum(s, c->off.get(), c->n_body, q, y + nb);
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
-  launch_spread<T>(s, c->B, q, gA, c->gg);
+  { ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8); launch_spread<T>(s, c->B, q, gA, c->gg); }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
-  launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false);
-  launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), ck_bead(c), y);
+  { ProfScope ps(c->prof, s, PE_PROF_GATHER, sizeof(T) == 8); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
+  { ProfScope ps(c->prof, s, PE_PROF_SPMV, sizeof(T) == 8); launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), ck_bead(c), y); }
 }
 
 void apply_saddle_prec(pe_context* c, int prec, const double* x, double* y) {
@@ -204,11 +204,18 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
   if (ni) launch_moments(s, qi, c->ion_sig.get(), 0.0, ni, ck_coef(c), c->red.get(), ck_ion(c), nullptr);
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
-  launch_spread<T>(s, c->B, qb, gA, c->gg);
-  if (ni) launch_spread<T>(s, c->I, qi, gA, c->gg);
+  {
+    ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8);
+    launch_spread<T>(s, c->B, qb, gA, c->gg);
+    if (ni) launch_spread<T>(s, c->I, qi, gA, c->gg);
+  }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
-  launch_gather<T>(s, c->B, gB, c->gg, phi, E, true);
-  if (ni) launch_gather<T>(s, c->I, gB, c->gg, phi + nb, E ? E + 3 * nb : nullptr, true);
+  {
+    ProfScope ps(c->prof, s, PE_PROF_GATHER, sizeof(T) == 8);
+    launch_gather<T>(s, c->B, gB, c->gg, phi, E, true);
+    if (ni) launch_gather<T>(s, c->I, gB, c->gg, phi + nb, E ? E + 3 * nb : nullptr, true);
+  }
+  ProfScope ps_pair(c->prof, s, PE_PROF_PAIR, sizeof(T) == 8);
   launch_pair_onfly<T>(s, c->B, c->B, qb, c->rg, phi, E);
   if (ni) {
     launch_pair_onfly<T>(s, c->B, c->I, qi, c->rg, phi, E);
@@ -288,6 +295,7 @@ double fetch(pe_context* c, const double* d) {
   double h;
   PE_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   PE_HIP(hipStreamSynchronize(c->stream));
+  c->prof.flush();
   return h;
 }
 
@@ -335,13 +343,16 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
       double* vj = k.V + (size_t)j * n;
       apply_saddle_prec(c, prec, vj, k.w);
       (prec == PE_MIXED ? *mv32 : *mv64) += 1;
-      launch_mdot(s, k.V, n, j + 1, k.w, n, partial, k.h1, false);
-      launch_maxpy(s, k.V, n, j + 1, k.h1, k.w, n, 1.0);
-      launch_mdot(s, k.V, n, j + 1, k.w, n, partial, k.h2, false);
-      launch_maxpy(s, k.V, n, j + 1, k.h2, k.w, n, 1.0);
-      launch_mdot(s, k.w, n, 1, k.w, n, partial, k.nrm, true);
-      launch_scale(s, k.w, k.nrm, k.V + (size_t)(j + 1) * n, n);
-      launch_givens(s, k.h1, k.h2, k.nrm, k.st, m, j, k.res);
+      {
+        ProfScope ps(c->prof, s, PE_PROF_KRYLOV, true);
+        launch_mdot(s, k.V, n, j + 1, k.w, n, partial, k.h1, false);
+        launch_maxpy(s, k.V, n, j + 1, k.h1, k.w, n, 1.0);
+        launch_mdot(s, k.V, n, j + 1, k.w, n, partial, k.h2, false);
+        launch_maxpy(s, k.V, n, j + 1, k.h2, k.w, n, 1.0);
+        launch_mdot(s, k.w, n, 1, k.w, n, partial, k.nrm, true);
+        launch_scale(s, k.w, k.nrm, k.V + (size_t)(j + 1) * n, n);
+        launch_givens(s, k.h1, k.h2, k.nrm, k.st, m, j, k.res);
+      }
       const double est = fetch(c, k.res);
       out.iters += 1;
       if (info && info->n_hist < 1024) info->hist[info->n_hist++] = est / bnorm;
@@ -660,6 +671,7 @@ pe_status pe_apply_potential(pe_context* c, const double* charges, double* psi_o
   else
     all_potential<double>(c, charges, charges + nb, psi_out, field_out, nullptr, nullptr, nullptr);
   PE_HIP(hipStreamSynchronize(c->stream));
+  c->prof.flush();
   PE_API_END(c)
 }
 
@@ -684,6 +696,7 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
   KWork k = kwork(c, n, std::max(1, std::min(c->p.gmres_restart, kMaxK - 1)));
   launch_mdot(s, b, n, 1, b, n, c->red.get(), k.nrm, true);
   const double bnorm = fetch(c, k.nrm);
+  inf->rhs_norm = bnorm;
   const auto t1 = Clock::now();
   // initial guess
   bool x_zero = true;
@@ -764,6 +777,7 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
   if (dipole_out) launch_body_outputs(s, c->off.get(), nbody, c->rel.get(), x, nullptr, nullptr, dipole_out,
                                       nullptr, nullptr, nullptr);
   PE_HIP(hipStreamSynchronize(s));
+  c->prof.flush();
   const auto t3 = Clock::now();
   inf->t_rhs = secs(t0, t1);
   inf->t_guess = secs(t1, t2);
@@ -773,6 +787,40 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
   if (status != PE_OK) {
     c->err = status == PE_ERR_NOT_CONVERGED ? "GMRES did not reach rel_tol within max_iters" : "solve failed";
     return status;
+  }
+  PE_API_END(c)
+}
+
+pe_status pe_apply_saddle(pe_context* c, const double* x, double* y, int32_t precision) {
+  if (!c) return PE_ERR_ARG;
+  PE_API_BEGIN
+  if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
+  require(x && y, "null vector");
+  require(precision == PE_FP64 || precision == PE_MIXED, "unknown precision");
+  clean_grid(c);
+  apply_saddle_prec(c, precision, x, y);
+  PE_HIP(hipStreamSynchronize(c->stream));
+  c->prof.flush();
+  PE_API_END(c)
+}
+
+pe_status pe_profile_enable(pe_context* c, int32_t on) {
+  if (!c) return PE_ERR_ARG;
+  PE_API_BEGIN
+  PE_HIP(hipStreamSynchronize(c->stream));
+  c->prof.reset();
+  c->prof.on = on != 0;
+  PE_API_END(c)
+}
+
+pe_status pe_profile_read(pe_context* c, double* out) {
+  if (!c || !out) return PE_ERR_ARG;
+  PE_API_BEGIN
+  PE_HIP(hipStreamSynchronize(c->stream));
+  c->prof.flush();
+  for (int i = 0; i < 2 * PE_PROF_NCLASS; ++i) {
+    out[2 * i] = c->prof.cnt[i];
+    out[2 * i + 1] = c->prof.ms[i];
   }
   PE_API_END(c)
 }

@@ -113,6 +113,78 @@ struct FFTPlan1D {
   int radix[16];
 };
 
+// ------------------------------------------------------------- profiling
+
+// HIP events around kernel launches on the context stream, resolved after
+// the stream has been synchronized.
+struct Prof {
+  bool on = false;
+  double ms[2 * PE_PROF_NCLASS] = {};
+  double cnt[2 * PE_PROF_NCLASS] = {};
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void reset() {
+    flush();
+    for (int i = 0; i < 2 * PE_PROF_NCLASS; ++i) ms[i] = cnt[i] = 0;
+  }
+  // call only when the stream is idle
+  void flush() {
+    for (auto& r : pending) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.cls] += t;
+        cnt[r.cls] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  ~Prof() {
+    for (auto& r : pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct ProfScope {
+  Prof* p;
+  hipStream_t s;
+  int cls;
+  hipEvent_t a = nullptr;
+  // dbl: the launch computes in double (its class is offset by PE_PROF_NCLASS)
+  ProfScope(Prof& prof, hipStream_t st, int c, bool dbl) : p(prof.on ? &prof : nullptr), s(st),
+      cls(c + (dbl ? PE_PROF_NCLASS : 0)) {
+    if (p) {
+      a = p->take();
+      (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (p) {
+      hipEvent_t b = p->take();
+      (void)hipEventRecord(b, s);
+      p->pending.push_back({cls, a, b});
+    }
+  }
+};
+
 // ----------------------------------------------------------------- context
 
 struct LearnedGuess;  // defined in the guess translation unit
@@ -178,6 +250,8 @@ struct pe_context {
 
   // learned guess
   pe::LearnedGuess* guess = nullptr;
+
+  pe::Prof prof;
 };
 
 namespace pe {
