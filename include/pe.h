@@ -93,7 +93,7 @@ typedef struct pe_params {
   int32_t precision;      /* pe_precision, default PE_FP64 */
   int32_t reg;            /* pe_reg, default PE_REG_GAUSSIAN */
   double shell_radius;    /* PE_REG_SHELL only */
-  int32_t gmres_restart;  /* default 30 */
+  int32_t gmres_restart;  /* Krylov basis size before a restart, default 100, at most 255 */
   int32_t max_iters;      /* total Krylov iterations, default 1000 */
   double rel_tol;         /* target ||b - A x|| / ||b|| with the double operator, default 1e-6 */
   double inner_tol;       /* PE_MIXED: relative tolerance of each inner solve, default 1e-4 */

@@ -179,7 +179,7 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
   launch_seg_sum(s, c->off.get(), c->n_body, q, y + nb);
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
-  { ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8); launch_spread<T>(s, c->B, q, gA, c->gg); }
+  { ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8); launch_spread<T>(s, c->B, q, gA, c->gg, false); }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
   { ProfScope ps(c->prof, s, PE_PROF_GATHER, sizeof(T) == 8); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
   { ProfScope ps(c->prof, s, PE_PROF_SPMV, sizeof(T) == 8); launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), ck_bead(c), y); }
@@ -206,8 +206,8 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
   T* gB = grid_real<T>(c->gridB);
   {
     ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8);
-    launch_spread<T>(s, c->B, qb, gA, c->gg);
-    if (ni) launch_spread<T>(s, c->I, qi, gA, c->gg);
+    launch_spread<T>(s, c->B, qb, gA, c->gg, false);
+    if (ni) launch_spread<T>(s, c->I, qi, gA, c->gg, true);
   }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
   {
@@ -245,7 +245,7 @@ void build_rhs(pe_context* c, double* b) {
     launch_moments(s, c->ion_q.get(), c->ion_sig.get(), 0.0, ni, ck_coef(c), c->red.get(), ck_ion(c), nullptr);
     double* gA = c->gridA.get();
     double* gB = c->gridB.get();
-    launch_spread<double>(s, c->I, c->ion_q.get(), gA, c->gg);
+    launch_spread<double>(s, c->I, c->ion_q.get(), gA, c->gg, false);
     launch_wave_pipeline<double>(s, c, gA, gB, c->gridC.get());
     launch_gather<double>(s, c->B, gB, c->gg, phi_ion, nullptr, false);
     launch_pair_onfly<double>(s, c->B, c->I, c->ion_q.get(), c->rg, phi_ion, nullptr);
@@ -393,6 +393,7 @@ void compute_params(pe_context* c) {
   g.h3 = g.h[0] * g.h[1] * g.h[2];
   g.eps = p.eps;
   g.fcoef = -4.0 * c->xi * c->xi * g.h3 / (p.eps * c->eta);
+  for (int d = 0; d < 3; ++d) g.ntile[d] = (p.mesh[d] + 7) / 8;
 }
 
 void build_twiddles(pe_context* c) {
@@ -417,19 +418,9 @@ void build_twiddles(pe_context* c) {
 void ensure_grids(pe_context* c) {
   const int64_t G = (int64_t)c->p.mesh[0] * c->p.mesh[1] * c->p.mesh[2];
   const int64_t Gc = (int64_t)c->p.mesh[0] * c->p.mesh[1] * (c->p.mesh[2] / 2 + 1);
-  const bool fresh = c->gridA.cap < (size_t)G;
   c->gridA.ensure(G);
   c->gridB.ensure(G);
   c->gridC.ensure(Gc);
-  if (fresh) PE_HIP(hipMemsetAsync(c->gridA.get(), 0, sizeof(double) * G, c->stream));
-}
-
-// The spread accumulates into grid A and the first FFT pass zeroes it after
-// reading; clear it at every entry point in case an earlier call stopped
-// between the two.
-void clean_grid(pe_context* c) {
-  const int64_t G = (int64_t)c->p.mesh[0] * c->p.mesh[1] * c->p.mesh[2];
-  PE_HIP(hipMemsetAsync(c->gridA.get(), 0, sizeof(double) * G, c->stream));
 }
 
 }  // namespace
@@ -465,7 +456,7 @@ pe_status pe_default_params(pe_params* p) {
   p->precision = PE_FP64;
   p->reg = PE_REG_GAUSSIAN;
   p->shell_radius = 0.0;
-  p->gmres_restart = 30;
+  p->gmres_restart = 100;
   p->max_iters = 1000;
   p->rel_tol = 1e-6;
   p->inner_tol = 1e-4;
@@ -489,7 +480,8 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
   }
   require(p.mesh[2] % 2 == 0, "mesh[2] must be even (real-to-complex transform)");
   require(p.P >= 2 && p.P <= 16, "P must be in [2, 16]");
-  require(p.P <= p.mesh[0] && p.P <= p.mesh[1] && p.P <= p.mesh[2], "P must not exceed the mesh");
+  for (int d = 0; d < 3; ++d)
+    require(p.mesh[d] >= p.P + 8, "each mesh dimension must be at least P + 8");
   require(p.eps > 0 && std::isfinite(p.eps), "eps must be positive");
   require(p.eta_c > 0, "eta_c must be positive");
   require(p.split_tol > 0 && p.split_tol < 1, "split_tol must be in (0,1)");
@@ -509,8 +501,9 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
   compute_params(c);
   require(c->eta > 0 && c->eta < 1, "eta = (h xi)^2 P/(pi c^2) must lie in (0, 1); refine the mesh or lower xi");
   build_twiddles(c);
+  build_green_tables(c);
   c->sums.ensure(64);
-  c->red.ensure((size_t)kMaxK * 1024 + 4096);
+  c->red.ensure((size_t)kMaxK * 1024 + 8192);
   *out = c;
   c = nullptr;
   PE_API_END(c)
@@ -643,6 +636,8 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   PE_CHECK_LAUNCH();
   build_cells(s, c->B, c->bead_x.get(), c->bead_sig.get(), 0.0, nb, rg);
   build_cells(s, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, n_ion, rg);
+  build_tiles(s, c->B, c->gg);
+  build_tiles(s, c->I, c->gg);
   build_bead_matrix(c);
   ensure_grids(c);
   c->phi_w.ensure(nb + n_ion + 1);
@@ -664,7 +659,6 @@ pe_status pe_apply_potential(pe_context* c, const double* charges, double* psi_o
   if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
   require(charges && psi_out, "null charges or output");
   require(precision == PE_FP64 || precision == PE_MIXED, "unknown precision");
-  clean_grid(c);
   const int64_t nb = c->n_bead;
   if (precision == PE_MIXED)
     all_potential<float>(c, charges, charges + nb, psi_out, field_out, nullptr, nullptr, nullptr);
@@ -687,7 +681,6 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
   std::memset(inf, 0, sizeof(*inf));
   hipStream_t s = c->stream;
   const auto t0 = Clock::now();
-  clean_grid(c);
   const int64_t nb = c->n_bead, nbody = c->n_body, n = nb + nbody;
   double* b = c->rhs_b.get();
   double* x = c->xsol.get();
@@ -797,7 +790,6 @@ pe_status pe_apply_saddle(pe_context* c, const double* x, double* y, int32_t pre
   if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
   require(x && y, "null vector");
   require(precision == PE_FP64 || precision == PE_MIXED, "unknown precision");
-  clean_grid(c);
   apply_saddle_prec(c, precision, x, y);
   PE_HIP(hipStreamSynchronize(c->stream));
   c->prof.flush();
@@ -832,7 +824,6 @@ pe_status pe_forces_torques(pe_context* c, double* body_force, double* body_torq
   if (!c->have_solution) throw Error(PE_ERR_STATE, "pe_solve_polarization has not been called");
   require(total_energy != nullptr, "total_energy is null");
   hipStream_t s = c->stream;
-  clean_grid(c);
   const int64_t nb = c->n_bead, ni = c->n_ion, na = nb + ni;
   c->phi_all.ensure(na + 1);
   c->E_all.ensure(3 * na + 1);

@@ -6,8 +6,7 @@
 // the grid through LDS:
 //   1. z, real -> complex: two real lines packed into one complex line, one
 //      complex FFT, then split (X_a = (Z_k + conj Z_{N-k})/2,
-//      X_b = (Z_k - conj Z_{N-k})/2i); the real input is zeroed after it is
-//      read, so the next spread starts from a clean grid.
+//      X_b = (Z_k - conj Z_{N-k})/2i).
 //   2. y, complex, forward.
 //   3. x forward, multiply by G_k / (Nx Ny Nz), x inverse: the whole x line
 //      stays in LDS, so scaling and both x transforms cost one pass.
@@ -19,6 +18,7 @@
 // passes are taken along the contiguous kz / (y,kz) index so global loads
 // and stores are coalesced.
 #include <cmath>
+#include <vector>
 
 #include "pe_internal.hpp"
 
@@ -57,14 +57,15 @@ __device__ __forceinline__ void dft4(C& v0, C& v1, C& v2, C& v3, int fwd) {
   v3 = csub(t1, t3);
 }
 
-template <typename T, typename C>
-__device__ __forceinline__ void butterfly(int R, C* v, int fwd) {
+// In-register DFT of compile-time size R.
+template <typename T, typename C, int R>
+__device__ __forceinline__ void butterfly(C (&v)[R], int fwd) {
   const T r2 = (T)0.70710678118654752440;
-  if (R == 2) {
+  if constexpr (R == 2) {
     dft2<T, C>(v[0], v[1]);
-  } else if (R == 4) {
+  } else if constexpr (R == 4) {
     dft4<T, C>(v[0], v[1], v[2], v[3], fwd);
-  } else if (R == 8) {
+  } else if constexpr (R == 8) {
     // even / odd halves, then combine with W8^k
     dft4<T, C>(v[0], v[2], v[4], v[6], fwd);
     dft4<T, C>(v[1], v[3], v[5], v[7], fwd);
@@ -84,7 +85,7 @@ __device__ __forceinline__ void butterfly(int R, C* v, int fwd) {
     v[6] = csub(e2, o2);
     v[3] = cadd(e3, o3);
     v[7] = csub(e3, o3);
-  } else if (R == 3) {
+  } else if constexpr (R == 3) {
     const T s3 = (T)0.86602540378443864676 * (T)fwd;
     C t = cadd(v[1], v[2]);
     C u = csub(v[1], v[2]);
@@ -94,7 +95,7 @@ __device__ __forceinline__ void butterfly(int R, C* v, int fwd) {
     v[0] = cadd(v[0], t);
     v[1] = csub(a, iu);
     v[2] = cadd(a, iu);
-  } else if (R == 5) {
+  } else if constexpr (R == 5) {
     const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
     const T s1 = (T)0.95105651629515357212 * (T)fwd, s2 = (T)0.58778525229247312917 * (T)fwd;
     C a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
@@ -114,6 +115,36 @@ __device__ __forceinline__ void butterfly(int R, C* v, int fwd) {
   }
 }
 
+// One Stockham stage of radix R over nl lines of length n (line stride ls).
+template <typename T, typename C, int R>
+__device__ __forceinline__ void stockham_stage(const C* __restrict__ in, C* __restrict__ out, int n, int nl,
+                                               int ls, int Ns, const C* __restrict__ tw, int fwd) {
+  const int nb = n / R;
+  const int tws = n / (Ns * R);
+  for (int t = threadIdx.x; t < nl * nb; t += blockDim.x) {
+    const int line = t / nb;
+    const int j = t - line * nb;
+    const int k = j % Ns;
+    C v[R];
+    const C* src = in + line * ls;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C w = tw[r * k * tws];
+        if (fwd < 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+    }
+    butterfly<T, C, R>(v, fwd);
+    C* dst = out + line * ls;
+    const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  }
+}
+
 // Transform `nl` lines of length n held in LDS (`in`, line stride ls).
 // Returns the buffer that holds the result (in or out).
 template <typename T, typename C>
@@ -122,26 +153,12 @@ __device__ C* lds_fft(C* in, C* out, int n, int nl, int ls, const FFTPlan1D& pla
   int Ns = 1;
   for (int s = 0; s < plan.nstage; ++s) {
     const int R = plan.radix[s];
-    const int nb = n / R;
-    const int tws = n / (Ns * R);
-    for (int t = threadIdx.x; t < nl * nb; t += blockDim.x) {
-      const int line = t / nb;
-      const int j = t - line * nb;
-      const int k = j % Ns;
-      C v[8];
-      const C* src = in + line * ls;
-      for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
-      if (Ns > 1) {
-        for (int r = 1; r < R; ++r) {
-          C w = tw[r * k * tws];
-          if (fwd < 0) w.y = -w.y;
-          v[r] = cmul(v[r], w);
-        }
-      }
-      butterfly<T, C>(R, v, fwd);
-      C* dst = out + line * ls;
-      const int base = (j / Ns) * Ns * R + k;
-      for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+    switch (R) {
+      case 8: stockham_stage<T, C, 8>(in, out, n, nl, ls, Ns, tw, fwd); break;
+      case 4: stockham_stage<T, C, 4>(in, out, n, nl, ls, Ns, tw, fwd); break;
+      case 2: stockham_stage<T, C, 2>(in, out, n, nl, ls, Ns, tw, fwd); break;
+      case 3: stockham_stage<T, C, 3>(in, out, n, nl, ls, Ns, tw, fwd); break;
+      default: stockham_stage<T, C, 5>(in, out, n, nl, ls, Ns, tw, fwd); break;
     }
     __syncthreads();
     C* tmp = in;
@@ -152,15 +169,19 @@ __device__ C* lds_fft(C* in, C* out, int n, int nl, int ls, const FFTPlan1D& pla
   return in;
 }
 
-// Green's function of the wave-space part, with the inverse-DFT normalization.
+// Green's function of the wave-space part, with the inverse-DFT
+// normalization, in separable form: G = ex[x] ey[y] ez[z] / (kx^2 + ky^2 + kz^2)
+// with e_d = exp(-(1 - eta) k_d^2 / (4 xi^2)) tabulated per axis on the host.
 struct ScaleArgs {
   int Nx, Ny, Nz, Nzc;
-  double kfx, kfy, kfz;   // 2 pi / L
-  double gexp;            // (1 - eta) / (4 xi^2)
-  double norm;            // 1 / (Nx Ny Nz)
+  const double* ex;   // Nx
+  const double* ey;   // Ny
+  const double* ez;   // Nzc
+  const double* kx2;  // Nx
+  const double* ky2;  // Ny
+  const double* kz2;  // Nzc
+  double norm;        // 1 / (Nx Ny Nz)
 };
-
-__device__ __forceinline__ int signed_idx(int m, int N) { return (m < (N + 1) / 2) ? m : m - N; }
 
 // Lines along a strided axis: line L (0..nlines-1), element j at
 // base(L) + j*stride, base(L) = (L / inner) * outer + (L % inner).
@@ -172,34 +193,41 @@ __global__ void __launch_bounds__(256) fft_lines_kernel(typename C2<T>::type* __
                                                         int fwd, ScaleArgs sa) {
   using C = typename C2<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int64_t lbase[64];
+  __shared__ T lfac[64], lksq[64];
   C* b0 = reinterpret_cast<C*>(smem_raw);
   const int ls = n + 1;
   C* b1 = b0 + lpb * ls;
   const int64_t L0 = (int64_t)blockIdx.x * lpb;
+  if ((int)threadIdx.x < lpb) {
+    const int64_t L = L0 + threadIdx.x;
+    lbase[threadIdx.x] = (L / inner) * outer + (L % inner);
+    if (SCALE && L < nlines) {
+      // x lines: L = y * Nzc + kz
+      const int y = (int)(L / sa.Nzc);
+      const int kz = (int)(L - (int64_t)y * sa.Nzc);
+      lfac[threadIdx.x] = (T)(sa.ey[y] * sa.ez[kz] * sa.norm);
+      lksq[threadIdx.x] = (T)(sa.ky2[y] + sa.kz2[kz]);
+    }
+  }
+  __syncthreads();
+  const int nvalid = (int)min<int64_t>((int64_t)lpb, nlines - L0);
   for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
     const int j = t / lpb;
     const int c = t - j * lpb;
-    const int64_t L = L0 + c;
     C v = {0, 0};
-    if (L < nlines) v = data[(L / inner) * outer + (L % inner) + (int64_t)j * stride];
+    if (c < nvalid) v = data[lbase[c] + (int64_t)j * stride];
     b0[c * ls + j] = v;
   }
   __syncthreads();
   C* res = lds_fft<T, C>(b0, b1, n, lpb, ls, plan, tw, fwd);
   if (SCALE) {
-    // x lines: j = x index, L = y * Nzc + kz
     for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
       const int c = t / n;
       const int j = t - c * n;
-      const int64_t L = L0 + c;
-      if (L >= nlines) continue;
-      const int y = (int)(L / sa.Nzc);
-      const int kz = (int)(L - (int64_t)y * sa.Nzc);
-      const double kx = sa.kfx * signed_idx(j, sa.Nx);
-      const double ky = sa.kfy * signed_idx(y, sa.Ny);
-      const double kzz = sa.kfz * kz;
-      const double k2 = kx * kx + ky * ky + kzz * kzz;
-      const T gk = k2 > 0 ? (T)(exp(-sa.gexp * k2) / k2 * sa.norm) : (T)0;
+      if (c >= nvalid) continue;
+      const T k2 = (T)sa.kx2[j] + lksq[c];
+      const T gk = k2 > (T)0 ? (T)sa.ex[j] * lfac[c] / k2 : (T)0;
       C v = res[c * ls + j];
       res[c * ls + j] = {v.x * gk, v.y * gk};
     }
@@ -210,14 +238,13 @@ __global__ void __launch_bounds__(256) fft_lines_kernel(typename C2<T>::type* __
   for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
     const int j = t / lpb;
     const int c = t - j * lpb;
-    const int64_t L = L0 + c;
-    if (L < nlines) data[(L / inner) * outer + (L % inner) + (int64_t)j * stride] = res[c * ls + j];
+    if (c < nvalid) data[lbase[c] + (int64_t)j * stride] = res[c * ls + j];
   }
 }
 
 // z pass, real -> half complex, two real lines per complex transform.
 template <typename T>
-__global__ void __launch_bounds__(256) fft_z_r2c_kernel(T* __restrict__ real,
+__global__ void __launch_bounds__(256) fft_z_r2c_kernel(const T* __restrict__ real,
                                                         typename C2<T>::type* __restrict__ cplx,
                                                         int Nz, int64_t nlines, int ppb, FFTPlan1D plan,
                                                         const typename C2<T>::type* __restrict__ tw) {
@@ -233,14 +260,8 @@ __global__ void __launch_bounds__(256) fft_z_r2c_kernel(T* __restrict__ real,
     const int j = t - c * Nz;
     const int64_t la = 2 * (p0 + c), lb = la + 1;
     T a = 0, b = 0;
-    if (la < nlines) {
-      a = real[la * Nz + j];
-      real[la * Nz + j] = 0;
-    }
-    if (lb < nlines) {
-      b = real[lb * Nz + j];
-      real[lb * Nz + j] = 0;
-    }
+    if (la < nlines) a = real[la * Nz + j];
+    if (lb < nlines) b = real[lb * Nz + j];
     b0[c * ls + j] = {a, b};
   }
   __syncthreads();
@@ -299,15 +320,38 @@ __global__ void __launch_bounds__(256) fft_z_c2r_kernel(const typename C2<T>::ty
   }
 }
 
+// About 2048 complex values per block (8 per thread) so a pass launches
+// many blocks; two ping-pong LDS buffers of (n+1) values per line must fit
+// the budget.
 inline int lines_per_block(int n, size_t elem, size_t lds_budget) {
-  // two ping-pong buffers of (n+1) complex per line
-  int l = (int)(lds_budget / (2 * (size_t)(n + 1) * elem));
+  int l = 2048 / n;
+  const int cap = (int)(lds_budget / (2 * (size_t)(n + 1) * elem));
+  if (l > cap) l = cap;
   if (l < 1) l = 1;
   if (l > 64) l = 64;
   return l;
 }
 
 }  // namespace
+
+void build_green_tables(pe_context* c) {
+  const int Nx = c->p.mesh[0], Ny = c->p.mesh[1], Nz = c->p.mesh[2], Nzc = Nz / 2 + 1;
+  const int ns[3] = {Nx, Ny, Nzc};
+  const double gexp = (1.0 - c->eta) / (4.0 * c->xi * c->xi);
+  std::vector<double> e, k2;
+  for (int d = 0; d < 3; ++d) {
+    const int N = c->p.mesh[d];
+    for (int m = 0; m < ns[d]; ++m) {
+      const int sm = (d < 2 && m >= (N + 1) / 2) ? m - N : m;
+      const double k = 2.0 * M_PI * sm / c->p.box[d];
+      e.push_back(std::exp(-gexp * k * k));
+      k2.push_back(k * k);
+    }
+  }
+  e.insert(e.end(), k2.begin(), k2.end());
+  c->gtab.ensure(e.size());
+  PE_HIP(hipMemcpy(c->gtab.get(), e.data(), sizeof(double) * e.size(), hipMemcpyHostToDevice));
+}
 
 void make_fft_plan(int n, FFTPlan1D& plan) {
   require(n >= 1 && n <= 1024, "FFT length must be in [1, 1024]");
@@ -357,8 +401,13 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   }
   ScaleArgs sa{};
   sa.Nx = Nx; sa.Ny = Ny; sa.Nz = Nz; sa.Nzc = Nzc;
-  sa.kfx = 2 * M_PI / g.L[0]; sa.kfy = 2 * M_PI / g.L[1]; sa.kfz = 2 * M_PI / g.L[2];
-  sa.gexp = (1.0 - c->eta) / (4.0 * c->xi * c->xi);
+  const double* gt = c->gtab.get();
+  sa.ex = gt;
+  sa.ey = gt + Nx;
+  sa.ez = gt + Nx + Ny;
+  sa.kx2 = gt + Nx + Ny + Nzc;
+  sa.ky2 = sa.kx2 + Nx;
+  sa.kz2 = sa.ky2 + Ny;
   sa.norm = 1.0 / ((double)Nx * Ny * Nz);
   // 2. y forward: lines (x, kz), element y
   auto ypass = [&](int fwd) {

@@ -1,18 +1,20 @@
 // Gaussian spreading and contraction (section "Spectral Ewald
 // implementation", steps 2 and 6; window of section "Wave-space sum").
 //
-// One 64-lane wavefront per particle.  Lanes 0..3P-1 first evaluate the
-// separable window factors w_x[j], w_y[j], w_z[j] (3P exponentials per
-// particle instead of P^3) and the wrapped grid indices into LDS; then the
-// wavefront sweeps the P x P (y,z) lines of the support, lane t owning line
-// (t / P, t % P) and looping over the P x-points.  Consecutive lanes touch
-// consecutive z addresses.  Particles are visited in cell order, so
-// neighbouring wavefronts work on neighbouring grid regions (cache reuse).
+// Contraction: one 64-lane wavefront per particle.  Lanes 0..3P-1 first
+// evaluate the separable window factors w_x[j], w_y[j], w_z[j] (3P
+// exponentials per particle instead of P^3) and the wrapped grid indices into
+// LDS; then the wavefront sweeps the P x P (y,z) lines of the support, lane t
+// owning line (t / P, t % P) and looping over the P x-points, and reduces
+// across lanes.  Particles are visited in cell order, so neighbouring
+// wavefronts read neighbouring grid regions (cache reuse).
 //
 // Support (the P closest grid points per axis): even P takes
 // m0-P/2+1 .. m0+P/2 with m0 = floor(x/h); odd P is centred on rint(x/h).
 // Index and displacement are computed in double for both precisions, so
 // the float and double paths use the same support.
+#include <vector>
+
 #include "pe_internal.hpp"
 
 namespace pe {
@@ -37,44 +39,178 @@ __device__ __forceinline__ void window_setup(const double4 p, const GridGeom& g,
     const int N = g.N[ax];
     long mw = m % N;
     if (mw < 0) mw += N;
-    w_s[lane] = (T)(g.wnorm * exp(-g.wexp * d * d));
+    w_s[lane] = (T)g.wnorm * exp((T)(-g.wexp * d * d));
     i_s[lane] = (int)mw;
     if (d_s) d_s[lane] = (T)d;
   }
 }
 
+// ------------------------------------------------------------------ spread
+//
+// Tile-binned spreading.  The grid is cut into tiles of kTile^3 points; for
+// every tile, set_system lists the particles whose support overlaps it (a
+// particle overlaps about 8 tiles at P = 8).  The tile is written to HBM
+// once, with no atomics; every tile is written (empty ones with zeros), so
+// the grid needs no clearing between products.  Requires mesh >= P + 8 per
+// axis, so a support never reaches the same tile from both sides.
+
+constexpr int kTile = 8;
+constexpr int kTile3 = kTile * kTile * kTile;
+
+// Per-axis support start (unwrapped) of coordinate x.
+__device__ __forceinline__ long support_start(double x, double inv_h, int P) {
+  const double u = x * inv_h;
+  return (P & 1) ? (long)rint(u) - (P - 1) / 2 : (long)floor(u) - P / 2 + 1;
+}
+
+__device__ __forceinline__ int wrap_idx(long m, int N) {
+  long w = m % N;
+  return (int)(w < 0 ? w + N : w);
+}
+
+// Distinct tiles (per axis) touched by the support of a particle; returns count (<= 4).
+__device__ __forceinline__ int axis_tiles(long m0, int P, int N, int* t) {
+  int n = 0;
+  int last = -1;
+  for (int j = 0; j < P; ++j) {
+    const int tile = wrap_idx(m0 + j, N) / kTile;
+    if (tile != last) {
+      bool seen = false;
+      for (int k = 0; k < n; ++k) seen |= (t[k] == tile);
+      if (!seen && n < 4) t[n++] = tile;
+      last = tile;
+    }
+  }
+  return n;
+}
+
+__global__ void tile_count_kernel(const double4* __restrict__ pos, int64_t n, GridGeom g,
+                                  int* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = pos[i];
+  int tx[4], ty[4], tz[4];
+  const int nx = axis_tiles(support_start(p.x, g.inv_h[0], g.P), g.P, g.N[0], tx);
+  const int ny = axis_tiles(support_start(p.y, g.inv_h[1], g.P), g.P, g.N[1], ty);
+  const int nz = axis_tiles(support_start(p.z, g.inv_h[2], g.P), g.P, g.N[2], tz);
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < ny; ++b)
+      for (int c = 0; c < nz; ++c) atomicAdd(&count[(tx[a] * g.ntile[1] + ty[b]) * g.ntile[2] + tz[c]], 1);
+}
+
+__global__ void tile_fill_kernel(const double4* __restrict__ pos, int64_t n, GridGeom g,
+                                 int* __restrict__ cursor, int* __restrict__ entries) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = pos[i];
+  int tx[4], ty[4], tz[4];
+  const int nx = axis_tiles(support_start(p.x, g.inv_h[0], g.P), g.P, g.N[0], tx);
+  const int ny = axis_tiles(support_start(p.y, g.inv_h[1], g.P), g.P, g.N[1], ty);
+  const int nz = axis_tiles(support_start(p.z, g.inv_h[2], g.P), g.P, g.N[2], tz);
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < ny; ++b)
+      for (int c = 0; c < nz; ++c) {
+        const int slot = atomicAdd(&cursor[(tx[a] * g.ntile[1] + ty[b]) * g.ntile[2] + tz[c]], 1);
+        entries[slot] = (int)i;
+      }
+}
+
+// One workgroup (four wavefronts) per tile.  The tile's particle list is
+// processed in chunks of kChunk: all threads stage each particle's window
+// factors in tile-local coordinates (f_x[a] q, f_y[b], f_z[c], zero where the
+// support misses the tile) in LDS.  Lane (a, b) of a wavefront owns the
+// z-pencil (a, b, 0..7) of the tile in eight registers and adds
+// q f_x[a] f_y[b] f_z[c] for the particles of its share of the chunk.  The four
+// partial tiles are summed in a fixed order and the tile is written once.
+// No atomics; the lists are sorted, so the result is the same bit for bit on
+// every run.
+constexpr int kChunk = 64;
+
 template <typename T>
-__global__ void __launch_bounds__(256) spread_kernel(const double4* __restrict__ pos,
-                                                     const int* __restrict__ idx,
-                                                     const double* __restrict__ q, int64_t n,
-                                                     T* __restrict__ grid, GridGeom g) {
-  __shared__ T w_s[kWaves][3 * kMaxP];
-  __shared__ int i_s[kWaves][3 * kMaxP];
+__global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restrict__ pos,
+                                                          const int* __restrict__ idx,
+                                                          const double* __restrict__ q,
+                                                          const int* __restrict__ tile_start,
+                                                          const int* __restrict__ entries,
+                                                          T* __restrict__ grid, GridGeom g, int accumulate) {
+  __shared__ T f_s[kChunk][3][kTile];
+  __shared__ double4 p_s[kChunk];
+  __shared__ T q_s[kChunk];
+  __shared__ T red[kWaves][kTile3];
+  const int tid = blockIdx.x;
+  const int uz = tid % g.ntile[2];
+  const int uy = (tid / g.ntile[2]) % g.ntile[1];
+  const int ux = tid / (g.ntile[2] * g.ntile[1]);
+  const int P = g.P;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * kWaves + wv;
-  const bool live = i < n;
-  double4 p = make_double4(0, 0, 0, 0);
-  T qi = 0;
-  if (live) {
-    p = pos[i];
-    qi = (T)q[idx[i]];
-    window_setup<T>(p, g, lane, w_s[wv], i_s[wv], (T*)nullptr);
-  }
-  __syncthreads();
-  if (!live) return;
-  const int P = g.P;
-  const int PP = P * P;
-  const int64_t sx = (int64_t)g.N[1] * g.N[2];
-  for (int t = lane; t < PP; t += 64) {
-    const int jy = t / P;
-    const int jz = t - jy * P;
-    const T wyz = qi * w_s[wv][P + jy] * w_s[wv][2 * P + jz];
-    const int64_t off_yz = (int64_t)i_s[wv][P + jy] * g.N[2] + i_s[wv][2 * P + jz];
-    for (int jx = 0; jx < P; ++jx) {
-      const T v = wyz * w_s[wv][jx];
-      atomicAdd(&grid[(int64_t)i_s[wv][jx] * sx + off_yz], v);
+  const int pa = lane >> 3, pb = lane & 7;
+  T acc[kTile];
+#pragma unroll
+  for (int c = 0; c < kTile; ++c) acc[c] = 0;
+  const int e0 = tile_start[tid], e1 = tile_start[tid + 1];
+  for (int c0 = e0; c0 < e1; c0 += kChunk) {
+    const int nc = min(kChunk, e1 - c0);
+    if ((int)threadIdx.x < nc) {
+      const int i = entries[c0 + threadIdx.x];
+      p_s[threadIdx.x] = pos[i];
+      q_s[threadIdx.x] = (T)q[idx[i]];
     }
+    for (int t = threadIdx.x; t < nc * 3 * kTile; t += blockDim.x) (&f_s[0][0][0])[t] = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < nc * 3 * P; t += blockDim.x) {
+      const int c = t / (3 * P);
+      const int l = t - c * 3 * P;
+      const int ax = l / P;
+      const int j = l - ax * P;
+      const double4 p = p_s[c];
+      const double x = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
+      const long m = support_start(x, g.inv_h[ax], P) + j;
+      const int u = ax == 0 ? ux : (ax == 1 ? uy : uz);
+      const int loc = wrap_idx(m, g.N[ax]) - kTile * u;
+      if (loc >= 0 && loc < kTile) {
+        const double d = (double)m * g.h[ax] - x;
+        T w = (T)g.wnorm * exp((T)(-g.wexp * d * d));
+        if (ax == 0) w *= q_s[c];
+        f_s[c][ax][loc] = w;
+      }
+    }
+    __syncthreads();
+    for (int c = wv; c < nc; c += kWaves) {
+      const T coef = f_s[c][0][pa] * f_s[c][1][pb];
+#pragma unroll
+      for (int z = 0; z < kTile; ++z) acc[z] += coef * f_s[c][2][z];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int z = 0; z < kTile; ++z) red[wv][lane * kTile + z] = acc[z];
+  __syncthreads();
+  for (int k = threadIdx.x; k < kTile3; k += blockDim.x) {
+    const T v = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+    const int a = k / (kTile * kTile), b = (k / kTile) % kTile, c = k % kTile;
+    const int gx = kTile * ux + a, gy = kTile * uy + b, gz = kTile * uz + c;
+    if (gx < g.N[0] && gy < g.N[1] && gz < g.N[2]) {
+      const int64_t o = ((int64_t)gx * g.N[1] + gy) * g.N[2] + gz;
+      grid[o] = accumulate ? grid[o] + v : v;
+    }
+  }
+}
+
+// Sort each tile's list (sorted-particle indices) so the accumulation order
+// is fixed.
+__global__ void sort_tiles_kernel(const int* __restrict__ start, int ntile, int* __restrict__ ent) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntile) return;
+  const int b = start[t], e = start[t + 1];
+  for (int i = b + 1; i < e; ++i) {
+    const int v = ent[i];
+    int j = i - 1;
+    while (j >= b && ent[j] > v) {
+      ent[j + 1] = ent[j];
+      --j;
+    }
+    ent[j + 1] = v;
   }
 }
 
@@ -146,13 +282,43 @@ __global__ void __launch_bounds__(256) gather_kernel(const double4* __restrict__
 
 }  // namespace
 
+void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
+  const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];
+  ps.tile_start.ensure(nt + 1);
+  ps.tile_count.ensure(nt);
+  PE_HIP(hipMemsetAsync(ps.tile_count.get(), 0, sizeof(int) * nt, s));
+  const unsigned nb = (unsigned)((ps.n + 255) / 256);
+  if (ps.n > 0) {
+    hipLaunchKernelGGL(tile_count_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get());
+    PE_CHECK_LAUNCH();
+  }
+  std::vector<int> cnt(nt), start(nt + 1, 0);
+  PE_HIP(hipMemcpyAsync(cnt.data(), ps.tile_count.get(), sizeof(int) * nt, hipMemcpyDeviceToHost, s));
+  PE_HIP(hipStreamSynchronize(s));
+  for (int t = 0; t < nt; ++t) start[t + 1] = start[t] + cnt[t];
+  ps.n_entries = start[nt];
+  ps.tile_entries.ensure(ps.n_entries);
+  PE_HIP(hipMemcpyAsync(ps.tile_start.get(), start.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(ps.tile_count.get(), start.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  if (ps.n > 0) {
+    hipLaunchKernelGGL(tile_fill_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get(),
+                       ps.tile_entries.get());
+    PE_CHECK_LAUNCH();
+    hipLaunchKernelGGL(sort_tiles_kernel, dim3((unsigned)((nt + 127) / 128)), dim3(128), 0, s, ps.tile_start.get(),
+                       nt, ps.tile_entries.get());
+    PE_CHECK_LAUNCH();
+  }
+  PE_HIP(hipStreamSynchronize(s));
+}
+
 template <typename T>
-void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* grid, const GridGeom& g) {
-  if (ps.n == 0) return;
+void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* grid, const GridGeom& g,
+                   bool accumulate) {
+  if (ps.n == 0 && accumulate) return;
   require(g.P <= kMaxP, "support P must be <= 16");
-  const int64_t nb = (ps.n + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(spread_kernel<T>, dim3((unsigned)nb), dim3(256), 0, s, ps.pos.get(),
-                     ps.idx.get(), q, ps.n, grid, g);
+  const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];
+  hipLaunchKernelGGL(spread_tile_kernel<T>, dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(), ps.idx.get(), q,
+                     ps.tile_start.get(), ps.tile_entries.get(), grid, g, accumulate ? 1 : 0);
   PE_CHECK_LAUNCH();
 }
 
@@ -171,8 +337,8 @@ void launch_gather(hipStream_t s, const ParticleSet& ps, const T* grid, const Gr
   PE_CHECK_LAUNCH();
 }
 
-template void launch_spread<float>(hipStream_t, const ParticleSet&, const double*, float*, const GridGeom&);
-template void launch_spread<double>(hipStream_t, const ParticleSet&, const double*, double*, const GridGeom&);
+template void launch_spread<float>(hipStream_t, const ParticleSet&, const double*, float*, const GridGeom&, bool);
+template void launch_spread<double>(hipStream_t, const ParticleSet&, const double*, double*, const GridGeom&, bool);
 template void launch_gather<float>(hipStream_t, const ParticleSet&, const float*, const GridGeom&, double*, double*, bool);
 template void launch_gather<double>(hipStream_t, const ParticleSet&, const double*, const GridGeom&, double*, double*, bool);
 

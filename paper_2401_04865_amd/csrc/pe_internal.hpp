@@ -80,6 +80,7 @@ struct GridGeom {
   double h3;        // h_x h_y h_z
   double eps;
   double fcoef;     // -4 xi^2 h3 / (eps eta)  (field prefactor)
+  int ntile[3];     // spreading tiles per axis (ceil(N / 8))
 };
 
 // Real-space geometry.
@@ -104,6 +105,11 @@ struct ParticleSet {
   DevBuf<int> cell_count;   // ncell (scratch)
   DevBuf<int> cell_of;      // caller order (scratch)
   DevBuf<double4> tmp;      // caller order wrapped positions (scratch)
+  // grid tiles overlapped by each particle's support (spreading lists)
+  DevBuf<int> tile_start;   // ntile + 1
+  DevBuf<int> tile_count;   // ntile (scratch)
+  DevBuf<int> tile_entries; // sorted-particle indices, grouped by tile
+  int64_t n_entries = 0;
 };
 
 // 1-D FFT factorization (radices 8, 4, 2, 3, 5).
@@ -203,6 +209,7 @@ struct pe_context {
   pe::FFTPlan1D plan[3]{};
   pe::DevBuf<double2> tw64[3];
   pe::DevBuf<float2> tw32[3];
+  pe::DevBuf<double> gtab;   // separable Green's-function tables (exp factors, k_d^2)
 
   // system
   bool have_system = false;
@@ -221,9 +228,9 @@ struct pe_context {
   pe::ParticleSet B, I;
   double bead_sig_uniform = -1.0;  // >0 if all bead widths are equal
 
-  // bead-bead real-space operator, sliced ELLPACK with 64-row slices
-  int64_t nslice = 0, nnz = 0;
-  pe::DevBuf<int64_t> slice_ptr;
+  // bead-bead real-space operator, CSR over sorted bead rows
+  int64_t nnz = 0;
+  pe::DevBuf<int64_t> row_ptr;
   pe::DevBuf<int> cnt;
   pe::DevBuf<int> col;
   pe::DevBuf<double> val64;
@@ -260,18 +267,21 @@ namespace pe {
 // (each enqueues on the given stream; geometry passed by value)
 
 // grid: spread charges q (indexed by caller index through idx) into grid (accumulate)
+void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g);
 template <typename T>
-void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* grid, const GridGeom& g);
+void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* grid, const GridGeom& g,
+                   bool accumulate);
 // grid: gather potential (and optionally field) at the particles of ps;
 // writes (or adds, if accumulate) phi[idx] and E[idx*3+d]
 template <typename T>
 void launch_gather(hipStream_t s, const ParticleSet& ps, const T* grid, const GridGeom& g,
                    double* phi, double* E, bool accumulate);
 
-// FFT pipeline: real grid A (zeroed on read) -> complex -> scaled -> real grid B
+// FFT pipeline: real grid A -> complex -> scaled -> real grid B
 template <typename T>
 void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gridA, T* gridB, void* gridC);
 void make_fft_plan(int n, FFTPlan1D& plan);
+void build_green_tables(pe_context* c);
 
 // real space
 void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,

@@ -15,9 +15,8 @@
 // digits to cancellation.
 //
 // Positions are fixed during a solve, so the bead-bead block is evaluated once
-// per configuration and stored as a sliced-ELLPACK matrix (64-row slices,
-// entries of a slice interleaved so that each wavefront reads coalesced
-// columns and values).  Every Krylov iteration then applies it as a sparse
+// per configuration and stored as a CSR matrix (rows in cell order, entries
+// in traversal order).  Every Krylov iteration then applies it as a sparse
 // matrix-vector product.  One-off passes (ion -> bead for the right-hand
 // side, all pairs with fields for the forces) are evaluated on the fly.
 #include <algorithm>
@@ -197,16 +196,12 @@ __global__ void count_pairs_kernel(const double4* __restrict__ pos, const int* _
 
 __global__ void fill_pairs_kernel(const double4* __restrict__ pos, const int* __restrict__ idx,
                                   const int* __restrict__ start, int64_t n, RealGeom g,
-                                  const int64_t* __restrict__ slice_ptr, int* __restrict__ col,
+                                  const int64_t* __restrict__ row_ptr, int* __restrict__ col,
                                   double* __restrict__ v64, float* __restrict__ v32) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t sl = i >> 6;
-  const int lane = (int)(i & 63);
-  const int64_t base = slice_ptr[sl];
-  const int width = (int)((slice_ptr[sl + 1] - base) >> 6);
   const double4 p = pos[i];
-  int k = 0;
+  int64_t o = row_ptr[i];
   for_neighbours(p, pos, start, g, [&](int s, double, double, double, double r2, double sw) {
     const double s2 = p.w * p.w + sw * sw;
     double R;
@@ -216,43 +211,38 @@ __global__ void fill_pairs_kernel(const double4* __restrict__ pos, const int* __
       double dR;
       pair_kernel<double>(sqrt(r2), s2, g, R, dR, false);
     }
-    const int64_t o = base + (int64_t)k * 64 + lane;
     col[o] = idx[s];
     v64[o] = R;
     if (v32) v32[o] = (float)R;
-    ++k;
+    ++o;
   });
-  for (; k < width; ++k) {
-    const int64_t o = base + (int64_t)k * 64 + lane;
-    col[o] = idx[i];
-    v64[o] = 0.0;
-    if (v32) v32[o] = 0.0f;
-  }
 }
 
 // y_top[b] = -(phi_wave[b] + sum_j R_bj q_j - ck0_b) + dpsi[body(b)] for every bead b.
 // ck0_b = ck[0] - ck[1] * sigma_b^2 (the k = 0 constant of the split).
+// CSR rows in cell order; 16 lanes per row read the row's entries
+// contiguously and reduce with lane shuffles (4 rows per wavefront).
 template <typename T>
 __global__ void __launch_bounds__(256) spmv_assemble_kernel(
-    const int64_t* __restrict__ slice_ptr, const int* __restrict__ col, const T* __restrict__ val,
+    const int64_t* __restrict__ row_ptr, const int* __restrict__ col, const T* __restrict__ val,
     const int* __restrict__ idx, const double4* __restrict__ pos, int64_t n,
     const double* __restrict__ q, const double* __restrict__ phi_wave, const double* __restrict__ ck,
     const double* __restrict__ dpsi, const int* __restrict__ body_of, double* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t sl = i >> 6;
-  const int lane = (int)(i & 63);
-  const int64_t base = slice_ptr[sl] + lane;
-  const int width = (int)((slice_ptr[sl + 1] - slice_ptr[sl]) >> 6);
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int sub = threadIdx.x & 15;
   T acc = 0;
-  for (int k = 0; k < width; ++k) {
-    const int64_t o = base + (int64_t)k * 64;
-    acc += val[o] * (T)q[col[o]];
+  if (i < n) {
+    const int64_t e = row_ptr[i + 1];
+    for (int64_t o = row_ptr[i] + sub; o < e; o += 16) acc += val[o] * (T)q[col[o]];
   }
-  const int b = idx[i];
-  const double sg = pos[i].w;
-  const double phi = (double)acc + phi_wave[b] - (ck[0] - ck[1] * sg * sg);
-  y[b] = -phi + (dpsi ? dpsi[body_of[b]] : 0.0);
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+  if (i < n && sub == 0) {
+    const int b = idx[i];
+    const double sg = pos[i].w;
+    const double phi = (double)acc + phi_wave[b] - (ck[0] - ck[1] * sg * sg);
+    y[b] = -phi + (dpsi ? dpsi[body_of[b]] : 0.0);
+  }
 }
 
 // On-the-fly potential (and field) at targets from sources; adds into
@@ -340,7 +330,6 @@ void build_bead_matrix(pe_context* c) {
   const int64_t n = c->n_bead;
   ParticleSet& B = c->B;
   c->cnt.ensure(n);
-  c->nslice = (n + 63) / 64;
   if (n > 0) {
     hipLaunchKernelGGL(count_pairs_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, B.pos.get(),
                        B.cell_start.get(), n, c->rg, c->cnt.get());
@@ -349,28 +338,18 @@ void build_bead_matrix(pe_context* c) {
   std::vector<int> cnt(n);
   if (n > 0) PE_HIP(hipMemcpyAsync(cnt.data(), c->cnt.get(), sizeof(int) * n, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
-  std::vector<int64_t> sp(c->nslice + 1, 0);
-  int64_t real_pairs = 0;
-  for (int64_t sl = 0; sl < c->nslice; ++sl) {
-    int w = 0;
-    for (int64_t i = sl * 64; i < std::min<int64_t>(n, sl * 64 + 64); ++i) {
-      w = std::max(w, cnt[i]);
-      real_pairs += cnt[i];
-    }
-    sp[sl + 1] = sp[sl] + (int64_t)w * 64;
-  }
-  c->nnz = real_pairs;
-  const int64_t total = sp[c->nslice];
-  require(total < (int64_t)1 << 40, "real-space operator too large");
-  c->slice_ptr.ensure(c->nslice + 1);
-  c->col.ensure(total);
-  c->val64.ensure(total);
+  std::vector<int64_t> rp(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) rp[i + 1] = rp[i] + cnt[i];
+  c->nnz = rp[n];
+  c->row_ptr.ensure(n + 1);
+  c->col.ensure(c->nnz);
+  c->val64.ensure(c->nnz);
   c->have_val32 = c->p.precision == PE_MIXED;
-  if (c->have_val32) c->val32.ensure(total);
-  PE_HIP(hipMemcpyAsync(c->slice_ptr.get(), sp.data(), sizeof(int64_t) * (c->nslice + 1), hipMemcpyHostToDevice, s));
+  if (c->have_val32) c->val32.ensure(c->nnz);
+  PE_HIP(hipMemcpyAsync(c->row_ptr.get(), rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
   if (n > 0) {
     hipLaunchKernelGGL(fill_pairs_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, B.pos.get(), B.idx.get(),
-                       B.cell_start.get(), n, c->rg, c->slice_ptr.get(), c->col.get(), c->val64.get(),
+                       B.cell_start.get(), n, c->rg, c->row_ptr.get(), c->col.get(), c->val64.get(),
                        c->have_val32 ? c->val32.get() : (float*)nullptr);
     PE_CHECK_LAUNCH();
   }
@@ -388,7 +367,7 @@ void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const d
     require(c->have_val32, "float real-space operator not built (precision is PE_FP64)");
     val = c->val32.get();
   }
-  hipLaunchKernelGGL(spmv_assemble_kernel<T>, dim3(nblk(n, 256)), dim3(256), 0, s, c->slice_ptr.get(),
+  hipLaunchKernelGGL(spmv_assemble_kernel<T>, dim3(nblk(16 * n, 256)), dim3(256), 0, s, c->row_ptr.get(),
                      c->col.get(), val, c->B.idx.get(), c->B.pos.get(), n, q, phi_wave, ck0, dpsi,
                      c->body_of.get(), y_top);
   PE_CHECK_LAUNCH();

@@ -5,6 +5,8 @@
 // and multi-axpy for classical Gram-Schmidt, Givens rotations, back
 // substitution).  Every reduction is two-stage with a fixed order, so
 // results are bitwise reproducible run to run.
+#include <algorithm>
+
 #include "pe_internal.hpp"
 #include "vector.hpp"
 
@@ -132,34 +134,19 @@ __global__ void __launch_bounds__(kBS) body_outputs_kernel(
   }
 }
 
-// out[i] = (sum over vectors k of) V_k . w, partial per block, K <= kMaxK
-__global__ void __launch_bounds__(kBS) mdot_partial_kernel(const double* __restrict__ V, int64_t ldv, int K,
+// partial[k * gridDim.x + c] = V_k . w over chunk c (grid: chunks x K)
+__global__ void __launch_bounds__(kBS) mdot_partial_kernel(const double* __restrict__ V, int64_t ldv,
                                                            const double* __restrict__ w, int64_t n,
-                                                           double* __restrict__ partial) {
-  double acc[kMaxK];
-#pragma unroll
-  for (int k = 0; k < kMaxK; ++k) acc[k] = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double wi = w[i];
-#pragma unroll
-    for (int k = 0; k < kMaxK; ++k)
-      if (k < K) acc[k] += V[k * ldv + i] * wi;
-  }
-  __shared__ double sh[kBS / 64][kMaxK];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < kMaxK; ++k) {
-    if (k < K) {
-      const double s = wsum(acc[k]);
-      if (lane == 0) sh[wv][k] = s;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < K) {
-    double s = 0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i][threadIdx.x];
-    partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
-  }
+                                                           int64_t chunk, double* __restrict__ partial) {
+  const int k = blockIdx.y;
+  const double* v = V + (int64_t)k * ldv;
+  const int64_t b = (int64_t)blockIdx.x * chunk;
+  const int64_t e = b + chunk < n ? b + chunk : n;
+  double acc[1] = {0};
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) acc[0] += v[i] * w[i];
+  __shared__ double o[1];
+  block_sum<1>(acc, o);
+  if (threadIdx.x == 0) partial[(int64_t)k * gridDim.x + blockIdx.x] = o[0];
 }
 
 __global__ void mdot_final_kernel(const double* __restrict__ partial, int nb, int K, double* __restrict__ out,
@@ -297,8 +284,10 @@ void launch_body_outputs(hipStream_t s, const int64_t* off, int64_t n_body, cons
 void launch_mdot(hipStream_t s, const double* V, int64_t ldv, int K, const double* w, int64_t n,
                  double* partial, double* out, bool take_sqrt) {
   require(K >= 1 && K <= kMaxK, "mdot: too many vectors");
-  const unsigned nb = nred(n);
-  hipLaunchKernelGGL(mdot_partial_kernel, dim3(nb), dim3(kBS), 0, s, V, ldv, K, w, n, partial);
+  int64_t chunk = 1024;
+  if ((n + chunk - 1) / chunk > 1024) chunk = (n + 1023) / 1024;
+  const unsigned nb = (unsigned)std::max<int64_t>(1, (n + chunk - 1) / chunk);
+  hipLaunchKernelGGL(mdot_partial_kernel, dim3(nb, K), dim3(kBS), 0, s, V, ldv, w, n, chunk, partial);
   PE_CHECK_LAUNCH();
   hipLaunchKernelGGL(mdot_final_kernel, dim3(K), dim3(64), 0, s, partial, (int)nb, K, out, take_sqrt ? 1 : 0);
   PE_CHECK_LAUNCH();

@@ -5,7 +5,7 @@
 
 namespace pe {
 
-constexpr int kMaxK = 32;  // max Krylov vectors in one multi-dot (restart + 1)
+constexpr int kMaxK = 256;  // max Krylov vectors in one multi-dot (restart + 1)
 
 // Coefficients of the k = 0 constant of the split.
 struct CkCoef {

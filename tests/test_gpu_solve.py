@@ -141,7 +141,7 @@ def test_solve_and_forces_converge_to_exact_oracle(gpu_lib):
     # momentum balance: sum of all forces = Q_tot E0
     tot = Fg.sum(0) + f["ion_force"].cpu().numpy().sum(0)
     Qt = s.body_charge.sum() + s.ion_charge.sum()
-    np.testing.assert_allclose(tot, Qt * s.E0, atol=1e-8)
+    np.testing.assert_allclose(tot, Qt * s.E0, atol=1e-7 * np.abs(Fg).max())
     ctx.close()
 
 
