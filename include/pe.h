@@ -99,6 +99,8 @@ typedef struct pe_params {
   double inner_tol;       /* PE_MIXED: relative tolerance of each inner solve, default 1e-4 */
   int32_t max_refine;     /* PE_MIXED: max outer refinement steps, default 8 */
   int32_t use_learned_guess; /* 1: start from the network's prediction (needs a loaded model) */
+  int32_t precond;        /* 1 (default): block-Jacobi preconditioner (inverse of each body's
+                             free-space saddle block) inside flexible GMRES; 0: none */
 } pe_params;
 
 typedef struct pe_solve_info {
@@ -226,6 +228,7 @@ typedef enum {
   PE_PROF_SPMV,
   PE_PROF_PAIR,
   PE_PROF_KRYLOV,
+  PE_PROF_PRECOND,
   PE_PROF_NCLASS
 } pe_prof_class;
 pe_status pe_profile_enable(pe_context* ctx, int32_t on);

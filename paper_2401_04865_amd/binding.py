@@ -19,7 +19,7 @@ PE_OK, PE_ERR_ARG, PE_ERR_STATE, PE_ERR_DEVICE, PE_ERR_NOMEM, PE_ERR_NOT_CONVERG
 PE_FP64, PE_MIXED = 0, 1
 PE_REG_GAUSSIAN, PE_REG_SHELL = 0, 1
 PROF_CLASSES = ["spread", "fft_z_r2c", "fft_y_fwd", "fft_x_scale", "fft_y_inv", "fft_z_c2r", "gather",
-                "spmv", "pair", "krylov"]
+                "spmv", "pair", "krylov", "precond"]
 STATUS_NAMES = {0: "PE_OK", 1: "PE_ERR_ARG", 2: "PE_ERR_STATE", 3: "PE_ERR_DEVICE", 4: "PE_ERR_NOMEM",
                 5: "PE_ERR_NOT_CONVERGED", 6: "PE_ERR_NUMERIC"}
 
@@ -43,6 +43,7 @@ class pe_params(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("max_refine", ctypes.c_int32),
         ("use_learned_guess", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
     ]
 
 

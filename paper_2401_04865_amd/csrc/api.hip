@@ -10,6 +10,7 @@
 #include "pe_internal.hpp"
 #include "vector.hpp"
 #include "guess.hpp"
+#include "precond.hpp"
 
 using namespace pe;
 
@@ -261,6 +262,7 @@ void build_rhs(pe_context* c, double* b) {
 
 struct KWork {
   double* V;      // (m+1) x n
+  double* Z;      // m x n preconditioned directions (flexible GMRES)
   double* w;      // n
   double* r;      // n
   double* tmp;    // n
@@ -275,10 +277,12 @@ struct KWork {
 KWork kwork(pe_context* c, int64_t n, int m) {
   KWork k;
   c->Vb.ensure((size_t)(m + 1) * n);
+  c->Zb.ensure((size_t)m * n);
   c->kvec.ensure((size_t)3 * n);
   const size_t nst = (size_t)(m + 1) * m + 2 * m + (m + 1);
   c->hs.ensure(nst + 3 * (m + 1) + 4 + m);
   k.V = c->Vb.get();
+  k.Z = c->Zb.get();
   k.w = c->kvec.get();
   k.r = k.w + n;
   k.tmp = k.r + n;
@@ -339,8 +343,18 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
     launch_scale(s, k.r, k.nrm, k.V, n);
     launch_init_g(s, k.st, m, k.nrm);
     int jend = 0;
+    const bool pre = c->p.precond != 0 && !c->pc.types.empty();
     for (int j = 0; j < m; ++j) {
       double* vj = k.V + (size_t)j * n;
+      if (pre) {
+        double* zj = k.Z + (size_t)j * n;
+        {
+          ProfScope ps(c->prof, s, PE_PROF_PRECOND, prec != PE_MIXED);
+          if (prec == PE_MIXED) precond_apply<float>(s, c, vj, zj);
+          else precond_apply<double>(s, c, vj, zj);
+        }
+        vj = zj;
+      }
       apply_saddle_prec(c, prec, vj, k.w);
       (prec == PE_MIXED ? *mv32 : *mv64) += 1;
       {
@@ -361,7 +375,7 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
       if (est <= tol * bnorm || out.iters >= max_iters) break;
     }
     launch_backsolve(s, k.st, m, jend, k.y);
-    launch_maxpy(s, k.V, n, jend, k.y, x, n, -1.0);  // x += V y
+    launch_maxpy(s, pre ? k.Z : k.V, n, jend, k.y, x, n, -1.0);  // x += Z y (flexible) or V y
   }
 }
 
@@ -462,6 +476,7 @@ pe_status pe_default_params(pe_params* p) {
   p->inner_tol = 1e-4;
   p->max_refine = 8;
   p->use_learned_guess = 0;
+  p->precond = 1;
   return PE_OK;
 }
 
@@ -543,7 +558,7 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   std::vector<int64_t> off(n_body + 1, 0);
   if (n_body) std::copy(body_offsets, body_offsets + n_body + 1, off.begin());
   require(off[0] == 0, "body_offsets[0] must be 0");
-  for (int64_t i = 0; i < n_body; ++i) require(off[i + 1] >= off[i], "body_offsets must be nondecreasing");
+  for (int64_t i = 0; i < n_body; ++i) require(off[i + 1] > off[i], "every body needs at least one bead");
   const int64_t nb = off[n_body];
   require(nb < ((int64_t)1 << 31) && n_ion < ((int64_t)1 << 31), "too many particles");
   require(nb == 0 || (bead_pos && bead_sigma), "bead arrays are null");
@@ -639,6 +654,7 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   build_tiles(s, c->B, c->gg);
   build_tiles(s, c->I, c->gg);
   build_bead_matrix(c);
+  if (c->p.precond) precond_setup(c);
   ensure_grids(c);
   c->phi_w.ensure(nb + n_ion + 1);
   c->phi_all.ensure(nb + n_ion + 1);

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <deque>
 #include <vector>
 
 #include "../../include/pe.h"
@@ -191,6 +192,24 @@ struct ProfScope {
   }
 };
 
+// ----------------------------------------------------------- preconditioner
+
+// One rigid-body shape: reference geometry (relative bead positions of the
+// first body seen), widths, the inverse of its body saddle block, and the
+// bodies of the current configuration that have this shape.
+struct BodyType {
+  int N = 0;
+  std::vector<double> ref, sig;
+  DevBuf<double> Ainv;
+  DevBuf<float> Ainv32;
+  std::vector<int> bodies;
+  DevBuf<int> dbodies;
+};
+
+struct Precond {
+  std::deque<BodyType> types;
+};
+
 // ----------------------------------------------------------------- context
 
 struct LearnedGuess;  // defined in the guess translation unit
@@ -248,6 +267,7 @@ struct pe_context {
 
   // Krylov
   pe::DevBuf<double> Vb;       // (m+1) x n basis
+  pe::DevBuf<double> Zb;       // m x n preconditioned directions
   pe::DevBuf<double> kvec;     // x, b, r, w, ... (several n-vectors)
   pe::DevBuf<double> hs;       // Hessenberg, rotations, g, y, scalars
   pe::DevBuf<double> rhs_b;    // right-hand side
@@ -259,6 +279,7 @@ struct pe_context {
   pe::LearnedGuess* guess = nullptr;
 
   pe::Prof prof;
+  pe::Precond pc;
 };
 
 namespace pe {
