@@ -264,6 +264,20 @@ pe_status pe_guess_save(const pe_context* ctx, const char* path);
 pe_status pe_guess_load(pe_context* ctx, const char* path);
 
 /*
+ * Test hooks of the learned guess.  pe_guess_debug: copy the kNPar = 4996
+ * float parameters out (set_params = 0) or in (1), and if n_rows > 0 return
+ * the gradient of the mean squared loss over the first n_rows recorded rows
+ * (grad host kNPar floats, loss host).  Parameter order: W1[64][8], b1[64],
+ * W2[64][64], b2[64], W3[4][64], b3[4].  pe_guess_rows: copy the first n_rows
+ * recorded rows (11 floats each: 8 features, Q_i/N_i, solved q, 0) to host;
+ * pe_guess_add_rows appends host rows of the same layout to the training set.
+ */
+pe_status pe_guess_debug(pe_context* ctx, float* params_inout, int32_t set_params, int64_t n_rows,
+                         float* grad, double* loss);
+pe_status pe_guess_rows(pe_context* ctx, float* rows, int64_t n_rows);
+pe_status pe_guess_add_rows(pe_context* ctx, const float* rows, int64_t n_rows);
+
+/*
  * One overdamped Brownian-dynamics step (section "Brownian dynamics
  * simulations...": Euler-Maruyama, free draining, no hydrodynamic
  * interactions) using the forces of the last pe_forces_torques call:

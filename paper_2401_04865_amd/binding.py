@@ -105,6 +105,9 @@ SIGNATURES = {
     "pe_guess_save": [_vp, ctypes.c_char_p],
     "pe_guess_load": [_vp, ctypes.c_char_p],
     "pe_bd_step": [_vp, _dbl, _dbl, _dbl, _u64, _u64, _vp, _vp, _vp, _vp],
+    "pe_guess_debug": [_vp, _vp, _i32, _i64, _vp, ctypes.POINTER(_dbl)],
+    "pe_guess_rows": [_vp, _vp, _i64],
+    "pe_guess_add_rows": [_vp, _vp, _i64],
 }
 
 
@@ -278,6 +281,26 @@ class Context:
 
     def pe_guess_load(self, path):
         self._chk(_lib.pe_guess_load(self.h, str(path).encode()))
+
+    def pe_guess_debug(self, params=None, n_rows=0):
+        """(params, grad, loss): read (params None) or set the parameters; gradient over n_rows."""
+        NP = 4996
+        p = np.zeros(NP, dtype=np.float32) if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        g = np.zeros(NP, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._chk(_lib.pe_guess_debug(self.h, p.ctypes.data_as(ctypes.c_void_p), 0 if params is None else 1,
+                                      int(n_rows), g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
+        return p, g, loss.value
+
+    def pe_guess_rows(self, n_rows):
+        out = np.zeros((int(n_rows), 11), dtype=np.float32)
+        self._chk(_lib.pe_guess_rows(self.h, out.ctypes.data_as(ctypes.c_void_p), int(n_rows)))
+        return out
+
+    def pe_guess_add_rows(self, rows):
+        r = np.ascontiguousarray(rows, dtype=np.float32)
+        assert r.ndim == 2 and r.shape[1] == 11
+        self._chk(_lib.pe_guess_add_rows(self.h, r.ctypes.data_as(ctypes.c_void_p), int(r.shape[0])))
 
     def pe_bd_step(self, dt, kT, gamma, seed, step, bead_pos, body_center, body_quat, ion_pos):
         self._chk(_lib.pe_bd_step(self.h, float(dt), float(kT), float(gamma), int(seed), int(step),

@@ -248,9 +248,16 @@ void build_rhs(pe_context* c, double* b) {
     double* gB = c->gridB.get();
     launch_spread<double>(s, c->I, c->ion_q.get(), gA, c->gg, false);
     launch_wave_pipeline<double>(s, c, gA, gB, c->gridC.get());
-    launch_gather<double>(s, c->B, gB, c->gg, phi_ion, nullptr, false);
-    launch_pair_onfly<double>(s, c->B, c->I, c->ion_q.get(), c->rg, phi_ion, nullptr);
+    // with the learned guess active, the same pass also yields the ion field at the beads
+    double* E = nullptr;
+    if (c->guess) {
+      c->E_ion.ensure(3 * std::max<int64_t>(nb, 1));
+      E = c->E_ion.get();
+    }
+    launch_gather<double>(s, c->B, gB, c->gg, phi_ion, E, false);
+    launch_pair_onfly<double>(s, c->B, c->I, c->ion_q.get(), c->rg, phi_ion, E);
   }
+  c->have_eion = c->guess != nullptr;
   if (nb)
     hipLaunchKernelGGL(rhs_top_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, c->rel.get(), c->E0[0],
                        c->E0[1], c->E0[2], phi_ion, c->bead_sig.get(), ck_ion(c), b);
@@ -551,6 +558,7 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   c->have_system = false;
   c->have_solution = false;
   c->have_forces = false;
+  c->have_eion = false;
   require(n_body >= 0 && n_ion >= 0, "negative sizes");
   require(n_body == 0 || body_offsets != nullptr, "body_offsets is null");
   require(E0 != nullptr, "E0 is null");
@@ -661,6 +669,7 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   c->E_all.ensure(3 * (nb + n_ion) + 1);
   c->forces.ensure(3 * (nb + n_ion) + 1);
   c->xsol.ensure(nb + n_body + 1);
+  c->sums.ensure(64 + n_body);
   c->rhs_b.ensure(nb + n_body + 1);
   c->have_system = true;
   if (c->guess) guess_on_system(c);
@@ -854,8 +863,12 @@ pe_status pe_forces_torques(pe_context* c, double* body_force, double* body_torq
     all_potential<float>(c, chg, chg + nb, c->phi_all.get(), c->E_all.get(), f, u, chg);
   else
     all_potential<double>(c, chg, chg + nb, c->phi_all.get(), c->E_all.get(), f, u, chg);
-  launch_body_outputs(s, c->off.get(), c->n_body, c->rel.get(), chg, f, u, nullptr, body_force, body_torque,
+  c->bodyF.ensure(3 * std::max<int64_t>(c->n_body, 1));
+  c->bodyL.ensure(3 * std::max<int64_t>(c->n_body, 1));
+  launch_body_outputs(s, c->off.get(), c->n_body, c->rel.get(), chg, f, u, nullptr, c->bodyF.get(), c->bodyL.get(),
                       body_energy);
+  if (body_force) dcopy(s, c->bodyF.get(), body_force, 3 * c->n_body);
+  if (body_torque) dcopy(s, c->bodyL.get(), body_torque, 3 * c->n_body);
   if (ion_force) dcopy(s, f + 3 * nb, ion_force, 3 * ni);
   if (bead_force) dcopy(s, f, bead_force, 3 * nb);
   double* tot = scal(c);

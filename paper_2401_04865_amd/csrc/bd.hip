@@ -1,0 +1,207 @@
+// One overdamped Brownian-dynamics step (section "Brownian dynamics
+// simulations of charged and polarizable colloids in explicit electrolytes":
+// Euler-Maruyama integration of the overdamped Langevin equation, Stokes drag
+// gamma per particle, no hydrodynamic interactions between particles).
+//
+// Ions:   x += f dt / gamma + sqrt(2 kT dt / gamma) xi
+// Bodies: a rigid set of N beads, each with drag gamma, moving freely
+//         (free draining): translational drag N gamma, rotational drag
+//         K = gamma sum_j (|r_j|^2 I - r_j r_j^T) about the centroid;
+//         X += F dt / (N gamma) + sqrt(2 kT dt / (N gamma)) xi,
+//         dtheta = K^{-1} L dt + sqrt(2 kT dt) C xi   with C C^T = K^{-1},
+//         orientation q <- exp(dtheta / 2) q, beads x = X + R(q) r'.
+// Gaussian noise: Philox-4x32-10 (Salmon, Moraes, Dror, Shaw 2011) with key =
+// seed and counter = (particle, stream, step lo, step hi), two uniforms per
+// normal by the Box-Muller transform.  Ions use streams 0/1, bodies 2/3
+// (translation / rotation), so every number is fixed by (seed, step, index).
+#include <cmath>
+
+#include "pe_internal.hpp"
+
+namespace pe {
+
+namespace {
+
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)M0 * c.x;
+    const uint64_t p1 = (uint64_t)M1 * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += W0;
+    k1 += W1;
+  }
+  return c;
+}
+
+// uniform in (0, 1]: (u + 1) / 2^32
+__device__ __forceinline__ double uni(uint32_t u) { return ((double)u + 1.0) * 2.3283064365386963e-10; }
+
+// Three standard normals for (index, stream, step).
+__device__ __forceinline__ void normals3(uint64_t seed, uint64_t step, uint32_t index, uint32_t stream, double* g) {
+  const U4 r = philox4x32_10(U4{index, stream, (uint32_t)step, (uint32_t)(step >> 32)}, (uint32_t)seed,
+                             (uint32_t)(seed >> 32));
+  const double two_pi = 6.283185307179586477;
+  const double a = sqrt(-2.0 * log(uni(r.x))), b = sqrt(-2.0 * log(uni(r.z)));
+  g[0] = a * cos(two_pi * uni(r.y));
+  g[1] = a * sin(two_pi * uni(r.y));
+  g[2] = b * cos(two_pi * uni(r.w));
+}
+
+__global__ void bd_ions_kernel(int64_t n, const double* __restrict__ f, double dt, double kT, double gamma,
+                               uint64_t seed, uint64_t step, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double g[3];
+  normals3(seed, step, (uint32_t)i, 0u, g);
+  const double s = sqrt(2.0 * kT * dt / gamma);
+  for (int d = 0; d < 3; ++d) x[3 * i + d] += f[3 * i + d] * dt / gamma + s * g[d];
+}
+
+__device__ __forceinline__ void quat_to_R(const double* q, double R[3][3]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0][0] = 1 - 2 * (y * y + z * z); R[0][1] = 2 * (x * y - w * z); R[0][2] = 2 * (x * z + w * y);
+  R[1][0] = 2 * (x * y + w * z); R[1][1] = 1 - 2 * (x * x + z * z); R[1][2] = 2 * (y * z - w * x);
+  R[2][0] = 2 * (x * z - w * y); R[2][1] = 2 * (y * z + w * x); R[2][2] = 1 - 2 * (x * x + y * y);
+}
+
+// One thread per body: rotational drag, its inverse and a Cholesky factor of
+// the inverse, the rigid-body displacement and rotation.  Writes the new
+// centre/orientation and the rotation (old -> new) for the bead update.
+__global__ void bd_bodies_kernel(int64_t nb, const int64_t* __restrict__ off, const double* __restrict__ rel,
+                                 const double* __restrict__ F, const double* __restrict__ L, double dt, double kT,
+                                 double gamma, uint64_t seed, uint64_t step, double* __restrict__ X,
+                                 double* __restrict__ quat, double* __restrict__ Rnew) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int64_t o0 = off[b], o1 = off[b + 1];
+  const double N = (double)(o1 - o0);
+  double K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int64_t j = o0; j < o1; ++j) {
+    const double r[3] = {rel[3 * j], rel[3 * j + 1], rel[3 * j + 2]};
+    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) K[a][c] += gamma * ((a == c ? r2 : 0.0) - r[a] * r[c]);
+  }
+  // inverse by cofactors (K is SPD for a body that is not a single point or a line)
+  double Ki[3][3];
+  const double det = K[0][0] * (K[1][1] * K[2][2] - K[1][2] * K[2][1]) - K[0][1] * (K[1][0] * K[2][2] - K[1][2] * K[2][0]) +
+                     K[0][2] * (K[1][0] * K[2][1] - K[1][1] * K[2][0]);
+  const bool rot = N > 1 && det > 1e-300;
+  if (rot) {
+    Ki[0][0] = (K[1][1] * K[2][2] - K[1][2] * K[2][1]) / det;
+    Ki[0][1] = (K[0][2] * K[2][1] - K[0][1] * K[2][2]) / det;
+    Ki[0][2] = (K[0][1] * K[1][2] - K[0][2] * K[1][1]) / det;
+    Ki[1][0] = (K[1][2] * K[2][0] - K[1][0] * K[2][2]) / det;
+    Ki[1][1] = (K[0][0] * K[2][2] - K[0][2] * K[2][0]) / det;
+    Ki[1][2] = (K[0][2] * K[1][0] - K[0][0] * K[1][2]) / det;
+    Ki[2][0] = (K[1][0] * K[2][1] - K[1][1] * K[2][0]) / det;
+    Ki[2][1] = (K[0][1] * K[2][0] - K[0][0] * K[2][1]) / det;
+    Ki[2][2] = (K[0][0] * K[1][1] - K[0][1] * K[1][0]) / det;
+  }
+  // translation
+  double g[3];
+  normals3(seed, step, (uint32_t)b, 2u, g);
+  const double st = sqrt(2.0 * kT * dt / (N * gamma));
+  for (int d = 0; d < 3; ++d) X[3 * b + d] += F[3 * b + d] * dt / (N * gamma) + st * g[d];
+  // rotation vector
+  double th[3] = {0, 0, 0};
+  if (rot) {
+    // Cholesky C of Ki (symmetrized)
+    const double a00 = Ki[0][0], a10 = 0.5 * (Ki[1][0] + Ki[0][1]), a11 = Ki[1][1];
+    const double a20 = 0.5 * (Ki[2][0] + Ki[0][2]), a21 = 0.5 * (Ki[2][1] + Ki[1][2]), a22 = Ki[2][2];
+    const double c00 = sqrt(a00);
+    const double c10 = a10 / c00, c20 = a20 / c00;
+    const double c11 = sqrt(fmax(a11 - c10 * c10, 0.0));
+    const double c21 = c11 > 0 ? (a21 - c20 * c10) / c11 : 0.0;
+    const double c22 = sqrt(fmax(a22 - c20 * c20 - c21 * c21, 0.0));
+    normals3(seed, step, (uint32_t)b, 3u, g);
+    const double sr = sqrt(2.0 * kT * dt);
+    const double cg[3] = {c00 * g[0], c10 * g[0] + c11 * g[1], c20 * g[0] + c21 * g[1] + c22 * g[2]};
+    for (int a = 0; a < 3; ++a)
+      th[a] = (Ki[a][0] * L[3 * b] + Ki[a][1] * L[3 * b + 1] + Ki[a][2] * L[3 * b + 2]) * dt + sr * cg[a];
+  }
+  // dq = (cos(|th|/2), sin(|th|/2) th/|th|);  q <- dq * q
+  const double ang = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+  double dq[4] = {1, 0, 0, 0};
+  if (ang > 0) {
+    const double s = sin(0.5 * ang) / ang;
+    dq[0] = cos(0.5 * ang);
+    dq[1] = s * th[0];
+    dq[2] = s * th[1];
+    dq[3] = s * th[2];
+  }
+  double* q = quat + 4 * b;
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  double nq[4] = {dq[0] * w - dq[1] * x - dq[2] * y - dq[3] * z, dq[0] * x + dq[1] * w + dq[2] * z - dq[3] * y,
+                  dq[0] * y - dq[1] * z + dq[2] * w + dq[3] * x, dq[0] * z + dq[1] * y - dq[2] * x + dq[3] * w};
+  const double nn = sqrt(nq[0] * nq[0] + nq[1] * nq[1] + nq[2] * nq[2] + nq[3] * nq[3]);
+  for (int k = 0; k < 4; ++k) q[k] = nq[k] / nn;
+  double R[3][3];
+  quat_to_R(dq, R);
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) Rnew[9 * b + 3 * a + c] = R[a][c];
+}
+
+// beads: x = X_new + dR r  (dR rotates the old relative position to the new one)
+__global__ void bd_beads_kernel(int64_t n, const int* __restrict__ body_of, const double* __restrict__ rel,
+                                const double* __restrict__ X, const double* __restrict__ dR, double* __restrict__ x) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int b = body_of[j];
+  const double* R = dR + 9 * b;
+  const double r0 = rel[3 * j], r1 = rel[3 * j + 1], r2 = rel[3 * j + 2];
+  for (int a = 0; a < 3; ++a) x[3 * j + a] = X[3 * b + a] + R[3 * a] * r0 + R[3 * a + 1] * r1 + R[3 * a + 2] * r2;
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+}  // namespace pe
+
+using namespace pe;
+
+extern "C" pe_status pe_bd_step(pe_context* c, double dt, double kT, double gamma, uint64_t seed, uint64_t step,
+                                double* bead_pos, double* body_center, double* body_quat, double* ion_pos) {
+  if (!c) return PE_ERR_ARG;
+  try {
+    if (!c->have_forces) throw Error(PE_ERR_STATE, "pe_forces_torques has not been called");
+    require(dt > 0 && kT >= 0 && gamma > 0, "dt, gamma must be positive and kT non-negative");
+    require((c->n_bead == 0 || bead_pos) && (c->n_body == 0 || (body_center && body_quat)) &&
+                (c->n_ion == 0 || ion_pos),
+            "null state array");
+    hipStream_t s = c->stream;
+    const int64_t nb = c->n_bead, nbody = c->n_body, ni = c->n_ion;
+    if (ni)
+      hipLaunchKernelGGL(bd_ions_kernel, dim3(nblk(ni, 256)), dim3(256), 0, s, ni, c->forces.get() + 3 * nb, dt, kT,
+                         gamma, seed, step, ion_pos);
+    c->bd_R.ensure(9 * std::max<int64_t>(nbody, 1));
+    if (nbody) {
+      hipLaunchKernelGGL(bd_bodies_kernel, dim3(nblk(nbody, 64)), dim3(64), 0, s, nbody, c->off.get(), c->rel.get(),
+                         c->bodyF.get(), c->bodyL.get(), dt, kT, gamma, seed, step, body_center, body_quat,
+                         c->bd_R.get());
+      hipLaunchKernelGGL(bd_beads_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, c->body_of.get(), c->rel.get(),
+                         body_center, c->bd_R.get(), bead_pos);
+    }
+    PE_CHECK_LAUNCH();
+    PE_HIP(hipStreamSynchronize(s));
+    c->have_system = false;  // positions moved: pe_set_system must run again
+    c->have_solution = false;
+    c->have_forces = false;
+  } catch (const Error& e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return PE_ERR_DEVICE;
+  }
+  return PE_OK;
+}

@@ -273,6 +273,10 @@ struct pe_context {
   pe::DevBuf<double> rhs_b;    // right-hand side
   pe::DevBuf<double> xsol;     // last solution [q; dpsi]
   pe::DevBuf<double> forces;   // f per particle (n_bead+n_ion) x 3
+  pe::DevBuf<double> bodyF, bodyL;  // n_body x 3 from the last force pass
+  pe::DevBuf<double> bd_R;     // per-body rotation of the last BD step
+  pe::DevBuf<double> E_ion;    // n_bead x 3, field of the ions at the beads (learned-guess features)
+  bool have_eion = false;
   pe::DevBuf<double> host_pin; // unused placeholder
 
   // learned guess
