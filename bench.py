@@ -39,25 +39,24 @@ WORKLOADS = {
 SPLIT_TOL = {"cfg2": 1e-8, "cfg3": 1e-6, "cfg4": 1e-6, "cfg5": 1e-6}
 
 
-def algorithmic_bytes(cls, dbl, n_part, n_set_particles, G, Gc, nnz_stored):
-    """Minimum HBM bytes one launch of a kernel class must move.
+def kernel_model(cls, dbl, nb, ni, G, Gc, nnz, system):
+    """(bound, algorithmic amount per launch, unit, peak) for a kernel class.
 
-    s = bytes per real.  Particle records read by spread/gather: position
-    (4 doubles incl. width), caller index (4 B), charge or output (8 B).
+    Byte counts are the minimum HBM traffic one launch must move; s = bytes
+    per real.  Spread/gather launches of the Krylov operator cover the beads;
+    particle records are position + width (32 B), index (4 B) and charge or
+    output (8 B).  The FFT passes read and write the half spectrum (or the
+    real grid).  The sparse real-space product reads its matrix once.
     """
     s = 8 if dbl else 4
-    if cls == "spread":
-        return n_set_particles * (32 + 4 + 8) + G * s            # particles in, grid out
-    if cls == "gather":
-        return n_set_particles * (32 + 4 + 8) + G * s            # grid in, potentials out
+    if cls in ("spread", "gather"):
+        return "hbm", nb * (32 + 4 + 8) + G * s, "GB/s", HBM_PEAK_GBS
     if cls in ("fft_y_fwd", "fft_y_inv", "fft_x_scale"):
-        return 2 * Gc * 2 * s                                     # complex half grid in and out
-    if cls == "fft_z_r2c":
-        return G * s + Gc * 2 * s
-    if cls == "fft_z_c2r":
-        return Gc * 2 * s + G * s
+        return "hbm", 2 * Gc * 2 * s, "GB/s", HBM_PEAK_GBS
+    if cls in ("fft_z_r2c", "fft_z_c2r"):
+        return "hbm", G * s + Gc * 2 * s, "GB/s", HBM_PEAK_GBS
     if cls == "spmv":
-        return nnz_stored * (s + 4) + n_part * (8 + 8 + 8 + 32)  # matrix + q, phi_wave, y, row data
+        return "hbm", nnz * (s + 4) + nb * (8 + 8 + 8 + 32 + 8), "GB/s", HBM_PEAK_GBS
     return None
 
 
@@ -98,11 +97,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
-    ap.add_argument("--model", default=None, help="trained learned-guess weights (pe_guess_save format)")
+    ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
+    ap.add_argument("--train-systems", type=int, default=4,
+                    help="independent configurations of the workload whose solves train the learned guess "
+                         "(0: no learned guess)")
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-arm", action="store_true")
-    ap.add_argument("--matvec-reps", type=int, default=50)
+    ap.add_argument("--fp64-solves", type=int, default=2)
+    ap.add_argument("--matvec-reps", type=int, default=20)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -110,38 +113,29 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    import tempfile
+
     import torch
     from paper_2401_04865_amd import binding as B
     from paper_2401_04865_amd import inputs
 
     torch.cuda.set_device(0)
     k, desc = WORKLOADS[args.workload]
+    bd_mode = args.workload == "cfg5"
     t0 = time.perf_counter()
     system = inputs.config(k)
     t_gen = time.perf_counter() - t0
-    print(f"[bench] {args.workload}: {system.n_bead} beads, {system.n_body} bodies, {system.n_ion} ions, "
-          f"mesh {system.mesh} (inputs {t_gen:.1f} s)", file=sys.stderr, flush=True)
+    log(f"{args.workload}: {system.n_bead} beads, {system.n_body} bodies, {system.n_ion} ions, "
+        f"mesh {system.mesh} (inputs {t_gen:.1f} s)")
     tol = SPLIT_TOL[args.workload]
-
-    def make_ctx(prec, learned=False):
-        p = B.make_params(system.box, system.mesh, P=8, split_tol=tol, rel_tol=1e-6, precision=prec,
-                          use_learned_guess=1 if learned else 0)
-        ctx = B.Context(p)
-        ctx.load(system)
-        return ctx
-
-    learned = False
-    ctx = make_ctx(B.PE_MIXED)
-    if args.model and os.path.exists(args.model):
-        ctx.pe_guess_load(args.model)
-        ctx.close()
-        ctx = make_ctx(B.PE_MIXED, learned=True)
-        ctx.pe_guess_load(args.model)
-        learned = True
-    d = ctx.pe_get_derived()
-    dev = ctx.sys_dev
-    off = system.body_offsets
     nb, nbody, ni = system.n_bead, system.n_body, system.n_ion
+    off = system.body_offsets
+    dt, kT, gamma, seed = 1e-4, 1.0, 1.0, 20240109
+
+    def params(prec, learned=False, precond=1):
+        return B.make_params(system.box, system.mesh, P=8, split_tol=tol, rel_tol=1e-6, precision=prec,
+                             use_learned_guess=1 if learned else 0, precond=precond)
+
     q = torch.empty(nb, dtype=torch.float64, device="cuda")
     dpsi = torch.empty(nbody, dtype=torch.float64, device="cuda")
     S = torch.empty((nbody, 3), dtype=torch.float64, device="cuda")
@@ -149,38 +143,88 @@ def main():
     L = torch.empty((nbody, 3), dtype=torch.float64, device="cuda")
     U = torch.empty(nbody, dtype=torch.float64, device="cuda")
     fi = torch.empty((max(ni, 1), 3), dtype=torch.float64, device="cuda")
+    counter = {"step": 0}
 
-    def step(c):
+    def step(c, dev, record=False, move=bd_mode):
+        tp = [time.perf_counter()]
         c.pe_set_system(off, dev["bead_pos"], dev["bead_sigma"], dev["body_center"], dev["body_quat"],
                         dev["body_charge"], dev["ion_pos"] if ni else None, dev["ion_charge"] if ni else None,
                         dev["ion_sigma"] if ni else None, system.E0)
+        tp.append(time.perf_counter())
         st, info = c.pe_solve_polarization(None, q, dpsi, S)
+        tp.append(time.perf_counter())
+        if record:
+            c.pe_guess_record(q)
         c.pe_forces_torques(F, L, U, fi if ni else None, None)
-        return info
+        tp.append(time.perf_counter())
+        if move:
+            c.pe_bd_step(dt, kT, gamma, seed, counter["step"], dev["bead_pos"], dev["body_center"],
+                         dev["body_quat"], dev["ion_pos"] if ni else None)
+            counter["step"] += 1
+        tp.append(time.perf_counter())
+        return info, np.diff(tp)
 
+    # ---- learned guess: train on solves of the method from untimed steps
+    learned = args.train_systems > 0
+    train_info = None
+    wfile = os.path.join(tempfile.mkdtemp(), "guess.bin")
+    ctx = B.Context(params(B.PE_MIXED))
+    if learned:
+        ctx.pe_guess_init(1)
+        ta = time.perf_counter()
+        for t in range(args.train_systems):
+            ts = inputs.config(k, seed=inputs.SEED_BASE + 1000 + t)
+            ctx.load(ts)
+            ctx.pe_guess_set_types(ts.body_type)
+            st, _ = ctx.pe_solve_polarization(None, q, dpsi, S)
+            ctx.pe_guess_record(q)
+        tb = time.perf_counter()
+        loss0 = ctx.pe_guess_train(1, 4096, 1e-3, 1)
+        loss = ctx.pe_guess_train(args.epochs, 4096, 2e-3, 2)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        ctx.pe_guess_save(wfile)
+        train_info = {"solves": args.train_systems, "rows": args.train_systems * nb, "epochs": args.epochs + 1,
+                      "loss_first_epoch": loss0, "loss_last_epoch": loss, "generate_s": round(tb - ta, 2),
+                      "train_s": round(tc - tb, 2)}
+        log(f"learned guess: {train_info}")
+        ctx.close()
+        ctx = B.Context(params(B.PE_MIXED, learned=True))
+        ctx.pe_guess_load(wfile)
+        ctx.load(system)
+        dev = ctx.sys_dev
+        ctx.pe_set_system(off, dev["bead_pos"], dev["bead_sigma"], dev["body_center"], dev["body_quat"],
+                          dev["body_charge"], dev["ion_pos"] if ni else None, dev["ion_charge"] if ni else None,
+                          dev["ion_sigma"] if ni else None, system.E0)
+        ctx.pe_guess_set_types(system.body_type)
+    else:
+        ctx.load(system)
+        dev = ctx.sys_dev
+    d = ctx.pe_get_derived()
     for _ in range(args.warmup):
-        step(ctx)
+        step(ctx, dev)
     torch.cuda.synchronize()
     ctx.pe_profile_enable(True)
-    infos = []
-    t_steps = []
+    infos, phases = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ts = time.perf_counter()
-        info = step(ctx)
-        t_steps.append(time.perf_counter() - ts)
+        info, ph = step(ctx, dev)
         infos.append(info)
+        phases.append(ph)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = ctx.pe_profile_read()
     ctx.pe_profile_enable(False)
     solve_ms = [1e3 * i.t_total for i in infos]
-    print(f"[bench] timed {args.steps} steps: {elapsed:.3f} s; solve p50 {np.median(solve_ms):.2f} ms, "
-          f"iters {infos[-1].iters}, outer {infos[-1].outer_refinements}, rel {infos[-1].rel_residual:.2e}",
-          file=sys.stderr, flush=True)
+    ph = 1e3 * np.median(np.array(phases), axis=0)
+    log(f"timed {args.steps} steps: {elapsed:.3f} s; solve p50 {np.median(solve_ms):.2f} ms, iters "
+        f"{[i.iters for i in infos]}, guess residual {infos[-1].rel_residual_guess:.3f}")
 
-    # bead-only PME matvec throughput (the Krylov operator), both precisions
+    # bead-only PME matvec throughput (the Krylov operator), both precisions, on the current configuration
+    ctx.pe_set_system(off, dev["bead_pos"], dev["bead_sigma"], dev["body_center"], dev["body_quat"],
+                      dev["body_charge"], dev["ion_pos"] if ni else None, dev["ion_charge"] if ni else None,
+                      dev["ion_sigma"] if ni else None, system.E0)
     x = torch.randn(nb + nbody, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     matvec = {}
@@ -193,55 +237,59 @@ def main():
             ctx.pe_apply_saddle(x, y, prec)
         torch.cuda.synchronize()
         tm = (time.perf_counter() - ta) / args.matvec_reps
-        matvec[name] = {"ms": 1e3 * tm, "mbeads_s": nb / tm / 1e6}
+        matvec[name] = {"ms": round(1e3 * tm, 4), "mbeads_s": round(nb / tm / 1e6, 2)}
 
-    # plain FP64 arm (zero guess)
+    # plain FP64 arm: the method as stated (double, unpreconditioned GMRES, zero guess), same configuration
     fp64 = None
     if not args.no_fp64_arm:
-        c64 = make_ctx(B.PE_FP64)
-        for _ in range(1):
-            step(c64)
-        torch.cuda.synchronize()
-        i64 = []
-        n64 = max(3, min(args.steps, 10))
-        for _ in range(n64):
-            i64.append(step(c64))
-        ms64 = [1e3 * i.t_total for i in i64]
-        fp64 = {"solve_ms_p50": float(np.median(ms64)), "iters": int(i64[-1].iters),
-                "rel_residual": float(i64[-1].rel_residual), "solves": n64}
-        c64.close()
+        arms = {}
+        for name, prec, pre in (("plain_fp64", B.PE_FP64, 0), ("fp64_precond", B.PE_FP64, 1)):
+            p = params(prec, precond=pre)
+            p.max_iters = 4000
+            c64 = B.Context(p)
+            c64.sys_dev = dev
+            ms, its = [], []
+            for _ in range(args.fp64_solves):
+                info, _ = step(c64, dev, move=False)
+                ms.append(1e3 * info.t_total)
+                its.append(info.iters)
+            arms[name] = {"solve_ms_p50": round(float(np.median(ms)), 3), "iters": its,
+                          "rel_residual": float(info.rel_residual)}
+            c64.close()
+        fp64 = arms
 
     # roofline of the dominant kernel (live HIP-event timing of the timed region)
     G = int(np.prod(system.mesh))
     Gc = system.mesh[0] * system.mesh[1] * (system.mesh[2] // 2 + 1)
-    nnz_stored = d["nnz"]
-    classes = B.PROF_CLASSES
     per_class = {}
-    for name in classes:
+    for name in B.PROF_CLASSES:
         for dbl in (False, True):
             cnt, ms = prof[name] if not dbl else prof[name + "_f64"]
             if cnt:
                 per_class[(name, dbl)] = (cnt, ms)
-    dom = max(per_class, key=lambda kk: per_class[kk][1])
-    cnt, ms = per_class[dom]
-    avg_ms = ms / cnt
-    name, dbl = dom
-    # spread/gather launches per matvec cover beads (solve) or beads+ions (RHS / forces):
-    n_launch_particles = nb
-    abytes = algorithmic_bytes(name, dbl, nb, n_launch_particles, G, Gc, nnz_stored)
+    ranked = sorted(per_class, key=lambda kk: -per_class[kk][1])
     roof = None
-    if abytes is not None:
-        achieved = abytes / (avg_ms * 1e-3) / 1e9
-        roof = {"kernel": f"{name}_{'f64' if dbl else 'f32'}", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_us": round(1e3 * avg_ms, 2), "launches": int(cnt), "alg_bytes_per_launch": int(abytes)}
+    for name, dbl in ranked:
+        cnt, ms = per_class[(name, dbl)]
+        model = kernel_model(name, dbl, nb, ni, G, Gc, d["nnz"], system)
+        if model is None:
+            continue
+        avg_s = ms / cnt * 1e-3
+        bound, amount, unit, peak = model
+        achieved = amount / avg_s / (1e9 if unit == "GB/s" else 1e12)
+        roof = {"kernel": f"{name}_{'f64' if dbl else 'f32'}", "bound": bound, "achieved": round(achieved, 2),
+                "peak": peak, "unit": unit, "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_launch_us": round(1e6 * avg_s, 2), "launches": int(cnt),
+                "algorithmic_per_launch": amount, "share_of_kernel_time": round(ms / sum(
+                    v[1] for v in per_class.values()), 3)}
+        break
     breakdown = {f"{n}_{'f64' if db else 'f32'}": {"launches": int(c), "total_ms": round(m, 3),
                                                    "avg_us": round(1e3 * m / c, 2)}
                  for (n, db), (c, m) in sorted(per_class.items(), key=lambda kv: -kv[1][1])}
 
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a bounded sample ...", file=sys.stderr, flush=True)
+        log("timing the CPU oracle on a bounded sample ...")
         cpu = cpu_baseline(system)
 
     ms_per_step = 1e3 * elapsed / args.steps
@@ -259,26 +307,37 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "n_bead": nb, "n_body": nbody, "n_ion": ni,
-                   "mesh": list(system.mesh), "P": 8, "xi": round(d["xi"], 5), "r_cut": round(d["r_cut"], 5),
-                   "eta": round(d["eta"], 5), "bead_pairs_stored": nnz_stored, "rel_tol": 1e-6,
-                   "learned_guess": learned, "parallelism": "single GPU"},
+        "config": {"workload": f"{args.workload}: {desc}" + (", Brownian dynamics dt=1e-4" if bd_mode else ""),
+                   "n_bead": nb, "n_body": nbody, "n_ion": ni, "mesh": list(system.mesh), "P": 8,
+                   "xi": round(d["xi"], 5), "r_cut": round(d["r_cut"], 5), "eta": round(d["eta"], 5),
+                   "bead_pairs_stored": d["nnz"], "rel_tol": 1e-6, "learned_guess": learned,
+                   "precond": "block-Jacobi", "parallelism": "single GPU"},
+        "step_phases_ms_p50": {"set_system": round(ph[0], 3), "solve": round(ph[1], 3), "forces": round(ph[2], 3),
+                               "bd_update": round(ph[3], 3)},
+        "steps_per_s": round(args.steps / elapsed, 3),
         "solve_ms_p50": round(float(np.median(solve_ms)), 3),
         "solve_ms_p99": round(float(np.percentile(solve_ms, 99)), 3),
-        "iters": int(infos[-1].iters),
+        "iters": [int(i.iters) for i in infos],
         "outer_refinements": int(infos[-1].outer_refinements),
         "matvecs_fp32": int(infos[-1].matvecs_fp32),
         "matvecs_fp64": int(infos[-1].matvecs_fp64),
         "rel_residual": float(infos[-1].rel_residual),
+        "rel_residual_guess": float(infos[-1].rel_residual_guess),
+        "learned_guess_training": train_info,
         "matvec": matvec,
-        "fp64_arm": fp64,
-        "speedup_solve_vs_fp64": (round(fp64["solve_ms_p50"] / float(np.median(solve_ms)), 3) if fp64 else None),
+        "fp64_arms": fp64,
+        "speedup_solve_vs_plain_fp64": (round(fp64["plain_fp64"]["solve_ms_p50"] / float(np.median(solve_ms)), 2)
+                                        if fp64 else None),
         "roofline": roof,
         "kernels": breakdown,
         "cpu_baseline": cpu,
     }
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":
