@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "pe_internal.hpp"
+#include "vector.hpp"
 
 namespace pe {
 
@@ -23,6 +24,29 @@ namespace {
 
 constexpr int kWaves = 4;      // particles per 256-thread block
 constexpr int kMaxP = 16;
+
+// Support start m0 (unwrapped; positions are already wrapped into the box, so
+// m0 lies in [1 - P, N)) and its offset delta = m0 - x / h on one axis.  The
+// displacement of support point j is d_j = (j + delta) h.
+__device__ __forceinline__ int support_start(double x, double inv_h, int P, double& delta) {
+  const double u = x * inv_h;
+  const double m0 = (P & 1) ? rint(u) - (double)((P - 1) / 2) : floor(u) - (double)(P / 2 - 1);
+  delta = m0 - u;
+  return (int)m0;
+}
+
+// m in [-N, 2N) -> [0, N)
+__device__ __forceinline__ int wrap_idx(int m, int N) {
+  m = m < 0 ? m + N : m;
+  return m >= N ? m - N : m;
+}
+
+// Window factor w(d_j) = wnorm exp(-wexp d_j^2) of support point j.
+template <typename T>
+__device__ __forceinline__ T window(const GridGeom& g, int ax, int j, double delta) {
+  const double dj = ((double)j + delta) * g.h[ax];
+  return (T)g.wnorm * exp((T)(-g.wexp * dj * dj));
+}
 
 template <typename T>
 __device__ __forceinline__ void window_setup(const double4 p, const GridGeom& g, int lane,
@@ -32,16 +56,11 @@ __device__ __forceinline__ void window_setup(const double4 p, const GridGeom& g,
     const int ax = lane / P;
     const int j = lane - ax * P;
     const double x = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
-    const double u = x * g.inv_h[ax];
-    const long m0 = (P & 1) ? (long)rint(u) - (P - 1) / 2 : (long)floor(u) - P / 2 + 1;
-    const long m = m0 + j;
-    const double d = (double)m * g.h[ax] - x;
-    const int N = g.N[ax];
-    long mw = m % N;
-    if (mw < 0) mw += N;
-    w_s[lane] = (T)g.wnorm * exp((T)(-g.wexp * d * d));
-    i_s[lane] = (int)mw;
-    if (d_s) d_s[lane] = (T)d;
+    double delta;
+    const int m0 = support_start(x, g.inv_h[ax], P, delta);
+    w_s[lane] = window<T>(g, ax, j, delta);
+    i_s[lane] = wrap_idx(m0 + j, g.N[ax]);
+    if (d_s) d_s[lane] = (T)(((double)j + delta) * g.h[ax]);
   }
 }
 
@@ -57,19 +76,8 @@ __device__ __forceinline__ void window_setup(const double4 p, const GridGeom& g,
 constexpr int kTile = 8;
 constexpr int kTile3 = kTile * kTile * kTile;
 
-// Per-axis support start (unwrapped) of coordinate x.
-__device__ __forceinline__ long support_start(double x, double inv_h, int P) {
-  const double u = x * inv_h;
-  return (P & 1) ? (long)rint(u) - (P - 1) / 2 : (long)floor(u) - P / 2 + 1;
-}
-
-__device__ __forceinline__ int wrap_idx(long m, int N) {
-  long w = m % N;
-  return (int)(w < 0 ? w + N : w);
-}
-
 // Distinct tiles (per axis) touched by the support of a particle; returns count (<= 4).
-__device__ __forceinline__ int axis_tiles(long m0, int P, int N, int* t) {
+__device__ __forceinline__ int axis_tiles(int m0, int P, int N, int* t) {
   int n = 0;
   int last = -1;
   for (int j = 0; j < P; ++j) {
@@ -84,15 +92,20 @@ __device__ __forceinline__ int axis_tiles(long m0, int P, int N, int* t) {
   return n;
 }
 
+__device__ __forceinline__ int axis_start(double x, double inv_h, int P) {
+  double delta;
+  return support_start(x, inv_h, P, delta);
+}
+
 __global__ void tile_count_kernel(const double4* __restrict__ pos, int64_t n, GridGeom g,
                                   int* __restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 p = pos[i];
   int tx[4], ty[4], tz[4];
-  const int nx = axis_tiles(support_start(p.x, g.inv_h[0], g.P), g.P, g.N[0], tx);
-  const int ny = axis_tiles(support_start(p.y, g.inv_h[1], g.P), g.P, g.N[1], ty);
-  const int nz = axis_tiles(support_start(p.z, g.inv_h[2], g.P), g.P, g.N[2], tz);
+  const int nx = axis_tiles(axis_start(p.x, g.inv_h[0], g.P), g.P, g.N[0], tx);
+  const int ny = axis_tiles(axis_start(p.y, g.inv_h[1], g.P), g.P, g.N[1], ty);
+  const int nz = axis_tiles(axis_start(p.z, g.inv_h[2], g.P), g.P, g.N[2], tz);
   for (int a = 0; a < nx; ++a)
     for (int b = 0; b < ny; ++b)
       for (int c = 0; c < nz; ++c) atomicAdd(&count[(tx[a] * g.ntile[1] + ty[b]) * g.ntile[2] + tz[c]], 1);
@@ -104,9 +117,9 @@ __global__ void tile_fill_kernel(const double4* __restrict__ pos, int64_t n, Gri
   if (i >= n) return;
   const double4 p = pos[i];
   int tx[4], ty[4], tz[4];
-  const int nx = axis_tiles(support_start(p.x, g.inv_h[0], g.P), g.P, g.N[0], tx);
-  const int ny = axis_tiles(support_start(p.y, g.inv_h[1], g.P), g.P, g.N[1], ty);
-  const int nz = axis_tiles(support_start(p.z, g.inv_h[2], g.P), g.P, g.N[2], tz);
+  const int nx = axis_tiles(axis_start(p.x, g.inv_h[0], g.P), g.P, g.N[0], tx);
+  const int ny = axis_tiles(axis_start(p.y, g.inv_h[1], g.P), g.P, g.N[1], ty);
+  const int nz = axis_tiles(axis_start(p.z, g.inv_h[2], g.P), g.P, g.N[2], tz);
   for (int a = 0; a < nx; ++a)
     for (int b = 0; b < ny; ++b)
       for (int c = 0; c < nz; ++c) {
@@ -116,8 +129,8 @@ __global__ void tile_fill_kernel(const double4* __restrict__ pos, int64_t n, Gri
 }
 
 // One workgroup (four wavefronts) per tile.  The tile's particle list is
-// processed in chunks of kChunk: all threads stage each particle's window
-// factors in tile-local coordinates (f_x[a] q, f_y[b], f_z[c], zero where the
+// processed in chunks of kChunk: one thread per (particle, axis) stages the
+// eight tile-local window factors (f_x[a] q, f_y[b], f_z[c], zero where the
 // support misses the tile) in LDS.  Lane (a, b) of a wavefront owns the
 // z-pencil (a, b, 0..7) of the tile in eight registers and adds
 // q f_x[a] f_y[b] f_z[c] for the particles of its share of the chunk.  The four
@@ -134,8 +147,6 @@ __global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restr
                                                           const int* __restrict__ entries,
                                                           T* __restrict__ grid, GridGeom g, int accumulate) {
   __shared__ T f_s[kChunk][3][kTile];
-  __shared__ double4 p_s[kChunk];
-  __shared__ T q_s[kChunk];
   __shared__ T red[kWaves][kTile3];
   const int tid = blockIdx.x;
   const int uz = tid % g.ntile[2];
@@ -151,28 +162,25 @@ __global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restr
   const int e0 = tile_start[tid], e1 = tile_start[tid + 1];
   for (int c0 = e0; c0 < e1; c0 += kChunk) {
     const int nc = min(kChunk, e1 - c0);
-    if ((int)threadIdx.x < nc) {
-      const int i = entries[c0 + threadIdx.x];
-      p_s[threadIdx.x] = pos[i];
-      q_s[threadIdx.x] = (T)q[idx[i]];
-    }
-    for (int t = threadIdx.x; t < nc * 3 * kTile; t += blockDim.x) (&f_s[0][0][0])[t] = 0;
-    __syncthreads();
-    for (int t = threadIdx.x; t < nc * 3 * P; t += blockDim.x) {
-      const int c = t / (3 * P);
-      const int l = t - c * 3 * P;
-      const int ax = l / P;
-      const int j = l - ax * P;
-      const double4 p = p_s[c];
-      const double x = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
-      const long m = support_start(x, g.inv_h[ax], P) + j;
+    // one thread per (particle, axis): the eight tile-local factors
+    if ((int)threadIdx.x < 3 * nc) {
+      const int c = threadIdx.x / 3;
+      const int ax = threadIdx.x - 3 * c;
+      const int i = entries[c0 + c];
+      const double x = reinterpret_cast<const double*>(pos + i)[ax];
+      double delta;
+      const int m0 = support_start(x, g.inv_h[ax], P, delta);
+      const int N = g.N[ax];
       const int u = ax == 0 ? ux : (ax == 1 ? uy : uz);
-      const int loc = wrap_idx(m, g.N[ax]) - kTile * u;
-      if (loc >= 0 && loc < kTile) {
-        const double d = (double)m * g.h[ax] - x;
-        T w = (T)g.wnorm * exp((T)(-g.wexp * d * d));
-        if (ax == 0) w *= q_s[c];
-        f_s[c][ax][loc] = w;
+      // tile-local position of support point 0, taken in [1 - P, kTile - 1]
+      int s0 = wrap_idx(m0, N) - kTile * u;
+      if (s0 > kTile - 1) s0 -= N;
+      if (s0 < 1 - P) s0 += N;
+      const T scale = ax == 0 ? (T)q[idx[i]] : (T)1;
+#pragma unroll
+      for (int loc = 0; loc < kTile; ++loc) {
+        const int j = loc - s0;
+        f_s[c][ax][loc] = (j >= 0 && j < P) ? window<T>(g, ax, j, delta) * scale : (T)0;
       }
     }
     __syncthreads();
@@ -194,23 +202,6 @@ __global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restr
       const int64_t o = ((int64_t)gx * g.N[1] + gy) * g.N[2] + gz;
       grid[o] = accumulate ? grid[o] + v : v;
     }
-  }
-}
-
-// Sort each tile's list (sorted-particle indices) so the accumulation order
-// is fixed.
-__global__ void sort_tiles_kernel(const int* __restrict__ start, int ntile, int* __restrict__ ent) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntile) return;
-  const int b = start[t], e = start[t + 1];
-  for (int i = b + 1; i < e; ++i) {
-    const int v = ent[i];
-    int j = i - 1;
-    while (j >= b && ent[j] > v) {
-      ent[j + 1] = ent[j];
-      --j;
-    }
-    ent[j + 1] = v;
   }
 }
 
@@ -304,9 +295,8 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
     hipLaunchKernelGGL(tile_fill_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get(),
                        ps.tile_entries.get());
     PE_CHECK_LAUNCH();
-    hipLaunchKernelGGL(sort_tiles_kernel, dim3((unsigned)((nt + 127) / 128)), dim3(128), 0, s, ps.tile_start.get(),
-                       nt, ps.tile_entries.get());
-    PE_CHECK_LAUNCH();
+    // sort each tile's list so the accumulation order is the same on every run
+    launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get());
   }
   PE_HIP(hipStreamSynchronize(s));
 }

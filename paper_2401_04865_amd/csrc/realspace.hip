@@ -23,6 +23,7 @@
 #include <numeric>
 
 #include "pe_internal.hpp"
+#include "vector.hpp"
 
 namespace pe {
 
@@ -124,23 +125,6 @@ __global__ void scatter_cells_kernel(const int* __restrict__ cell_of, int64_t n,
   if (i >= n) return;
   const int slot = atomicAdd(&cursor[cell_of[i]], 1);
   idx[slot] = (int)i;
-}
-
-// Sort each cell's slice by caller index so the order (and every sum over
-// it) is the same on every run.
-__global__ void sort_cells_kernel(const int* __restrict__ start, int ncell, int* __restrict__ idx) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const int b = start[c], e = start[c + 1];
-  for (int i = b + 1; i < e; ++i) {
-    const int v = idx[i];
-    int j = i - 1;
-    while (j >= b && idx[j] > v) {
-      idx[j + 1] = idx[j];
-      --j;
-    }
-    idx[j + 1] = v;
-  }
 }
 
 __global__ void gather_sorted_kernel(const double4* __restrict__ tmp, const int* __restrict__ idx,
@@ -314,9 +298,9 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
     hipLaunchKernelGGL(scatter_cells_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.cell_of.get(), n,
                        ps.cell_count.get(), ps.idx.get());
     PE_CHECK_LAUNCH();
-    hipLaunchKernelGGL(sort_cells_kernel, dim3(nblk(ncell, 128)), dim3(128), 0, s, ps.cell_start.get(),
-                       ncell, ps.idx.get());
-    PE_CHECK_LAUNCH();
+    // sort each cell's slice by caller index so the order (and every sum over
+    // it) is the same on every run
+    launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get());
     hipLaunchKernelGGL(gather_sorted_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.tmp.get(),
                        ps.idx.get(), n, ps.pos.get());
     PE_CHECK_LAUNCH();

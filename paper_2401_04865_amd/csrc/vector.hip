@@ -257,6 +257,57 @@ inline unsigned nred(int64_t n) {
   return (unsigned)b;
 }
 
+
+// Segmented sort: one workgroup per segment.  Segments of up to kSortMax keys
+// are sorted in LDS by a bitonic network in the form where every comparator
+// puts the smaller key at the lower index, so padding with INT_MAX past the
+// end needs no special case.  Longer segments (none at the workloads'
+// densities) fall back to an insertion sort by one thread.
+constexpr int kSortMax = 4096;
+
+__global__ void __launch_bounds__(256) segment_sort_kernel(const int* __restrict__ start, int* __restrict__ keys) {
+  __shared__ int key[kSortMax];
+  const int b = start[blockIdx.x], e = start[blockIdx.x + 1];
+  const int n = e - b;
+  if (n <= 1) return;
+  if (n > kSortMax) {
+    if (threadIdx.x == 0) {
+      for (int i = b + 1; i < e; ++i) {
+        const int v = keys[i];
+        int j = i - 1;
+        while (j >= b && keys[j] > v) {
+          keys[j + 1] = keys[j];
+          --j;
+        }
+        keys[j + 1] = v;
+      }
+    }
+    return;
+  }
+  int m = 1;
+  while (m < n) m <<= 1;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) key[i] = i < n ? keys[b + i] : 0x7fffffff;
+  __syncthreads();
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      // first stage of each merge compares mirrored pairs, later stages halves
+      const int mask = (j == (k >> 1)) ? k - 1 : j;
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        if ((i & j) == 0) {
+          const int p = i ^ mask;
+          const int a = key[i], c = key[p];
+          if (a > c) {
+            key[i] = c;
+            key[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) keys[b + i] = key[i];
+}
+
 }  // namespace
 
 void launch_moments(hipStream_t s, const double* q, const double* sig, double sig_const, int64_t n,
@@ -332,6 +383,12 @@ void launch_init_g(hipStream_t s, double* st, int m, const double* beta) {
 
 void launch_backsolve(hipStream_t s, const double* st, int m, int k, double* y) {
   hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, s, st, m, k, y);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_segment_sort(hipStream_t s, const int* start, int nseg, int* keys) {
+  if (nseg <= 0) return;
+  hipLaunchKernelGGL(segment_sort_kernel, dim3((unsigned)nseg), dim3(256), 0, s, start, keys);
   PE_CHECK_LAUNCH();
 }
 

@@ -32,6 +32,9 @@ void launch_givens(hipStream_t s, const double* h1, const double* h2, const doub
 void launch_init_g(hipStream_t s, double* st, int m, const double* beta);
 void launch_backsolve(hipStream_t s, const double* st, int m, int k, double* y);
 
+// Sort every segment [start[k], start[k+1]) of keys ascending, in place.
+void launch_segment_sort(hipStream_t s, const int* start, int nseg, int* keys);
+
 // per-particle kernels of the solve / force passes (solver unit)
 void launch_rhs_top(hipStream_t s, int64_t n, const double* rel, const double* E0, const double* phi_ion,
                     double* b);
