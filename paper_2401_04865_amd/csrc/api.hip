@@ -217,12 +217,8 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
     if (ni) launch_gather<T>(s, c->I, gB, c->gg, phi + nb, E ? E + 3 * nb : nullptr, true);
   }
   ProfScope ps_pair(c->prof, s, PE_PROF_PAIR, sizeof(T) == 8);
-  launch_pair_onfly<T>(s, c->B, c->B, qb, c->rg, phi, E);
-  if (ni) {
-    launch_pair_onfly<T>(s, c->B, c->I, qi, c->rg, phi, E);
-    launch_pair_onfly<T>(s, c->I, c->B, qb, c->rg, phi + nb, E ? E + 3 * nb : nullptr);
-    launch_pair_onfly<T>(s, c->I, c->I, qi, c->rg, phi + nb, E ? E + 3 * nb : nullptr);
-  }
+  launch_pair_onfly<T>(s, c->B, &c->B, qb, &c->I, qi, c->rg, phi, E);
+  launch_pair_onfly<T>(s, c->I, &c->B, qb, &c->I, qi, c->rg, phi + nb, E ? E + 3 * nb : nullptr);
   // k = 0 constant, then forces and energies
   if (nb)
     hipLaunchKernelGGL(finish_particles_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, chg_all,
@@ -255,7 +251,8 @@ void build_rhs(pe_context* c, double* b) {
       E = c->E_ion.get();
     }
     launch_gather<double>(s, c->B, gB, c->gg, phi_ion, E, false);
-    launch_pair_onfly<double>(s, c->B, c->I, c->ion_q.get(), c->rg, phi_ion, E);
+    // the field only feeds the guess features: single precision
+    launch_pair_onfly<double>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, phi_ion, E, true);
   }
   c->have_eion = c->guess != nullptr;
   if (nb)

@@ -101,11 +101,14 @@ struct RealGeom {
 struct ParticleSet {
   int64_t n = 0;
   DevBuf<double4> pos;      // sorted: wrapped x,y,z and sigma in w
+  DevBuf<float4> posf;      // sorted: x,y,z relative to the cell origin, sigma (single precision)
   DevBuf<int> idx;          // sorted slot -> caller index within the set
   DevBuf<int> cell_start;   // ncell + 1
   DevBuf<int> cell_count;   // ncell (scratch)
   DevBuf<int> cell_of;      // caller order (scratch)
   DevBuf<double4> tmp;      // caller order wrapped positions (scratch)
+  DevBuf<int2> chunks;      // pair-traversal work units: (first sorted slot, cell), <= 64 each
+  int n_chunks = 0;
   // grid tiles overlapped by each particle's support (spreading lists)
   DevBuf<int> tile_start;   // ntile + 1
   DevBuf<int> tile_count;   // ntile (scratch)
@@ -315,9 +318,12 @@ void build_bead_matrix(pe_context* c);
 template <typename T>
 void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const double* dpsi,
                           const double* phi_wave, const double* ck0, double* y_top);
+// Adds the real-space potential (and field, if E) at the targets from up to
+// two source sets; field_single evaluates the field in single precision.
 template <typename T>
-void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet& src,
-                       const double* q_src, const RealGeom& rg, double* phi, double* E);
+void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet* src0, const double* q0,
+                       const ParticleSet* src1, const double* q1, const RealGeom& rg, double* phi, double* E,
+                       bool field_single = false);
 
 // body / vector kernels
 void launch_body_sums(hipStream_t s, pe_context* c, const double* q, double* out_sum, double* out_sig2);

@@ -101,7 +101,10 @@ __global__ void assemble_inverse_kernel(const double* __restrict__ Minv, const d
 
 // z = A^{-1} x for every body of one type: Y (Np x nb) = Ainv (Np x Np) X (Np x nb),
 // column b of X is [x[off(b) .. off(b)+N); x[n_bead + body(b)]].
-constexpr int kBM = 64, kBN = 64, kBK = 16;
+// 32 x 32 output tiles (a few hundred workgroups even for one shape of a few
+// hundred beads), K staged through LDS 32 at a time; thread (tx, ty) of the
+// 16 x 16 block owns rows {ty, ty + 16} and columns {tx, tx + 16} of the tile.
+constexpr int kBM = 32, kBN = 32, kBK = 32;
 
 template <typename T>
 __global__ void __launch_bounds__(256) apply_type_kernel(const T* __restrict__ Ainv, int N,
@@ -115,7 +118,7 @@ __global__ void __launch_bounds__(256) apply_type_kernel(const T* __restrict__ A
   __shared__ int64_t bpsi[kBN];
   const int row0 = blockIdx.x * kBM;
   const int col0 = blockIdx.y * kBN;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;  // 16 x 16 threads, 4 x 4 outputs each
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   if (threadIdx.x < kBN) {
     const int b = col0 + threadIdx.x;
     if (b < nbt) {
@@ -128,11 +131,7 @@ __global__ void __launch_bounds__(256) apply_type_kernel(const T* __restrict__ A
     }
   }
   __syncthreads();
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+  T acc[2][2] = {{0, 0}, {0, 0}};
   for (int k0 = 0; k0 < Np; k0 += kBK) {
     for (int t = threadIdx.x; t < kBK * kBM; t += blockDim.x) {
       const int kk = t % kBK, r = t / kBK;
@@ -147,28 +146,24 @@ __global__ void __launch_bounds__(256) apply_type_kernel(const T* __restrict__ A
       Xs[kk][cc] = v;
     }
     __syncthreads();
-#pragma unroll
+#pragma unroll 8
     for (int kk = 0; kk < kBK; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[kk][ty * 4 + q];
-        b[q] = Xs[kk][tx * 4 + q];
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+      const T a0 = As[kk][ty], a1 = As[kk][ty + 16];
+      const T b0 = Xs[kk][tx], b1 = Xs[kk][tx + 16];
+      acc[0][0] += a0 * b0;
+      acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0;
+      acc[1][1] += a1 * b1;
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int gr = row0 + ty * 4 + p;
+  for (int p = 0; p < 2; ++p) {
+    const int gr = row0 + ty + 16 * p;
     if (gr >= Np) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int cc = tx * 4 + q;
+    for (int q = 0; q < 2; ++q) {
+      const int cc = tx + 16 * q;
       if (boff[cc] < 0) continue;
       const int64_t o = gr < N ? boff[cc] + gr : bpsi[cc];
       z[o] = (double)acc[p][q];

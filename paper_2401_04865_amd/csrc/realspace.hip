@@ -12,7 +12,20 @@
 //            (4a - r)/(16 pi eps a^2) (r < 2a);  R(0) = 1/(4 pi eps a) - xi/(2 pi^1.5 eps)
 // The difference of error functions is formed as erf - erf where both are
 // small and as erfc - erfc where both are close to one, so neither loses
-// digits to cancellation.
+// digits to cancellation; erfc(b r) is dropped once b r is so large that it
+// is below the rounding of the other term.
+//
+// Pair traversal (one kernel for every pass): a wavefront takes up to 64
+// targets of one cell, one per lane, so every lane scans the same candidate
+// sources.  The wavefront loads 64 candidates at a time (one per lane) and
+// broadcasts them lane by lane; each lane tests the distance in single
+// precision against a slightly enlarged cutoff and, on a hit, appends the
+// source to its own queue in LDS.  Whenever every lane has work queued (or
+// a queue runs close to full) the wavefront pops one entry per lane and
+// evaluates the pair kernel with all lanes busy, redoing the distance in
+// double with the exact cutoff.  So the expensive error-function evaluations
+// run at full width instead of once per candidate for any hit in the
+// wavefront, and each lane still sums its own pairs in a fixed order.
 //
 // Positions are fixed during a solve, so the bead-bead block is evaluated once
 // per configuration and stored as a CSR matrix (rows in cell order, entries
@@ -29,6 +42,7 @@ namespace pe {
 
 namespace {
 
+constexpr int kWaves = 4;  // wavefronts per 256-thread block
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kInv4Pi = 0.07957747154594766788;
 constexpr double kTwoOverSqrtPi = 1.12837916709551257390;
@@ -42,11 +56,17 @@ __device__ __forceinline__ double min_img(double d, double L, double invL) {
   return d - L * rint(d * invL);
 }
 
+// b r beyond which erfc(b r) is dropped: erfc(6.5) = 3.8e-20, erfc(5) = 1.5e-12.
+template <typename T>
+__device__ __forceinline__ T erfc_drop() { return sizeof(T) == 8 ? (T)6.5 : (T)5.0; }
+
 template <typename T>
 __device__ __forceinline__ T erf_diff(T b, T xi, T r) {
   // erf(b r) - erf(xi r)
-  if (b * r < (T)1.0) return erf(b * r) - erf(xi * r);
-  return erfc(xi * r) - erfc(b * r);
+  const T br = b * r;
+  if (br < (T)1.0) return erf(br) - erf(xi * r);
+  if (br > erfc_drop<T>()) return erfc(xi * r);
+  return erfc(xi * r) - erfc(br);
 }
 
 // R(r) and dR/dr for one pair (r > 0).
@@ -61,7 +81,8 @@ __device__ __forceinline__ void pair_kernel(T r, T s2, const RealGeom& g, T& R, 
     R = c * D * inv_r;
     if (want_d) {
       // d/dr [D/r] = (D' r - D)/r^2, D' = (2/sqrt pi)(b e^{-b^2 r^2} - xi e^{-xi^2 r^2})
-      const T Dp = (T)kTwoOverSqrtPi * (b * exp(-b * b * r * r) - xi * exp(-xi * xi * r * r));
+      const T eb = b * r > erfc_drop<T>() ? (T)0 : b * exp(-b * b * r * r);
+      const T Dp = (T)kTwoOverSqrtPi * (eb - xi * exp(-xi * xi * r * r));
       dR = c * (Dp * r - D) * inv_r * inv_r;
     }
   } else {
@@ -128,78 +149,252 @@ __global__ void scatter_cells_kernel(const int* __restrict__ cell_of, int64_t n,
 }
 
 __global__ void gather_sorted_kernel(const double4* __restrict__ tmp, const int* __restrict__ idx,
-                                     int64_t n, double4* __restrict__ pos) {
+                                     int64_t n, RealGeom g, double4* __restrict__ pos,
+                                     float4* __restrict__ posf) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  pos[i] = tmp[idx[i]];
+  const double4 p = tmp[idx[i]];
+  pos[i] = p;
+  // single-precision copy relative to the origin of the particle's cell
+  const double ax = g.L[0] / g.nc[0], ay = g.L[1] / g.nc[1], az = g.L[2] / g.nc[2];
+  const int cx = cell_coord(p.x, g.cell_inv[0], g.nc[0]);
+  const int cy = cell_coord(p.y, g.cell_inv[1], g.nc[1]);
+  const int cz = cell_coord(p.z, g.cell_inv[2], g.nc[2]);
+  posf[i] = make_float4((float)(p.x - cx * ax), (float)(p.y - cy * ay), (float)(p.z - cz * az), (float)p.w);
 }
 
 // ------------------------------------------------------------ pair traversal
 
-// Visit every source within r_c of target point p: f(slot, dx, dy, dz, r2, src_sigma).
-template <typename F>
-__device__ __forceinline__ void for_neighbours(const double4 p, const double4* __restrict__ spos,
-                                               const int* __restrict__ start, const RealGeom& g, F&& f) {
-  const int cx = cell_coord(p.x, g.cell_inv[0], g.nc[0]);
-  const int cy = cell_coord(p.y, g.cell_inv[1], g.nc[1]);
-  const int cz = cell_coord(p.z, g.cell_inv[2], g.nc[2]);
-  const int rx = g.nc[0] >= 3 ? 1 : 0, ry = g.nc[1] >= 3 ? 1 : 0, rz = g.nc[2] >= 3 ? 1 : 0;
-  for (int ox = -rx; ox <= rx; ++ox) {
-    int x = cx + ox;
-    x += (x < 0) ? g.nc[0] : (x >= g.nc[0] ? -g.nc[0] : 0);
-    for (int oy = -ry; oy <= ry; ++oy) {
-      int y = cy + oy;
-      y += (y < 0) ? g.nc[1] : (y >= g.nc[1] ? -g.nc[1] : 0);
-      for (int oz = -rz; oz <= rz; ++oz) {
-        int z = cz + oz;
-        z += (z < 0) ? g.nc[2] : (z >= g.nc[2] ? -g.nc[2] : 0);
-        const int c = (x * g.nc[1] + y) * g.nc[2] + z;
-        const int e = start[c + 1];
-        for (int s = start[c]; s < e; ++s) {
-          const double4 q = spos[s];
-          const double dx = min_img(p.x - q.x, g.L[0], g.inv_L[0]);
-          const double dy = min_img(p.y - q.y, g.L[1], g.inv_L[1]);
-          const double dz = min_img(p.z - q.z, g.L[2], g.inv_L[2]);
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < g.rc2) f(s, dx, dy, dz, r2, q.w);
-        }
+// One source set of a traversal.
+struct SrcSet {
+  const double4* pos;   // sorted by cell: wrapped x, y, z, sigma
+  const float4* posf;   // the same in single precision, relative to the cell origin
+  const int* idx;       // sorted slot -> caller index
+  const int* start;     // cell_start
+  const double* q;      // charges in caller order (potential passes)
+};
+
+// Outputs of a traversal; which ones are used depends on the mode.
+struct PairOut {
+  double* phi;          // potential, caller order of the targets (added to)
+  double* E;            // field (3 per target) or null
+  int* cnt;             // per sorted target: pairs within r_c (count mode)
+  const int64_t* row_ptr;
+  int* col;             // CSR of the bead block (fill mode)
+  double* v64;
+  float* v32;
+};
+
+enum { MODE_COUNT = 0, MODE_FILL = 1, MODE_POT = 2, MODE_FIELD = 3 };
+
+constexpr int kQ = 32;          // queue entries per lane
+constexpr int kQFlush = 16;     // candidates between flushes (kQ - kQFlush entries stay free)
+constexpr int kSetBit = 30;     // queue entry: sorted source index | set << kSetBit
+
+__device__ __forceinline__ float bcast(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+template <int MODE, typename T, typename TF>
+__global__ void __launch_bounds__(256) pair_queue_kernel(
+    const double4* __restrict__ tpos, const int* __restrict__ tidx, const int* __restrict__ tstart,
+    const int2* __restrict__ chunks, int nchunk, SrcSet s0, SrcSet s1, int nsrc, RealGeom g, float rc2f,
+    PairOut out) {
+  __shared__ int qbuf[kWaves][kQ][64];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = blockIdx.x * kWaves + wv;
+  if (w >= nchunk) return;  // whole wavefront; the kernel has no block barrier
+  const int2 ch = chunks[w];
+  const int begin = __builtin_amdgcn_readfirstlane(ch.x);
+  const int cell = __builtin_amdgcn_readfirstlane(ch.y);
+  const int end = min(begin + 64, tstart[cell + 1]);
+  const int t = begin + lane;
+  const bool active = t < end;
+  const double4 p = tpos[active ? t : begin];
+  const int nc0 = g.nc[0], nc1 = g.nc[1], nc2 = g.nc[2];
+  const int cz = cell % nc2, cy = (cell / nc2) % nc1, cx = cell / (nc1 * nc2);
+  const bool per_pair_image = nc0 < 3 || nc1 < 3 || nc2 < 3;
+  const int rx = nc0 >= 3 ? 1 : 0, ry = nc1 >= 3 ? 1 : 0, rz = nc2 >= 3 ? 1 : 0;
+  const float Lf0 = (float)g.L[0], Lf1 = (float)g.L[1], Lf2 = (float)g.L[2];
+  const double a0 = g.L[0] / nc0, a1 = g.L[1] / nc1, a2 = g.L[2] / nc2;
+  int (*qb)[64] = qbuf[wv];
+  int pushed = 0, popped = 0;
+
+  // per-target results
+  T acc = 0;
+  TF ex = 0, ey = 0, ez = 0;
+  int cnt = 0;
+  int64_t o = 0, o_end = 0;
+  if (MODE == MODE_FILL && active) {
+    o = out.row_ptr[t];
+    o_end = out.row_ptr[t + 1];
+  }
+
+  auto evaluate = [&](int e) {
+    const int set = e >> kSetBit;
+    const int sidx = e & ((1 << kSetBit) - 1);
+    const double4 qp = set ? s1.pos[sidx] : s0.pos[sidx];
+    double dx = p.x - qp.x, dy = p.y - qp.y, dz = p.z - qp.z;
+    dx -= g.L[0] * rint(dx * g.inv_L[0]);
+    dy -= g.L[1] * rint(dy * g.inv_L[1]);
+    dz -= g.L[2] * rint(dz * g.inv_L[2]);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < g.rc2)) return;
+    if constexpr (MODE == MODE_COUNT) {
+      ++cnt;
+      return;
+    }
+    const double s2 = p.w * p.w + qp.w * qp.w;
+    if constexpr (MODE == MODE_FILL) {
+      double R;
+      if (r2 == 0.0) {
+        R = self_value<double>(s2, g);
+      } else {
+        double dR;
+        pair_kernel<double>(sqrt(r2), s2, g, R, dR, false);
+      }
+      // the row was sized by the count pass; never write past it
+      if (o < o_end) {
+        out.col[o] = s0.idx[sidx];
+        out.v64[o] = R;
+        if (out.v32) out.v32[o] = (float)R;
+        ++o;
+      }
+      return;
+    }
+    const int ci = set ? s1.idx[sidx] : s0.idx[sidx];
+    const double qd = set ? s1.q[ci] : s0.q[ci];
+    if (r2 == 0.0) {
+      acc += self_value<T>((T)s2, g) * (T)qd;
+      return;
+    }
+    T R, dR = 0;
+    const T r = (T)sqrt(r2);
+    constexpr bool same = sizeof(T) == sizeof(TF);
+    pair_kernel<T>(r, (T)s2, g, R, dR, MODE == MODE_FIELD && same);
+    acc += R * (T)qd;
+    if constexpr (MODE == MODE_FIELD) {
+      TF dRf;
+      if constexpr (same) {
+        dRf = (TF)dR;
+      } else {
+        TF Rf;
+        pair_kernel<TF>((TF)r, (TF)s2, g, Rf, dRf, true);
+      }
+      const TF f = -dRf / (TF)r * (TF)qd;  // E = -grad_t R q = -R'(r) d/r q
+      ex += f * (TF)dx;
+      ey += f * (TF)dy;
+      ez += f * (TF)dz;
+    }
+  };
+
+  // The candidate stream: for each source set, the stencil cells in order,
+  // each read in batches of up to 64 (one per lane), tested in groups of
+  // kQFlush.  After every group the queues are drained: as many rounds as
+  // keep every lane busy, and at least enough that kQFlush more pushes cannot
+  // overflow any queue; after the last group, everything left.  (One drain
+  // site, so the pair evaluation is emitted once.)
+  const int sx = 2 * rx + 1, sy = 2 * ry + 1, sz = 2 * rz + 1;
+  const int n_open = nsrc * sx * sy * sz;
+  int it = 0;                  // next stencil cell to open
+  int base = 0, ce = 0;        // unread range of the open cell
+  int bbase = 0, nbat = 0, k0 = 0;
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  float px = 0.f, py = 0.f, pz = 0.f;
+  int tag = 0;
+  const float* Sf = nullptr;
+  for (;;) {
+    bool finished = false;
+    if (k0 >= nbat) {
+      while (base >= ce && it < n_open) {
+        const int set = it / (sx * sy * sz);
+        const int rem = it - set * (sx * sy * sz);
+        const int ox = rem / (sy * sz) - rx, oy = (rem / sz) % sy - ry, oz = rem % sz - rz;
+        ++it;
+        const SrcSet& S = set ? s1 : s0;
+        int x = cx + ox, y = cy + oy, z = cz + oz;
+        double shx = 0, shy = 0, shz = 0;
+        if (x < 0) { x += nc0; shx = -g.L[0]; }
+        if (x >= nc0) { x -= nc0; shx = g.L[0]; }
+        if (y < 0) { y += nc1; shy = -g.L[1]; }
+        if (y >= nc1) { y -= nc1; shy = g.L[1]; }
+        if (z < 0) { z += nc2; shz = -g.L[2]; }
+        if (z >= nc2) { z -= nc2; shz = g.L[2]; }
+        const int c = (x * nc1 + y) * nc2 + z;
+        base = __builtin_amdgcn_readfirstlane(S.start[c]);
+        ce = __builtin_amdgcn_readfirstlane(S.start[c + 1]);
+        // target relative to the origin of the source cell's image
+        px = (float)(p.x - shx - x * a0);
+        py = (float)(p.y - shy - y * a1);
+        pz = (float)(p.z - shz - z * a2);
+        tag = set << kSetBit;
+        Sf = reinterpret_cast<const float*>(S.posf);
+      }
+      if (base < ce) {
+        nbat = min(64, ce - base);
+        bbase = base;
+        base += nbat;
+        k0 = 0;
+        v = lane < nbat ? reinterpret_cast<const float4*>(Sf)[bbase + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        finished = true;
       }
     }
-  }
-}
-
-// Count bead neighbours (incl. the bead itself) of every sorted bead.
-__global__ void count_pairs_kernel(const double4* __restrict__ pos, const int* __restrict__ start,
-                                   int64_t n, RealGeom g, int* __restrict__ cnt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int k = 0;
-  for_neighbours(pos[i], pos, start, g, [&](int, double, double, double, double, double) { ++k; });
-  cnt[i] = k;
-}
-
-__global__ void fill_pairs_kernel(const double4* __restrict__ pos, const int* __restrict__ idx,
-                                  const int* __restrict__ start, int64_t n, RealGeom g,
-                                  const int64_t* __restrict__ row_ptr, int* __restrict__ col,
-                                  double* __restrict__ v64, float* __restrict__ v32) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double4 p = pos[i];
-  int64_t o = row_ptr[i];
-  for_neighbours(p, pos, start, g, [&](int s, double, double, double, double r2, double sw) {
-    const double s2 = p.w * p.w + sw * sw;
-    double R;
-    if (r2 == 0.0) {
-      R = self_value<double>(s2, g);
-    } else {
-      double dR;
-      pair_kernel<double>(sqrt(r2), s2, g, R, dR, false);
+    if (!finished) {
+      const int kend = min(k0 + kQFlush, nbat);
+      for (int k = k0; k < kend; ++k) {
+        float dx = px - bcast(v.x, k);
+        float dy = py - bcast(v.y, k);
+        float dz = pz - bcast(v.z, k);
+        if (per_pair_image) {
+          dx -= Lf0 * rintf(dx / Lf0);
+          dy -= Lf1 * rintf(dy / Lf1);
+          dz -= Lf2 * rintf(dz / Lf2);
+        }
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        // the slot at pushed is free (at most kQ - 1 entries pending)
+        qb[pushed & (kQ - 1)][lane] = (bbase + k) | tag;
+        pushed += (active && r2 < rc2f) ? 1 : 0;
+      }
+      k0 = kend;
     }
-    col[o] = idx[s];
-    v64[o] = R;
-    if (v32) v32[o] = (float)R;
-    ++o;
-  });
+    const int pend = pushed - popped;
+    int mn = active ? pend : 1 << 30, mx = pend;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      mn = min(mn, __shfl_xor(mn, off, 64));
+      mx = max(mx, __shfl_xor(mx, off, 64));
+    }
+    const int rounds = finished ? mx : max(mn, mx - (kQ - kQFlush));
+    for (int r = 0; r < rounds; ++r) {
+      if (popped < pushed) {
+        const int e = qb[popped & (kQ - 1)][lane];
+        ++popped;
+        evaluate(e);
+      }
+    }
+    if (finished) break;
+  }
+  if (!active) return;
+  if (MODE == MODE_COUNT) {
+    out.cnt[t] = cnt;
+  } else if (MODE == MODE_FILL) {
+    // a pair counted but not found again (rounding at the cutoff) adds nothing
+    for (; o < o_end; ++o) {
+      out.col[o] = tidx[t];
+      out.v64[o] = 0.0;
+      if (out.v32) out.v32[o] = 0.0f;
+    }
+  } else if (MODE == MODE_POT || MODE == MODE_FIELD) {
+    const int oi = tidx[t];
+    out.phi[oi] += (double)acc;
+    if (MODE == MODE_FIELD) {
+      out.E[3 * oi] += (double)ex;
+      out.E[3 * oi + 1] += (double)ey;
+      out.E[3 * oi + 2] += (double)ez;
+    }
+  }
 }
 
 // y_top[b] = -(phi_wave[b] + sum_j R_bj q_j - ck0_b) + dpsi[body(b)] for every bead b.
@@ -229,53 +424,27 @@ __global__ void __launch_bounds__(256) spmv_assemble_kernel(
   }
 }
 
-// On-the-fly potential (and field) at targets from sources; adds into
-// phi[idx_t] and E[3 idx_t + d].
-template <typename T, bool FIELD>
-__global__ void __launch_bounds__(256) pair_onfly_kernel(
-    const double4* __restrict__ tpos, const int* __restrict__ tidx, int64_t nt,
-    const double4* __restrict__ spos, const int* __restrict__ sidx, const int* __restrict__ sstart,
-    const double* __restrict__ q, RealGeom g, double* __restrict__ phi, double* __restrict__ E) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nt) return;
-  const double4 p = tpos[i];
-  T acc = 0, ex = 0, ey = 0, ez = 0;
-  for_neighbours(p, spos, sstart, g, [&](int s, double dx, double dy, double dz, double r2, double sw) {
-    const T qs = (T)q[sidx[s]];
-    const T s2 = (T)(p.w * p.w + sw * sw);
-    if (r2 == 0.0) {
-      acc += self_value<T>(s2, g) * qs;
-      return;
-    }
-    T R, dR = 0;
-    const T r = (T)sqrt(r2);
-    pair_kernel<T>(r, s2, g, R, dR, FIELD);
-    acc += R * qs;
-    if (FIELD) {
-      const T f = -dR / r * qs;  // E = -grad_t R q = -R'(r) d/r q
-      ex += f * (T)dx;
-      ey += f * (T)dy;
-      ez += f * (T)dz;
-    }
-  });
-  const int o = tidx[i];
-  phi[o] += (double)acc;
-  if (FIELD) {
-    E[3 * o] += (double)ex;
-    E[3 * o + 1] += (double)ey;
-    E[3 * o + 2] += (double)ez;
-  }
-}
-
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
+
+// Cutoff of the single-precision candidate test: r_c enlarged by more than
+// the rounding of the cell-relative float coordinates (|x| <= 2 cell edges),
+// so no pair inside r_c is missed; the exact test is redone in double.
+float candidate_rc2(const RealGeom& g) {
+  double amax = 0;
+  for (int d = 0; d < 3; ++d) amax = std::max(amax, g.L[d] / g.nc[d]);
+  const double rc = std::sqrt(g.rc2);
+  const double rcf = rc * (1.0 + 1e-5) + 16.0 * amax * std::ldexp(1.0, -24);
+  return (float)(rcf * rcf);
+}
 
 void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
                  double sig_const, int64_t n, const RealGeom& rg) {
   ps.n = n;
   const int ncell = rg.nc[0] * rg.nc[1] * rg.nc[2];
   ps.pos.ensure(n);
+  ps.posf.ensure(n);
   ps.idx.ensure(n);
   ps.tmp.ensure(n);
   ps.cell_of.ensure(n);
@@ -291,6 +460,14 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   PE_HIP(hipMemcpyAsync(cnt.data(), ps.cell_count.get(), sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
   for (int c = 0; c < ncell; ++c) start[c + 1] = start[c] + cnt[c];
+  // traversal work units: runs of at most 64 particles of one cell
+  std::vector<int2> chunks;
+  for (int c = 0; c < ncell; ++c)
+    for (int b = start[c]; b < start[c + 1]; b += 64) chunks.push_back(make_int2(b, c));
+  ps.n_chunks = (int)chunks.size();
+  ps.chunks.ensure(std::max<int64_t>(ps.n_chunks, 1));
+  if (ps.n_chunks)
+    PE_HIP(hipMemcpyAsync(ps.chunks.get(), chunks.data(), sizeof(int2) * ps.n_chunks, hipMemcpyHostToDevice, s));
   PE_HIP(hipMemcpyAsync(ps.cell_start.get(), start.data(), sizeof(int) * (ncell + 1), hipMemcpyHostToDevice, s));
   // cursor = start (reuse cell_count)
   PE_HIP(hipMemcpyAsync(ps.cell_count.get(), start.data(), sizeof(int) * ncell, hipMemcpyHostToDevice, s));
@@ -302,23 +479,41 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
     // it) is the same on every run
     launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get());
     hipLaunchKernelGGL(gather_sorted_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.tmp.get(),
-                       ps.idx.get(), n, ps.pos.get());
+                       ps.idx.get(), n, rg, ps.pos.get(), ps.posf.get());
     PE_CHECK_LAUNCH();
   }
   // the host vectors go out of scope after the copies above complete
   PE_HIP(hipStreamSynchronize(s));
 }
 
+namespace {
+
+SrcSet src_of(const ParticleSet& ps, const double* q) {
+  return SrcSet{ps.pos.get(), ps.posf.get(), ps.idx.get(), ps.cell_start.get(), q};
+}
+
+template <int MODE, typename T, typename TF>
+void launch_queue(hipStream_t s, const ParticleSet& tgt, const SrcSet& s0, const SrcSet& s1, int nsrc,
+                  const RealGeom& rg, const PairOut& out) {
+  if (tgt.n_chunks == 0) return;
+  hipLaunchKernelGGL((pair_queue_kernel<MODE, T, TF>), dim3(nblk(tgt.n_chunks, kWaves)), dim3(64 * kWaves), 0, s,
+                     tgt.pos.get(), tgt.idx.get(), tgt.cell_start.get(), tgt.chunks.get(), tgt.n_chunks, s0, s1,
+                     nsrc, rg, candidate_rc2(rg), out);
+  PE_CHECK_LAUNCH();
+}
+
+}  // namespace
+
 void build_bead_matrix(pe_context* c) {
   hipStream_t s = c->stream;
   const int64_t n = c->n_bead;
   ParticleSet& B = c->B;
+  require(n < (int64_t(1) << kSetBit), "too many particles in one set for the pair traversal");
   c->cnt.ensure(n);
-  if (n > 0) {
-    hipLaunchKernelGGL(count_pairs_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, B.pos.get(),
-                       B.cell_start.get(), n, c->rg, c->cnt.get());
-    PE_CHECK_LAUNCH();
-  }
+  const SrcSet sb = src_of(B, nullptr);
+  PairOut out{};
+  out.cnt = c->cnt.get();
+  if (n > 0) launch_queue<MODE_COUNT, double, double>(s, B, sb, sb, 1, c->rg, out);
   std::vector<int> cnt(n);
   if (n > 0) PE_HIP(hipMemcpyAsync(cnt.data(), c->cnt.get(), sizeof(int) * n, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
@@ -331,12 +526,11 @@ void build_bead_matrix(pe_context* c) {
   c->have_val32 = c->p.precision == PE_MIXED;
   if (c->have_val32) c->val32.ensure(c->nnz);
   PE_HIP(hipMemcpyAsync(c->row_ptr.get(), rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
-  if (n > 0) {
-    hipLaunchKernelGGL(fill_pairs_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, B.pos.get(), B.idx.get(),
-                       B.cell_start.get(), n, c->rg, c->row_ptr.get(), c->col.get(), c->val64.get(),
-                       c->have_val32 ? c->val32.get() : (float*)nullptr);
-    PE_CHECK_LAUNCH();
-  }
+  out.row_ptr = c->row_ptr.get();
+  out.col = c->col.get();
+  out.v64 = c->val64.get();
+  out.v32 = c->have_val32 ? c->val32.get() : nullptr;
+  if (n > 0) launch_queue<MODE_FILL, double, double>(s, B, sb, sb, 1, c->rg, out);
   PE_HIP(hipStreamSynchronize(s));
 }
 
@@ -358,23 +552,38 @@ void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const d
 }
 
 template <typename T>
-void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet& src, const double* q_src,
-                       const RealGeom& rg, double* phi, double* E) {
-  if (tgt.n == 0 || src.n == 0) return;
-  if (E)
-    hipLaunchKernelGGL((pair_onfly_kernel<T, true>), dim3(nblk(tgt.n, 256)), dim3(256), 0, s,
-                       tgt.pos.get(), tgt.idx.get(), tgt.n, src.pos.get(), src.idx.get(),
-                       src.cell_start.get(), q_src, rg, phi, E);
+void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet* src0, const double* q0,
+                       const ParticleSet* src1, const double* q1, const RealGeom& rg, double* phi, double* E,
+                       bool field_single) {
+  if (tgt.n == 0) return;
+  if (src1 && src1->n == 0) src1 = nullptr;
+  if (src0 && src0->n == 0) {
+    src0 = src1;
+    q0 = q1;
+    src1 = nullptr;
+  }
+  if (!src0) return;
+  require(src0->n < (int64_t(1) << kSetBit) && (!src1 || src1->n < (int64_t(1) << kSetBit)),
+          "too many particles in one set for the pair traversal");
+  const SrcSet a = src_of(*src0, q0);
+  const SrcSet b = src1 ? src_of(*src1, q1) : a;
+  const int nsrc = src1 ? 2 : 1;
+  PairOut out{};
+  out.phi = phi;
+  out.E = E;
+  if (!E)
+    launch_queue<MODE_POT, T, T>(s, tgt, a, b, nsrc, rg, out);
+  else if (field_single)
+    launch_queue<MODE_FIELD, T, float>(s, tgt, a, b, nsrc, rg, out);
   else
-    hipLaunchKernelGGL((pair_onfly_kernel<T, false>), dim3(nblk(tgt.n, 256)), dim3(256), 0, s,
-                       tgt.pos.get(), tgt.idx.get(), tgt.n, src.pos.get(), src.idx.get(),
-                       src.cell_start.get(), q_src, rg, phi, E);
-  PE_CHECK_LAUNCH();
+    launch_queue<MODE_FIELD, T, T>(s, tgt, a, b, nsrc, rg, out);
 }
 
 template void launch_spmv_assemble<float>(hipStream_t, pe_context*, const double*, const double*, const double*, const double*, double*);
 template void launch_spmv_assemble<double>(hipStream_t, pe_context*, const double*, const double*, const double*, const double*, double*);
-template void launch_pair_onfly<float>(hipStream_t, const ParticleSet&, const ParticleSet&, const double*, const RealGeom&, double*, double*);
-template void launch_pair_onfly<double>(hipStream_t, const ParticleSet&, const ParticleSet&, const double*, const RealGeom&, double*, double*);
+template void launch_pair_onfly<float>(hipStream_t, const ParticleSet&, const ParticleSet*, const double*,
+                                       const ParticleSet*, const double*, const RealGeom&, double*, double*, bool);
+template void launch_pair_onfly<double>(hipStream_t, const ParticleSet&, const ParticleSet*, const double*,
+                                        const ParticleSet*, const double*, const RealGeom&, double*, double*, bool);
 
 }  // namespace pe
