@@ -16,7 +16,8 @@ OUT = os.path.join(HERE, "libpe.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PE_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "grid.hip", "fft.hip", "realspace.hip", "vector.hip", "precond.hip", "guess.hip", "bd.hip"]
+SOURCES = ["api.hip", "grid.hip", "fft.hip", "realspace.hip", "vector.hip", "shapes.hip", "precond.hip", "guess.hip",
+           "bd.hip"]
 
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

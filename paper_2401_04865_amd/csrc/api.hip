@@ -183,7 +183,19 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
   { ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8); launch_spread<T>(s, c->B, q, gA, c->gg, false); }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
   { ProfScope ps(c->prof, s, PE_PROF_GATHER, sizeof(T) == 8); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
-  { ProfScope ps(c->prof, s, PE_PROF_SPMV, sizeof(T) == 8); launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), ck_bead(c), y); }
+  {
+    // real space: dense intra-body blocks per shape, then the sparse pairs
+    ProfScope ps(c->prof, s, PE_PROF_SPMV, sizeof(T) == 8);
+    for (auto& t : c->pc.types) {
+      if (!t.near || t.bodies.empty()) continue;
+      const T* R;
+      if constexpr (sizeof(T) == 8) R = t.R64.get();
+      else R = t.R32.get();
+      launch_body_gemm<T>(s, R, t.N, false, true, t.dbodies.get(), (int)t.bodies.size(), c->off.get(), nb,
+                          q, c->phi_w.get());
+    }
+    launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), ck_bead(c), y);
+  }
 }
 
 void apply_saddle_prec(pe_context* c, int prec, const double* x, double* y) {
@@ -316,8 +328,11 @@ struct GmresOut {
 // Restarted GMRES on A x = b with operator precision `prec`; x is updated in
 // place.  Convergence: ||b - A x|| <= tol * bnorm, checked with the true
 // residual of the operator at every restart.
+// r0 (optional, with its norm r0n): the residual b - A x at the starting x,
+// already formed by the caller, so the first cycle does not recompute it.
 GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero, double bnorm, double tol,
-               int max_iters, pe_solve_info* info, int* mv64, int* mv32) {
+               int max_iters, pe_solve_info* info, int* mv64, int* mv32, const double* r0 = nullptr,
+               double r0n = 0.0) {
   hipStream_t s = c->stream;
   const int64_t n = c->n_bead + c->n_body;
   const int m = std::max(1, std::min(c->p.gmres_restart, kMaxK - 1));
@@ -327,16 +342,24 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
   bool first = true;
   for (;;) {
     // r = b - A x
-    if (first && x_zero) {
-      dcopy(s, b, k.r, n);
+    double beta;
+    if (first && r0) {
+      if (r0 != k.r) dcopy(s, r0, k.r, n);
+      beta = r0n;
+      PE_HIP(hipStreamSynchronize(s));
+      PE_HIP(hipMemcpy(k.nrm, &beta, sizeof(double), hipMemcpyHostToDevice));
     } else {
-      apply_saddle_prec(c, prec, x, k.tmp);
-      (prec == PE_MIXED ? *mv32 : *mv64) += 1;
-      launch_sub(s, b, k.tmp, k.r, n);
+      if (first && x_zero) {
+        dcopy(s, b, k.r, n);
+      } else {
+        apply_saddle_prec(c, prec, x, k.tmp);
+        (prec == PE_MIXED ? *mv32 : *mv64) += 1;
+        launch_sub(s, b, k.tmp, k.r, n);
+      }
+      launch_mdot(s, k.r, n, 1, k.r, n, partial, k.nrm, true);
+      beta = fetch(c, k.nrm);
     }
     first = false;
-    launch_mdot(s, k.r, n, 1, k.r, n, partial, k.nrm, true);
-    const double beta = fetch(c, k.nrm);
     if (!std::isfinite(beta)) throw Error(PE_ERR_NUMERIC, "non-finite residual in GMRES");
     out.rel = beta / bnorm;
     if (beta <= tol * bnorm) {
@@ -658,8 +681,8 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   build_cells(s, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, n_ion, rg);
   build_tiles(s, c->B, c->gg);
   build_tiles(s, c->I, c->gg);
+  shape_setup(c);
   build_bead_matrix(c);
-  if (c->p.precond) precond_setup(c);
   ensure_grids(c);
   c->phi_w.ensure(nb + n_ion + 1);
   c->phi_all.ensure(nb + n_ion + 1);
@@ -729,19 +752,23 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
   if (bnorm == 0.0) {
     inf->rel_residual = 0;
   } else {
-    // residual at the guess (double operator)
+    // residual at the guess (double operator); it is also the first
+    // residual of the solve below
+    double rgn = bnorm;
     if (!x_zero) {
       apply_saddle_prec(c, PE_FP64, x, k.tmp);
       mv64++;
       launch_sub(s, b, k.tmp, k.r, n);
       launch_mdot(s, k.r, n, 1, k.r, n, c->red.get(), k.nrm, true);
-      inf->rel_residual_guess = fetch(c, k.nrm) / bnorm;
+      rgn = fetch(c, k.nrm);
+      inf->rel_residual_guess = rgn / bnorm;
     } else {
       inf->rel_residual_guess = 1.0;
     }
     const double tol = c->p.rel_tol;
     if (c->p.precision == PE_FP64) {
-      GmresOut o = gmres(c, PE_FP64, b, x, x_zero, bnorm, tol, c->p.max_iters, inf, &mv64, &mv32);
+      GmresOut o = gmres(c, PE_FP64, b, x, x_zero, bnorm, tol, c->p.max_iters, inf, &mv64, &mv32,
+                         x_zero ? nullptr : k.r, rgn);
       inf->iters = o.iters;
       inf->rel_residual = o.rel;
       if (!o.converged) status = PE_ERR_NOT_CONVERGED;
@@ -757,16 +784,18 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
       bool conv = false;
       double rel = 1.0;
       for (int outer = 0; outer <= c->p.max_refine; ++outer) {
-        // r = b - A64 x
-        if (x_zero && outer == 0) {
-          dcopy(s, b, r, n);
+        // r = b - A64 x (at the start: b, or the residual of the guess)
+        double rn;
+        if (outer == 0) {
+          dcopy(s, x_zero ? b : k.r, r, n);
+          rn = rgn;
         } else {
           apply_saddle_prec(c, PE_FP64, x, k.tmp);
           mv64++;
           launch_sub(s, b, k.tmp, r, n);
+          launch_mdot(s, r, n, 1, r, n, c->red.get(), k.nrm, true);
+          rn = fetch(c, k.nrm);
         }
-        launch_mdot(s, r, n, 1, r, n, c->red.get(), k.nrm, true);
-        const double rn = fetch(c, k.nrm);
         if (!std::isfinite(rn)) throw Error(PE_ERR_NUMERIC, "non-finite residual in refinement");
         rel = rn / bnorm;
         if (rel <= tol) { conv = true; break; }

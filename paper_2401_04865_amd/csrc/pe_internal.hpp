@@ -195,22 +195,38 @@ struct ProfScope {
   }
 };
 
-// ----------------------------------------------------------- preconditioner
+// ------------------------------------------------------------ body shapes
 
 // One rigid-body shape: reference geometry (relative bead positions of the
-// first body seen), widths, the inverse of its body saddle block, and the
-// bodies of the current configuration that have this shape.
+// first body seen), widths, the distances of every bead to up to four
+// reference beads (the matching signature), and the dense per-shape blocks:
+// the inverse of the body saddle block (preconditioner) and the intra-body
+// real-space block (near field).  `bodies` lists the bodies of the current
+// configuration that have this shape.
 struct BodyType {
   int N = 0;
   std::vector<double> ref, sig;
+  int nref = 0;
+  int refidx[4] = {0, 0, 0, 0};
+  double scale = 0;                // largest reference distance
+  double extent = 0;               // largest distance of a bead from the centroid
+  DevBuf<double> dref;             // N x nref reference distances
+  DevBuf<double> dsig;             // N widths
+  DevBuf<int> drefidx;             // nref
+  bool have_inv = false;
   DevBuf<double> Ainv;
   DevBuf<float> Ainv32;
+  bool near = false;               // intra-body real-space block stored densely
+  DevBuf<double> R64;
+  DevBuf<float> R32;
   std::vector<int> bodies;
   DevBuf<int> dbodies;
 };
 
 struct Precond {
   std::deque<BodyType> types;
+  DevBuf<int> assigned;            // per body: type index
+  DevBuf<unsigned char> dense;     // per body: intra-body pairs held by a dense block
 };
 
 // ----------------------------------------------------------------- context
@@ -324,6 +340,18 @@ template <typename T>
 void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet* src0, const double* q0,
                        const ParticleSet* src1, const double* q1, const RealGeom& rg, double* phi, double* E,
                        bool field_single = false);
+
+// body shapes (shapes.hip): group bodies into shape types (device-side
+// matching, types cached across configurations), build the per-shape blocks
+void shape_setup(pe_context* c);
+// y[:, b] (+)= A x[:, b] for the bodies b of one shape: column b is the
+// body's bead segment of x (plus its dPsi entry when bordered, A then
+// (N+1) x (N+1)); accumulate adds into y.
+template <typename T>
+void launch_body_gemm(hipStream_t s, const T* A, int N, bool bordered, bool accumulate, const int* bodies,
+                      int nbt, const int64_t* off, int64_t n_bead, const double* x, double* y);
+// dense intra-body real-space block of one shape (realspace.hip)
+void build_near_block(hipStream_t s, const BodyType& t, const RealGeom& rg, double* R64, float* R32);
 
 // body / vector kernels
 void launch_body_sums(hipStream_t s, pe_context* c, const double* q, double* out_sum, double* out_sig2);

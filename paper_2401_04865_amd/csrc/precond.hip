@@ -11,8 +11,7 @@
 // orientation.  With M_ii SPD, u = M_ii^{-1} 1 and s = 1^T u,
 //     A_i^{-1} = [ -M^{-1} + u u^T / s   u / s ]
 //                [  u^T / s              1 / s ].
-// Bodies are grouped into shape types on the host (bead count, widths and the
-// distances of every bead to three reference beads), M^{-1} is formed per type
+// Bodies are grouped into shape types (shapes.hip), M^{-1} is formed per type
 // on the device by Gauss-Jordan elimination (no pivoting: M is SPD), and the
 // preconditioner is applied to all bodies of a type at once as one dense
 // product (N+1) x (N+1) times (N+1) x n_bodies.  Types are cached across
@@ -99,95 +98,7 @@ __global__ void assemble_inverse_kernel(const double* __restrict__ Minv, const d
   Ainv32[t] = (float)v;
 }
 
-// z = A^{-1} x for every body of one type: Y (Np x nb) = Ainv (Np x Np) X (Np x nb),
-// column b of X is [x[off(b) .. off(b)+N); x[n_bead + body(b)]].
-// 32 x 32 output tiles (a few hundred workgroups even for one shape of a few
-// hundred beads), K staged through LDS 32 at a time; thread (tx, ty) of the
-// 16 x 16 block owns rows {ty, ty + 16} and columns {tx, tx + 16} of the tile.
-constexpr int kBM = 32, kBN = 32, kBK = 32;
-
-template <typename T>
-__global__ void __launch_bounds__(256) apply_type_kernel(const T* __restrict__ Ainv, int N,
-                                                         const int* __restrict__ bodies, int nbt,
-                                                         const int64_t* __restrict__ off, int64_t n_bead,
-                                                         const double* __restrict__ x, double* __restrict__ z) {
-  const int Np = N + 1;
-  __shared__ T As[kBK][kBM + 1];
-  __shared__ T Xs[kBK][kBN + 1];
-  __shared__ int64_t boff[kBN];
-  __shared__ int64_t bpsi[kBN];
-  const int row0 = blockIdx.x * kBM;
-  const int col0 = blockIdx.y * kBN;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  if (threadIdx.x < kBN) {
-    const int b = col0 + threadIdx.x;
-    if (b < nbt) {
-      const int body = bodies[b];
-      boff[threadIdx.x] = off[body];
-      bpsi[threadIdx.x] = n_bead + body;
-    } else {
-      boff[threadIdx.x] = -1;
-      bpsi[threadIdx.x] = -1;
-    }
-  }
-  __syncthreads();
-  T acc[2][2] = {{0, 0}, {0, 0}};
-  for (int k0 = 0; k0 < Np; k0 += kBK) {
-    for (int t = threadIdx.x; t < kBK * kBM; t += blockDim.x) {
-      const int kk = t % kBK, r = t / kBK;
-      const int gr = row0 + r, gk = k0 + kk;
-      As[kk][r] = (gr < Np && gk < Np) ? Ainv[(int64_t)gr * Np + gk] : (T)0;
-    }
-    for (int t = threadIdx.x; t < kBK * kBN; t += blockDim.x) {
-      const int cc = t / kBK, kk = t % kBK;
-      const int gk = k0 + kk;
-      T v = 0;
-      if (boff[cc] >= 0 && gk < Np) v = (T)(gk < N ? x[boff[cc] + gk] : x[bpsi[cc]]);
-      Xs[kk][cc] = v;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < kBK; ++kk) {
-      const T a0 = As[kk][ty], a1 = As[kk][ty + 16];
-      const T b0 = Xs[kk][tx], b1 = Xs[kk][tx + 16];
-      acc[0][0] += a0 * b0;
-      acc[0][1] += a0 * b1;
-      acc[1][0] += a1 * b0;
-      acc[1][1] += a1 * b1;
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const int gr = row0 + ty + 16 * p;
-    if (gr >= Np) continue;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int cc = tx + 16 * q;
-      if (boff[cc] < 0) continue;
-      const int64_t o = gr < N ? boff[cc] + gr : bpsi[cc];
-      z[o] = (double)acc[p][q];
-    }
-  }
-}
-
-bool same_shape(const BodyType& t, const double* rel, const double* sig, int N) {
-  if (t.N != N) return false;
-  double scale = 0;
-  for (int j = 0; j < 3 * N; ++j) scale = std::max(scale, std::fabs(t.ref[j]));
-  const double tol = 1e-9 * std::max(scale, 1e-300);
-  auto dist = [](const double* a, const double* b) {
-    const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
-    return std::sqrt(dx * dx + dy * dy + dz * dz);
-  };
-  const int nref = std::min(N, 3);
-  for (int j = 0; j < N; ++j) {
-    if (std::fabs(t.sig[j] - sig[j]) > 1e-12 * std::fabs(sig[j])) return false;
-    for (int r = 0; r < nref; ++r)
-      if (std::fabs(dist(&t.ref[3 * j], &t.ref[3 * r]) - dist(&rel[3 * j], &rel[3 * r])) > tol) return false;
-  }
-  return true;
-}
+}  // namespace
 
 void build_type_inverse(pe_context* c, BodyType& t) {
   hipStream_t s = c->stream;
@@ -229,63 +140,15 @@ void build_type_inverse(pe_context* c, BodyType& t) {
   PE_HIP(hipStreamSynchronize(s));
 }
 
-}  // namespace
-
-void precond_setup(pe_context* c) {
-  Precond& pc = c->pc;
-  for (auto& t : pc.types) t.bodies.clear();
-  const int64_t nb = c->n_bead, nbody = c->n_body;
-  if (nbody == 0) return;
-  std::vector<double> rel(3 * nb), sig(nb);
-  if (nb) {
-    PE_HIP(hipMemcpyAsync(rel.data(), c->rel.get(), sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, c->stream));
-    PE_HIP(hipMemcpyAsync(sig.data(), c->bead_sig.get(), sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
-  }
-  PE_HIP(hipStreamSynchronize(c->stream));
-  for (int64_t i = 0; i < nbody; ++i) {
-    const int64_t o = c->h_off[i];
-    const int N = (int)(c->h_off[i + 1] - o);
-    if (N == 0) continue;
-    BodyType* found = nullptr;
-    for (auto& t : pc.types)
-      if (same_shape(t, &rel[3 * o], &sig[o], N)) {
-        found = &t;
-        break;
-      }
-    if (!found) {
-      require(N <= 16384, "body too large for the block preconditioner (N > 16384)");
-      pc.types.emplace_back();
-      BodyType& t = pc.types.back();
-      t.N = N;
-      t.ref.assign(rel.begin() + 3 * o, rel.begin() + 3 * (o + N));
-      t.sig.assign(sig.begin() + o, sig.begin() + o + N);
-      build_type_inverse(c, t);
-      found = &t;
-    }
-    found->bodies.push_back((int)i);
-  }
-  for (auto& t : pc.types) {
-    t.dbodies.ensure(std::max<size_t>(1, t.bodies.size()));
-    if (!t.bodies.empty())
-      PE_HIP(hipMemcpyAsync(t.dbodies.get(), t.bodies.data(), sizeof(int) * t.bodies.size(), hipMemcpyHostToDevice,
-                            c->stream));
-  }
-  PE_HIP(hipStreamSynchronize(c->stream));
-}
-
 template <typename T>
 void precond_apply(hipStream_t s, pe_context* c, const double* x, double* z) {
   for (auto& t : c->pc.types) {
     const int nbt = (int)t.bodies.size();
     if (nbt == 0) continue;
-    const int Np = t.N + 1;
     const T* A;
     if constexpr (sizeof(T) == 8) A = t.Ainv.get();
     else A = t.Ainv32.get();
-    dim3 grid((unsigned)((Np + kBM - 1) / kBM), (unsigned)((nbt + kBN - 1) / kBN));
-    hipLaunchKernelGGL(apply_type_kernel<T>, grid, dim3(256), 0, s, A, t.N, t.dbodies.get(), nbt, c->off.get(),
-                       c->n_bead, x, z);
-    PE_CHECK_LAUNCH();
+    launch_body_gemm<T>(s, A, t.N, true, false, t.dbodies.get(), nbt, c->off.get(), c->n_bead, x, z);
   }
 }
 

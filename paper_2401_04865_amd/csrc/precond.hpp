@@ -5,8 +5,8 @@
 
 namespace pe {
 
-// Group bodies into shape types and build (or reuse) each type's inverse.
-void precond_setup(pe_context* c);
+// Inverse of the free-space body saddle block of one shape (double and float).
+void build_type_inverse(pe_context* c, BodyType& t);
 // z = P^{-1} x over the saddle vector [q; dPsi] (every body's block).
 template <typename T>
 void precond_apply(hipStream_t s, pe_context* c, const double* x, double* z);

@@ -183,6 +183,8 @@ struct PairOut {
   int* col;             // CSR of the bead block (fill mode)
   double* v64;
   float* v32;
+  const int* body_of;          // count / fill: body of each bead (caller order)
+  const unsigned char* dense;  // count / fill: per body, intra-body pairs held by a dense block
 };
 
 enum { MODE_COUNT = 0, MODE_FILL = 1, MODE_POT = 2, MODE_FIELD = 3 };
@@ -230,6 +232,12 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     o = out.row_ptr[t];
     o_end = out.row_ptr[t + 1];
   }
+  // count / fill: pairs inside a body with a dense intra-body block are left out
+  int own_body = -1;
+  if ((MODE == MODE_COUNT || MODE == MODE_FILL) && out.dense) {
+    const int b = out.body_of[tidx[active ? t : begin]];
+    if (out.dense[b]) own_body = b;
+  }
 
   auto evaluate = [&](int e) {
     const int set = e >> kSetBit;
@@ -241,6 +249,9 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     dz -= g.L[2] * rint(dz * g.inv_L[2]);
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 < g.rc2)) return;
+    if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) {
+      if (own_body >= 0 && out.body_of[s0.idx[sidx]] == own_body) return;
+    }
     if constexpr (MODE == MODE_COUNT) {
       ++cnt;
       return;
@@ -513,6 +524,10 @@ void build_bead_matrix(pe_context* c) {
   const SrcSet sb = src_of(B, nullptr);
   PairOut out{};
   out.cnt = c->cnt.get();
+  if (c->n_body > 0) {
+    out.body_of = c->body_of.get();
+    out.dense = c->pc.dense.get();
+  }
   if (n > 0) launch_queue<MODE_COUNT, double, double>(s, B, sb, sb, 1, c->rg, out);
   std::vector<int> cnt(n);
   if (n > 0) PE_HIP(hipMemcpyAsync(cnt.data(), c->cnt.get(), sizeof(int) * n, hipMemcpyDeviceToHost, s));
@@ -531,6 +546,46 @@ void build_bead_matrix(pe_context* c) {
   out.v64 = c->val64.get();
   out.v32 = c->have_val32 ? c->val32.get() : nullptr;
   if (n > 0) launch_queue<MODE_FILL, double, double>(s, B, sb, sb, 1, c->rg, out);
+  PE_HIP(hipStreamSynchronize(s));
+}
+
+namespace {
+
+// Dense intra-body block of one shape: every pair of the reference geometry
+// (all closer than half the box, so each is its own minimum image), the
+// diagonal by the self value.
+__global__ void near_block_kernel(const double* __restrict__ ref, const double* __restrict__ sig, int N, RealGeom g,
+                                  double* __restrict__ R64, float* __restrict__ R32) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)N * N) return;
+  const int i = (int)(e / N), j = (int)(e - (int64_t)i * N);
+  const double dx = ref[3 * i] - ref[3 * j], dy = ref[3 * i + 1] - ref[3 * j + 1], dz = ref[3 * i + 2] - ref[3 * j + 2];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double s2 = sig[i] * sig[i] + sig[j] * sig[j];
+  double R;
+  if (r2 == 0.0) {
+    R = self_value<double>(s2, g);
+  } else {
+    double dR;
+    pair_kernel<double>(sqrt(r2), s2, g, R, dR, false);
+  }
+  R64[e] = R;
+  R32[e] = (float)R;
+}
+
+}  // namespace
+
+void build_near_block(hipStream_t s, const BodyType& t, const RealGeom& rg, double* R64, float* R32) {
+  const int N = t.N;
+  DevBuf<double> dref, dsig;
+  dref.ensure(3 * (size_t)N);
+  dsig.ensure(N);
+  PE_HIP(hipMemcpyAsync(dref.get(), t.ref.data(), sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(dsig.get(), t.sig.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+  const int64_t NN = (int64_t)N * N;
+  hipLaunchKernelGGL(near_block_kernel, dim3(nblk(NN, 256)), dim3(256), 0, s, dref.get(), dsig.get(), N, rg, R64,
+                     R32);
+  PE_CHECK_LAUNCH();
   PE_HIP(hipStreamSynchronize(s));
 }
 
