@@ -192,7 +192,7 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
       if constexpr (sizeof(T) == 8) R = t.R64.get();
       else R = t.R32.get();
       launch_body_gemm<T>(s, R, t.N, false, true, t.dbodies.get(), (int)t.bodies.size(), c->off.get(), nb,
-                          q, c->phi_w.get());
+                          q, c->phi_w.get(), c->pc.gemm_ws.get());
     }
     launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), ck_bead(c), y);
   }
@@ -245,6 +245,23 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
 }
 
 // Right-hand side b = [-r.E0 + phi_ion(beads); Q] in double.
+// Ion potential (and, with the learned guess active, ion field) at the beads,
+// in precision T: the wave part by one ion-only SE pass, plus the ion->bead
+// real-space pairs.  Mixed precision runs it in float like every other
+// real- and wave-space sum; the double path keeps it in double.
+template <typename T>
+void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E) {
+  hipStream_t s = c->stream;
+  T* gA = grid_real<T>(c->gridA);
+  T* gB = grid_real<T>(c->gridB);
+  launch_spread<T>(s, c->I, c->ion_q.get(), gA, c->gg, false);
+  launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
+  launch_gather<T>(s, c->B, gB, c->gg, phi_ion, E, false);
+  // the field only feeds the guess features: single precision
+  launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, phi_ion, E, true);
+}
+
+// Right-hand side b = [-r.E0 + phi_ion(beads); Q].
 void build_rhs(pe_context* c, double* b) {
   hipStream_t s = c->stream;
   const int64_t nb = c->n_bead, ni = c->n_ion;
@@ -252,19 +269,14 @@ void build_rhs(pe_context* c, double* b) {
   if (ni) {
     phi_ion = c->phi_w.get();
     launch_moments(s, c->ion_q.get(), c->ion_sig.get(), 0.0, ni, ck_coef(c), c->red.get(), ck_ion(c), nullptr);
-    double* gA = c->gridA.get();
-    double* gB = c->gridB.get();
-    launch_spread<double>(s, c->I, c->ion_q.get(), gA, c->gg, false);
-    launch_wave_pipeline<double>(s, c, gA, gB, c->gridC.get());
     // with the learned guess active, the same pass also yields the ion field at the beads
     double* E = nullptr;
     if (c->guess) {
       c->E_ion.ensure(3 * std::max<int64_t>(nb, 1));
       E = c->E_ion.get();
     }
-    launch_gather<double>(s, c->B, gB, c->gg, phi_ion, E, false);
-    // the field only feeds the guess features: single precision
-    launch_pair_onfly<double>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, phi_ion, E, true);
+    if (c->p.precision == PE_MIXED) ion_potential_at_beads<float>(c, phi_ion, E);
+    else ion_potential_at_beads<double>(c, phi_ion, E);
   }
   c->have_eion = c->guess != nullptr;
   if (nb)
@@ -677,8 +689,8 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
     hipLaunchKernelGGL(rel_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, c->bead_x.get(), body_center,
                        c->body_of.get(), nb, c->rel.get());
   PE_CHECK_LAUNCH();
-  build_cells(s, c->B, c->bead_x.get(), c->bead_sig.get(), 0.0, nb, rg);
-  build_cells(s, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, n_ion, rg);
+  build_cells(s, c->B, c->bead_x.get(), c->bead_sig.get(), 0.0, c->body_of.get(), nb, rg);
+  build_cells(s, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, nullptr, n_ion, rg);
   build_tiles(s, c->B, c->gg);
   build_tiles(s, c->I, c->gg);
   shape_setup(c);

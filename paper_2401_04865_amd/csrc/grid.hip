@@ -1,13 +1,15 @@
 // Gaussian spreading and contraction (section "Spectral Ewald
 // implementation", steps 2 and 6; window of section "Wave-space sum").
 //
-// Contraction: one 64-lane wavefront per particle.  Lanes 0..3P-1 first
-// evaluate the separable window factors w_x[j], w_y[j], w_z[j] (3P
+// Contraction: per home tile (the tile holding a particle's first support
+// point), the reachable grid region is staged in LDS once and contracted by
+// groups of 16 lanes, one particle each.  Where that region does not fit in
+// LDS (large P in double), one 64-lane wavefront per particle: lanes 0..3P-1
+// first evaluate the separable window factors w_x[j], w_y[j], w_z[j] (3P
 // exponentials per particle instead of P^3) and the wrapped grid indices into
 // LDS; then the wavefront sweeps the P x P (y,z) lines of the support, lane t
 // owning line (t / P, t % P) and looping over the P x-points, and reduces
-// across lanes.  Particles are visited in cell order, so neighbouring
-// wavefronts read neighbouring grid regions (cache reuse).
+// across lanes.
 //
 // Support (the P closest grid points per axis): even P takes
 // m0-P/2+1 .. m0+P/2 with m0 = floor(x/h); odd P is centred on rint(x/h).
@@ -126,6 +128,27 @@ __global__ void tile_fill_kernel(const double4* __restrict__ pos, int64_t n, Gri
         const int slot = atomicAdd(&cursor[(tx[a] * g.ntile[1] + ty[b]) * g.ntile[2] + tz[c]], 1);
         entries[slot] = (int)i;
       }
+}
+
+// Home tile of a particle: the tile that holds its first support point.
+__device__ __forceinline__ int home_tile(const double4 p, const GridGeom& g) {
+  const int hx = wrap_idx(axis_start(p.x, g.inv_h[0], g.P), g.N[0]) / kTile;
+  const int hy = wrap_idx(axis_start(p.y, g.inv_h[1], g.P), g.N[1]) / kTile;
+  const int hz = wrap_idx(axis_start(p.z, g.inv_h[2], g.P), g.N[2]) / kTile;
+  return (hx * g.ntile[1] + hy) * g.ntile[2] + hz;
+}
+
+__global__ void home_count_kernel(const double4* __restrict__ pos, int64_t n, GridGeom g, int* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(&count[home_tile(pos[i], g)], 1);
+}
+
+__global__ void home_fill_kernel(const double4* __restrict__ pos, int64_t n, GridGeom g, int* __restrict__ cursor,
+                                 int* __restrict__ entries) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  entries[atomicAdd(&cursor[home_tile(pos[i], g)], 1)] = (int)i;
 }
 
 // One workgroup (four wavefronts) per tile.  The tile's particle list is
@@ -271,6 +294,127 @@ __global__ void __launch_bounds__(256) gather_kernel(const double4* __restrict__
   }
 }
 
+// Tile-staged contraction: one workgroup per home tile.  The grid region the
+// supports of the tile's home particles can reach, (kTile + P - 1)^3 points
+// from the tile's first point, is read once into LDS; then each group of 16
+// lanes contracts one particle from LDS (four per wavefront), lane s taking
+// the (y, z) lines s, s + 16, ... of the support and looping over x, and the
+// group reduces with lane shuffles.  The result is the same sum as the
+// per-particle kernel, in another order.
+constexpr int kGatherLDS = 48 * 1024;
+
+template <typename T, bool FIELD>
+__global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restrict__ pos,
+                                                          const int* __restrict__ idx,
+                                                          const int* __restrict__ home_start,
+                                                          const int* __restrict__ home_entries,
+                                                          const int* __restrict__ home_tiles,
+                                                          const T* __restrict__ grid, GridGeom g,
+                                                          double* __restrict__ phi, double* __restrict__ E,
+                                                          int accumulate) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* H = reinterpret_cast<T*>(smem_raw);
+  __shared__ T w_s[16][3 * kMaxP];
+  __shared__ T d_s[16][3 * kMaxP];
+  __shared__ int gidx[3][kTile + kMaxP];  // wrapped grid index of each region plane, per axis
+  const int tile = home_tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  const int uz = tile % g.ntile[2];
+  const int uy = (tile / g.ntile[2]) % g.ntile[1];
+  const int ux = tile / (g.ntile[2] * g.ntile[1]);
+  const int P = g.P;
+  const int Hs = kTile + P - 1;
+  const int Hs2 = Hs * Hs;
+  if ((int)threadIdx.x < 3 * Hs) {
+    const int ax = threadIdx.x / Hs, l = threadIdx.x - ax * Hs;
+    const int u = ax == 0 ? ux : (ax == 1 ? uy : uz);
+    gidx[ax][l] = wrap_idx(kTile * u + l, g.N[ax]);
+  }
+  __syncthreads();
+  // region rows (lx, ly) of Hs contiguous z values; 16 threads per row
+  for (int row = threadIdx.x >> 4; row < Hs2; row += 16) {
+    const int lx = row / Hs;
+    const int ly = row - lx * Hs;
+    const int64_t rb = ((int64_t)gidx[0][lx] * g.N[1] + gidx[1][ly]) * g.N[2];
+    for (int lz = threadIdx.x & 15; lz < Hs; lz += 16) H[row * Hs + lz] = grid[rb + gidx[2][lz]];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sub = lane >> 4, s = lane & 15;
+  const int slot = 4 * wv + sub;
+  const int e0 = home_start[tile], e1 = home_start[tile + 1];
+  for (int base = e0; base < e1; base += 16) {
+    const int e = base + slot;
+    const bool valid = e < e1;
+    const int i = home_entries[valid ? e : e1 - 1];
+    const double4 p = pos[i];
+    // window factors and displacements of the three axes
+    for (int k = s; k < 3 * P; k += 16) {
+      const int ax = k / P;
+      const int j = k - ax * P;
+      const double x = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
+      double delta;
+      support_start(x, g.inv_h[ax], P, delta);
+      w_s[slot][k] = window<T>(g, ax, j, delta);
+      if (FIELD) d_s[slot][k] = (T)(((double)j + delta) * g.h[ax]);
+    }
+    // first support point relative to the region origin, per axis
+    double dl;
+    const int ox = wrap_idx(support_start(p.x, g.inv_h[0], P, dl), g.N[0]) - kTile * ux;
+    const int oy = wrap_idx(support_start(p.y, g.inv_h[1], P, dl), g.N[1]) - kTile * uy;
+    const int oz = wrap_idx(support_start(p.z, g.inv_h[2], P, dl), g.N[2]) - kTile * uz;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const T* wsl = w_s[slot];
+    const T* dsl = d_s[slot];
+    T acc = 0, axf = 0, ayf = 0, azf = 0;
+    for (int t = s; t < P * P; t += 16) {
+      const int jy = t / P;
+      const int jz = t - jy * P;
+      const T wyz = wsl[P + jy] * wsl[2 * P + jz];
+      const T* col = H + (ox * Hs + oy + jy) * Hs + oz + jz;
+      T lacc = 0, lx = 0;
+      for (int jx = 0; jx < P; ++jx) {
+        const T v = col[jx * Hs2] * wsl[jx];
+        lacc += v;
+        if (FIELD) lx += v * dsl[jx];
+      }
+      acc += lacc * wyz;
+      if (FIELD) {
+        axf += lx * wyz;
+        ayf += lacc * wyz * dsl[P + jy];
+        azf += lacc * wyz * dsl[2 * P + jz];
+      }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      acc += __shfl_xor(acc, o, 16);
+      if (FIELD) {
+        axf += __shfl_xor(axf, o, 16);
+        ayf += __shfl_xor(ayf, o, 16);
+        azf += __shfl_xor(azf, o, 16);
+      }
+    }
+    if (valid && s == 0) {
+      const int oi = idx[i];
+      const double ph = (double)acc * (g.h3 / g.eps);
+      if (accumulate) phi[oi] += ph; else phi[oi] = ph;
+      if (FIELD) {
+        const double ex = g.fcoef * (double)axf, ey = g.fcoef * (double)ayf, ez = g.fcoef * (double)azf;
+        if (accumulate) {
+          E[3 * oi] += ex; E[3 * oi + 1] += ey; E[3 * oi + 2] += ez;
+        } else {
+          E[3 * oi] = ex; E[3 * oi + 1] = ey; E[3 * oi + 2] = ez;
+        }
+      }
+    }
+    // the slot's factors are rewritten next round
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 }  // namespace
 
 void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
@@ -298,6 +442,32 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
     // sort each tile's list so the accumulation order is the same on every run
     launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get());
   }
+  // home lists (each particle once; order within a tile does not matter)
+  ps.home_start.ensure(nt + 1);
+  ps.home_entries.ensure(std::max<int64_t>(ps.n, 1));
+  PE_HIP(hipMemsetAsync(ps.tile_count.get(), 0, sizeof(int) * nt, s));
+  if (ps.n > 0) {
+    hipLaunchKernelGGL(home_count_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get());
+    PE_CHECK_LAUNCH();
+  }
+  PE_HIP(hipMemcpyAsync(cnt.data(), ps.tile_count.get(), sizeof(int) * nt, hipMemcpyDeviceToHost, s));
+  PE_HIP(hipStreamSynchronize(s));
+  std::vector<int> hstart(nt + 1, 0), htiles;
+  for (int t = 0; t < nt; ++t) {
+    hstart[t + 1] = hstart[t] + cnt[t];
+    if (cnt[t]) htiles.push_back(t);
+  }
+  ps.n_home_tiles = (int)htiles.size();
+  ps.home_tiles.ensure(std::max<size_t>(htiles.size(), 1));
+  PE_HIP(hipMemcpyAsync(ps.home_start.get(), hstart.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
+  if (!htiles.empty())
+    PE_HIP(hipMemcpyAsync(ps.home_tiles.get(), htiles.data(), sizeof(int) * htiles.size(), hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(ps.tile_count.get(), hstart.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  if (ps.n > 0) {
+    hipLaunchKernelGGL(home_fill_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get(),
+                       ps.home_entries.get());
+    PE_CHECK_LAUNCH();
+  }
   PE_HIP(hipStreamSynchronize(s));
 }
 
@@ -317,6 +487,22 @@ void launch_gather(hipStream_t s, const ParticleSet& ps, const T* grid, const Gr
                    double* phi, double* E, bool accumulate) {
   if (ps.n == 0) return;
   require(g.P <= kMaxP, "support P must be <= 16");
+  const int Hs = kTile + g.P - 1;
+  const size_t region = (size_t)Hs * Hs * Hs * sizeof(T);
+  if (region <= (size_t)kGatherLDS) {
+    if (ps.n_home_tiles == 0) return;
+    const dim3 blocks((unsigned)ps.n_home_tiles);
+    if (E)
+      hipLaunchKernelGGL((gather_tile_kernel<T, true>), blocks, dim3(256), region, s, ps.pos.get(), ps.idx.get(),
+                         ps.home_start.get(), ps.home_entries.get(), ps.home_tiles.get(), grid, g, phi, E,
+                         accumulate ? 1 : 0);
+    else
+      hipLaunchKernelGGL((gather_tile_kernel<T, false>), blocks, dim3(256), region, s, ps.pos.get(), ps.idx.get(),
+                         ps.home_start.get(), ps.home_entries.get(), ps.home_tiles.get(), grid, g, phi, E,
+                         accumulate ? 1 : 0);
+    PE_CHECK_LAUNCH();
+    return;
+  }
   const int64_t nb = (ps.n + kWaves - 1) / kWaves;
   if (E)
     hipLaunchKernelGGL((gather_kernel<T, true>), dim3((unsigned)nb), dim3(256), 0, s,

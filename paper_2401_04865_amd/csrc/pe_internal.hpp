@@ -84,6 +84,18 @@ struct GridGeom {
   int ntile[3];     // spreading tiles per axis (ceil(N / 8))
 };
 
+// Workgroups are handed to the eight XCDs round robin (workgroup b to XCD
+// b % 8), and each XCD has its own L2.  This maps workgroup b to a logical
+// index so that each XCD receives one contiguous range of logical indices:
+// work items that are neighbours in space (and share cached data) then run
+// under one L2.  A bijection of [0, n).
+constexpr int kNumXCD = 8;
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n / kNumXCD, r = n % kNumXCD;
+  const int x = b % kNumXCD;
+  return x * q + min(x, r) + b / kNumXCD;
+}
+
 // Real-space geometry.
 struct RealGeom {
   double L[3];
@@ -101,19 +113,26 @@ struct RealGeom {
 struct ParticleSet {
   int64_t n = 0;
   DevBuf<double4> pos;      // sorted: wrapped x,y,z and sigma in w
-  DevBuf<float4> posf;      // sorted: x,y,z relative to the cell origin, sigma (single precision)
+  DevBuf<float4> posf;      // sorted: x, y relative to the cell origin, z (single precision); owner body as int bits
   DevBuf<int> idx;          // sorted slot -> caller index within the set
   DevBuf<int> cell_start;   // ncell + 1
   DevBuf<int> cell_count;   // ncell (scratch)
   DevBuf<int> cell_of;      // caller order (scratch)
   DevBuf<double4> tmp;      // caller order wrapped positions (scratch)
-  DevBuf<int2> chunks;      // pair-traversal work units: (first sorted slot, cell), <= 64 each
+  DevBuf<int4> chunks;      // pair-traversal work units: (first, end sorted slot, first cell, cells), <= 64 each
+  DevBuf<double> qsorted;   // charges in sorted order for the pair passes (scratch)
   int n_chunks = 0;
   // grid tiles overlapped by each particle's support (spreading lists)
   DevBuf<int> tile_start;   // ntile + 1
   DevBuf<int> tile_count;   // ntile (scratch)
   DevBuf<int> tile_entries; // sorted-particle indices, grouped by tile
   int64_t n_entries = 0;
+  // home tile of each particle (the tile holding its first support point):
+  // contraction lists
+  DevBuf<int> home_start;   // ntile + 1
+  DevBuf<int> home_entries; // sorted-particle indices, grouped by home tile
+  DevBuf<int> home_tiles;   // tiles with at least one home particle
+  int n_home_tiles = 0;
 };
 
 // 1-D FFT factorization (radices 8, 4, 2, 3, 5).
@@ -227,6 +246,7 @@ struct Precond {
   std::deque<BodyType> types;
   DevBuf<int> assigned;            // per body: type index
   DevBuf<unsigned char> dense;     // per body: intra-body pairs held by a dense block
+  DevBuf<double> gemm_ws;          // partial tiles of the split per-shape products
 };
 
 // ----------------------------------------------------------------- context
@@ -328,8 +348,10 @@ void make_fft_plan(int n, FFTPlan1D& plan);
 void build_green_tables(pe_context* c);
 
 // real space
+// owner (caller order, may be null): body of each particle, kept as a tag in
+// the single-precision copy
 void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
-                 double sig_const, int64_t n, const RealGeom& rg);
+                 double sig_const, const int* owner, int64_t n, const RealGeom& rg);
 void build_bead_matrix(pe_context* c);
 template <typename T>
 void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const double* dpsi,
@@ -347,9 +369,11 @@ void shape_setup(pe_context* c);
 // y[:, b] (+)= A x[:, b] for the bodies b of one shape: column b is the
 // body's bead segment of x (plus its dPsi entry when bordered, A then
 // (N+1) x (N+1)); accumulate adds into y.
+// ws: workspace of body_gemm_workspace(N, nbt, bordered) doubles.
 template <typename T>
 void launch_body_gemm(hipStream_t s, const T* A, int N, bool bordered, bool accumulate, const int* bodies,
-                      int nbt, const int64_t* off, int64_t n_bead, const double* x, double* y);
+                      int nbt, const int64_t* off, int64_t n_bead, const double* x, double* y, double* ws);
+size_t body_gemm_workspace(int N, int nbt, bool bordered);
 // dense intra-body real-space block of one shape (realspace.hip)
 void build_near_block(hipStream_t s, const BodyType& t, const RealGeom& rg, double* R64, float* R32);
 

@@ -148,7 +148,8 @@ void precond_apply(hipStream_t s, pe_context* c, const double* x, double* z) {
     const T* A;
     if constexpr (sizeof(T) == 8) A = t.Ainv.get();
     else A = t.Ainv32.get();
-    launch_body_gemm<T>(s, A, t.N, true, false, t.dbodies.get(), nbt, c->off.get(), c->n_bead, x, z);
+    launch_body_gemm<T>(s, A, t.N, true, false, t.dbodies.get(), nbt, c->off.get(), c->n_bead, x, z,
+                        c->pc.gemm_ws.get());
   }
 }
 

@@ -149,18 +149,27 @@ __global__ void scatter_cells_kernel(const int* __restrict__ cell_of, int64_t n,
 }
 
 __global__ void gather_sorted_kernel(const double4* __restrict__ tmp, const int* __restrict__ idx,
-                                     int64_t n, RealGeom g, double4* __restrict__ pos,
-                                     float4* __restrict__ posf) {
+                                     const int* __restrict__ owner, int64_t n, RealGeom g,
+                                     double4* __restrict__ pos, float4* __restrict__ posf) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 p = tmp[idx[i]];
   pos[i] = p;
-  // single-precision copy relative to the origin of the particle's cell
-  const double ax = g.L[0] / g.nc[0], ay = g.L[1] / g.nc[1], az = g.L[2] / g.nc[2];
+  // single-precision copy: x and y relative to the origin of the particle's
+  // cell, z as is (cells of one (x, y) column are read as one run)
+  const double ax = g.L[0] / g.nc[0], ay = g.L[1] / g.nc[1];
   const int cx = cell_coord(p.x, g.cell_inv[0], g.nc[0]);
   const int cy = cell_coord(p.y, g.cell_inv[1], g.nc[1]);
-  const int cz = cell_coord(p.z, g.cell_inv[2], g.nc[2]);
-  posf[i] = make_float4((float)(p.x - cx * ax), (float)(p.y - cy * ay), (float)(p.z - cz * az), (float)p.w);
+  const int tag = owner ? owner[idx[i]] : -1;
+  posf[i] = make_float4((float)(p.x - cx * ax), (float)(p.y - cy * ay), (float)p.z, __int_as_float(tag));
+}
+
+// Charges of a set in its sorted (cell) order, so the pair kernels read them
+// without the index indirection.
+__global__ void sort_charges_kernel(const int* __restrict__ idx, const double* __restrict__ q, int64_t n,
+                                    double* __restrict__ qs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) qs[i] = q[idx[i]];
 }
 
 // ------------------------------------------------------------ pair traversal
@@ -168,10 +177,10 @@ __global__ void gather_sorted_kernel(const double4* __restrict__ tmp, const int*
 // One source set of a traversal.
 struct SrcSet {
   const double4* pos;   // sorted by cell: wrapped x, y, z, sigma
-  const float4* posf;   // the same in single precision, relative to the cell origin
+  const float4* posf;   // single precision: x, y relative to the cell origin, z; w: owner tag
   const int* idx;       // sorted slot -> caller index
   const int* start;     // cell_start
-  const double* q;      // charges in caller order (potential passes)
+  const double* q;      // charges in sorted order (potential passes)
 };
 
 // Outputs of a traversal; which ones are used depends on the mode.
@@ -193,24 +202,25 @@ constexpr int kQ = 32;          // queue entries per lane
 constexpr int kQFlush = 16;     // candidates between flushes (kQ - kQFlush entries stay free)
 constexpr int kSetBit = 30;     // queue entry: sorted source index | set << kSetBit
 
-__device__ __forceinline__ float bcast(float v, int k) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
 
 template <int MODE, typename T, typename TF>
 __global__ void __launch_bounds__(256) pair_queue_kernel(
     const double4* __restrict__ tpos, const int* __restrict__ tidx, const int* __restrict__ tstart,
-    const int2* __restrict__ chunks, int nchunk, SrcSet s0, SrcSet s1, int nsrc, RealGeom g, float rc2f,
+    const int4* __restrict__ chunks, int nchunk, SrcSet s0, SrcSet s1, int nsrc, RealGeom g, float rc2f,
     PairOut out) {
   __shared__ int qbuf[kWaves][kQ][64];
+  __shared__ float4 cbuf[kWaves][64];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int w = blockIdx.x * kWaves + wv;
+  const int w = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
   if (w >= nchunk) return;  // whole wavefront; the kernel has no block barrier
-  const int2 ch = chunks[w];
+  // chunk: sorted targets [begin, end) in the cells cell .. cell + nz - 1 of
+  // one (x, y) column
+  const int4 ch = chunks[w];
   const int begin = __builtin_amdgcn_readfirstlane(ch.x);
-  const int cell = __builtin_amdgcn_readfirstlane(ch.y);
-  const int end = min(begin + 64, tstart[cell + 1]);
+  const int end = __builtin_amdgcn_readfirstlane(ch.y);
+  const int cell = __builtin_amdgcn_readfirstlane(ch.z);
+  const int nz = __builtin_amdgcn_readfirstlane(ch.w);
   const int t = begin + lane;
   const bool active = t < end;
   const double4 p = tpos[active ? t : begin];
@@ -219,7 +229,7 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   const bool per_pair_image = nc0 < 3 || nc1 < 3 || nc2 < 3;
   const int rx = nc0 >= 3 ? 1 : 0, ry = nc1 >= 3 ? 1 : 0, rz = nc2 >= 3 ? 1 : 0;
   const float Lf0 = (float)g.L[0], Lf1 = (float)g.L[1], Lf2 = (float)g.L[2];
-  const double a0 = g.L[0] / nc0, a1 = g.L[1] / nc1, a2 = g.L[2] / nc2;
+  const double a0 = g.L[0] / nc0, a1 = g.L[1] / nc1;
   int (*qb)[64] = qbuf[wv];
   int pushed = 0, popped = 0;
 
@@ -249,9 +259,6 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     dz -= g.L[2] * rint(dz * g.inv_L[2]);
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 < g.rc2)) return;
-    if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) {
-      if (own_body >= 0 && out.body_of[s0.idx[sidx]] == own_body) return;
-    }
     if constexpr (MODE == MODE_COUNT) {
       ++cnt;
       return;
@@ -274,8 +281,7 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
       }
       return;
     }
-    const int ci = set ? s1.idx[sidx] : s0.idx[sidx];
-    const double qd = set ? s1.q[ci] : s0.q[ci];
+    const double qd = set ? s1.q[sidx] : s0.q[sidx];
     if (r2 == 0.0) {
       acc += self_value<T>((T)s2, g) * (T)qd;
       return;
@@ -300,75 +306,98 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     }
   };
 
-  // The candidate stream: for each source set, the stencil cells in order,
-  // each read in batches of up to 64 (one per lane), tested in groups of
-  // kQFlush.  After every group the queues are drained: as many rounds as
-  // keep every lane busy, and at least enough that kQFlush more pushes cannot
-  // overflow any queue; after the last group, everything left.  (One drain
-  // site, so the pair evaluation is emitted once.)
-  const int sx = 2 * rx + 1, sy = 2 * ry + 1, sz = 2 * rz + 1;
-  const int n_open = nsrc * sx * sy * sz;
-  int it = 0;                  // next stencil cell to open
-  int base = 0, ce = 0;        // unread range of the open cell
+  // The candidate stream: for each source set and each (x, y) column of the
+  // stencil, the run of stencil cells along z (contiguous in the sorted
+  // order; a second run holds the cell reached through the periodic wrap in
+  // z), read in batches of up to 64 staged in LDS and tested in unrolled
+  // groups of kQFlush (the batch is padded with NaN points, which never hit).
+  // After every group the queues are drained: as many rounds as keep every
+  // lane busy, and at least enough that kQFlush more pushes cannot overflow
+  // any queue; after the last group, everything left.  (One drain site, so
+  // the pair evaluation is emitted once.)
+  float4* cb = cbuf[wv];
+  const int sx = 2 * rx + 1, sy = 2 * ry + 1;
+  const int n_open = nsrc * sx * sy * 2;
+  int it = 0;                  // next (set, x, y, run) to open
+  int base = 0, ce = 0;        // unread range of the open run
   int bbase = 0, nbat = 0, k0 = 0;
-  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
   float px = 0.f, py = 0.f, pz = 0.f;
   int tag = 0;
-  const float* Sf = nullptr;
+  const float4* Sf = nullptr;
+  const float nanf_ = __int_as_float(0x7fc00000);
   for (;;) {
     bool finished = false;
     if (k0 >= nbat) {
       while (base >= ce && it < n_open) {
-        const int set = it / (sx * sy * sz);
-        const int rem = it - set * (sx * sy * sz);
-        const int ox = rem / (sy * sz) - rx, oy = (rem / sz) % sy - ry, oz = rem % sz - rz;
+        const int set = it / (sx * sy * 2);
+        const int rem = it - set * (sx * sy * 2);
+        const int ox = rem / (sy * 2) - rx, oy = (rem >> 1) % sy - ry, run = rem & 1;
         ++it;
         const SrcSet& S = set ? s1 : s0;
-        int x = cx + ox, y = cy + oy, z = cz + oz;
+        int x = cx + ox, y = cy + oy;
         double shx = 0, shy = 0, shz = 0;
         if (x < 0) { x += nc0; shx = -g.L[0]; }
         if (x >= nc0) { x -= nc0; shx = g.L[0]; }
         if (y < 0) { y += nc1; shy = -g.L[1]; }
         if (y >= nc1) { y -= nc1; shy = g.L[1]; }
-        if (z < 0) { z += nc2; shz = -g.L[2]; }
-        if (z >= nc2) { z -= nc2; shz = g.L[2]; }
-        const int c = (x * nc1 + y) * nc2 + z;
-        base = __builtin_amdgcn_readfirstlane(S.start[c]);
-        ce = __builtin_amdgcn_readfirstlane(S.start[c + 1]);
-        // target relative to the origin of the source cell's image
+        int z0 = 0, z1 = 0;
+        if (rz == 0) {
+          if (run == 0) { z0 = cz; z1 = cz + 1; }
+        } else if (run == 0) {
+          z0 = max(cz - 1, 0);
+          z1 = min(cz + nz + 1, nc2);
+        } else if (cz == 0) {
+          z0 = nc2 - 1; z1 = nc2; shz = -g.L[2];
+        } else if (cz + nz == nc2) {
+          z0 = 0; z1 = 1; shz = g.L[2];
+        }
+        const int c0 = (x * nc1 + y) * nc2;
+        base = __builtin_amdgcn_readfirstlane(S.start[c0 + z0]);
+        ce = __builtin_amdgcn_readfirstlane(S.start[c0 + z1]);
+        // target relative to the source cell column's origin (x, y) and to
+        // the image of the run (z)
         px = (float)(p.x - shx - x * a0);
         py = (float)(p.y - shy - y * a1);
-        pz = (float)(p.z - shz - z * a2);
+        pz = (float)(p.z - shz);
         tag = set << kSetBit;
-        Sf = reinterpret_cast<const float*>(S.posf);
+        Sf = S.posf;
       }
       if (base < ce) {
         nbat = min(64, ce - base);
         bbase = base;
         base += nbat;
         k0 = 0;
-        v = lane < nbat ? reinterpret_cast<const float4*>(Sf)[bbase + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+        cb[lane] = lane < nbat ? Sf[bbase + lane] : make_float4(nanf_, nanf_, nanf_, nanf_);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       } else {
         finished = true;
       }
     }
     if (!finished) {
-      const int kend = min(k0 + kQFlush, nbat);
-      for (int k = k0; k < kend; ++k) {
-        float dx = px - bcast(v.x, k);
-        float dy = py - bcast(v.y, k);
-        float dz = pz - bcast(v.z, k);
+#pragma unroll
+      for (int kk = 0; kk < kQFlush; ++kk) {
+        const float4 cnd = cb[k0 + kk];
+        float dx = px - cnd.x;
+        float dy = py - cnd.y;
+        float dz = pz - cnd.z;
         if (per_pair_image) {
           dx -= Lf0 * rintf(dx / Lf0);
           dy -= Lf1 * rintf(dy / Lf1);
           dz -= Lf2 * rintf(dz / Lf2);
         }
         const float r2 = dx * dx + dy * dy + dz * dz;
+        bool hit = active && r2 < rc2f;
+        if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) {
+          // pairs inside a body with a dense intra-body block are not listed
+          hit = hit && (own_body < 0 || __float_as_int(cnd.w) != own_body);
+        }
         // the slot at pushed is free (at most kQ - 1 entries pending)
-        qb[pushed & (kQ - 1)][lane] = (bbase + k) | tag;
-        pushed += (active && r2 < rc2f) ? 1 : 0;
+        qb[pushed & (kQ - 1)][lane] = (bbase + k0 + kk) | tag;
+        pushed += hit ? 1 : 0;
       }
-      k0 = kend;
+      k0 += kQFlush;
     }
     const int pend = pushed - popped;
     int mn = active ? pend : 1 << 30, mx = pend;
@@ -440,18 +469,18 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 }  // namespace
 
 // Cutoff of the single-precision candidate test: r_c enlarged by more than
-// the rounding of the cell-relative float coordinates (|x| <= 2 cell edges),
-// so no pair inside r_c is missed; the exact test is redone in double.
+// the rounding of the float coordinates (at most a box length in size), so
+// no pair inside r_c is missed; the exact test is redone in double.
 float candidate_rc2(const RealGeom& g) {
-  double amax = 0;
-  for (int d = 0; d < 3; ++d) amax = std::max(amax, g.L[d] / g.nc[d]);
+  double lmax = 0;
+  for (int d = 0; d < 3; ++d) lmax = std::max(lmax, g.L[d]);
   const double rc = std::sqrt(g.rc2);
-  const double rcf = rc * (1.0 + 1e-5) + 16.0 * amax * std::ldexp(1.0, -24);
+  const double rcf = rc * (1.0 + 1e-5) + 16.0 * lmax * std::ldexp(1.0, -24);
   return (float)(rcf * rcf);
 }
 
 void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
-                 double sig_const, int64_t n, const RealGeom& rg) {
+                 double sig_const, const int* owner, int64_t n, const RealGeom& rg) {
   ps.n = n;
   const int ncell = rg.nc[0] * rg.nc[1] * rg.nc[2];
   ps.pos.ensure(n);
@@ -471,14 +500,28 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   PE_HIP(hipMemcpyAsync(cnt.data(), ps.cell_count.get(), sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
   for (int c = 0; c < ncell; ++c) start[c + 1] = start[c] + cnt[c];
-  // traversal work units: runs of at most 64 particles of one cell
-  std::vector<int2> chunks;
-  for (int c = 0; c < ncell; ++c)
-    for (int b = start[c]; b < start[c + 1]; b += 64) chunks.push_back(make_int2(b, c));
+  // traversal work units: at most 64 particles; a cell with more is split,
+  // and two neighbouring cells of one z column with 64 or fewer together
+  // share a unit (when the column has room for the wider stencil), so sparse
+  // cells do not leave most lanes of a wavefront idle
+  std::vector<int4> chunks;
+  const bool merge = rg.nc[2] >= 6;
+  for (int c = 0; c < ncell;) {
+    const int n0 = cnt[c];
+    if (n0 == 0) { ++c; continue; }
+    const int z = c % rg.nc[2];
+    if (merge && n0 < 64 && z + 1 < rg.nc[2] && n0 + cnt[c + 1] <= 64 && cnt[c + 1] > 0) {
+      chunks.push_back(make_int4(start[c], start[c + 2], c, 2));
+      c += 2;
+      continue;
+    }
+    for (int b = start[c]; b < start[c + 1]; b += 64) chunks.push_back(make_int4(b, std::min(b + 64, start[c + 1]), c, 1));
+    ++c;
+  }
   ps.n_chunks = (int)chunks.size();
   ps.chunks.ensure(std::max<int64_t>(ps.n_chunks, 1));
   if (ps.n_chunks)
-    PE_HIP(hipMemcpyAsync(ps.chunks.get(), chunks.data(), sizeof(int2) * ps.n_chunks, hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(ps.chunks.get(), chunks.data(), sizeof(int4) * ps.n_chunks, hipMemcpyHostToDevice, s));
   PE_HIP(hipMemcpyAsync(ps.cell_start.get(), start.data(), sizeof(int) * (ncell + 1), hipMemcpyHostToDevice, s));
   // cursor = start (reuse cell_count)
   PE_HIP(hipMemcpyAsync(ps.cell_count.get(), start.data(), sizeof(int) * ncell, hipMemcpyHostToDevice, s));
@@ -490,7 +533,7 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
     // it) is the same on every run
     launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get());
     hipLaunchKernelGGL(gather_sorted_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.tmp.get(),
-                       ps.idx.get(), n, rg, ps.pos.get(), ps.posf.get());
+                       ps.idx.get(), owner, n, rg, ps.pos.get(), ps.posf.get());
     PE_CHECK_LAUNCH();
   }
   // the host vectors go out of scope after the copies above complete
@@ -499,8 +542,8 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
 
 namespace {
 
-SrcSet src_of(const ParticleSet& ps, const double* q) {
-  return SrcSet{ps.pos.get(), ps.posf.get(), ps.idx.get(), ps.cell_start.get(), q};
+SrcSet src_of(const ParticleSet& ps, const double* qsorted) {
+  return SrcSet{ps.pos.get(), ps.posf.get(), ps.idx.get(), ps.cell_start.get(), qsorted};
 }
 
 template <int MODE, typename T, typename TF>
@@ -620,8 +663,16 @@ void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet*
   if (!src0) return;
   require(src0->n < (int64_t(1) << kSetBit) && (!src1 || src1->n < (int64_t(1) << kSetBit)),
           "too many particles in one set for the pair traversal");
-  const SrcSet a = src_of(*src0, q0);
-  const SrcSet b = src1 ? src_of(*src1, q1) : a;
+  auto sorted_q = [&](const ParticleSet& ps, const double* q) {
+    ParticleSet& m = const_cast<ParticleSet&>(ps);
+    m.qsorted.ensure(std::max<int64_t>(ps.n, 1));
+    hipLaunchKernelGGL(sort_charges_kernel, dim3(nblk(ps.n, 256)), dim3(256), 0, s, ps.idx.get(), q, ps.n,
+                       m.qsorted.get());
+    PE_CHECK_LAUNCH();
+    return m.qsorted.get();
+  };
+  const SrcSet a = src_of(*src0, sorted_q(*src0, q0));
+  const SrcSet b = src1 ? src_of(*src1, sorted_q(*src1, q1)) : a;
   const int nsrc = src1 ? 2 : 1;
   PairOut out{};
   out.phi = phi;

@@ -59,25 +59,55 @@ __global__ void __launch_bounds__(256) match_kernel(const double* __restrict__ r
   if (threadIdx.x == 0 && bad == 0) assigned[b] = type_id;
 }
 
-// Tiled product for the bodies of one shape: 32 x 32 output tiles (rows of A
-// x bodies), K staged through LDS 64 at a time, the next chunk's loads issued
-// before the current chunk's products so they are in flight meanwhile.
-// Thread (tx, ty) owns rows {ty, ty + 16} and columns {tx, tx + 16}.
-constexpr int kGM = 32, kGN = 32, kGK = 64, kGLoads = kGK * kGM / 256;
+// Tiled product for the bodies of one shape on the matrix cores (a dense
+// contraction: every entry of A meets every body): 64 x 64 output tiles (rows
+// of A x bodies) per workgroup, a 32 x 32 quarter per wavefront made of 2 x 2
+// MFMA 16 x 16 x 4 blocks (fp32: v_mfma_f32_16x16x4f32, fp64:
+// v_mfma_f64_16x16x4f64).  K is staged through LDS 32 at a time; the next
+// chunk's global loads are issued before the current chunk's products.
+// Operand layout (one wavefront): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; it receives D[4 (l / 16) + i][l % 16] in register i for
+// fp32, and D[4 i + l / 16][l % 16] for fp64 (row groups of one), i = 0..3.
+constexpr int kGM = 64, kGN = 64, kGK = 32, kGPad = kGM + 1, kGLoads = kGK * kGM / 256;
 
-template <typename T, bool BORDER, bool ACCUM>
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<float> {
+  using type = f32x4_t;
+  static __device__ __forceinline__ type step(float a, float b, type c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct MfmaAcc<double> {
+  using type = f64x4_t;
+  static __device__ __forceinline__ type step(double a, double b, type c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// K is split over gridDim.z workgroups (enough workgroups to fill the chip
+// even for one shape); each writes its partial tile to part[z][row][body],
+// summed in a fixed order by body_gemm_reduce_kernel.
+template <typename T, bool BORDER>
 __global__ void __launch_bounds__(256) body_gemm_kernel(const T* __restrict__ A, int N,
                                                         const int* __restrict__ bodies, int nbt,
                                                         const int64_t* __restrict__ off, int64_t n_bead,
-                                                        const double* __restrict__ x, double* __restrict__ y) {
+                                                        const double* __restrict__ x, int kspan,
+                                                        T* __restrict__ part) {
+  using Acc = typename MfmaAcc<T>::type;
   const int Np = BORDER ? N + 1 : N;
-  __shared__ T As[kGK][kGM + 1];
-  __shared__ T Xs[kGK][kGN + 1];
+  const int kbeg = blockIdx.z * kspan;
+  const int kend = min(Np, kbeg + kspan);
+  __shared__ T As[kGK][kGPad];   // As[k][row]
+  __shared__ T Xs[kGK][kGPad];   // Xs[k][col]
   __shared__ int64_t boff[kGN];
   __shared__ int64_t bpsi[kGN];
   const int row0 = blockIdx.x * kGM;
   const int col0 = blockIdx.y * kGN;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;  // the wavefront's quarter
   if (threadIdx.x < kGN) {
     const int b = col0 + threadIdx.x;
     if (b < nbt) {
@@ -98,15 +128,20 @@ __global__ void __launch_bounds__(256) body_gemm_kernel(const T* __restrict__ A,
       const int e = threadIdx.x + 256 * i;
       const int kk = e % kGK, r = e / kGK;
       const int gr = row0 + r, gk = k0 + kk;
-      ra[i] = (gr < Np && gk < Np) ? A[(int64_t)gr * Np + gk] : (T)0;
+      ra[i] = (gr < Np && gk < kend) ? A[(int64_t)gr * Np + gk] : (T)0;
       T v = 0;
-      if (boff[r] >= 0 && gk < Np) v = (T)((!BORDER || gk < N) ? x[boff[r] + gk] : x[bpsi[r]]);
+      if (boff[r] >= 0 && gk < kend) v = (T)((!BORDER || gk < N) ? x[boff[r] + gk] : x[bpsi[r]]);
       rx[i] = v;
     }
   };
-  T acc[2][2] = {{0, 0}, {0, 0}};
-  load(0);
-  for (int k0 = 0; k0 < Np; k0 += kGK) {
+  Acc acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+  const int li = lane & 15, lk = lane >> 4;
+  load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kGK) {
 #pragma unroll
     for (int i = 0; i < kGLoads; ++i) {
       const int e = threadIdx.x + 256 * i;
@@ -115,30 +150,44 @@ __global__ void __launch_bounds__(256) body_gemm_kernel(const T* __restrict__ A,
       Xs[kk][r] = rx[i];
     }
     __syncthreads();
-    if (k0 + kGK < Np) load(k0 + kGK);
-#pragma unroll 16
-    for (int kk = 0; kk < kGK; ++kk) {
-      const T a0 = As[kk][ty], a1 = As[kk][ty + 16];
-      const T b0 = Xs[kk][tx], b1 = Xs[kk][tx + 16];
-      acc[0][0] += a0 * b0;
-      acc[0][1] += a0 * b1;
-      acc[1][0] += a1 * b0;
-      acc[1][1] += a1 * b1;
+    if (k0 + kGK < kend) load(k0 + kGK);
+#pragma unroll
+    for (int ks = 0; ks < kGK; ks += 4) {
+      const T a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
+      const T b0 = Xs[ks + lk][wc + li], b1 = Xs[ks + lk][wc + 16 + li];
+      acc[0][0] = MfmaAcc<T>::step(a0, b0, acc[0][0]);
+      acc[0][1] = MfmaAcc<T>::step(a0, b1, acc[0][1]);
+      acc[1][0] = MfmaAcc<T>::step(a1, b0, acc[1][0]);
+      acc[1][1] = MfmaAcc<T>::step(a1, b1, acc[1][1]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const int gr = row0 + ty + 16 * p;
-    if (gr >= Np) continue;
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int cc = tx + 16 * q;
-      if (boff[cc] < 0) continue;
-      const int64_t o = (!BORDER || gr < N) ? boff[cc] + gr : bpsi[cc];
-      y[o] = ACCUM ? y[o] + (double)acc[p][q] : (double)acc[p][q];
-    }
-  }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = row0 + wr + 16 * a + (sizeof(T) == 8 ? 4 * i + lk : 4 * lk + i);
+        const int cb = col0 + wc + 16 * b + li;
+        if (gr >= Np || cb >= nbt) continue;
+        part[((int64_t)blockIdx.z * Np + gr) * nbt + cb] = acc[a][b][i];
+      }
+}
+
+template <typename T, bool BORDER, bool ACCUM>
+__global__ void body_gemm_reduce_kernel(const T* __restrict__ part, int nsplit, int N, int nbt,
+                                        const int* __restrict__ bodies, const int64_t* __restrict__ off,
+                                        int64_t n_bead, double* __restrict__ y) {
+  const int Np = BORDER ? N + 1 : N;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)Np * nbt) return;
+  const int gr = (int)(e / nbt), cb = (int)(e - (int64_t)gr * nbt);
+  double v = 0;
+  for (int z = 0; z < nsplit; ++z) v += (double)part[((int64_t)z * Np + gr) * nbt + cb];
+  const int body = bodies[cb];
+  const int64_t o = (!BORDER || gr < N) ? off[body] + gr : n_bead + body;
+  y[o] = ACCUM ? y[o] + v : v;
 }
 
 double dist3(const double* a, const double* b) {
@@ -281,33 +330,66 @@ void shape_setup(pe_context* c) {
     if (t.near)
       for (int b : t.bodies) dense[b] = 1;
   }
+  // workspace of the split products (in doubles; float partials use half)
+  size_t ws = 1;
+  for (auto& t : pc.types)
+    if (!t.bodies.empty())
+      ws = std::max({ws, body_gemm_workspace(t.N, (int)t.bodies.size(), true),
+                     body_gemm_workspace(t.N, (int)t.bodies.size(), false)});
+  pc.gemm_ws.ensure(ws);
   PE_HIP(hipMemcpyAsync(pc.dense.get(), dense.data(), nbody, hipMemcpyHostToDevice, s));
   PE_HIP(hipStreamSynchronize(s));
 }
 
+int body_gemm_splits(int N, int nbt, bool bordered) {
+  const int Np = bordered ? N + 1 : N;
+  const int tiles = ((Np + kGM - 1) / kGM) * ((nbt + kGN - 1) / kGN);
+  const int chunks = (Np + kGK - 1) / kGK;
+  int z = (1024 + tiles - 1) / tiles;  // aim at about a thousand workgroups
+  z = std::min(z, std::max(1, chunks / 2));  // at least two K chunks each
+  return std::max(1, std::min(z, 8));
+}
+
+size_t body_gemm_workspace(int N, int nbt, bool bordered) {
+  const int Np = bordered ? N + 1 : N;
+  return (size_t)body_gemm_splits(N, nbt, bordered) * Np * nbt;
+}
+
 template <typename T>
 void launch_body_gemm(hipStream_t s, const T* A, int N, bool bordered, bool accumulate, const int* bodies,
-                      int nbt, const int64_t* off, int64_t n_bead, const double* x, double* y) {
+                      int nbt, const int64_t* off, int64_t n_bead, const double* x, double* y, double* ws) {
   if (nbt == 0 || N == 0) return;
+  require(!(bordered && accumulate), "bordered product overwrites");
   const int Np = bordered ? N + 1 : N;
-  const dim3 grid((unsigned)((Np + kGM - 1) / kGM), (unsigned)((nbt + kGN - 1) / kGN));
-  if (bordered) {
-    require(!accumulate, "bordered product overwrites");
-    hipLaunchKernelGGL((body_gemm_kernel<T, true, false>), grid, dim3(256), 0, s, A, N, bodies, nbt, off, n_bead,
-                       x, y);
-  } else if (accumulate) {
-    hipLaunchKernelGGL((body_gemm_kernel<T, false, true>), grid, dim3(256), 0, s, A, N, bodies, nbt, off, n_bead,
-                       x, y);
-  } else {
-    hipLaunchKernelGGL((body_gemm_kernel<T, false, false>), grid, dim3(256), 0, s, A, N, bodies, nbt, off, n_bead,
-                       x, y);
-  }
+  const int nz = body_gemm_splits(N, nbt, bordered);
+  const int chunks = (Np + kGK - 1) / kGK;
+  const int kspan = ((chunks + nz - 1) / nz) * kGK;
+  T* part = reinterpret_cast<T*>(ws);
+  const dim3 grid((unsigned)((Np + kGM - 1) / kGM), (unsigned)((nbt + kGN - 1) / kGN), (unsigned)nz);
+  if (bordered)
+    hipLaunchKernelGGL((body_gemm_kernel<T, true>), grid, dim3(256), 0, s, A, N, bodies, nbt, off, n_bead, x,
+                       kspan, part);
+  else
+    hipLaunchKernelGGL((body_gemm_kernel<T, false>), grid, dim3(256), 0, s, A, N, bodies, nbt, off, n_bead, x,
+                       kspan, part);
+  PE_CHECK_LAUNCH();
+  const int64_t ne = (int64_t)Np * nbt;
+  const dim3 rg((unsigned)((ne + 255) / 256));
+  if (bordered)
+    hipLaunchKernelGGL((body_gemm_reduce_kernel<T, true, false>), rg, dim3(256), 0, s, part, nz, N, nbt, bodies, off,
+                       n_bead, y);
+  else if (accumulate)
+    hipLaunchKernelGGL((body_gemm_reduce_kernel<T, false, true>), rg, dim3(256), 0, s, part, nz, N, nbt, bodies,
+                       off, n_bead, y);
+  else
+    hipLaunchKernelGGL((body_gemm_reduce_kernel<T, false, false>), rg, dim3(256), 0, s, part, nz, N, nbt, bodies,
+                       off, n_bead, y);
   PE_CHECK_LAUNCH();
 }
 
 template void launch_body_gemm<float>(hipStream_t, const float*, int, bool, bool, const int*, int, const int64_t*,
-                                      int64_t, const double*, double*);
+                                      int64_t, const double*, double*, double*);
 template void launch_body_gemm<double>(hipStream_t, const double*, int, bool, bool, const int*, int, const int64_t*,
-                                       int64_t, const double*, double*);
+                                       int64_t, const double*, double*, double*);
 
 }  // namespace pe

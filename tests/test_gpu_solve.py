@@ -266,6 +266,10 @@ def test_block_preconditioner_same_solution_fewer_iterations(gpu_lib):
     q0, i0 = out[(0, gpu_lib.PE_FP64)]
     for key, (q, info) in out.items():
         assert info["rel_residual"] <= 1e-10
-        assert np.linalg.norm(q - q0) <= 1e-7 * np.linalg.norm(q0), key
+        # mixed precision forms the right-hand side (ion potential at the
+        # beads) in single precision like every other sum, so it solves a
+        # system whose data differ at the float level: the float bound
+        bound = 1e-7 if key[1] == gpu_lib.PE_FP64 else 2e-6
+        assert np.linalg.norm(q - q0) <= bound * np.linalg.norm(q0), key
     print({k: v[1]["iters"] for k, v in out.items()})
     assert out[(1, gpu_lib.PE_FP64)][1]["iters"] < 0.5 * i0["iters"]
