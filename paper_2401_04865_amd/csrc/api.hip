@@ -550,6 +550,12 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
   if (c->p.inner_tol <= 0) c->p.inner_tol = 1e-4;
   if (c->p.max_refine <= 0) c->p.max_refine = 8;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  {
+    int dev = 0, lds = 0;
+    PE_HIP(hipGetDevice(&dev));
+    PE_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    c->lds_per_block = lds;
+  }
   pe::FFTPlan1D tmp;
   for (int d = 0; d < 3; ++d) make_fft_plan(p.mesh[d], tmp);
   compute_params(c);

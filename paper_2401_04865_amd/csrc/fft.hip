@@ -17,6 +17,7 @@
 // double.  A block transforms several lines at once; lines of the strided
 // passes are taken along the contiguous kz / (y,kz) index so global loads
 // and stores are coalesced.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -115,20 +116,44 @@ __device__ __forceinline__ void butterfly(C (&v)[R], int fwd) {
   }
 }
 
-// One Stockham stage of radix R over nl lines of length n (line stride ls).
+// Position of element j of line `line` in an LDS buffer: lines `ls` apart,
+// and the low bits of j XORed with the line number (a bijection within each
+// line when n is a multiple of smask + 1), so that reading one element of
+// many lines at once, as the strided passes do, hits different banks even
+// without padding the lines.
+struct LdsLayout {
+  int ls;
+  int smask;
+  __device__ __forceinline__ int at(int line, int j) const { return line * ls + (j ^ (line & smask)); }
+};
+
+// One Stockham stage of radix R over nl lines of length n.  When n is a
+// power of two (so are nb = n / R and Ns), the index splits use shifts and
+// masks instead of integer division.
 template <typename T, typename C, int R>
 __device__ __forceinline__ void stockham_stage(const C* __restrict__ in, C* __restrict__ out, int n, int nl,
-                                               int ls, int Ns, const C* __restrict__ tw, int fwd) {
+                                               LdsLayout L, int Ns, const C* __restrict__ tw, int fwd) {
   const int nb = n / R;
   const int tws = n / (Ns * R);
+  const bool pow2 = (n & (n - 1)) == 0;
+  const int lnb = pow2 ? __builtin_ctz(nb) : 0;
+  const int lns = pow2 ? __builtin_ctz(Ns) : 0;
   for (int t = threadIdx.x; t < nl * nb; t += blockDim.x) {
-    const int line = t / nb;
-    const int j = t - line * nb;
-    const int k = j % Ns;
+    int line, j, k, jq;
+    if (pow2) {
+      line = t >> lnb;
+      j = t & (nb - 1);
+      k = j & (Ns - 1);
+      jq = j >> lns;
+    } else {
+      line = t / nb;
+      j = t - line * nb;
+      jq = j / Ns;
+      k = j - jq * Ns;
+    }
     C v[R];
-    const C* src = in + line * ls;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+    for (int r = 0; r < R; ++r) v[r] = in[L.at(line, j + r * nb)];
     if (Ns > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
@@ -138,17 +163,16 @@ __device__ __forceinline__ void stockham_stage(const C* __restrict__ in, C* __re
       }
     }
     butterfly<T, C, R>(v, fwd);
-    C* dst = out + line * ls;
-    const int base = (j / Ns) * Ns * R + k;
+    const int base = jq * Ns * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+    for (int r = 0; r < R; ++r) out[L.at(line, base + r * Ns)] = v[r];
   }
 }
 
-// Transform `nl` lines of length n held in LDS (`in`, line stride ls).
+// Transform `nl` lines of length n held in LDS (`in`, layout L).
 // Returns the buffer that holds the result (in or out).
 template <typename T, typename C>
-__device__ C* lds_fft(C* in, C* out, int n, int nl, int ls, const FFTPlan1D& plan,
+__device__ C* lds_fft(C* in, C* out, int n, int nl, LdsLayout ls, const FFTPlan1D& plan,
                       const C* __restrict__ tw, int fwd) {
   int Ns = 1;
   for (int s = 0; s < plan.nstage; ++s) {
@@ -186,7 +210,7 @@ struct ScaleArgs {
 // Lines along a strided axis: line L (0..nlines-1), element j at
 // base(L) + j*stride, base(L) = (L / inner) * outer + (L % inner).
 template <typename T, bool SCALE>
-__global__ void __launch_bounds__(256) fft_lines_kernel(typename C2<T>::type* __restrict__ data, int n,
+__global__ void __launch_bounds__(512) fft_lines_kernel(typename C2<T>::type* __restrict__ data, int n,
                                                         int64_t nlines, int64_t inner, int64_t outer,
                                                         int64_t stride, int lpb, FFTPlan1D plan,
                                                         const typename C2<T>::type* __restrict__ tw,
@@ -196,8 +220,8 @@ __global__ void __launch_bounds__(256) fft_lines_kernel(typename C2<T>::type* __
   __shared__ int64_t lbase[64];
   __shared__ T lfac[64], lksq[64];
   C* b0 = reinterpret_cast<C*>(smem_raw);
-  const int ls = n + 1;
-  C* b1 = b0 + lpb * ls;
+  const LdsLayout ll{n, (n % 16 == 0) ? 15 : ((n % 8 == 0) ? 7 : ((n % 4 == 0) ? 3 : ((n % 2 == 0) ? 1 : 0)))};
+  C* b1 = b0 + lpb * n;
   const int64_t L0 = (int64_t)blockIdx.x * lpb;
   if ((int)threadIdx.x < lpb) {
     const int64_t L = L0 + threadIdx.x;
@@ -212,15 +236,16 @@ __global__ void __launch_bounds__(256) fft_lines_kernel(typename C2<T>::type* __
   }
   __syncthreads();
   const int nvalid = (int)min<int64_t>((int64_t)lpb, nlines - L0);
+  const int llpb = __builtin_ctz(lpb);  // lpb is a power of two
   for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
-    const int j = t / lpb;
-    const int c = t - j * lpb;
+    const int j = t >> llpb;
+    const int c = t & (lpb - 1);
     C v = {0, 0};
     if (c < nvalid) v = data[lbase[c] + (int64_t)j * stride];
-    b0[c * ls + j] = v;
+    b0[ll.at(c, j)] = v;
   }
   __syncthreads();
-  C* res = lds_fft<T, C>(b0, b1, n, lpb, ls, plan, tw, fwd);
+  C* res = lds_fft<T, C>(b0, b1, n, lpb, ll, plan, tw, fwd);
   if (SCALE) {
     for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
       const int c = t / n;
@@ -228,17 +253,17 @@ __global__ void __launch_bounds__(256) fft_lines_kernel(typename C2<T>::type* __
       if (c >= nvalid) continue;
       const T k2 = (T)sa.kx2[j] + lksq[c];
       const T gk = k2 > (T)0 ? (T)sa.ex[j] * lfac[c] / k2 : (T)0;
-      C v = res[c * ls + j];
-      res[c * ls + j] = {v.x * gk, v.y * gk};
+      C v = res[ll.at(c, j)];
+      res[ll.at(c, j)] = {v.x * gk, v.y * gk};
     }
     __syncthreads();
     C* other = (res == b0) ? b1 : b0;
-    res = lds_fft<T, C>(res, other, n, lpb, ls, plan, tw, -fwd);
+    res = lds_fft<T, C>(res, other, n, lpb, ll, plan, tw, -fwd);
   }
   for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
-    const int j = t / lpb;
-    const int c = t - j * lpb;
-    if (c < nvalid) data[lbase[c] + (int64_t)j * stride] = res[c * ls + j];
+    const int j = t >> llpb;
+    const int c = t & (lpb - 1);
+    if (c < nvalid) data[lbase[c] + (int64_t)j * stride] = res[ll.at(c, j)];
   }
 }
 
@@ -265,7 +290,7 @@ __global__ void __launch_bounds__(256) fft_z_r2c_kernel(const T* __restrict__ re
     b0[c * ls + j] = {a, b};
   }
   __syncthreads();
-  C* res = lds_fft<T, C>(b0, b1, Nz, ppb, ls, plan, tw, 1);
+  C* res = lds_fft<T, C>(b0, b1, Nz, ppb, LdsLayout{ls, 0}, plan, tw, 1);
   for (int t = threadIdx.x; t < Nzc * ppb; t += blockDim.x) {
     const int c = t / Nzc;
     const int k = t - c * Nzc;
@@ -309,7 +334,7 @@ __global__ void __launch_bounds__(256) fft_z_c2r_kernel(const typename C2<T>::ty
     b0[c * ls + k] = {A.x - Bv.y, A.y + Bv.x};  // A + i B
   }
   __syncthreads();
-  C* res = lds_fft<T, C>(b0, b1, Nz, ppb, ls, plan, tw, -1);
+  C* res = lds_fft<T, C>(b0, b1, Nz, ppb, LdsLayout{ls, 0}, plan, tw, -1);
   for (int t = threadIdx.x; t < Nz * ppb; t += blockDim.x) {
     const int c = t / Nz;
     const int j = t - c * Nz;
@@ -323,6 +348,18 @@ __global__ void __launch_bounds__(256) fft_z_c2r_kernel(const typename C2<T>::ty
 // About 2048 complex values per block (8 per thread) so a pass launches
 // many blocks; two ping-pong LDS buffers of (n+1) values per line must fit
 // the budget.
+// Strided passes: up to 4096 values per block, as many lines as fit (a power
+// of two, so the contiguous index is read in aligned runs of 128 bytes or
+// more); two unpadded LDS buffers must fit the budget.
+inline int strided_lines_per_block(int n, size_t elem, size_t lds_budget) {
+  int cap = 4096 / n;
+  const int lds_cap = (int)(lds_budget / (2 * (size_t)n * elem));
+  if (lds_cap < cap) cap = lds_cap;
+  int l = 1;
+  while (2 * l <= cap && 2 * l <= 64) l *= 2;
+  return l;
+}
+
 inline int lines_per_block(int n, size_t elem, size_t lds_budget) {
   int l = 2048 / n;
   const int cap = (int)(lds_budget / (2 * (size_t)(n + 1) * elem));
@@ -387,6 +424,9 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
     twx = c->tw32[0].get(); twy = c->tw32[1].get(); twz = c->tw32[2].get();
   }
   const size_t budget = 64 * 1024;
+  // strided passes: what the device allows per workgroup, less the static
+  // per-line tables (64-line maximum)
+  const size_t sbudget = std::min<size_t>((size_t)c->lds_per_block, 80 * 1024) - 2048;
   // 1. z, r2c
   {
     ProfScope ps(c->prof, s, PE_PROF_FFT_Z_R2C, sizeof(T) == 8);
@@ -413,10 +453,10 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   auto ypass = [&](int fwd) {
     ProfScope ps(c->prof, s, fwd > 0 ? PE_PROF_FFT_Y_FWD : PE_PROF_FFT_Y_INV, sizeof(T) == 8);
     const int64_t nlines = (int64_t)Nx * Nzc;
-    const int lpb = lines_per_block(Ny, sizeof(C), budget);
+    const int lpb = strided_lines_per_block(Ny, sizeof(C), sbudget);
     const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
-    const size_t sh = 2 * (size_t)lpb * (Ny + 1) * sizeof(C);
-    hipLaunchKernelGGL((fft_lines_kernel<T, false>), dim3(nb), dim3(256), sh, s, gC, Ny, nlines,
+    const size_t sh = 2 * (size_t)lpb * Ny * sizeof(C);
+    hipLaunchKernelGGL((fft_lines_kernel<T, false>), dim3(nb), dim3(lpb * Ny >= 4096 ? 512 : 256), sh, s, gC, Ny, nlines,
                        (int64_t)Nzc, (int64_t)Ny * Nzc, (int64_t)Nzc, lpb, c->plan[1], twy, fwd, sa);
     PE_CHECK_LAUNCH();
   };
@@ -425,10 +465,10 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   {
     ProfScope ps(c->prof, s, PE_PROF_FFT_X_SCALE, sizeof(T) == 8);
     const int64_t nlines = (int64_t)Ny * Nzc;
-    const int lpb = lines_per_block(Nx, sizeof(C), budget);
+    const int lpb = strided_lines_per_block(Nx, sizeof(C), sbudget);
     const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
-    const size_t sh = 2 * (size_t)lpb * (Nx + 1) * sizeof(C);
-    hipLaunchKernelGGL((fft_lines_kernel<T, true>), dim3(nb), dim3(256), sh, s, gC, Nx, nlines,
+    const size_t sh = 2 * (size_t)lpb * Nx * sizeof(C);
+    hipLaunchKernelGGL((fft_lines_kernel<T, true>), dim3(nb), dim3(lpb * Nx >= 4096 ? 512 : 256), sh, s, gC, Nx, nlines,
                        nlines, (int64_t)0, (int64_t)Ny * Nzc, lpb, c->plan[0], twx, 1, sa);
     PE_CHECK_LAUNCH();
   }

@@ -1,10 +1,11 @@
 // Gaussian spreading and contraction (section "Spectral Ewald
 // implementation", steps 2 and 6; window of section "Wave-space sum").
 //
-// Contraction: per home tile (the tile holding a particle's first support
-// point), the reachable grid region is staged in LDS once and contracted by
-// groups of 16 lanes, one particle each.  Where that region does not fit in
-// LDS (large P in double), one 64-lane wavefront per particle: lanes 0..3P-1
+// Contraction (single precision): per home tile (the tile holding a
+// particle's first support point), the reachable grid region is staged in LDS
+// once and contracted by groups of 16 lanes, one particle each.  In double,
+// or where that region does not fit in LDS, one 64-lane wavefront per
+// particle: lanes 0..3P-1
 // first evaluate the separable window factors w_x[j], w_y[j], w_z[j] (3P
 // exponentials per particle instead of P^3) and the wrapped grid indices into
 // LDS; then the wavefront sweeps the P x P (y,z) lines of the support, lane t
@@ -489,7 +490,9 @@ void launch_gather(hipStream_t s, const ParticleSet& ps, const T* grid, const Gr
   require(g.P <= kMaxP, "support P must be <= 16");
   const int Hs = kTile + g.P - 1;
   const size_t region = (size_t)Hs * Hs * Hs * sizeof(T);
-  if (region <= (size_t)kGatherLDS) {
+  // single precision: tile-staged; double: per particle (measured faster for
+  // double, whose region halves the workgroups an LDS can hold)
+  if (sizeof(T) == 4 && region <= (size_t)kGatherLDS) {
     if (ps.n_home_tiles == 0) return;
     const dim3 blocks((unsigned)ps.n_home_tiles);
     if (E)

@@ -260,6 +260,8 @@ struct pe_context {
   hipStream_t stream = nullptr;
   std::string err;
 
+  int lds_per_block = 65536;  // device limit on LDS per workgroup (bytes)
+
   // derived parameters
   double xi = 0, rc = 0, eta = 0, hmax = 0, V = 0;
   pe::GridGeom gg{};
