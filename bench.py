@@ -38,25 +38,56 @@ WORKLOADS = {
 }
 SPLIT_TOL = {"cfg2": 1e-8, "cfg3": 1e-6, "cfg4": 1e-6, "cfg5": 1e-6}
 
+# HBM bytes per launch of a kernel class on the default workload, from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes (one step's launches of
+# the class, averaged; FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the
+# ratios a plain 256 MiB device copy reads on those counters).  Each entry
+# records the source file the kernels live in and its sha1 at measurement;
+# once that file changes the figure is stale and `traffic` is reported null.
+TRAFFIC = {}
 
-def kernel_model(cls, dbl, nb, ni, G, Gc, nnz, system):
-    """(bound, algorithmic amount per launch, unit, peak) for a kernel class.
 
-    Byte counts are the minimum HBM traffic one launch must move; s = bytes
-    per real.  Spread/gather launches of the Krylov operator cover the beads;
-    particle records are position + width (32 B), index (4 B) and charge or
-    output (8 B).  The FFT passes read and write the half spectrum (or the
-    real grid).  The sparse real-space product reads its matrix once.
+def traffic_current(entry):
+    import hashlib
+    path = os.path.join(ROOT, entry["source"])
+    try:
+        with open(path, "rb") as f:
+            return hashlib.sha1(f.read()).hexdigest() == entry["sha1"]
+    except OSError:
+        return False
+
+
+# Peaks of one MI355X: HBM bandwidth, dense matrix-core and vector rates.
+MFMA_PEAK_TFLOPS = {False: 157.3, True: 78.6}     # fp32, fp64 dense matrix
+VALU_PEAK_TFLOPS = {False: 157.3, True: 78.6}     # fp32, fp64 vector
+PAIR_FLOP = 40   # arithmetic of one pair evaluation inside the cutoff
+
+
+def kernel_model(cls, dbl, cnt, work, nb, G, Gc):
+    """(bound, algorithmic amount over all launches, unit, peak) of a kernel class.
+
+    cnt launches did `work` units (particles, pairs, stored entries or
+    multiply-adds, as the library reports them).  Byte counts are the minimum
+    HBM traffic: s = bytes per real; a particle record is position + width
+    (32 B), index (4 B) and charge or output (8 B); a spread writes and a
+    contraction reads the whole grid; the FFT passes read and write the half
+    spectrum (or the real grid); the sparse product reads each stored entry
+    once.  Dense per-shape products and pair evaluations are counted in
+    floating-point operations.
     """
     s = 8 if dbl else 4
     if cls in ("spread", "gather"):
-        return "hbm", nb * (32 + 4 + 8) + G * s, "GB/s", HBM_PEAK_GBS
+        return "hbm", work * (32 + 4 + 8) + cnt * G * s, "GB/s", HBM_PEAK_GBS
     if cls in ("fft_y_fwd", "fft_y_inv", "fft_x_scale"):
-        return "hbm", 2 * Gc * 2 * s, "GB/s", HBM_PEAK_GBS
+        return "hbm", cnt * 2 * Gc * 2 * s, "GB/s", HBM_PEAK_GBS
     if cls in ("fft_z_r2c", "fft_z_c2r"):
-        return "hbm", G * s + Gc * 2 * s, "GB/s", HBM_PEAK_GBS
+        return "hbm", cnt * (G * s + Gc * 2 * s), "GB/s", HBM_PEAK_GBS
     if cls == "spmv":
-        return "hbm", nnz * (s + 4) + nb * (8 + 8 + 8 + 32 + 8), "GB/s", HBM_PEAK_GBS
+        return "hbm", work * (s + 4) + cnt * nb * (8 + 4 + 32 + 8 + 8 + 4 + 8), "GB/s", HBM_PEAK_GBS
+    if cls in ("near", "precond"):
+        return "mfma", 2.0 * work, "TFLOP/s", MFMA_PEAK_TFLOPS[dbl]
+    if cls == "pair":
+        return "alu", PAIR_FLOP * work, "TFLOP/s", VALU_PEAK_TFLOPS[dbl]
     return None
 
 
@@ -239,11 +270,14 @@ def main():
         tm = (time.perf_counter() - ta) / args.matvec_reps
         matvec[name] = {"ms": round(1e3 * tm, 4), "mbeads_s": round(nb / tm / 1e6, 2)}
 
-    # plain FP64 arm: the method as stated (double, unpreconditioned GMRES, zero guess), same configuration
+    # comparison arms on the same configuration, zero initial guess: the method as stated (double,
+    # unpreconditioned GMRES), double with the block preconditioner, and mixed precision with the
+    # preconditioner but without the learned guess
     fp64 = None
     if not args.no_fp64_arm:
         arms = {}
-        for name, prec, pre in (("plain_fp64", B.PE_FP64, 0), ("fp64_precond", B.PE_FP64, 1)):
+        for name, prec, pre in (("plain_fp64", B.PE_FP64, 0), ("fp64_precond", B.PE_FP64, 1),
+                                ("mixed_precond_zero_guess", B.PE_MIXED, 1)):
             p = params(prec, precond=pre)
             p.max_iters = 4000
             c64 = B.Context(p)
@@ -258,34 +292,38 @@ def main():
             c64.close()
         fp64 = arms
 
-    # roofline of the dominant kernel (live HIP-event timing of the timed region)
+    # roofline of the dominant kernel class (live HIP-event timing of the timed region)
     G = int(np.prod(system.mesh))
     Gc = system.mesh[0] * system.mesh[1] * (system.mesh[2] // 2 + 1)
     per_class = {}
     for name in B.PROF_CLASSES:
         for dbl in (False, True):
-            cnt, ms = prof[name] if not dbl else prof[name + "_f64"]
+            cnt, ms, work = prof[name] if not dbl else prof[name + "_f64"]
             if cnt:
-                per_class[(name, dbl)] = (cnt, ms)
+                per_class[(name, dbl)] = (cnt, ms, work)
+    total_ms = sum(v[1] for v in per_class.values())
     ranked = sorted(per_class, key=lambda kk: -per_class[kk][1])
-    roof = None
-    for name, dbl in ranked:
-        cnt, ms = per_class[(name, dbl)]
-        model = kernel_model(name, dbl, nb, ni, G, Gc, d["nnz"], system)
+
+    def roofline(name, dbl):
+        cnt, ms, work = per_class[(name, dbl)]
+        model = kernel_model(name, dbl, cnt, work, nb, G, Gc)
         if model is None:
-            continue
-        avg_s = ms / cnt * 1e-3
+            return None
         bound, amount, unit, peak = model
-        achieved = amount / avg_s / (1e9 if unit == "GB/s" else 1e12)
-        roof = {"kernel": f"{name}_{'f64' if dbl else 'f32'}", "bound": bound, "achieved": round(achieved, 2),
-                "peak": peak, "unit": unit, "frac": round(achieved / peak, 4), "traffic": None,
-                "avg_launch_us": round(1e6 * avg_s, 2), "launches": int(cnt),
-                "algorithmic_per_launch": amount, "share_of_kernel_time": round(ms / sum(
-                    v[1] for v in per_class.values()), 3)}
-        break
+        achieved = amount / (ms * 1e-3) / (1e9 if unit == "GB/s" else 1e12)
+        key = f"{name}_{'f64' if dbl else 'f32'}"
+        tr = TRAFFIC.get(key)
+        traffic = tr["bytes_per_launch"] if tr and traffic_current(tr) else None
+        return {"kernel": key, "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "avg_launch_us": round(1e3 * ms / cnt, 2), "launches": int(cnt),
+                "algorithmic_per_launch": amount / cnt, "share_of_kernel_time": round(ms / total_ms, 3)}
+
+    roofs = [r for r in (roofline(n, db) for n, db in ranked) if r is not None]
+    roof = roofs[0] if roofs else None
     breakdown = {f"{n}_{'f64' if db else 'f32'}": {"launches": int(c), "total_ms": round(m, 3),
-                                                   "avg_us": round(1e3 * m / c, 2)}
-                 for (n, db), (c, m) in sorted(per_class.items(), key=lambda kv: -kv[1][1])}
+                                                   "avg_us": round(1e3 * m / c, 2), "work": w}
+                 for (n, db), (c, m, w) in sorted(per_class.items(), key=lambda kv: -kv[1][1])}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -329,6 +367,7 @@ def main():
         "speedup_solve_vs_plain_fp64": (round(fp64["plain_fp64"]["solve_ms_p50"] / float(np.median(solve_ms)), 2)
                                         if fp64 else None),
         "roofline": roof,
+        "roofline_by_class": roofs[1:6],
         "kernels": breakdown,
         "cpu_baseline": cpu,
     }

@@ -211,11 +211,15 @@ pe_status pe_apply_saddle(pe_context* ctx, const double* x, double* y, int32_t p
 
 /*
  * Kernel timing with HIP events recorded around every launch on the
- * context's stream, accumulated per kernel class and precision.
- * pe_profile_enable(ctx, 1) resets and starts; pe_profile_read fills
- * out[4*PE_PROF_NCLASS] with (launch count, total milliseconds) per class in
- * enum order, first for the float kernels, then for the double kernels (the
- * Krylov vector kernels are always double).
+ * context's stream, accumulated per kernel class and precision, with the
+ * work each class did.  pe_profile_enable(ctx, 1) resets and starts;
+ * pe_profile_read fills out[6*PE_PROF_NCLASS] with (launch count, total
+ * milliseconds, work units) per class in enum order, first for the float
+ * kernels, then for the double kernels (the Krylov vector kernels are always
+ * double).  Work units: particles spread or contracted (SPREAD, GATHER),
+ * pairs inside the real-space cutoff evaluated (PAIR), stored sparse
+ * real-space entries applied (SPMV), multiply-adds of the dense per-shape
+ * products (NEAR, PRECOND), launches (FFT passes), 0 otherwise.
  */
 typedef enum {
   PE_PROF_SPREAD = 0,
@@ -229,6 +233,7 @@ typedef enum {
   PE_PROF_PAIR,
   PE_PROF_KRYLOV,
   PE_PROF_PRECOND,
+  PE_PROF_NEAR,
   PE_PROF_NCLASS
 } pe_prof_class;
 pe_status pe_profile_enable(pe_context* ctx, int32_t on);

@@ -19,7 +19,7 @@ PE_OK, PE_ERR_ARG, PE_ERR_STATE, PE_ERR_DEVICE, PE_ERR_NOMEM, PE_ERR_NOT_CONVERG
 PE_FP64, PE_MIXED = 0, 1
 PE_REG_GAUSSIAN, PE_REG_SHELL = 0, 1
 PROF_CLASSES = ["spread", "fft_z_r2c", "fft_y_fwd", "fft_x_scale", "fft_y_inv", "fft_z_c2r", "gather",
-                "spmv", "pair", "krylov", "precond"]
+                "spmv", "pair", "krylov", "precond", "near"]
 STATUS_NAMES = {0: "PE_OK", 1: "PE_ERR_ARG", 2: "PE_ERR_STATE", 3: "PE_ERR_DEVICE", 4: "PE_ERR_NOMEM",
                 5: "PE_ERR_NOT_CONVERGED", 6: "PE_ERR_NUMERIC"}
 
@@ -231,12 +231,12 @@ class Context:
         self._chk(_lib.pe_profile_enable(self.h, 1 if on else 0))
 
     def pe_profile_read(self):
-        """{class: (launches, total ms)} for float kernels, {class + '_f64': ...} for double."""
+        """{class: (launches, total ms, work units)} for float kernels, {class + '_f64': ...} for double."""
         nc = len(PROF_CLASSES)
-        out = (ctypes.c_double * (4 * nc))()
+        out = (ctypes.c_double * (6 * nc))()
         self._chk(_lib.pe_profile_read(self.h, out))
-        res = {n: (int(out[2 * i]), float(out[2 * i + 1])) for i, n in enumerate(PROF_CLASSES)}
-        res.update({n + "_f64": (int(out[2 * (nc + i)]), float(out[2 * (nc + i) + 1]))
+        res = {n: (int(out[3 * i]), float(out[3 * i + 1]), float(out[3 * i + 2])) for i, n in enumerate(PROF_CLASSES)}
+        res.update({n + "_f64": (int(out[3 * (nc + i)]), float(out[3 * (nc + i) + 1]), float(out[3 * (nc + i) + 2]))
                     for i, n in enumerate(PROF_CLASSES)})
         return res
 

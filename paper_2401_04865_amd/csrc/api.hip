@@ -168,6 +168,12 @@ double* scal(pe_context* c) { return c->sums.get() + 8; }   // misc device scala
 template <typename T>
 T* grid_real(pe::DevBuf<double>& g) { return reinterpret_cast<T*>(g.get()); }
 
+// Device counter of pair evaluations for the profiler (null when not profiling).
+template <typename T>
+unsigned long long* pair_counter(pe_context* c) {
+  return c->prof.on ? c->pair_count.get() + (sizeof(T) == 8 ? 1 : 0) : nullptr;
+}
+
 // M q for the beads with bead charges q (caller order), assembled into the
 // saddle operator: y[0:nb] = -(M q) + Sigma^T dpsi, y[nb:] = Sigma q.
 template <typename T>
@@ -180,20 +186,22 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
   launch_seg_sum(s, c->off.get(), c->n_body, q, y + nb);
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
-  { ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8); launch_spread<T>(s, c->B, q, gA, c->gg, false); }
+  const bool dbl = sizeof(T) == 8;
+  { ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)nb); launch_spread<T>(s, c->B, q, gA, c->gg, false); }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
-  { ProfScope ps(c->prof, s, PE_PROF_GATHER, sizeof(T) == 8); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
+  { ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
+  // real space: dense intra-body blocks per shape, then the sparse pairs
+  for (auto& t : c->pc.types) {
+    if (!t.near || t.bodies.empty()) continue;
+    const T* R;
+    if constexpr (sizeof(T) == 8) R = t.R64.get();
+    else R = t.R32.get();
+    ProfScope ps(c->prof, s, PE_PROF_NEAR, dbl, (double)t.N * t.N * (double)t.bodies.size());
+    launch_body_gemm<T>(s, R, t.N, false, true, t.dbodies.get(), (int)t.bodies.size(), c->off.get(), nb,
+                        q, c->phi_w.get(), c->pc.gemm_ws.get());
+  }
   {
-    // real space: dense intra-body blocks per shape, then the sparse pairs
-    ProfScope ps(c->prof, s, PE_PROF_SPMV, sizeof(T) == 8);
-    for (auto& t : c->pc.types) {
-      if (!t.near || t.bodies.empty()) continue;
-      const T* R;
-      if constexpr (sizeof(T) == 8) R = t.R64.get();
-      else R = t.R32.get();
-      launch_body_gemm<T>(s, R, t.N, false, true, t.dbodies.get(), (int)t.bodies.size(), c->off.get(), nb,
-                          q, c->phi_w.get(), c->pc.gemm_ws.get());
-    }
+    ProfScope ps(c->prof, s, PE_PROF_SPMV, dbl, (double)c->nnz);
     launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), ck_bead(c), y);
   }
 }
@@ -218,19 +226,20 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
   {
-    ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8);
+    ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8, (double)(nb + ni));
     launch_spread<T>(s, c->B, qb, gA, c->gg, false);
     if (ni) launch_spread<T>(s, c->I, qi, gA, c->gg, true);
   }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
   {
-    ProfScope ps(c->prof, s, PE_PROF_GATHER, sizeof(T) == 8);
+    ProfScope ps(c->prof, s, PE_PROF_GATHER, sizeof(T) == 8, (double)(nb + ni));
     launch_gather<T>(s, c->B, gB, c->gg, phi, E, true);
     if (ni) launch_gather<T>(s, c->I, gB, c->gg, phi + nb, E ? E + 3 * nb : nullptr, true);
   }
   ProfScope ps_pair(c->prof, s, PE_PROF_PAIR, sizeof(T) == 8);
-  launch_pair_onfly<T>(s, c->B, &c->B, qb, &c->I, qi, c->rg, phi, E);
-  launch_pair_onfly<T>(s, c->I, &c->B, qb, &c->I, qi, c->rg, phi + nb, E ? E + 3 * nb : nullptr);
+  unsigned long long* npc = pair_counter<T>(c);
+  launch_pair_onfly<T>(s, c->B, &c->B, qb, &c->I, qi, c->rg, phi, E, false, npc);
+  launch_pair_onfly<T>(s, c->I, &c->B, qb, &c->I, qi, c->rg, phi + nb, E ? E + 3 * nb : nullptr, false, npc);
   // k = 0 constant, then forces and energies
   if (nb)
     hipLaunchKernelGGL(finish_particles_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, chg_all,
@@ -252,13 +261,22 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
 template <typename T>
 void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E) {
   hipStream_t s = c->stream;
+  const bool dbl = sizeof(T) == 8;
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
-  launch_spread<T>(s, c->I, c->ion_q.get(), gA, c->gg, false);
+  {
+    ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)c->n_ion);
+    launch_spread<T>(s, c->I, c->ion_q.get(), gA, c->gg, false);
+  }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
-  launch_gather<T>(s, c->B, gB, c->gg, phi_ion, E, false);
+  {
+    ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)c->n_bead);
+    launch_gather<T>(s, c->B, gB, c->gg, phi_ion, E, false);
+  }
   // the field only feeds the guess features: single precision
-  launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, phi_ion, E, true);
+  ProfScope ps(c->prof, s, PE_PROF_PAIR, dbl);
+  launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, phi_ion, E, true,
+                       pair_counter<T>(c));
 }
 
 // Right-hand side b = [-r.E0 + phi_ion(beads); Q].
@@ -340,6 +358,13 @@ struct GmresOut {
 // Restarted GMRES on A x = b with operator precision `prec`; x is updated in
 // place.  Convergence: ||b - A x|| <= tol * bnorm, checked with the true
 // residual of the operator at every restart.
+// Multiply-adds of one preconditioner application (all shapes).
+double precond_madds(const pe_context* c) {
+  double m = 0;
+  for (const auto& t : c->pc.types) m += (double)(t.N + 1) * (t.N + 1) * (double)t.bodies.size();
+  return m;
+}
+
 // r0 (optional, with its norm r0n): the residual b - A x at the starting x,
 // already formed by the caller, so the first cycle does not recompute it.
 GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero, double bnorm, double tol,
@@ -388,7 +413,7 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
       if (pre) {
         double* zj = k.Z + (size_t)j * n;
         {
-          ProfScope ps(c->prof, s, PE_PROF_PRECOND, prec != PE_MIXED);
+          ProfScope ps(c->prof, s, PE_PROF_PRECOND, prec != PE_MIXED, precond_madds(c));
           if (prec == PE_MIXED) precond_apply<float>(s, c, vj, zj);
           else precond_apply<double>(s, c, vj, zj);
         }
@@ -770,12 +795,15 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
   if (bnorm == 0.0) {
     inf->rel_residual = 0;
   } else {
-    // residual at the guess (double operator); it is also the first
-    // residual of the solve below
+    // residual at the guess; it is also the first residual of the solve
+    // below.  Mixed precision forms it with the float operator: it only
+    // starts the first refinement, whose correction is checked by the next
+    // double residual.
     double rgn = bnorm;
     if (!x_zero) {
-      apply_saddle_prec(c, PE_FP64, x, k.tmp);
-      mv64++;
+      const int rp = c->p.precision == PE_MIXED ? PE_MIXED : PE_FP64;
+      apply_saddle_prec(c, rp, x, k.tmp);
+      (rp == PE_MIXED ? mv32 : mv64)++;
       launch_sub(s, b, k.tmp, k.r, n);
       launch_mdot(s, k.r, n, 1, k.r, n, c->red.get(), k.nrm, true);
       rgn = fetch(c, k.nrm);
@@ -871,6 +899,9 @@ pe_status pe_profile_enable(pe_context* c, int32_t on) {
   PE_HIP(hipStreamSynchronize(c->stream));
   c->prof.reset();
   c->prof.on = on != 0;
+  c->pair_count.ensure(2);
+  PE_HIP(hipMemsetAsync(c->pair_count.get(), 0, 2 * sizeof(unsigned long long), c->stream));
+  PE_HIP(hipStreamSynchronize(c->stream));
   PE_API_END(c)
 }
 
@@ -879,9 +910,16 @@ pe_status pe_profile_read(pe_context* c, double* out) {
   PE_API_BEGIN
   PE_HIP(hipStreamSynchronize(c->stream));
   c->prof.flush();
+  unsigned long long np[2] = {0, 0};
+  if (c->pair_count.get())
+    PE_HIP(hipMemcpy(np, c->pair_count.get(), sizeof(np), hipMemcpyDeviceToHost));
   for (int i = 0; i < 2 * PE_PROF_NCLASS; ++i) {
-    out[2 * i] = c->prof.cnt[i];
-    out[2 * i + 1] = c->prof.ms[i];
+    double w = c->prof.work[i];
+    if (i == PE_PROF_PAIR) w = (double)np[0];
+    if (i == PE_PROF_PAIR + PE_PROF_NCLASS) w = (double)np[1];
+    out[3 * i] = c->prof.cnt[i];
+    out[3 * i + 1] = c->prof.ms[i];
+    out[3 * i + 2] = w;
   }
   PE_API_END(c)
 }

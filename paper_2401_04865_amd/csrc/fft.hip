@@ -429,7 +429,7 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   const size_t sbudget = std::min<size_t>((size_t)c->lds_per_block, 80 * 1024) - 2048;
   // 1. z, r2c
   {
-    ProfScope ps(c->prof, s, PE_PROF_FFT_Z_R2C, sizeof(T) == 8);
+    ProfScope ps(c->prof, s, PE_PROF_FFT_Z_R2C, sizeof(T) == 8, 1.0);
     const int64_t nlines = (int64_t)Nx * Ny;
     const int ppb = lines_per_block(Nz, sizeof(C), budget);
     const int64_t npairs = (nlines + 1) / 2;
@@ -451,7 +451,7 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   sa.norm = 1.0 / ((double)Nx * Ny * Nz);
   // 2. y forward: lines (x, kz), element y
   auto ypass = [&](int fwd) {
-    ProfScope ps(c->prof, s, fwd > 0 ? PE_PROF_FFT_Y_FWD : PE_PROF_FFT_Y_INV, sizeof(T) == 8);
+    ProfScope ps(c->prof, s, fwd > 0 ? PE_PROF_FFT_Y_FWD : PE_PROF_FFT_Y_INV, sizeof(T) == 8, 1.0);
     const int64_t nlines = (int64_t)Nx * Nzc;
     const int lpb = strided_lines_per_block(Ny, sizeof(C), sbudget);
     const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
@@ -463,7 +463,7 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   ypass(1);
   // 3. x forward + scale + x inverse: lines (y, kz), element x
   {
-    ProfScope ps(c->prof, s, PE_PROF_FFT_X_SCALE, sizeof(T) == 8);
+    ProfScope ps(c->prof, s, PE_PROF_FFT_X_SCALE, sizeof(T) == 8, 1.0);
     const int64_t nlines = (int64_t)Ny * Nzc;
     const int lpb = strided_lines_per_block(Nx, sizeof(C), sbudget);
     const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
@@ -476,7 +476,7 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   ypass(-1);
   // 5. z, c2r into grid B
   {
-    ProfScope ps(c->prof, s, PE_PROF_FFT_Z_C2R, sizeof(T) == 8);
+    ProfScope ps(c->prof, s, PE_PROF_FFT_Z_C2R, sizeof(T) == 8, 1.0);
     const int64_t nlines = (int64_t)Nx * Ny;
     const int ppb = lines_per_block(Nz, sizeof(C), budget);
     const int64_t npairs = (nlines + 1) / 2;

@@ -150,9 +150,11 @@ struct Prof {
   bool on = false;
   double ms[2 * PE_PROF_NCLASS] = {};
   double cnt[2 * PE_PROF_NCLASS] = {};
+  double work[2 * PE_PROF_NCLASS] = {};
   struct Rec {
     int cls;
     hipEvent_t a, b;
+    double work;
   };
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
@@ -168,7 +170,7 @@ struct Prof {
   }
   void reset() {
     flush();
-    for (int i = 0; i < 2 * PE_PROF_NCLASS; ++i) ms[i] = cnt[i] = 0;
+    for (int i = 0; i < 2 * PE_PROF_NCLASS; ++i) ms[i] = cnt[i] = work[i] = 0;
   }
   // call only when the stream is idle
   void flush() {
@@ -177,6 +179,7 @@ struct Prof {
       if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
         ms[r.cls] += t;
         cnt[r.cls] += 1;
+        work[r.cls] += r.work;
       }
       pool.push_back(r.a);
       pool.push_back(r.b);
@@ -196,10 +199,12 @@ struct ProfScope {
   Prof* p;
   hipStream_t s;
   int cls;
+  double work;
   hipEvent_t a = nullptr;
-  // dbl: the launch computes in double (its class is offset by PE_PROF_NCLASS)
-  ProfScope(Prof& prof, hipStream_t st, int c, bool dbl) : p(prof.on ? &prof : nullptr), s(st),
-      cls(c + (dbl ? PE_PROF_NCLASS : 0)) {
+  // dbl: the launch computes in double (its class is offset by PE_PROF_NCLASS);
+  // w: work units of the launches inside the scope
+  ProfScope(Prof& prof, hipStream_t st, int c, bool dbl, double w = 0) : p(prof.on ? &prof : nullptr), s(st),
+      cls(c + (dbl ? PE_PROF_NCLASS : 0)), work(w) {
     if (p) {
       a = p->take();
       (void)hipEventRecord(a, s);
@@ -209,7 +214,7 @@ struct ProfScope {
     if (p) {
       hipEvent_t b = p->take();
       (void)hipEventRecord(b, s);
-      p->pending.push_back({cls, a, b});
+      p->pending.push_back({cls, a, b, work});
     }
   }
 };
@@ -324,6 +329,7 @@ struct pe_context {
   pe::LearnedGuess* guess = nullptr;
 
   pe::Prof prof;
+  pe::DevBuf<unsigned long long> pair_count;  // [float, double] pairs evaluated while profiling
   pe::Precond pc;
 };
 
@@ -363,7 +369,7 @@ void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const d
 template <typename T>
 void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet* src0, const double* q0,
                        const ParticleSet* src1, const double* q1, const RealGeom& rg, double* phi, double* E,
-                       bool field_single = false);
+                       bool field_single = false, unsigned long long* npairs = nullptr);
 
 // body shapes (shapes.hip): group bodies into shape types (device-side
 // matching, types cached across configurations), build the per-shape blocks

@@ -194,6 +194,7 @@ struct PairOut {
   float* v32;
   const int* body_of;          // count / fill: body of each bead (caller order)
   const unsigned char* dense;  // count / fill: per body, intra-body pairs held by a dense block
+  unsigned long long* npairs;  // if set: pairs inside the cutoff evaluated are added here
 };
 
 enum { MODE_COUNT = 0, MODE_FILL = 1, MODE_POT = 2, MODE_FIELD = 3 };
@@ -237,6 +238,7 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   T acc = 0;
   TF ex = 0, ey = 0, ez = 0;
   int cnt = 0;
+  int nev = 0;  // pairs inside the cutoff this lane evaluated
   int64_t o = 0, o_end = 0;
   if (MODE == MODE_FILL && active) {
     o = out.row_ptr[t];
@@ -259,6 +261,7 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     dz -= g.L[2] * rint(dz * g.inv_L[2]);
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 < g.rc2)) return;
+    ++nev;
     if constexpr (MODE == MODE_COUNT) {
       ++cnt;
       return;
@@ -415,6 +418,12 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
       }
     }
     if (finished) break;
+  }
+  if (out.npairs) {
+    unsigned long long v = (unsigned long long)nev;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) atomicAdd(out.npairs, v);
   }
   if (!active) return;
   if (MODE == MODE_COUNT) {
@@ -652,7 +661,7 @@ void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const d
 template <typename T>
 void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet* src0, const double* q0,
                        const ParticleSet* src1, const double* q1, const RealGeom& rg, double* phi, double* E,
-                       bool field_single) {
+                       bool field_single, unsigned long long* npairs) {
   if (tgt.n == 0) return;
   if (src1 && src1->n == 0) src1 = nullptr;
   if (src0 && src0->n == 0) {
@@ -677,6 +686,7 @@ void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet*
   PairOut out{};
   out.phi = phi;
   out.E = E;
+  out.npairs = npairs;
   if (!E)
     launch_queue<MODE_POT, T, T>(s, tgt, a, b, nsrc, rg, out);
   else if (field_single)
@@ -688,8 +698,10 @@ void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet*
 template void launch_spmv_assemble<float>(hipStream_t, pe_context*, const double*, const double*, const double*, const double*, double*);
 template void launch_spmv_assemble<double>(hipStream_t, pe_context*, const double*, const double*, const double*, const double*, double*);
 template void launch_pair_onfly<float>(hipStream_t, const ParticleSet&, const ParticleSet*, const double*,
-                                       const ParticleSet*, const double*, const RealGeom&, double*, double*, bool);
+                                       const ParticleSet*, const double*, const RealGeom&, double*, double*, bool,
+                                       unsigned long long*);
 template void launch_pair_onfly<double>(hipStream_t, const ParticleSet&, const ParticleSet*, const double*,
-                                        const ParticleSet*, const double*, const RealGeom&, double*, double*, bool);
+                                        const ParticleSet*, const double*, const RealGeom&, double*, double*, bool,
+                                        unsigned long long*);
 
 }  // namespace pe
