@@ -47,6 +47,21 @@ __global__ void rhs_top_kernel(int64_t n, const double* __restrict__ rel, double
   b[i] = v;
 }
 
+// Potential offsets of a starting point whose offsets are zero: with
+// r = b - A [q; 0], the offset of body i that minimizes the residual of its
+// bead rows is the mean of r over them (each row holds +dPsi_i once).
+// Writes dPsi_i = sum_i / N_i into x and removes it from r.
+__global__ void start_offsets_kernel(int64_t nb, int64_t n_body, const int64_t* __restrict__ off,
+                                     const int* __restrict__ body_of, const double* __restrict__ rsum,
+                                     double* __restrict__ r, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) {
+    const int b = body_of[i];
+    r[i] -= rsum[b] / (double)(off[b + 1] - off[b]);
+  }
+  if (i < n_body) x[nb + i] = rsum[i] / (double)(off[i + 1] - off[i]);
+}
+
 // phi[i] -= ck_total(sigma_i); then f = q (E0 + E), u = q phi / 2 - q x.E0
 __global__ void finish_particles_kernel(int64_t n, const double* __restrict__ chg, const double* __restrict__ pos,
                                         const double* __restrict__ sig, double ex, double ey, double ez,
@@ -805,6 +820,13 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
       apply_saddle_prec(c, rp, x, k.tmp);
       (rp == PE_MIXED ? mv32 : mv64)++;
       launch_sub(s, b, k.tmp, k.r, n);
+      // the guess sets charges only: give it the best potential offsets
+      c->sums.ensure(64 + nbody);
+      double* rs = c->sums.get() + 64;
+      launch_seg_sum(s, c->off.get(), nbody, k.r, rs);
+      hipLaunchKernelGGL(start_offsets_kernel, dim3(nblk(std::max(nb, nbody), 256)), dim3(256), 0, s, nb, nbody,
+                         c->off.get(), c->body_of.get(), rs, k.r, x);
+      PE_CHECK_LAUNCH();
       launch_mdot(s, k.r, n, 1, k.r, n, c->red.get(), k.nrm, true);
       rgn = fetch(c, k.nrm);
       inf->rel_residual_guess = rgn / bnorm;
