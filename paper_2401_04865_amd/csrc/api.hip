@@ -602,6 +602,8 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
   require(c->eta > 0 && c->eta < 1, "eta = (h xi)^2 P/(pi c^2) must lie in (0, 1); refine the mesh or lower xi");
   build_twiddles(c);
   build_green_tables(c);
+  build_erfcx_table(c->stream, c->erfcx_tab);
+  c->rg.erfcx = c->erfcx_tab.get();
   c->sums.ensure(64);
   c->red.ensure((size_t)kMaxK * 1024 + 8192);
   *out = c;

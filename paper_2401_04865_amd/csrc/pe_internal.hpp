@@ -107,7 +107,17 @@ struct RealGeom {
   double eps;
   int reg;          // pe_reg
   double a;         // shell radius
+  const float* erfcx = nullptr;  // device table of the scaled erfc (single-precision pair kernel)
 };
+
+// Piecewise table of the scaled complementary error function erfcx(x) =
+// exp(x^2) erfc(x) on [0, kErfcxPieces / kErfcxInvWidth), pieces of width
+// 1 / kErfcxInvWidth: per piece, the Taylor coefficients about its midpoint
+// up to degree kErfcxDeg (kErfcxDeg + 1 floats per piece).
+constexpr int kErfcxPieces = 24;
+constexpr int kErfcxDeg = 7;
+constexpr float kErfcxInvWidth = 4.0f;
+void build_erfcx_table(hipStream_t s, DevBuf<float>& tab);
 
 // A particle set sorted by real-space cell.
 struct ParticleSet {
@@ -275,6 +285,7 @@ struct pe_context {
   pe::DevBuf<double2> tw64[3];
   pe::DevBuf<float2> tw32[3];
   pe::DevBuf<double> gtab;   // separable Green's-function tables (exp factors, k_d^2)
+  pe::DevBuf<float> erfcx_tab;  // scaled erfc pieces for the single-precision pair kernel
 
   // system
   bool have_system = false;

@@ -116,6 +116,63 @@ __device__ __forceinline__ T self_value(T s2, const RealGeom& g) {
   return c * ((T)1 / (T)g.a - (T)2 * (T)g.xi / (T)sqrt(kPi));
 }
 
+// Single-precision Gaussian pair kernel with no data-dependent branch but a
+// rarely taken one for tiny distances.  erfc(x) = exp(-x^2) erfcx(x), erfcx
+// from the piecewise Taylor table (float relative error about 1e-7), and the
+// two Gaussians exp(-x^2) serve the derivative as well.  Where both arguments
+// are below 1/2 the difference of error functions comes from the Maclaurin
+// series of erf instead, which keeps its relative accuracy as r -> 0.
+//   R = c D / r,   F = -R'(r) / r = c (D - D' r) / r^3,
+//   D = erf(b r) - erf(xi r),  D' = (2/sqrt pi)(b e^{-b^2 r^2} - xi e^{-xi^2 r^2}).
+// Beyond the table's range the last piece is held (erfc(6) = 2e-17, so the
+// product is far below the rounding of every other term).
+__device__ __forceinline__ float erfcx_lookup(const float4* __restrict__ tab, float x) {
+  const float xc = fminf(x, (float)kErfcxPieces / kErfcxInvWidth);
+  const int k = min((int)(xc * kErfcxInvWidth), kErfcxPieces - 1);
+  const float s = xc - ((float)k + 0.5f) * (1.0f / kErfcxInvWidth);
+  static_assert(kErfcxDeg == 7, "two float4 per piece");
+  const float4 lo = tab[2 * k], hi = tab[2 * k + 1];
+  float v = fmaf(hi.w, s, hi.z);
+  v = fmaf(v, s, hi.y);
+  v = fmaf(v, s, hi.x);
+  v = fmaf(v, s, lo.w);
+  v = fmaf(v, s, lo.z);
+  v = fmaf(v, s, lo.y);
+  return fmaf(v, s, lo.x);
+}
+
+// erf(x) = (2/sqrt pi) sum_n (-1)^n x^(2n+1) / (n! (2n+1)), n <= 7: below
+// 1e-9 relative for x < 1/2.
+__device__ __forceinline__ float erf_series(float x) {
+  const float z = x * x;
+  float v = -1.0f / 75600.0f;
+  v = fmaf(v, z, 1.0f / 9360.0f);
+  v = fmaf(v, z, -1.0f / 1320.0f);
+  v = fmaf(v, z, 1.0f / 216.0f);
+  v = fmaf(v, z, -1.0f / 42.0f);
+  v = fmaf(v, z, 1.0f / 10.0f);
+  v = fmaf(v, z, -1.0f / 3.0f);
+  v = fmaf(v, z, 1.0f);
+  return (float)kTwoOverSqrtPi * x * v;
+}
+
+__device__ __forceinline__ void pair_kernel_fast(float r2, float s2, float xi, float c,
+                                                 const float4* __restrict__ tab, float& R, float& F) {
+  const float inv_r = __builtin_amdgcn_rsqf(r2);
+  const float r = r2 * inv_r;
+  const float b = __builtin_amdgcn_rsqf(2.0f * s2);
+  const float x1 = xi * r, x2 = b * r;
+  constexpr float kLog2e = 1.44269504088896341f;
+  const float e1 = __builtin_amdgcn_exp2f(-(x1 * x1) * kLog2e);
+  const float e2 = __builtin_amdgcn_exp2f(-(x2 * x2) * kLog2e);
+  float D;
+  if (fmaxf(x1, x2) < 0.5f) D = erf_series(x2) - erf_series(x1);
+  else D = e1 * erfcx_lookup(tab, x1) - e2 * erfcx_lookup(tab, x2);
+  const float Dp = (float)kTwoOverSqrtPi * (b * e2 - xi * e1);
+  R = c * D * inv_r;
+  F = c * (D - Dp * r) * (inv_r * inv_r * inv_r);
+}
+
 // ---------------------------------------------------------------- cell list
 
 __global__ void assign_cells_kernel(const double* __restrict__ pos, const double* __restrict__ sig,
@@ -211,10 +268,18 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     PairOut out) {
   __shared__ int qbuf[kWaves][kQ][64];
   __shared__ float4 cbuf[kWaves][64];
+  __shared__ float4 etab[2 * kErfcxPieces];
+  // single-precision Gaussian passes use the table-driven pair kernel
+  constexpr bool kFastT = sizeof(T) == 4 && (MODE == MODE_POT || MODE == MODE_FIELD);
+  const bool fast = kFastT && g.reg == PE_REG_GAUSSIAN && g.erfcx != nullptr;
+  if (fast) {
+    if (threadIdx.x < 2 * kErfcxPieces) etab[threadIdx.x] = reinterpret_cast<const float4*>(g.erfcx)[threadIdx.x];
+    __syncthreads();  // before any wavefront leaves
+  }
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int w = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wv;
-  if (w >= nchunk) return;  // whole wavefront; the kernel has no block barrier
+  if (w >= nchunk) return;  // whole wavefront; no block barrier follows
   // chunk: sorted targets [begin, end) in the cells cell .. cell + nz - 1 of
   // one (x, y) column
   const int4 ch = chunks[w];
@@ -285,27 +350,64 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
       return;
     }
     const double qd = set ? s1.q[sidx] : s0.q[sidx];
+    // the self pair (r = 0) has R(0) and no field; one accumulation site for
+    // both cases keeps the sums in registers
+    T R = 0;
+    TF F = 0;  // -R'(r) / r
     if (r2 == 0.0) {
-      acc += self_value<T>((T)s2, g) * (T)qd;
-      return;
+      R = self_value<T>((T)s2, g);
+    } else {
+      T dR = 0;
+      const T r = (T)sqrt(r2);
+      constexpr bool same = sizeof(T) == sizeof(TF);
+      pair_kernel<T>(r, (T)s2, g, R, dR, MODE == MODE_FIELD && same);
+      if constexpr (MODE == MODE_FIELD) {
+        TF dRf;
+        if constexpr (same) {
+          dRf = (TF)dR;
+        } else {
+          TF Rf;
+          pair_kernel<TF>((TF)r, (TF)s2, g, Rf, dRf, true);
+        }
+        F = -dRf / (TF)r;
+      }
     }
-    T R, dR = 0;
-    const T r = (T)sqrt(r2);
-    constexpr bool same = sizeof(T) == sizeof(TF);
-    pair_kernel<T>(r, (T)s2, g, R, dR, MODE == MODE_FIELD && same);
     acc += R * (T)qd;
     if constexpr (MODE == MODE_FIELD) {
-      TF dRf;
-      if constexpr (same) {
-        dRf = (TF)dR;
-      } else {
-        TF Rf;
-        pair_kernel<TF>((TF)r, (TF)s2, g, Rf, dRf, true);
-      }
-      const TF f = -dRf / (TF)r * (TF)qd;  // E = -grad_t R q = -R'(r) d/r q
+      const TF f = F * (TF)qd;  // E = -grad_t R q = -R'(r) d/r q
       ex += f * (TF)dx;
       ey += f * (TF)dy;
       ez += f * (TF)dz;
+    }
+  };
+
+  // single precision throughout once the minimum-image difference is formed
+  // in double (float coordinates of a large box would cost digits of r)
+  const float pw2 = (float)p.w * (float)p.w;
+  const float rc2e = (float)g.rc2;
+  const float xif = (float)g.xi, cf = (float)(kInv4Pi / g.eps);
+  auto evaluate_fast = [&](int e) {
+    const int set = e >> kSetBit;
+    const int sidx = e & ((1 << kSetBit) - 1);
+    const double4 qp = set ? s1.pos[sidx] : s0.pos[sidx];
+    const float dx = (float)min_img(p.x - qp.x, g.L[0], g.inv_L[0]);
+    const float dy = (float)min_img(p.y - qp.y, g.L[1], g.inv_L[1]);
+    const float dz = (float)min_img(p.z - qp.z, g.L[2], g.inv_L[2]);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (!(r2 < rc2e)) return;
+    ++nev;
+    const float qf = (float)(set ? s1.q[sidx] : s0.q[sidx]);
+    const float sw = (float)qp.w;
+    const float s2 = fmaf(sw, sw, pw2);
+    float R, F = 0.0f;
+    if (r2 == 0.0f) R = self_value<float>(s2, g);
+    else pair_kernel_fast(r2, s2, xif, cf, etab, R, F);
+    acc += R * qf;
+    if constexpr (MODE == MODE_FIELD) {
+      const float fq = F * qf;
+      ex += fq * dx;
+      ey += fq * dy;
+      ez += fq * dz;
     }
   };
 
@@ -414,7 +516,12 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
       if (popped < pushed) {
         const int e = qb[popped & (kQ - 1)][lane];
         ++popped;
-        evaluate(e);
+        if constexpr (kFastT) {
+          if (fast) evaluate_fast(e);
+          else evaluate(e);
+        } else {
+          evaluate(e);
+        }
       }
     }
     if (finished) break;
@@ -693,6 +800,27 @@ void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet*
     launch_queue<MODE_FIELD, T, float>(s, tgt, a, b, nsrc, rg, out);
   else
     launch_queue<MODE_FIELD, T, T>(s, tgt, a, b, nsrc, rg, out);
+}
+
+// erfcx = exp(x^2) erfc(x) satisfies y' = 2 x y - 2/sqrt(pi); differentiating
+// n times gives y^(n+1) = 2 x y^(n) + 2 n y^(n-1), so the Taylor coefficients
+// e_n = y^(n)(x0)/n! about a midpoint x0 follow from erfcx(x0) by
+//   e_1 = 2 x0 e_0 - 2/sqrt(pi),  (n+1) e_(n+1) = 2 x0 e_n + 2 e_(n-1).
+// Degree 7 over half-widths of 1/8 leaves a truncation below 2e-9.
+void build_erfcx_table(hipStream_t s, DevBuf<float>& tab) {
+  constexpr int per = kErfcxDeg + 1;
+  std::vector<float> h((size_t)kErfcxPieces * per);
+  for (int k = 0; k < kErfcxPieces; ++k) {
+    const double x0 = (k + 0.5) / (double)kErfcxInvWidth;
+    double e[per];
+    e[0] = std::exp(x0 * x0) * std::erfc(x0);
+    e[1] = 2.0 * x0 * e[0] - kTwoOverSqrtPi;
+    for (int n = 1; n + 1 < per; ++n) e[n + 1] = (2.0 * x0 * e[n] + 2.0 * e[n - 1]) / (n + 1);
+    for (int n = 0; n < per; ++n) h[(size_t)k * per + n] = (float)e[n];
+  }
+  tab.ensure(h.size());
+  PE_HIP(hipMemcpyAsync(tab.get(), h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, s));
+  PE_HIP(hipStreamSynchronize(s));
 }
 
 template void launch_spmv_assemble<float>(hipStream_t, pe_context*, const double*, const double*, const double*, const double*, double*);
