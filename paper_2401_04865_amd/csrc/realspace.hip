@@ -259,6 +259,7 @@ enum { MODE_COUNT = 0, MODE_FILL = 1, MODE_POT = 2, MODE_FIELD = 3 };
 constexpr int kQ = 32;          // queue entries per lane
 constexpr int kQFlush = 16;     // candidates between flushes (kQ - kQFlush entries stay free)
 constexpr int kSetBit = 30;     // queue entry: sorted source index | set << kSetBit
+constexpr int kMaxRuns = 36;    // stencil runs: 2 source sets x 9 columns x 2 runs
 
 
 template <int MODE, typename T, typename TF>
@@ -269,6 +270,10 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   __shared__ int qbuf[kWaves][kQ][64];
   __shared__ float4 cbuf[kWaves][64];
   __shared__ float4 etab[2 * kErfcxPieces];
+  __shared__ int cownb[kWaves][64];          // owner tags of the staged candidates (count / fill)
+  __shared__ int rstart[kWaves][kMaxRuns + 1];
+  __shared__ int rbase[kWaves][kMaxRuns];
+  __shared__ int rcode[kWaves][kMaxRuns];    // per run: set | (ox+1) << 1 | (oy+1) << 3 | z image << 5
   // single-precision Gaussian passes use the table-driven pair kernel
   constexpr bool kFastT = sizeof(T) == 4 && (MODE == MODE_POT || MODE == MODE_FIELD);
   const bool fast = kFastT && g.reg == PE_REG_GAUSSIAN && g.erfcx != nullptr;
@@ -411,71 +416,128 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     }
   };
 
-  // The candidate stream: for each source set and each (x, y) column of the
-  // stencil, the run of stencil cells along z (contiguous in the sorted
+  // The candidate stream.  The stencil is a list of runs: for each source
+  // set and each (x, y) column, the cells along z (contiguous in the sorted
   // order; a second run holds the cell reached through the periodic wrap in
-  // z), read in batches of up to 64 staged in LDS and tested in unrolled
-  // groups of kQFlush (the batch is padded with NaN points, which never hit).
-  // After every group the queues are drained: as many rounds as keep every
-  // lane busy, and at least enough that kQFlush more pushes cannot overflow
-  // any queue; after the last group, everything left.  (One drain site, so
-  // the pair evaluation is emitted once.)
+  // z).  Lane r describes run r; the runs are concatenated into one list of
+  // M candidates that is visited in the order pos_j = j S mod M, with S
+  // coprime to M near M times the golden ratio, so every stretch of the
+  // stream samples all stencil cells evenly: each target then finds its
+  // pairs at a steady rate and the queues of all lanes fill alike (a
+  // cell-by-cell order feeds the targets near one face first and leaves the
+  // others idle).  Candidates are staged 64 at a time in LDS, relative to
+  // the target column's origin (x, y) and in the target's image (z), and
+  // tested in unrolled groups of kQFlush (the batch is padded with NaN
+  // points, which never hit).  After every group the queues are drained: as
+  // many rounds as keep every lane busy, and at least enough that kQFlush
+  // more pushes cannot overflow any queue; after the last group, everything
+  // left.  (One drain site, so the pair evaluation is emitted once.)
   float4* cb = cbuf[wv];
+  int* cown = cownb[wv];
+  int* rs = rstart[wv];
+  int* rb = rbase[wv];
+  int* rc = rcode[wv];
   const int sx = 2 * rx + 1, sy = 2 * ry + 1;
-  const int n_open = nsrc * sx * sy * 2;
-  int it = 0;                  // next (set, x, y, run) to open
-  int base = 0, ce = 0;        // unread range of the open run
-  int bbase = 0, nbat = 0, k0 = 0;
-  float px = 0.f, py = 0.f, pz = 0.f;
-  int tag = 0;
-  const float4* Sf = nullptr;
+  const int n_open = nsrc * sx * sy * 2;  // <= kMaxRuns
+  int rlen = 0;
+  if (lane < n_open) {
+    const int set = lane / (sx * sy * 2);
+    const int rem = lane - set * (sx * sy * 2);
+    const int ox = rem / (sy * 2) - rx, oy = (rem >> 1) % sy - ry, run = rem & 1;
+    const SrcSet& S = set ? s1 : s0;
+    int x = cx + ox, y = cy + oy;
+    if (x < 0) x += nc0;
+    if (x >= nc0) x -= nc0;
+    if (y < 0) y += nc1;
+    if (y >= nc1) y -= nc1;
+    int zimg = 0;  // 1: image at z - L, 2: at z + L
+    int z0 = 0, z1 = 0;
+    if (rz == 0) {
+      if (run == 0) { z0 = cz; z1 = cz + 1; }
+    } else if (run == 0) {
+      z0 = max(cz - 1, 0);
+      z1 = min(cz + nz + 1, nc2);
+    } else if (cz == 0) {
+      z0 = nc2 - 1; z1 = nc2; zimg = 1;
+    } else if (cz + nz == nc2) {
+      z0 = 0; z1 = 1; zimg = 2;
+    }
+    const int c0 = (x * nc1 + y) * nc2;
+    const int b0 = S.start[c0 + z0];
+    rlen = z1 > z0 ? S.start[c0 + z1] - b0 : 0;
+    rb[lane] = b0;
+    rc[lane] = set | (ox + 1) << 1 | (oy + 1) << 3 | zimg << 5;
+  }
+  int incl = rlen;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane < n_open) rs[lane + 1] = incl;
+  if (lane == 0) rs[0] = 0;
+  const int M = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+  // stride: near M / golden ratio, coprime to M (a permutation of 0 .. M-1)
+  int stride = 1;
+  if (M > 2) {
+    stride = max(1, (int)(0.6180339887 * M + 0.5));
+    for (;;) {
+      int ga = stride, gb = M;
+      while (gb) { const int tmp = ga % gb; ga = gb; gb = tmp; }
+      if (ga == 1) break;
+      ++stride;
+    }
+  }
+  stride = __builtin_amdgcn_readfirstlane(stride);
+  const int lane_pos = M > 0 ? (int)(((long long)lane * stride) % M) : 0;
+  const int step64 = M > 0 ? __builtin_amdgcn_readfirstlane((int)((64LL * stride) % M)) : 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // target relative to its column's origin (x, y); z as is.  A source's
+  // float x, y are relative to its own column's origin, which lies ox a0,
+  // oy a1 from the target column's origin in the target's image.
+  const float px = (float)(p.x - cx * a0), py = (float)(p.y - cy * a1), pz = (float)p.z;
+  const float a0f = (float)a0, a1f = (float)a1, Lz = Lf2;
+  int next = 0, pbase = 0;  // next stream position to stage and (next S) mod M
+  int nbat = 0, k0 = 0;
   const float nanf_ = __int_as_float(0x7fc00000);
   for (;;) {
     bool finished = false;
     if (k0 >= nbat) {
-      while (base >= ce && it < n_open) {
-        const int set = it / (sx * sy * 2);
-        const int rem = it - set * (sx * sy * 2);
-        const int ox = rem / (sy * 2) - rx, oy = (rem >> 1) % sy - ry, run = rem & 1;
-        ++it;
-        const SrcSet& S = set ? s1 : s0;
-        int x = cx + ox, y = cy + oy;
-        double shx = 0, shy = 0, shz = 0;
-        if (x < 0) { x += nc0; shx = -g.L[0]; }
-        if (x >= nc0) { x -= nc0; shx = g.L[0]; }
-        if (y < 0) { y += nc1; shy = -g.L[1]; }
-        if (y >= nc1) { y -= nc1; shy = g.L[1]; }
-        int z0 = 0, z1 = 0;
-        if (rz == 0) {
-          if (run == 0) { z0 = cz; z1 = cz + 1; }
-        } else if (run == 0) {
-          z0 = max(cz - 1, 0);
-          z1 = min(cz + nz + 1, nc2);
-        } else if (cz == 0) {
-          z0 = nc2 - 1; z1 = nc2; shz = -g.L[2];
-        } else if (cz + nz == nc2) {
-          z0 = 0; z1 = 1; shz = g.L[2];
+      if (next < M) {
+        float4 v = make_float4(nanf_, nanf_, nanf_, nanf_);
+        int own = -1;
+        if (next + lane < M) {
+          int pos = pbase + lane_pos;
+          if (pos >= M) pos -= M;
+          int lo = 0, hi = n_open;  // rs[lo] <= pos < rs[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (rs[mid] <= pos) lo = mid;
+            else hi = mid;
+          }
+          const int code = rc[lo];
+          const int set = code & 1;
+          const float ofx = (float)(((code >> 1) & 3) - 1) * a0f;
+          const float ofy = (float)(((code >> 3) & 3) - 1) * a1f;
+          const int zimg = code >> 5;
+          const float ofz = zimg == 1 ? -Lz : (zimg == 2 ? Lz : 0.0f);
+          const int sidx = rb[lo] + (pos - rs[lo]);
+          const float4 sp = (set ? s1.posf : s0.posf)[sidx];
+          v = make_float4(sp.x + ofx, sp.y + ofy, sp.z + ofz, __int_as_float(sidx | set << kSetBit));
+          own = __float_as_int(sp.w);
         }
-        const int c0 = (x * nc1 + y) * nc2;
-        base = __builtin_amdgcn_readfirstlane(S.start[c0 + z0]);
-        ce = __builtin_amdgcn_readfirstlane(S.start[c0 + z1]);
-        // target relative to the source cell column's origin (x, y) and to
-        // the image of the run (z)
-        px = (float)(p.x - shx - x * a0);
-        py = (float)(p.y - shy - y * a1);
-        pz = (float)(p.z - shz);
-        tag = set << kSetBit;
-        Sf = S.posf;
-      }
-      if (base < ce) {
-        nbat = min(64, ce - base);
-        bbase = base;
-        base += nbat;
-        k0 = 0;
-        cb[lane] = lane < nbat ? Sf[bbase + lane] : make_float4(nanf_, nanf_, nanf_, nanf_);
+        cb[lane] = v;
+        if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) cown[lane] = own;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        nbat = min(64, M - next);
+        next += nbat;
+        pbase += step64;
+        if (pbase >= M) pbase -= M;
+        k0 = 0;
       } else {
         finished = true;
       }
@@ -496,10 +558,10 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
         bool hit = active && r2 < rc2f;
         if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) {
           // pairs inside a body with a dense intra-body block are not listed
-          hit = hit && (own_body < 0 || __float_as_int(cnd.w) != own_body);
+          hit = hit && (own_body < 0 || cown[k0 + kk] != own_body);
         }
         // the slot at pushed is free (at most kQ - 1 entries pending)
-        qb[pushed & (kQ - 1)][lane] = (bbase + k0 + kk) | tag;
+        qb[pushed & (kQ - 1)][lane] = __float_as_int(cnd.w);
         pushed += hit ? 1 : 0;
       }
       k0 += kQFlush;
