@@ -480,6 +480,7 @@ void compute_params(pe_context* c) {
     g.L[d] = p.box[d];
   }
   g.Nzc = p.mesh[2] / 2 + 1;
+  g.Nzs = (g.Nzc + 15) / 16 * 16;
   g.P = p.P;
   g.wexp = 2.0 * c->xi * c->xi / c->eta;
   g.wnorm = std::sqrt(2.0 * c->xi * c->xi / (M_PI * c->eta));
@@ -510,7 +511,7 @@ void build_twiddles(pe_context* c) {
 
 void ensure_grids(pe_context* c) {
   const int64_t G = (int64_t)c->p.mesh[0] * c->p.mesh[1] * c->p.mesh[2];
-  const int64_t Gc = (int64_t)c->p.mesh[0] * c->p.mesh[1] * (c->p.mesh[2] / 2 + 1);
+  const int64_t Gc = (int64_t)c->p.mesh[0] * c->p.mesh[1] * c->gg.Nzs;
   c->gridA.ensure(G);
   c->gridB.ensure(G);
   c->gridC.ensure(Gc);

@@ -2,8 +2,11 @@
 // "Spectral Ewald implementation", steps 3-5).
 //
 // Layout: real grids [Nx][Ny][Nz] (z fastest); the half spectrum
-// [Nx][Ny][Nzc], Nzc = Nz/2 + 1.  Five passes, each one read and one write of
-// the grid through LDS:
+// [Nx][Ny][Nzs], Nzc = Nz/2 + 1 values used per row and the row stride Nzs
+// rounded up to a multiple of 16, so the strided passes read every group of
+// 16 lines as whole 128-byte segments (with Nzc odd, rows of Nzc values would
+// start at every alignment and each group would touch two segments).  Five
+// passes, each one read and one write of the grid through LDS:
 //   1. z, real -> complex: two real lines packed into one complex line, one
 //      complex FFT, then split (X_a = (Z_k + conj Z_{N-k})/2,
 //      X_b = (Z_k - conj Z_{N-k})/2i).
@@ -197,7 +200,7 @@ __device__ C* lds_fft(C* in, C* out, int n, int nl, LdsLayout ls, const FFTPlan1
 // normalization, in separable form: G = ex[x] ey[y] ez[z] / (kx^2 + ky^2 + kz^2)
 // with e_d = exp(-(1 - eta) k_d^2 / (4 xi^2)) tabulated per axis on the host.
 struct ScaleArgs {
-  int Nx, Ny, Nz, Nzc;
+  int Nx, Ny, Nz, Nzc, Nzs;
   const double* ex;   // Nx
   const double* ey;   // Ny
   const double* ez;   // Nzc
@@ -208,11 +211,13 @@ struct ScaleArgs {
 };
 
 // Lines along a strided axis: line L (0..nlines-1), element j at
-// base(L) + j*stride, base(L) = (L / inner) * outer + (L % inner).
+// base(L) + j*stride, base(L) = (L / inner) * outer + (L % inner); a line
+// with L % vmod >= vlim is row padding and is skipped.
 template <typename T, bool SCALE>
 __global__ void __launch_bounds__(512) fft_lines_kernel(typename C2<T>::type* __restrict__ data, int n,
                                                         int64_t nlines, int64_t inner, int64_t outer,
-                                                        int64_t stride, int lpb, FFTPlan1D plan,
+                                                        int64_t stride, int vmod, int vlim, int lpb,
+                                                        FFTPlan1D plan,
                                                         const typename C2<T>::type* __restrict__ tw,
                                                         int fwd, ScaleArgs sa) {
   using C = typename C2<T>::type;
@@ -225,23 +230,24 @@ __global__ void __launch_bounds__(512) fft_lines_kernel(typename C2<T>::type* __
   const int64_t L0 = (int64_t)blockIdx.x * lpb;
   if ((int)threadIdx.x < lpb) {
     const int64_t L = L0 + threadIdx.x;
-    lbase[threadIdx.x] = (L / inner) * outer + (L % inner);
-    if (SCALE && L < nlines) {
-      // x lines: L = y * Nzc + kz
-      const int y = (int)(L / sa.Nzc);
-      const int kz = (int)(L - (int64_t)y * sa.Nzc);
+    const bool valid = L < nlines && (int)(L % vmod) < vlim;
+    lbase[threadIdx.x] = valid ? (L / inner) * outer + (L % inner) : -1;
+    if (SCALE && valid) {
+      // x lines: L = y * Nzs + kz
+      const int y = (int)(L / sa.Nzs);
+      const int kz = (int)(L - (int64_t)y * sa.Nzs);
       lfac[threadIdx.x] = (T)(sa.ey[y] * sa.ez[kz] * sa.norm);
       lksq[threadIdx.x] = (T)(sa.ky2[y] + sa.kz2[kz]);
     }
   }
   __syncthreads();
-  const int nvalid = (int)min<int64_t>((int64_t)lpb, nlines - L0);
   const int llpb = __builtin_ctz(lpb);  // lpb is a power of two
   for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
     const int j = t >> llpb;
     const int c = t & (lpb - 1);
     C v = {0, 0};
-    if (c < nvalid) v = data[lbase[c] + (int64_t)j * stride];
+    const int64_t lb = lbase[c];
+    if (lb >= 0) v = data[lb + (int64_t)j * stride];
     b0[ll.at(c, j)] = v;
   }
   __syncthreads();
@@ -250,7 +256,7 @@ __global__ void __launch_bounds__(512) fft_lines_kernel(typename C2<T>::type* __
     for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
       const int c = t / n;
       const int j = t - c * n;
-      if (c >= nvalid) continue;
+      if (lbase[c] < 0) continue;
       const T k2 = (T)sa.kx2[j] + lksq[c];
       const T gk = k2 > (T)0 ? (T)sa.ex[j] * lfac[c] / k2 : (T)0;
       C v = res[ll.at(c, j)];
@@ -263,7 +269,8 @@ __global__ void __launch_bounds__(512) fft_lines_kernel(typename C2<T>::type* __
   for (int t = threadIdx.x; t < n * lpb; t += blockDim.x) {
     const int j = t >> llpb;
     const int c = t & (lpb - 1);
-    if (c < nvalid) data[lbase[c] + (int64_t)j * stride] = res[ll.at(c, j)];
+    const int64_t lb = lbase[c];
+    if (lb >= 0) data[lb + (int64_t)j * stride] = res[ll.at(c, j)];
   }
 }
 
@@ -271,7 +278,7 @@ __global__ void __launch_bounds__(512) fft_lines_kernel(typename C2<T>::type* __
 template <typename T>
 __global__ void __launch_bounds__(256) fft_z_r2c_kernel(const T* __restrict__ real,
                                                         typename C2<T>::type* __restrict__ cplx,
-                                                        int Nz, int64_t nlines, int ppb, FFTPlan1D plan,
+                                                        int Nz, int Nzs, int64_t nlines, int ppb, FFTPlan1D plan,
                                                         const typename C2<T>::type* __restrict__ tw) {
   using C = typename C2<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -301,15 +308,15 @@ __global__ void __launch_bounds__(256) fft_z_r2c_kernel(const T* __restrict__ re
     const C A = {(T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y - zn.y)};
     const T dr = zk.x - zn.x, di = zk.y + zn.y;
     const C Bv = {(T)0.5 * di, (T)-0.5 * dr};
-    if (la < nlines) cplx[la * Nzc + k] = A;
-    if (lb < nlines) cplx[lb * Nzc + k] = Bv;
+    if (la < nlines) cplx[la * Nzs + k] = A;
+    if (lb < nlines) cplx[lb * Nzs + k] = Bv;
   }
 }
 
 // z pass, half complex -> real (unnormalized inverse), two lines at once.
 template <typename T>
 __global__ void __launch_bounds__(256) fft_z_c2r_kernel(const typename C2<T>::type* __restrict__ cplx,
-                                                        T* __restrict__ real, int Nz, int64_t nlines,
+                                                        T* __restrict__ real, int Nz, int Nzs, int64_t nlines,
                                                         int ppb, FFTPlan1D plan,
                                                         const typename C2<T>::type* __restrict__ tw) {
   using C = typename C2<T>::type;
@@ -325,11 +332,11 @@ __global__ void __launch_bounds__(256) fft_z_c2r_kernel(const typename C2<T>::ty
     const int64_t la = 2 * (p0 + c), lb = la + 1;
     C A = {0, 0}, Bv = {0, 0};
     if (k < Nzc) {
-      if (la < nlines) A = cplx[la * Nzc + k];
-      if (lb < nlines) Bv = cplx[lb * Nzc + k];
+      if (la < nlines) A = cplx[la * Nzs + k];
+      if (lb < nlines) Bv = cplx[lb * Nzs + k];
     } else {
-      if (la < nlines) { A = cplx[la * Nzc + (Nz - k)]; A.y = -A.y; }
-      if (lb < nlines) { Bv = cplx[lb * Nzc + (Nz - k)]; Bv.y = -Bv.y; }
+      if (la < nlines) { A = cplx[la * Nzs + (Nz - k)]; A.y = -A.y; }
+      if (lb < nlines) { Bv = cplx[lb * Nzs + (Nz - k)]; Bv.y = -Bv.y; }
     }
     b0[c * ls + k] = {A.x - Bv.y, A.y + Bv.x};  // A + i B
   }
@@ -414,7 +421,7 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   using C = typename C2<T>::type;
   C* gC = reinterpret_cast<C*>(gCv);
   const GridGeom& g = c->gg;
-  const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2], Nzc = g.Nzc;
+  const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2], Nzc = g.Nzc, Nzs = g.Nzs;
   const C* twx;
   const C* twy;
   const C* twz;
@@ -435,12 +442,12 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
     const int64_t npairs = (nlines + 1) / 2;
     const unsigned nb = (unsigned)((npairs + ppb - 1) / ppb);
     const size_t sh = 2 * (size_t)ppb * (Nz + 1) * sizeof(C);
-    hipLaunchKernelGGL(fft_z_r2c_kernel<T>, dim3(nb), dim3(256), sh, s, gA, gC, Nz, nlines, ppb,
+    hipLaunchKernelGGL(fft_z_r2c_kernel<T>, dim3(nb), dim3(256), sh, s, gA, gC, Nz, Nzs, nlines, ppb,
                        c->plan[2], twz);
     PE_CHECK_LAUNCH();
   }
   ScaleArgs sa{};
-  sa.Nx = Nx; sa.Ny = Ny; sa.Nz = Nz; sa.Nzc = Nzc;
+  sa.Nx = Nx; sa.Ny = Ny; sa.Nz = Nz; sa.Nzc = Nzc; sa.Nzs = Nzs;
   const double* gt = c->gtab.get();
   sa.ex = gt;
   sa.ey = gt + Nx;
@@ -452,24 +459,24 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   // 2. y forward: lines (x, kz), element y
   auto ypass = [&](int fwd) {
     ProfScope ps(c->prof, s, fwd > 0 ? PE_PROF_FFT_Y_FWD : PE_PROF_FFT_Y_INV, sizeof(T) == 8, 1.0);
-    const int64_t nlines = (int64_t)Nx * Nzc;
+    const int64_t nlines = (int64_t)Nx * Nzs;
     const int lpb = strided_lines_per_block(Ny, sizeof(C), sbudget);
     const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
     const size_t sh = 2 * (size_t)lpb * Ny * sizeof(C);
     hipLaunchKernelGGL((fft_lines_kernel<T, false>), dim3(nb), dim3(lpb * Ny >= 4096 ? 512 : 256), sh, s, gC, Ny, nlines,
-                       (int64_t)Nzc, (int64_t)Ny * Nzc, (int64_t)Nzc, lpb, c->plan[1], twy, fwd, sa);
+                       (int64_t)Nzs, (int64_t)Ny * Nzs, (int64_t)Nzs, Nzs, Nzc, lpb, c->plan[1], twy, fwd, sa);
     PE_CHECK_LAUNCH();
   };
   ypass(1);
   // 3. x forward + scale + x inverse: lines (y, kz), element x
   {
     ProfScope ps(c->prof, s, PE_PROF_FFT_X_SCALE, sizeof(T) == 8, 1.0);
-    const int64_t nlines = (int64_t)Ny * Nzc;
+    const int64_t nlines = (int64_t)Ny * Nzs;
     const int lpb = strided_lines_per_block(Nx, sizeof(C), sbudget);
     const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
     const size_t sh = 2 * (size_t)lpb * Nx * sizeof(C);
     hipLaunchKernelGGL((fft_lines_kernel<T, true>), dim3(nb), dim3(lpb * Nx >= 4096 ? 512 : 256), sh, s, gC, Nx, nlines,
-                       nlines, (int64_t)0, (int64_t)Ny * Nzc, lpb, c->plan[0], twx, 1, sa);
+                       nlines, (int64_t)0, (int64_t)Ny * Nzs, Nzs, Nzc, lpb, c->plan[0], twx, 1, sa);
     PE_CHECK_LAUNCH();
   }
   // 4. y inverse
@@ -482,7 +489,7 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
     const int64_t npairs = (nlines + 1) / 2;
     const unsigned nb = (unsigned)((npairs + ppb - 1) / ppb);
     const size_t sh = 2 * (size_t)ppb * (Nz + 1) * sizeof(C);
-    hipLaunchKernelGGL(fft_z_c2r_kernel<T>, dim3(nb), dim3(256), sh, s, gC, gB, Nz, nlines, ppb,
+    hipLaunchKernelGGL(fft_z_c2r_kernel<T>, dim3(nb), dim3(256), sh, s, gC, gB, Nz, Nzs, nlines, ppb,
                        c->plan[2], twz);
     PE_CHECK_LAUNCH();
   }

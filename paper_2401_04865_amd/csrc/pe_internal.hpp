@@ -72,6 +72,7 @@ struct DevBuf {
 struct GridGeom {
   int N[3];         // mesh
   int Nzc;          // N[2]/2 + 1
+  int Nzs;          // row stride of the half spectrum: Nzc rounded up to a multiple of 16
   double h[3];      // spacing
   double inv_h[3];
   double L[3];
