@@ -121,6 +121,24 @@ __global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b
   if (i < n) b[i] = a[i];
 }
 
+// Sum of a[0..n) in a fixed order: sum_partial_kernel leaves one partial
+// per block of `chunk` values, sum_kernel (one block) adds the partials.
+__global__ void sum_partial_kernel(const double* __restrict__ a, int64_t n, int64_t chunk,
+                                   double* __restrict__ part) {
+  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+  double s = 0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) s += a[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __shared__ double sh[16];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+    part[blockIdx.x] = t;
+  }
+}
+
 __global__ void sum_kernel(const double* __restrict__ a, int64_t n, double* __restrict__ out) {
   // single block, fixed order
   double s = 0;
@@ -979,7 +997,12 @@ pe_status pe_forces_torques(pe_context* c, double* body_force, double* body_torq
   if (ion_force) dcopy(s, f + 3 * nb, ion_force, 3 * ni);
   if (bead_force) dcopy(s, f, bead_force, 3 * nb);
   double* tot = scal(c);
-  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, s, u, na, tot);
+  {
+    const int64_t chunk = std::max<int64_t>(4096, (na + 1023) / 1024);
+    const int64_t nparts = std::max<int64_t>(1, (na + chunk - 1) / chunk);
+    hipLaunchKernelGGL(sum_partial_kernel, dim3((unsigned)nparts), dim3(256), 0, s, u, na, chunk, c->red.get());
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, s, c->red.get(), nparts, tot);
+  }
   PE_CHECK_LAUNCH();
   *total_energy = fetch(c, tot);
   c->have_forces = true;

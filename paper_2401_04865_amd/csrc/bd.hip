@@ -72,24 +72,41 @@ __device__ __forceinline__ void quat_to_R(const double* q, double R[3][3]) {
   R[2][0] = 2 * (x * z - w * y); R[2][1] = 2 * (y * z + w * x); R[2][2] = 1 - 2 * (x * x + y * y);
 }
 
-// One thread per body: rotational drag, its inverse and a Cholesky factor of
-// the inverse, the rigid-body displacement and rotation.  Writes the new
-// centre/orientation and the rotation (old -> new) for the bead update.
-__global__ void bd_bodies_kernel(int64_t nb, const int64_t* __restrict__ off, const double* __restrict__ rel,
-                                 const double* __restrict__ F, const double* __restrict__ L, double dt, double kT,
-                                 double gamma, uint64_t seed, uint64_t step, double* __restrict__ X,
-                                 double* __restrict__ quat, double* __restrict__ Rnew) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per body: the lanes sum the rotational drag over the beads
+// (fixed order: lane strides, then a butterfly); lane 0 forms its inverse and
+// a Cholesky factor of the inverse, the rigid-body displacement and rotation.
+// Writes the new centre/orientation and the rotation (old -> new) for the
+// bead update.
+__global__ void __launch_bounds__(64) bd_bodies_kernel(int64_t nb, const int64_t* __restrict__ off,
+                                                       const double* __restrict__ rel, const double* __restrict__ F,
+                                                       const double* __restrict__ L, double dt, double kT,
+                                                       double gamma, uint64_t seed, uint64_t step,
+                                                       double* __restrict__ X, double* __restrict__ quat,
+                                                       double* __restrict__ Rnew) {
+  const int64_t b = blockIdx.x;
   if (b >= nb) return;
+  const int lane = threadIdx.x;
   const int64_t o0 = off[b], o1 = off[b + 1];
   const double N = (double)(o1 - o0);
-  double K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int64_t j = o0; j < o1; ++j) {
-    const double r[3] = {rel[3 * j], rel[3 * j + 1], rel[3 * j + 2]};
-    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-    for (int a = 0; a < 3; ++a)
-      for (int c = 0; c < 3; ++c) K[a][c] += gamma * ((a == c ? r2 : 0.0) - r[a] * r[c]);
+  // xx, xy, xz, yy, yz, zz of sum_j (r_j^2 I - r_j r_j^T)
+  double k6[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t j = o0 + lane; j < o1; j += 64) {
+    const double rx = rel[3 * j], ry = rel[3 * j + 1], rz = rel[3 * j + 2];
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    k6[0] += r2 - rx * rx;
+    k6[1] -= rx * ry;
+    k6[2] -= rx * rz;
+    k6[3] += r2 - ry * ry;
+    k6[4] -= ry * rz;
+    k6[5] += r2 - rz * rz;
   }
+#pragma unroll
+  for (int m = 0; m < 6; ++m)
+    for (int o = 32; o > 0; o >>= 1) k6[m] += __shfl_xor(k6[m], o, 64);
+  if (lane != 0) return;
+  double K[3][3] = {{gamma * k6[0], gamma * k6[1], gamma * k6[2]},
+                    {gamma * k6[1], gamma * k6[3], gamma * k6[4]},
+                    {gamma * k6[2], gamma * k6[4], gamma * k6[5]}};
   // inverse by cofactors (K is SPD for a body that is not a single point or a line)
   double Ki[3][3];
   const double det = K[0][0] * (K[1][1] * K[2][2] - K[1][2] * K[2][1]) - K[0][1] * (K[1][0] * K[2][2] - K[1][2] * K[2][0]) +
@@ -185,7 +202,7 @@ extern "C" pe_status pe_bd_step(pe_context* c, double dt, double kT, double gamm
                          gamma, seed, step, ion_pos);
     c->bd_R.ensure(9 * std::max<int64_t>(nbody, 1));
     if (nbody) {
-      hipLaunchKernelGGL(bd_bodies_kernel, dim3(nblk(nbody, 64)), dim3(64), 0, s, nbody, c->off.get(), c->rel.get(),
+      hipLaunchKernelGGL(bd_bodies_kernel, dim3((unsigned)nbody), dim3(64), 0, s, nbody, c->off.get(), c->rel.get(),
                          c->bodyF.get(), c->bodyL.get(), dt, kT, gamma, seed, step, body_center, body_quat,
                          c->bd_R.get());
       hipLaunchKernelGGL(bd_beads_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, c->body_of.get(), c->rel.get(),
