@@ -238,6 +238,14 @@ typedef enum {
 } pe_prof_class;
 pe_status pe_profile_enable(pe_context* ctx, int32_t on);
 pe_status pe_profile_read(pe_context* ctx, double* out);
+/*
+ * Restrict the event recording to the classes whose bit is set in
+ * class_mask (bit c = class c, float and double launches alike); the others
+ * run without events while profiling is on, so one class can be timed inside
+ * a run without slowing the rest.  The mask persists until changed;
+ * 0xffffffff (the default) records every class.  PE_ERR_ARG if ctx is null.
+ */
+pe_status pe_profile_select(pe_context* ctx, uint32_t class_mask);
 
 /*
  * Learned initial guess (a per-bead network, not in the paper).  Features of

@@ -96,6 +96,7 @@ SIGNATURES = {
     "pe_apply_saddle": [_vp, _vp, _vp, _i32],
     "pe_profile_enable": [_vp, _i32],
     "pe_profile_read": [_vp, ctypes.POINTER(_dbl)],
+    "pe_profile_select": [_vp, ctypes.c_uint32],
     "pe_guess_init": [_vp, _u64],
     "pe_guess_set_types": [_vp, ctypes.POINTER(_i32)],
     "pe_guess_record": [_vp, _vp],
@@ -229,6 +230,11 @@ class Context:
 
     def pe_profile_enable(self, on=True):
         self._chk(_lib.pe_profile_enable(self.h, 1 if on else 0))
+
+    def pe_profile_select(self, classes=None):
+        """Record events only for the named classes (None: all)."""
+        mask = 0xFFFFFFFF if classes is None else sum(1 << PROF_CLASSES.index(n) for n in classes)
+        self._chk(_lib.pe_profile_select(self.h, mask))
 
     def pe_profile_read(self):
         """{class: (launches, total ms, work units)} for float kernels, {class + '_f64': ...} for double."""

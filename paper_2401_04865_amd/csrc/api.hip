@@ -160,22 +160,43 @@ struct Stats {
   double bad, mx, mn;
 };
 
-Stats array_stats(pe_context* c, const double* a, int64_t n, int stride, int col) {
-  Stats st{0, -INFINITY, INFINITY};
-  if (n == 0 || !a) return st;
-  unsigned nb = nblk(n, 256);
-  if (nb > 256) nb = 256;
-  hipLaunchKernelGGL(stats_kernel, dim3(nb), dim3(256), 0, c->stream, a, n, stride, col, c->red.get());
-  PE_CHECK_LAUNCH();
-  std::vector<double> h(3 * nb);
-  PE_HIP(hipMemcpyAsync(h.data(), c->red.get(), sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, c->stream));
-  PE_HIP(hipStreamSynchronize(c->stream));
-  for (unsigned b = 0; b < nb; ++b) {
-    st.bad += h[3 * b];
-    st.mx = std::max(st.mx, h[3 * b + 1]);
-    st.mn = std::min(st.mn, h[3 * b + 2]);
+// Several arrays at once: every stats launch writes its own slice of the
+// reduction buffer, then one copy and one synchronization.
+struct StatReq {
+  const double* a;
+  int64_t n;
+  int stride, col;
+};
+
+std::vector<Stats> array_stats(pe_context* c, const std::vector<StatReq>& reqs) {
+  std::vector<Stats> out(reqs.size(), Stats{0, -INFINITY, INFINITY});
+  std::vector<unsigned> nbs(reqs.size(), 0);
+  size_t slot = 0;
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    const StatReq& q = reqs[r];
+    if (q.n == 0 || !q.a) continue;
+    unsigned nb = nblk(q.n, 256);
+    if (nb > 256) nb = 256;
+    nbs[r] = nb;
+    hipLaunchKernelGGL(stats_kernel, dim3(nb), dim3(256), 0, c->stream, q.a, q.n, q.stride, q.col,
+                       c->red.get() + 3 * slot);
+    PE_CHECK_LAUNCH();
+    slot += nb;
   }
-  return st;
+  if (slot == 0) return out;
+  require(3 * slot <= c->red.cap, "reduction buffer too small for the input checks");
+  std::vector<double> h(3 * slot);
+  PE_HIP(hipMemcpyAsync(h.data(), c->red.get(), sizeof(double) * 3 * slot, hipMemcpyDeviceToHost, c->stream));
+  PE_HIP(hipStreamSynchronize(c->stream));
+  size_t o = 0;
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    for (unsigned b = 0; b < nbs[r]; ++b, ++o) {
+      out[r].bad += h[3 * o];
+      out[r].mx = std::max(out[r].mx, h[3 * o + 1]);
+      out[r].mn = std::min(out[r].mn, h[3 * o + 2]);
+    }
+  }
+  return out;
 }
 
 void dcopy(hipStream_t s, const double* a, double* b, int64_t n) {
@@ -708,17 +729,25 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   }
   // validation on the device
   double sig_max = 0, sig_min = INFINITY;
-  for (int d = 0; d < 3; ++d) {
-    Stats a = array_stats(c, c->bead_x.get(), nb, 3, d);
-    require(a.bad == 0, "bead positions must be finite");
-    Stats b = array_stats(c, c->ion_x.get(), n_ion, 3, d);
-    require(b.bad == 0, "ion positions must be finite");
-  }
   {
-    Stats a = array_stats(c, c->bead_sig.get(), nb, 1, 0);
-    Stats b = array_stats(c, c->ion_sig.get(), n_ion, 1, 0);
-    Stats q1 = array_stats(c, c->ion_q.get(), n_ion, 1, 0);
-    Stats q2 = array_stats(c, c->body_Q.get(), n_body, 1, 0);
+    std::vector<StatReq> reqs;
+    for (int d = 0; d < 3; ++d) {
+      reqs.push_back({c->bead_x.get(), nb, 3, d});
+      reqs.push_back({c->ion_x.get(), n_ion, 3, d});
+    }
+    reqs.push_back({c->bead_sig.get(), nb, 1, 0});
+    reqs.push_back({c->ion_sig.get(), n_ion, 1, 0});
+    reqs.push_back({c->ion_q.get(), n_ion, 1, 0});
+    reqs.push_back({c->body_Q.get(), n_body, 1, 0});
+    const std::vector<Stats> st = array_stats(c, reqs);
+    for (int d = 0; d < 3; ++d) {
+      require(st[2 * d].bad == 0, "bead positions must be finite");
+      require(st[2 * d + 1].bad == 0, "ion positions must be finite");
+    }
+    const Stats& a = st[6];
+    const Stats& b = st[7];
+    const Stats& q1 = st[8];
+    const Stats& q2 = st[9];
     require(a.bad == 0 && b.bad == 0 && q1.bad == 0 && q2.bad == 0, "charges and widths must be finite");
     if (c->p.reg == PE_REG_GAUSSIAN) {
       require(nb == 0 || a.mn > 0, "bead widths must be positive");
@@ -946,6 +975,12 @@ pe_status pe_profile_enable(pe_context* c, int32_t on) {
   PE_HIP(hipMemsetAsync(c->pair_count.get(), 0, 2 * sizeof(unsigned long long), c->stream));
   PE_HIP(hipStreamSynchronize(c->stream));
   PE_API_END(c)
+}
+
+pe_status pe_profile_select(pe_context* c, uint32_t class_mask) {
+  if (!c) return PE_ERR_ARG;
+  c->prof.mask = class_mask;
+  return PE_OK;
 }
 
 pe_status pe_profile_read(pe_context* c, double* out) {

@@ -159,6 +159,7 @@ struct FFTPlan1D {
 // the stream has been synchronized.
 struct Prof {
   bool on = false;
+  uint32_t mask = 0xffffffffu;  // classes that record events
   double ms[2 * PE_PROF_NCLASS] = {};
   double cnt[2 * PE_PROF_NCLASS] = {};
   double work[2 * PE_PROF_NCLASS] = {};
@@ -214,7 +215,8 @@ struct ProfScope {
   hipEvent_t a = nullptr;
   // dbl: the launch computes in double (its class is offset by PE_PROF_NCLASS);
   // w: work units of the launches inside the scope
-  ProfScope(Prof& prof, hipStream_t st, int c, bool dbl, double w = 0) : p(prof.on ? &prof : nullptr), s(st),
+  ProfScope(Prof& prof, hipStream_t st, int c, bool dbl, double w = 0)
+      : p(prof.on && ((prof.mask >> c) & 1u) ? &prof : nullptr), s(st),
       cls(c + (dbl ? PE_PROF_NCLASS : 0)), work(w) {
     if (p) {
       a = p->take();
@@ -308,6 +310,7 @@ struct pe_context {
   // bead-bead real-space operator, CSR over sorted bead rows
   int64_t nnz = 0;
   pe::DevBuf<int64_t> row_ptr;
+  pe::DevBuf<int64_t> scan_tmp;    // prefix-sum workspace
   pe::DevBuf<int> cnt;
   pe::DevBuf<int> col;
   pe::DevBuf<double> val64;

@@ -750,24 +750,23 @@ void build_bead_matrix(pe_context* c) {
     out.dense = c->pc.dense.get();
   }
   if (n > 0) launch_queue<MODE_COUNT, double, double>(s, B, sb, sb, 1, c->rg, out);
-  std::vector<int> cnt(n);
-  if (n > 0) PE_HIP(hipMemcpyAsync(cnt.data(), c->cnt.get(), sizeof(int) * n, hipMemcpyDeviceToHost, s));
-  PE_HIP(hipStreamSynchronize(s));
-  std::vector<int64_t> rp(n + 1, 0);
-  for (int64_t i = 0; i < n; ++i) rp[i + 1] = rp[i] + cnt[i];
-  c->nnz = rp[n];
+  // row offsets on the device; only the total comes back to size the arrays
   c->row_ptr.ensure(n + 1);
+  c->scan_tmp.ensure((size_t)scan_workspace(n));
+  launch_exclusive_scan(s, c->cnt.get(), n, c->row_ptr.get(), c->scan_tmp.get());
+  int64_t nnz = 0;
+  PE_HIP(hipMemcpyAsync(&nnz, c->row_ptr.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PE_HIP(hipStreamSynchronize(s));
+  c->nnz = nnz;
   c->col.ensure(c->nnz);
   c->val64.ensure(c->nnz);
   c->have_val32 = c->p.precision == PE_MIXED;
   if (c->have_val32) c->val32.ensure(c->nnz);
-  PE_HIP(hipMemcpyAsync(c->row_ptr.get(), rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
   out.row_ptr = c->row_ptr.get();
   out.col = c->col.get();
   out.v64 = c->val64.get();
   out.v32 = c->have_val32 ? c->val32.get() : nullptr;
   if (n > 0) launch_queue<MODE_FILL, double, double>(s, B, sb, sb, 1, c->rg, out);
-  PE_HIP(hipStreamSynchronize(s));
 }
 
 namespace {

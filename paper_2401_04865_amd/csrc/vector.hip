@@ -392,4 +392,110 @@ void launch_segment_sort(hipStream_t s, const int* start, int nseg, int* keys) {
   PE_CHECK_LAUNCH();
 }
 
+// ------------------------------------------------------------------ scan
+//
+// Exclusive prefix sum of int counts into 64-bit offsets in three launches:
+// per-tile totals (kScanTile values per block), one block scanning the
+// totals in order, then every tile scanned again locally and offset.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__global__ void __launch_bounds__(kScanThreads) scan_tile_sum_kernel(const int* __restrict__ in, int64_t n,
+                                                                     int64_t* __restrict__ tot) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t v = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+    if (i < n) v += in[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __shared__ int64_t sh[kScanThreads / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) t += sh[w];
+    tot[blockIdx.x] = t;
+  }
+}
+
+// One block: tot[b] <- sum of tot[0..b), tot[nt] <- total.  Each thread
+// scans a contiguous run serially; the run totals are scanned in LDS.
+__global__ void __launch_bounds__(1024) scan_tile_offsets_kernel(int64_t* __restrict__ tot, int64_t nt) {
+  __shared__ int64_t run[1024];
+  const int64_t per = (nt + 1023) / 1024;
+  const int64_t b0 = threadIdx.x * per, b1 = min(nt, b0 + per);
+  int64_t s = 0;
+  for (int64_t b = b0; b < b1; ++b) s += tot[b];
+  run[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t acc = 0;
+    for (int k = 0; k < 1024; ++k) {
+      const int64_t t = run[k];
+      run[k] = acc;
+      acc += t;
+    }
+    tot[nt] = acc;
+  }
+  __syncthreads();
+  int64_t acc = run[threadIdx.x];
+  for (int64_t b = b0; b < b1; ++b) {
+    const int64_t t = tot[b];
+    tot[b] = acc;
+    acc += t;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_tile_write_kernel(const int* __restrict__ in, int64_t n,
+                                                                       const int64_t* __restrict__ tot,
+                                                                       int64_t* __restrict__ out) {
+  // thread t owns the kScanPer consecutive values t * kScanPer .. of the tile
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  int v[kScanPer];
+  int64_t own = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    const int64_t i = base + k;
+    v[k] = i < n ? in[i] : 0;
+    own += v[k];
+  }
+  // exclusive scan of the per-thread totals across the block
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t inc = own;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  __shared__ int64_t wsum[kScanThreads / 64];
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int64_t pre = tot[blockIdx.x];
+  for (int k = 0; k < w; ++k) pre += wsum[k];
+  int64_t acc = pre + inc - own;
+  for (int k = 0; k < kScanPer; ++k) {
+    const int64_t i = base + k;
+    if (i < n) out[i] = acc;
+    acc += v[k];
+  }
+}
+
+int64_t scan_workspace(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+void launch_exclusive_scan(hipStream_t s, const int* in, int64_t n, int64_t* out, int64_t* tmp) {
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  if (nt > 0) {
+    hipLaunchKernelGGL(scan_tile_sum_kernel, dim3((unsigned)nt), dim3(kScanThreads), 0, s, in, n, tmp);
+    PE_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(scan_tile_offsets_kernel, dim3(1), dim3(1024), 0, s, tmp, nt);
+  PE_CHECK_LAUNCH();
+  if (nt > 0) {
+    hipLaunchKernelGGL(scan_tile_write_kernel, dim3((unsigned)nt), dim3(kScanThreads), 0, s, in, n, tmp, out);
+    PE_CHECK_LAUNCH();
+  }
+  // out[n] = total
+  PE_HIP(hipMemcpyAsync(out + n, tmp + nt, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+}
+
 }  // namespace pe

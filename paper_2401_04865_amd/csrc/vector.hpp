@@ -34,6 +34,10 @@ void launch_backsolve(hipStream_t s, const double* st, int m, int k, double* y);
 
 // Sort every segment [start[k], start[k+1]) of keys ascending, in place.
 void launch_segment_sort(hipStream_t s, const int* start, int nseg, int* keys);
+// out[0] = 0, out[i+1] = in[0] + ... + in[i] (i < n), summed in 64 bits;
+// tmp holds scan_workspace(n) values.
+int64_t scan_workspace(int64_t n);
+void launch_exclusive_scan(hipStream_t s, const int* in, int64_t n, int64_t* out, int64_t* tmp);
 
 // per-particle kernels of the solve / force passes (solver unit)
 void launch_rhs_top(hipStream_t s, int64_t n, const double* rel, const double* E0, const double* phi_ion,
