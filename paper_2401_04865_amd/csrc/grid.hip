@@ -16,6 +16,7 @@
 // m0-P/2+1 .. m0+P/2 with m0 = floor(x/h); odd P is centred on rint(x/h).
 // Index and displacement are computed in double for both precisions, so
 // the float and double paths use the same support.
+#include <climits>
 #include <vector>
 
 #include "pe_internal.hpp"
@@ -100,35 +101,63 @@ __device__ __forceinline__ int axis_start(double x, double inv_h, int P) {
   return support_start(x, inv_h, P, delta);
 }
 
-__global__ void tile_count_kernel(const double4* __restrict__ pos, int64_t n, GridGeom g,
-                                  int* __restrict__ count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double4 p = pos[i];
-  int tx[4], ty[4], tz[4];
-  const int nx = axis_tiles(axis_start(p.x, g.inv_h[0], g.P), g.P, g.N[0], tx);
-  const int ny = axis_tiles(axis_start(p.y, g.inv_h[1], g.P), g.P, g.N[1], ty);
-  const int nz = axis_tiles(axis_start(p.z, g.inv_h[2], g.P), g.P, g.N[2], tz);
-  for (int a = 0; a < nx; ++a)
-    for (int b = 0; b < ny; ++b)
-      for (int c = 0; c < nz; ++c) atomicAdd(&count[(tx[a] * g.ntile[1] + ty[b]) * g.ntile[2] + tz[c]], 1);
+// Tiles a particle's support overlaps, per axis, in ascending order.
+__device__ __forceinline__ int sorted_axis_tiles(double x, double inv_h, int P, int N, int* t) {
+  const int n = axis_tiles(axis_start(x, inv_h, P), P, N, t);
+  for (int a = 1; a < n; ++a)
+    for (int b = a; b > 0 && t[b - 1] > t[b]; --b) {
+      const int u = t[b];
+      t[b] = t[b - 1];
+      t[b - 1] = u;
+    }
+  return n;
 }
 
-__global__ void tile_fill_kernel(const double4* __restrict__ pos, int64_t n, GridGeom g,
-                                 int* __restrict__ cursor, int* __restrict__ entries) {
+// Tile lists with one atomic per distinct tile of a wavefront: every lane
+// walks its tiles (x, y, z tile products) in ascending order and, round by
+// round, the lanes whose next tile is the wavefront's smallest pending tile
+// join one atomic (the particles of a wavefront are neighbours in the cell
+// order, so they share most of their tiles).  FILL: each joining lane takes
+// the slot base + its rank among the joining lanes.
+template <bool FILL>
+__global__ void __launch_bounds__(256) tile_list_kernel(const double4* __restrict__ pos, int64_t n, GridGeom g,
+                                                        int* __restrict__ cursor, int* __restrict__ entries) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double4 p = pos[i];
+  const int lane = threadIdx.x & 63;
   int tx[4], ty[4], tz[4];
-  const int nx = axis_tiles(axis_start(p.x, g.inv_h[0], g.P), g.P, g.N[0], tx);
-  const int ny = axis_tiles(axis_start(p.y, g.inv_h[1], g.P), g.P, g.N[1], ty);
-  const int nz = axis_tiles(axis_start(p.z, g.inv_h[2], g.P), g.P, g.N[2], tz);
-  for (int a = 0; a < nx; ++a)
-    for (int b = 0; b < ny; ++b)
-      for (int c = 0; c < nz; ++c) {
-        const int slot = atomicAdd(&cursor[(tx[a] * g.ntile[1] + ty[b]) * g.ntile[2] + tz[c]], 1);
-        entries[slot] = (int)i;
+  int nx = 0, ny = 0, nz = 0;
+  if (i < n) {
+    const double4 p = pos[i];
+    nx = sorted_axis_tiles(p.x, g.inv_h[0], g.P, g.N[0], tx);
+    ny = sorted_axis_tiles(p.y, g.inv_h[1], g.P, g.N[1], ty);
+    nz = sorted_axis_tiles(p.z, g.inv_h[2], g.P, g.N[2], tz);
+  }
+  int a = 0, b = 0, c = 0;  // next (x, y, z) tile of this lane; done when a == nx
+  for (;;) {
+    const int mine = a < nx ? (tx[a] * g.ntile[1] + ty[b]) * g.ntile[2] + tz[c] : INT_MAX;
+    int key = mine;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) key = min(key, __shfl_xor(key, o, 64));
+    if (key == INT_MAX) break;
+    const bool join = mine == key;
+    const unsigned long long m = __ballot(join);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cursor[key], __popcll(m));
+    if (FILL) {
+      base = __shfl(base, leader, 64);
+      if (join) entries[base + __popcll(m & ((1ull << lane) - 1ull))] = (int)i;
+    }
+    if (join) {
+      if (++c == nz) {
+        c = 0;
+        if (++b == ny) {
+          b = 0;
+          ++a;
+        }
       }
+    }
+  }
 }
 
 // Home tile of a particle: the tile that holds its first support point.
@@ -425,7 +454,8 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
   PE_HIP(hipMemsetAsync(ps.tile_count.get(), 0, sizeof(int) * nt, s));
   const unsigned nb = (unsigned)((ps.n + 255) / 256);
   if (ps.n > 0) {
-    hipLaunchKernelGGL(tile_count_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get());
+    hipLaunchKernelGGL(tile_list_kernel<false>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g,
+                       ps.tile_count.get(), (int*)nullptr);
     PE_CHECK_LAUNCH();
   }
   std::vector<int> cnt(nt), start(nt + 1, 0);
@@ -437,7 +467,7 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
   PE_HIP(hipMemcpyAsync(ps.tile_start.get(), start.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
   PE_HIP(hipMemcpyAsync(ps.tile_count.get(), start.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
   if (ps.n > 0) {
-    hipLaunchKernelGGL(tile_fill_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get(),
+    hipLaunchKernelGGL(tile_list_kernel<true>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get(),
                        ps.tile_entries.get());
     PE_CHECK_LAUNCH();
     // sort each tile's list so the accumulation order is the same on every run
