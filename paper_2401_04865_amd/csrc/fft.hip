@@ -274,6 +274,142 @@ __global__ void __launch_bounds__(512) fft_lines_kernel(typename C2<T>::type* __
   }
 }
 
+// ------------------------------------------------------- 256-point lines
+//
+// Strided passes of length 256 as two 16-point stages (256 = 16 x 16, the
+// four-step form of the DFT): with j = 16 j1 + j2 and k = k1 + 16 k2,
+//   X[k1 + 16 k2] = sum_j2 W16^(j2 k2) W256^(j2 k1) sum_j1 x[16 j1 + j2] W16^(j1 k1).
+// A block takes 16 lines; thread (c, g) = (t mod 16, t / 16) loads the 16
+// values x[16 j1 + g] of line c straight from HBM (16 neighbouring lines per
+// 128-byte segment), does the inner 16-point DFT and the twiddle in
+// registers, and writes through LDS once; then thread (c, g) reads the 16
+// values of k1 = g and does the outer DFT, and stores X[g + 16 k2].  The
+// 16-point DFT is itself 4 x 4 in registers.  One LDS exchange and one
+// barrier per transform, against one per radix stage in the Stockham form.
+// With SCALE the x pass scales X in registers and runs the inverse the same
+// way (inner DFT over k2 in registers, exchange, outer over k1).
+
+constexpr int kF16Lines = 16;
+constexpr int kF16Ld = 260;  // LDS values per k1 row (256 + 4: successive rows start in other banks)
+
+template <typename T>
+__device__ __forceinline__ T cos16(int m) {
+  constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                            0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                            -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                            0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+  return (T)c[m & 15];
+}
+template <typename T>
+__device__ __forceinline__ T sin16(int m) { return cos16<T>(m + 12); }  // sin(x) = cos(x - pi/2)
+
+// v <- 16-point DFT of v (natural order in and out), sign fwd.
+template <typename T, typename C>
+__device__ __forceinline__ void dft16(C (&v)[16], int fwd) {
+  C u[16];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    C t[4] = {v[b], v[4 + b], v[8 + b], v[12 + b]};
+    dft4<T, C>(t[0], t[1], t[2], t[3], fwd);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int m = b * c;
+      if (m == 0) {
+        u[4 * b + c] = t[c];
+      } else {
+        const C w = {cos16<T>(m), -(T)fwd * sin16<T>(m)};
+        u[4 * b + c] = cmul(t[c], w);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    C t[4] = {u[c], u[4 + c], u[8 + c], u[12 + c]};
+    dft4<T, C>(t[0], t[1], t[2], t[3], fwd);
+    v[c] = t[0];
+    v[c + 4] = t[1];
+    v[c + 8] = t[2];
+    v[c + 12] = t[3];
+  }
+}
+
+template <typename T, bool SCALE>
+__global__ void __launch_bounds__(256) fft256_lines_kernel(typename C2<T>::type* __restrict__ data, int64_t nlines,
+                                                           int64_t inner, int64_t outer, int64_t stride, int vmod,
+                                                           int vlim, const typename C2<T>::type* __restrict__ tw,
+                                                           int fwd, ScaleArgs sa) {
+  using C = typename C2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* X = reinterpret_cast<C*>(smem_raw);  // [16 rows][kF16Ld]
+  C* twl = X + 16 * kF16Ld;               // 256 twiddles exp(-2 pi i m / 256)
+  __shared__ int64_t lbase[kF16Lines];
+  __shared__ T lfac[kF16Lines], lksq[kF16Lines];
+  const int64_t L0 = (int64_t)blockIdx.x * kF16Lines;
+  if ((int)threadIdx.x < kF16Lines) {
+    const int64_t L = L0 + threadIdx.x;
+    const bool valid = L < nlines && (int)(L % vmod) < vlim;
+    lbase[threadIdx.x] = valid ? (L / inner) * outer + (L % inner) : -1;
+    if (SCALE && valid) {
+      const int y = (int)(L / sa.Nzs);
+      const int kz = (int)(L - (int64_t)y * sa.Nzs);
+      lfac[threadIdx.x] = (T)(sa.ey[y] * sa.ez[kz] * sa.norm);
+      lksq[threadIdx.x] = (T)(sa.ky2[y] + sa.kz2[kz]);
+    }
+  }
+  twl[threadIdx.x] = tw[threadIdx.x];
+  __syncthreads();
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t lb = lbase[c];
+  auto twiddle = [&](int m, int sgn) {  // W256^m for the transform of sign sgn
+    C w = twl[m & 255];
+    if (sgn < 0) w.y = -w.y;
+    return w;
+  };
+  C v[16];
+  // inner DFT over j1 of x[16 j1 + g], twiddle W256^(g k1), exchange
+#pragma unroll
+  for (int j1 = 0; j1 < 16; ++j1) v[j1] = lb >= 0 ? data[lb + (int64_t)(16 * j1 + g) * stride] : C{0, 0};
+  dft16<T, C>(v, fwd);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], twiddle(g * k1, fwd));
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) X[k1 * kF16Ld + g * 16 + c] = v[k1];
+  __syncthreads();
+  // outer DFT over j2 for k1 = g
+#pragma unroll
+  for (int j2 = 0; j2 < 16; ++j2) v[j2] = X[g * kF16Ld + j2 * 16 + c];
+  dft16<T, C>(v, fwd);
+  if (SCALE) {
+    // v[k2] = X[g + 16 k2]: scale by the Green's function, then the inverse
+    // with k = k1 + 16 k2 (k1 = g held here): inner DFT over k2 in registers,
+    // twiddle W256^-(g j1), exchange, outer DFT over k1
+    if (lb >= 0) {
+#pragma unroll
+      for (int k2 = 0; k2 < 16; ++k2) {
+        const int kx = g + 16 * k2;
+        const T k2s = (T)sa.kx2[kx] + lksq[c];
+        const T gk = k2s > (T)0 ? (T)sa.ex[kx] * lfac[c] / k2s : (T)0;
+        v[k2] = {v[k2].x * gk, v[k2].y * gk};
+      }
+    }
+    dft16<T, C>(v, -fwd);
+#pragma unroll
+    for (int j1 = 1; j1 < 16; ++j1) v[j1] = cmul(v[j1], twiddle(g * j1, -fwd));
+    __syncthreads();  // every read of the first exchange is done
+#pragma unroll
+    for (int j1 = 0; j1 < 16; ++j1) X[j1 * kF16Ld + g * 16 + c] = v[j1];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) v[k1] = X[g * kF16Ld + k1 * 16 + c];
+    dft16<T, C>(v, -fwd);
+  }
+  // v[m] is element g + 16 m of line c
+  if (lb >= 0) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) data[lb + (int64_t)(g + 16 * m) * stride] = v[m];
+  }
+}
+
 // z pass, real -> half complex, two real lines per complex transform.
 template <typename T>
 __global__ void __launch_bounds__(256) fft_z_r2c_kernel(const T* __restrict__ real,
@@ -434,6 +570,9 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   // strided passes: what the device allows per workgroup, less the static
   // per-line tables (64-line maximum)
   const size_t sbudget = std::min<size_t>((size_t)c->lds_per_block, 80 * 1024) - 2048;
+  // 256-point strided lines: the two-stage kernel, where its LDS fits
+  const size_t sh256 = (16 * (size_t)kF16Ld + 256) * sizeof(C);
+  auto use256 = [&](int n) { return n == 256 && sh256 + 1024 <= (size_t)c->lds_per_block; };
   // 1. z, r2c
   {
     ProfScope ps(c->prof, s, PE_PROF_FFT_Z_R2C, sizeof(T) == 8, 1.0);
@@ -460,6 +599,12 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   auto ypass = [&](int fwd) {
     ProfScope ps(c->prof, s, fwd > 0 ? PE_PROF_FFT_Y_FWD : PE_PROF_FFT_Y_INV, sizeof(T) == 8, 1.0);
     const int64_t nlines = (int64_t)Nx * Nzs;
+    if (use256(Ny)) {
+      hipLaunchKernelGGL((fft256_lines_kernel<T, false>), dim3((unsigned)((nlines + 15) / 16)), dim3(256), sh256, s,
+                         gC, nlines, (int64_t)Nzs, (int64_t)Ny * Nzs, (int64_t)Nzs, Nzs, Nzc, twy, fwd, sa);
+      PE_CHECK_LAUNCH();
+      return;
+    }
     const int lpb = strided_lines_per_block(Ny, sizeof(C), sbudget);
     const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
     const size_t sh = 2 * (size_t)lpb * Ny * sizeof(C);
@@ -472,12 +617,18 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   {
     ProfScope ps(c->prof, s, PE_PROF_FFT_X_SCALE, sizeof(T) == 8, 1.0);
     const int64_t nlines = (int64_t)Ny * Nzs;
+    if (use256(Nx)) {
+      hipLaunchKernelGGL((fft256_lines_kernel<T, true>), dim3((unsigned)((nlines + 15) / 16)), dim3(256), sh256, s,
+                         gC, nlines, nlines, (int64_t)0, (int64_t)Ny * Nzs, Nzs, Nzc, twx, 1, sa);
+      PE_CHECK_LAUNCH();
+    } else {
     const int lpb = strided_lines_per_block(Nx, sizeof(C), sbudget);
     const unsigned nb = (unsigned)((nlines + lpb - 1) / lpb);
     const size_t sh = 2 * (size_t)lpb * Nx * sizeof(C);
     hipLaunchKernelGGL((fft_lines_kernel<T, true>), dim3(nb), dim3(lpb * Nx >= 4096 ? 512 : 256), sh, s, gC, Nx, nlines,
                        nlines, (int64_t)0, (int64_t)Ny * Nzs, Nzs, Nzc, lpb, c->plan[0], twx, 1, sa);
     PE_CHECK_LAUNCH();
+    }
   }
   // 4. y inverse
   ypass(-1);

@@ -127,3 +127,26 @@ def test_apply_linear_and_symmetric(gpu_lib):
     assert abs(a @ Mb - b @ Ma) <= 1e-12 * abs(a @ Mb)
     np.testing.assert_allclose(Mab, 2 * Ma - 3 * Mb, atol=1e-12 * np.abs(Mab).max())
     ctx.close()
+
+
+def test_apply_256_point_lines_match_modeB(gpu_lib):
+    """x and y lines of 256 points (the two-stage strided transform) and
+    half-spectrum rows of 17 values padded to 32, against mode B, in double
+    to rounding and in float to the float bound."""
+    rng = np.random.default_rng(17)
+    box, mesh = (8.0, 8.0, 1.0), (256, 256, 32)
+    body = inputs.icosphere(0, 0.12)
+    n_ion = 48
+    ip = rng.uniform(0.0, 1.0, (n_ion, 3)) * np.asarray(box)
+    iq = np.where(np.arange(n_ion) % 2 == 0, 1.0, -1.0)
+    s = inputs.assemble(box, [body], [[4.0, 4.0, 0.5]], [[1.0, 0.0, 0.0, 0.0]], [0.5], [0], 0.03,
+                        ip, iq, np.full(n_ion, 0.03), mesh=mesh, name="lines256")
+    chg = _charges(s, 17)
+    for prec, tol_p, tol_e in ((gpu_lib.PE_FP64, 1e-11, 1e-10), (gpu_lib.PE_MIXED, 2e-6, 2e-5)):
+        p = gpu_lib.make_params(s.box, mesh, P=8, split_tol=1e-8, precision=prec)
+        psi, E, d = _gpu_apply(gpu_lib, s, p, chg, precision=prec)
+        if prec == gpu_lib.PE_FP64:
+            pb, Eb = _modeB(s, chg, d, 8)
+        print(prec, np.abs(psi - pb).max() / np.abs(pb).max(), np.abs(E - Eb).max() / np.abs(Eb).max(), d)
+        assert np.abs(psi - pb).max() <= tol_p * np.abs(pb).max()
+        assert np.abs(E - Eb).max() <= tol_e * np.abs(Eb).max()
