@@ -410,6 +410,120 @@ __global__ void __launch_bounds__(256) fft256_lines_kernel(typename C2<T>::type*
   }
 }
 
+// z passes of 256 points, two real lines per complex line, in the same
+// two-stage form.  Thread (c, g) = (t / 16, t mod 16) works on complex line c
+// of the block (16 per block), so the 16 lanes of a line read or write 16
+// neighbouring values.  The exchange between the stages goes through LDS
+// with the value index XORed by the row (k1 or j2), which keeps both the
+// writes of one row and the column reads of the other stage free of bank
+// conflicts.  r2c: Z_{N-k}, needed to split the packed transform, sits in
+// lane (c, 16 - g) of the same wavefront (register 15 - k2), or for g = 0 in
+// the lane itself (register 16 - k2): a lane shuffle, no second exchange.
+template <typename T>
+__global__ void __launch_bounds__(256) fft256_z_r2c_kernel(const T* __restrict__ real,
+                                                           typename C2<T>::type* __restrict__ cplx, int Nzs,
+                                                           int64_t nlines, const typename C2<T>::type* __restrict__ tw) {
+  using C = typename C2<T>::type;
+  constexpr int Nz = 256;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* X = reinterpret_cast<C*>(smem_raw);  // [16 lines][kF16Ld]
+  C* twl = X + 16 * kF16Ld;
+  twl[threadIdx.x] = tw[threadIdx.x];
+  const int c = threadIdx.x >> 4, g = threadIdx.x & 15;
+  const int64_t la = 2 * ((int64_t)blockIdx.x * 16 + c), lb = la + 1;
+  const bool va = la < nlines, vb = lb < nlines;
+  C v[16];
+#pragma unroll
+  for (int j1 = 0; j1 < 16; ++j1) {
+    const int j = 16 * j1 + g;
+    v[j1] = {va ? real[la * Nz + j] : (T)0, vb ? real[lb * Nz + j] : (T)0};
+  }
+  __syncthreads();  // twiddles
+  dft16<T, C>(v, 1);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) {
+    const C w = twl[(g * k1) & 255];
+    v[k1] = cmul(v[k1], w);
+  }
+  C* Xl = X + c * kF16Ld;
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) Xl[k1 * 16 + (g ^ k1)] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int j2 = 0; j2 < 16; ++j2) v[j2] = Xl[g * 16 + (j2 ^ g)];
+  dft16<T, C>(v, 1);
+  // v[k2] = Z_k, k = g + 16 k2
+  const int lane = threadIdx.x & 63;
+  const int partner = (lane & 48) | ((16 - g) & 15);
+#pragma unroll
+  for (int k2 = 0; k2 <= 8; ++k2) {
+    C p;
+    p.x = __shfl(v[15 - k2].x, partner, 64);
+    p.y = __shfl(v[15 - k2].y, partner, 64);
+    if (g == 0) p = v[(16 - k2) & 15];
+    const int k = g + 16 * k2;
+    if (k > Nz / 2) continue;
+    const C z = v[k2];
+    const C A = {(T)0.5 * (z.x + p.x), (T)0.5 * (z.y - p.y)};
+    const C Bv = {(T)0.5 * (z.y + p.y), (T)-0.5 * (z.x - p.x)};
+    if (va) cplx[la * Nzs + k] = A;
+    if (vb) cplx[lb * Nzs + k] = Bv;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) fft256_z_c2r_kernel(const typename C2<T>::type* __restrict__ cplx,
+                                                           T* __restrict__ real, int Nzs, int64_t nlines,
+                                                           const typename C2<T>::type* __restrict__ tw) {
+  using C = typename C2<T>::type;
+  constexpr int Nz = 256;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* X = reinterpret_cast<C*>(smem_raw);
+  C* twl = X + 16 * kF16Ld;
+  twl[threadIdx.x] = tw[threadIdx.x];
+  const int c = threadIdx.x >> 4, g = threadIdx.x & 15;
+  const int64_t la = 2 * ((int64_t)blockIdx.x * 16 + c), lb = la + 1;
+  const bool va = la < nlines, vb = lb < nlines;
+  C v[16];
+  // z_k = A_k + i B_k over the full spectrum (Hermitian extension above N/2)
+#pragma unroll
+  for (int j1 = 0; j1 < 16; ++j1) {
+    const int k = 16 * j1 + g;
+    const bool lo = k <= Nz / 2;
+    const int kk = lo ? k : Nz - k;
+    C A = {0, 0}, Bv = {0, 0};
+    if (va) A = cplx[la * Nzs + kk];
+    if (vb) Bv = cplx[lb * Nzs + kk];
+    if (!lo) {
+      A.y = -A.y;
+      Bv.y = -Bv.y;
+    }
+    v[j1] = {A.x - Bv.y, A.y + Bv.x};
+  }
+  __syncthreads();  // twiddles
+  dft16<T, C>(v, -1);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) {
+    C w = twl[(g * k1) & 255];
+    w.y = -w.y;
+    v[k1] = cmul(v[k1], w);
+  }
+  C* Xl = X + c * kF16Ld;
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) Xl[k1 * 16 + (g ^ k1)] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int j2 = 0; j2 < 16; ++j2) v[j2] = Xl[g * 16 + (j2 ^ g)];
+  dft16<T, C>(v, -1);
+  // v[k2] = x_j, j = g + 16 k2: real line a in x, b in y
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    const int j = g + 16 * k2;
+    if (va) real[la * Nz + j] = v[k2].x;
+    if (vb) real[lb * Nz + j] = v[k2].y;
+  }
+}
+
 // z pass, real -> half complex, two real lines per complex transform.
 template <typename T>
 __global__ void __launch_bounds__(256) fft_z_r2c_kernel(const T* __restrict__ real,
@@ -577,13 +691,19 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   {
     ProfScope ps(c->prof, s, PE_PROF_FFT_Z_R2C, sizeof(T) == 8, 1.0);
     const int64_t nlines = (int64_t)Nx * Ny;
-    const int ppb = lines_per_block(Nz, sizeof(C), budget);
     const int64_t npairs = (nlines + 1) / 2;
+    if (use256(Nz)) {
+      hipLaunchKernelGGL(fft256_z_r2c_kernel<T>, dim3((unsigned)((npairs + 15) / 16)), dim3(256), sh256, s, gA, gC,
+                         Nzs, nlines, twz);
+      PE_CHECK_LAUNCH();
+    } else {
+    const int ppb = lines_per_block(Nz, sizeof(C), budget);
     const unsigned nb = (unsigned)((npairs + ppb - 1) / ppb);
     const size_t sh = 2 * (size_t)ppb * (Nz + 1) * sizeof(C);
     hipLaunchKernelGGL(fft_z_r2c_kernel<T>, dim3(nb), dim3(256), sh, s, gA, gC, Nz, Nzs, nlines, ppb,
                        c->plan[2], twz);
     PE_CHECK_LAUNCH();
+    }
   }
   ScaleArgs sa{};
   sa.Nx = Nx; sa.Ny = Ny; sa.Nz = Nz; sa.Nzc = Nzc; sa.Nzs = Nzs;
@@ -636,13 +756,19 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   {
     ProfScope ps(c->prof, s, PE_PROF_FFT_Z_C2R, sizeof(T) == 8, 1.0);
     const int64_t nlines = (int64_t)Nx * Ny;
-    const int ppb = lines_per_block(Nz, sizeof(C), budget);
     const int64_t npairs = (nlines + 1) / 2;
+    if (use256(Nz)) {
+      hipLaunchKernelGGL(fft256_z_c2r_kernel<T>, dim3((unsigned)((npairs + 15) / 16)), dim3(256), sh256, s, gC, gB,
+                         Nzs, nlines, twz);
+      PE_CHECK_LAUNCH();
+    } else {
+    const int ppb = lines_per_block(Nz, sizeof(C), budget);
     const unsigned nb = (unsigned)((npairs + ppb - 1) / ppb);
     const size_t sh = 2 * (size_t)ppb * (Nz + 1) * sizeof(C);
     hipLaunchKernelGGL(fft_z_c2r_kernel<T>, dim3(nb), dim3(256), sh, s, gC, gB, Nz, Nzs, nlines, ppb,
                        c->plan[2], twz);
     PE_CHECK_LAUNCH();
+    }
   }
 }
 

@@ -129,17 +129,19 @@ def test_apply_linear_and_symmetric(gpu_lib):
     ctx.close()
 
 
-def test_apply_256_point_lines_match_modeB(gpu_lib):
-    """x and y lines of 256 points (the two-stage strided transform) and
-    half-spectrum rows of 17 values padded to 32, against mode B, in double
-    to rounding and in float to the float bound."""
+@pytest.mark.parametrize("box,mesh", [((8.0, 8.0, 1.0), (256, 256, 32)), ((1.0, 1.0, 8.0), (32, 32, 256))])
+def test_apply_256_point_lines_match_modeB(gpu_lib, box, mesh):
+    """Lines of 256 points (the two-stage transforms: strided x and y, and
+    the packed real z passes) and half-spectrum rows of 17 values padded to
+    32, against mode B, in double to rounding and in float to the float
+    bound."""
     rng = np.random.default_rng(17)
-    box, mesh = (8.0, 8.0, 1.0), (256, 256, 32)
     body = inputs.icosphere(0, 0.12)
     n_ion = 48
     ip = rng.uniform(0.0, 1.0, (n_ion, 3)) * np.asarray(box)
     iq = np.where(np.arange(n_ion) % 2 == 0, 1.0, -1.0)
-    s = inputs.assemble(box, [body], [[4.0, 4.0, 0.5]], [[1.0, 0.0, 0.0, 0.0]], [0.5], [0], 0.03,
+    centre = [0.5 * b for b in box]
+    s = inputs.assemble(box, [body], [centre], [[1.0, 0.0, 0.0, 0.0]], [0.5], [0], 0.03,
                         ip, iq, np.full(n_ion, 0.03), mesh=mesh, name="lines256")
     chg = _charges(s, 17)
     for prec, tol_p, tol_e in ((gpu_lib.PE_FP64, 1e-11, 1e-10), (gpu_lib.PE_MIXED, 2e-6, 2e-5)):
@@ -150,3 +152,31 @@ def test_apply_256_point_lines_match_modeB(gpu_lib):
         print(prec, np.abs(psi - pb).max() / np.abs(pb).max(), np.abs(E - Eb).max() / np.abs(Eb).max(), d)
         assert np.abs(psi - pb).max() <= tol_p * np.abs(pb).max()
         assert np.abs(E - Eb).max() <= tol_e * np.abs(Eb).max()
+
+
+def test_full_size_workload_sampled_sources(gpu_lib):
+    """The 512-sphere workload at full size (328704 beads + 1e6 ions, mesh
+    256^3) in the launch configuration the benchmark uses: with charge on 40
+    random particles only, the potential and field at 40 other particles
+    equal the oracle's sum over those sources (mode B on the full mesh)."""
+    s = inputs.config(5)
+    pos, sig, _ = saddle.all_particles(s, np.zeros(s.n_bead))
+    rng = np.random.default_rng(29)
+    pick = rng.choice(len(pos), 80, replace=False)
+    src, tgt = pick[:40], pick[40:]
+    q = rng.standard_normal(40)
+    chg = np.zeros(len(pos))
+    chg[src] = q
+    ref = None
+    for prec, tol_p, tol_e in ((gpu_lib.PE_FP64, 1e-10, 1e-9), (gpu_lib.PE_MIXED, 3e-6, 3e-5)):
+        p = gpu_lib.make_params(s.box, s.mesh, P=8, split_tol=1e-6, precision=prec)
+        psi, E, d = _gpu_apply(gpu_lib, s, p, chg, precision=prec)
+        if ref is None:
+            ref = se.apply(pos[tgt], sig[tgt], pos[src], sig[src], q, s.box, s.mesh, 8, d["xi"], d["eta"],
+                           d["r_cut"], want_field=True, same=False)
+        pb, Eb = ref
+        ep = np.abs(psi[tgt] - pb).max() / np.abs(pb).max()
+        ee = np.abs(E[tgt] - Eb).max() / np.abs(Eb).max()
+        print(prec, ep, ee)
+        assert ep <= tol_p
+        assert ee <= tol_e
