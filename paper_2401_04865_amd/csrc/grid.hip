@@ -181,7 +181,131 @@ __global__ void home_fill_kernel(const double4* __restrict__ pos, int64_t n, Gri
   entries[atomicAdd(&cursor[home_tile(pos[i], g)], 1)] = (int)i;
 }
 
-// One workgroup (four wavefronts) per tile.  The tile's particle list is
+// Charges in the particle set's sorted order (one load per staged particle
+// instead of two dependent ones).
+__global__ void sorted_charges_kernel(const int* __restrict__ idx, const double* __restrict__ q, int64_t n,
+                                      double* __restrict__ qs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) qs[i] = q[idx[i]];
+}
+
+// One workgroup per column of four tiles along z; wavefront w owns tile
+// (ux, uy, 4 bz + w) and walks that tile's particle list on its own, 16
+// particles at a time: lanes 0..47, one per (particle, axis), stage the eight
+// tile-local window factors (f_x[a] q, f_y[b], f_z[c], zero where the support
+// misses the tile) in the wavefront's LDS slice; then lane (a, b) adds
+// q f_x[a] f_y[b] f_z[c] into the z-pencil (a, b, 0..7) it holds in
+// registers.  No workgroup barrier inside the loop.  At the end the four
+// tiles meet in LDS and the column is written once, 32 values of z per row
+// (whole 128-byte lines in single precision), with no atomics; every tile is
+// written (empty ones with zeros), so the grid needs no clearing between
+// products.  The lists are sorted, so the result is the same bit for bit on
+// every run.
+constexpr int kWaveChunk = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restrict__ pos,
+                                                          const double* __restrict__ qs,
+                                                          const int* __restrict__ tile_start,
+                                                          const int* __restrict__ entries,
+                                                          T* __restrict__ grid, GridGeom g, int accumulate) {
+  __shared__ T f_s[kWaves][kWaveChunk][3][kTile];
+  __shared__ T col[kTile][kTile][kWaves * kTile];  // (a, b, z of the column)
+  const int nbz = (g.ntile[2] + kWaves - 1) / kWaves;
+  const int bz = blockIdx.x % nbz;
+  const int uy = (blockIdx.x / nbz) % g.ntile[1];
+  const int ux = blockIdx.x / (nbz * g.ntile[1]);
+  const int P = g.P;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int uz = kWaves * bz + wv;
+  const int pa = lane >> 3, pb = lane & 7;
+  T acc[kTile];
+#pragma unroll
+  for (int c = 0; c < kTile; ++c) acc[c] = 0;
+  if (uz < g.ntile[2]) {
+    const int tid = (ux * g.ntile[1] + uy) * g.ntile[2] + uz;
+    const int e0 = tile_start[tid], e1 = tile_start[tid + 1];
+    T (*fw)[3][kTile] = f_s[wv];
+    // staging lane: particle c3 of the round, axis ax3.  Loads run ahead of
+    // use: the entries two rounds ahead, the coordinate and charge one round
+    // ahead, so their latency overlaps the current round's work.
+    const int c3 = lane / 3, ax3 = lane - 3 * (lane / 3);
+    const bool stager = lane < 3 * kWaveChunk;
+    const int N = g.N[ax3];
+    const int u = ax3 == 0 ? ux : (ax3 == 1 ? uy : uz);
+    auto entry_at = [&](int c0) { return (stager && c0 + c3 < e1) ? entries[c0 + c3] : -1; };
+    int i1 = entry_at(e0), i2 = entry_at(e0 + kWaveChunk);
+    double x1 = 0, q1 = 1;
+    if (i1 >= 0) {
+      x1 = reinterpret_cast<const double*>(pos + i1)[ax3];
+      if (ax3 == 0) q1 = qs[i1];
+    }
+    for (int c0 = e0; c0 < e1; c0 += kWaveChunk) {
+      const int nc = min(kWaveChunk, e1 - c0);
+      const int i3 = entry_at(c0 + 2 * kWaveChunk);
+      double x2 = 0, q2 = 1;
+      if (i2 >= 0) {
+        x2 = reinterpret_cast<const double*>(pos + i2)[ax3];
+        if (ax3 == 0) q2 = qs[i2];
+      }
+      if (i1 >= 0) {
+        double delta;
+        const int m0 = support_start(x1, g.inv_h[ax3], P, delta);
+        // tile-local position of support point 0, taken in [1 - P, kTile - 1]
+        int s0 = wrap_idx(m0, N) - kTile * u;
+        if (s0 > kTile - 1) s0 -= N;
+        if (s0 < 1 - P) s0 += N;
+        // single precision once the support is placed: the displacement
+        // (j + delta) h is below P h, so float keeps it to rounding and the
+        // exponential to a few ulp
+        const float hf = (float)g.h[ax3], df = (float)delta, we = (float)g.wexp;
+        const float wn = (float)g.wnorm * (float)q1;
+#pragma unroll
+        for (int loc = 0; loc < kTile; ++loc) {
+          const int j = loc - s0;
+          const float d = ((float)j + df) * hf;
+          fw[c3][ax3][loc] = (j >= 0 && j < P) ? (T)(wn * __expf(-we * d * d)) : (T)0;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int c = 0; c < nc; ++c) {
+        const T coef = fw[c][0][pa] * fw[c][1][pb];
+#pragma unroll
+        for (int z = 0; z < kTile; ++z) acc[z] += coef * fw[c][2][z];
+      }
+      // the slice is restaged next round
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      i1 = i2;
+      i2 = i3;
+      x1 = x2;
+      q1 = q2;
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < kTile; ++z) col[pa][pb][kTile * wv + z] = acc[z];
+  __syncthreads();
+  // rows (a, b) of up to 32 z values: 8 threads per row, 4 values each
+  const int zlen = min(kWaves * kTile, g.N[2] - kWaves * kTile * bz);
+  for (int k = threadIdx.x; k < kTile * kTile * kWaves * kTile; k += blockDim.x) {
+    const int zz = k % (kWaves * kTile);
+    const int row = k / (kWaves * kTile);
+    const int a = row / kTile, b = row % kTile;
+    const int gx = kTile * ux + a, gy = kTile * uy + b, gz = kWaves * kTile * bz + zz;
+    if (gx < g.N[0] && gy < g.N[1] && zz < zlen) {
+      const int64_t o = ((int64_t)gx * g.N[1] + gy) * g.N[2] + gz;
+      const T v = col[a][b][zz];
+      grid[o] = accumulate ? grid[o] + v : v;
+    }
+  }
+}
+
+// Double precision: one workgroup (four wavefronts) per tile.  The tile's
+// particle list is
 // processed in chunks of kChunk: one thread per (particle, axis) stages the
 // eight tile-local window factors (f_x[a] q, f_y[b], f_z[c], zero where the
 // support misses the tile) in LDS.  Lane (a, b) of a wavefront owns the
@@ -193,7 +317,7 @@ __global__ void home_fill_kernel(const double4* __restrict__ pos, int64_t n, Gri
 constexpr int kChunk = 64;
 
 template <typename T>
-__global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restrict__ pos,
+__global__ void __launch_bounds__(256) spread_block_kernel(const double4* __restrict__ pos,
                                                           const int* __restrict__ idx,
                                                           const double* __restrict__ q,
                                                           const int* __restrict__ tile_start,
@@ -360,12 +484,32 @@ __global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restr
     gidx[ax][l] = wrap_idx(kTile * u + l, g.N[ax]);
   }
   __syncthreads();
-  // region rows (lx, ly) of Hs contiguous z values; 16 threads per row
-  for (int row = threadIdx.x >> 4; row < Hs2; row += 16) {
-    const int lx = row / Hs;
-    const int ly = row - lx * Hs;
-    const int64_t rb = ((int64_t)gidx[0][lx] * g.N[1] + gidx[1][ly]) * g.N[2];
-    for (int lz = threadIdx.x & 15; lz < Hs; lz += 16) H[row * Hs + lz] = grid[rb + gidx[2][lz]];
+  // region rows (lx, ly) of Hs contiguous z values, 16 threads per row;
+  // eight rows' loads are issued before their stores, so their latencies
+  // overlap
+  for (int r0 = threadIdx.x >> 4; r0 < Hs2; r0 += 16 * 8) {
+    T v[8][2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int row = r0 + 16 * u;
+      const int lx = row / Hs;
+      const int ly = row - lx * Hs;
+      const int64_t rb = row < Hs2 ? ((int64_t)gidx[0][lx] * g.N[1] + gidx[1][ly]) * g.N[2] : 0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int lz = (threadIdx.x & 15) + 16 * h;
+        v[u][h] = (row < Hs2 && lz < Hs) ? grid[rb + gidx[2][lz]] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int row = r0 + 16 * u;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int lz = (threadIdx.x & 15) + 16 * h;
+        if (row < Hs2 && lz < Hs) H[row * Hs + lz] = v[u][h];
+      }
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -507,9 +651,25 @@ void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* gri
                    bool accumulate) {
   if (ps.n == 0 && accumulate) return;
   require(g.P <= kMaxP, "support P must be <= 16");
-  const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];
-  hipLaunchKernelGGL(spread_tile_kernel<T>, dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(), ps.idx.get(), q,
-                     ps.tile_start.get(), ps.tile_entries.get(), grid, g, accumulate ? 1 : 0);
+  if constexpr (sizeof(T) == 4) {
+    ParticleSet& m = const_cast<ParticleSet&>(ps);
+    m.qspread.ensure((size_t)std::max<int64_t>(ps.n, 1));
+    if (ps.n > 0) {
+      hipLaunchKernelGGL(sorted_charges_kernel, dim3((unsigned)((ps.n + 255) / 256)), dim3(256), 0, s, ps.idx.get(),
+                         q, ps.n, m.qspread.get());
+      PE_CHECK_LAUNCH();
+    }
+    const int nbz = (g.ntile[2] + kWaves - 1) / kWaves;
+    const int nt = g.ntile[0] * g.ntile[1] * nbz;
+    hipLaunchKernelGGL(spread_tile_kernel<T>, dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(), m.qspread.get(),
+                       ps.tile_start.get(), ps.tile_entries.get(), grid, g, accumulate ? 1 : 0);
+  } else {
+    // double: the window exponentials dominate, and spreading them over the
+    // whole workgroup (one staging pass per 64 particles) measured faster
+    const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];
+    hipLaunchKernelGGL(spread_block_kernel<T>, dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(), ps.idx.get(), q,
+                       ps.tile_start.get(), ps.tile_entries.get(), grid, g, accumulate ? 1 : 0);
+  }
   PE_CHECK_LAUNCH();
 }
 

@@ -132,6 +132,7 @@ struct ParticleSet {
   DevBuf<double4> tmp;      // caller order wrapped positions (scratch)
   DevBuf<int4> chunks;      // pair-traversal work units: (first, end sorted slot, first cell, cells), <= 64 each
   DevBuf<double> qsorted;   // charges in sorted order for the pair passes (scratch)
+  DevBuf<double> qspread;   // charges in sorted order for spreading (scratch)
   int n_chunks = 0;
   // grid tiles overlapped by each particle's support (spreading lists)
   DevBuf<int> tile_start;   // ntile + 1
