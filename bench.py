@@ -40,13 +40,17 @@ WORKLOADS = {
 }
 SPLIT_TOL = {"cfg2": 1e-8, "cfg3": 1e-6, "cfg4": 1e-6, "cfg5": 1e-6}
 
-# HBM bytes per launch of a kernel class on the default workload, from
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes (one step's launches of
-# the class, averaged; FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the
-# ratios a plain 256 MiB device copy reads on those counters).  Each entry
+# HBM bytes per launch (profiler scope) of a kernel class on the default
+# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes over a short
+# run of this script (the class's dispatches of five steps, averaged;
+# FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the ratios a plain 256 MiB
+# device copy reads on those counters).  Each entry
 # records the source file the kernels live in and its sha1 at measurement;
 # once that file changes the figure is stale and `traffic` is reported null.
-TRAFFIC = {}
+TRAFFIC = {
+    "pair_f32": {"bytes_per_launch": 1.569e9, "source": "paper_2401_04865_amd/csrc/realspace.hip",
+                 "sha1": "3ef98cfb16d71b702ce0902ad60c3b5f42f4f3ee"},
+}
 
 
 def traffic_current(entry):
