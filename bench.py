@@ -47,20 +47,21 @@ SPLIT_TOL = {"cfg2": 1e-8, "cfg3": 1e-6, "cfg4": 1e-6, "cfg5": 1e-6}
 # device copy reads on those counters).  Each entry
 # records the source file the kernels live in and its sha1 at measurement;
 # once that file changes the figure is stale and `traffic` is reported null.
-TRAFFIC = {
-    "pair_f32": {"bytes_per_launch": 1.569e9, "source": "paper_2401_04865_amd/csrc/realspace.hip",
-                 "sha1": "3ef98cfb16d71b702ce0902ad60c3b5f42f4f3ee"},
-}
+TRAFFIC = {}
 
 
 def traffic_current(entry):
+    """True while every source file the figure depends on (the kernels and
+    the code that launches them) still has the sha1 recorded with it."""
     import hashlib
-    path = os.path.join(ROOT, entry["source"])
-    try:
-        with open(path, "rb") as f:
-            return hashlib.sha1(f.read()).hexdigest() == entry["sha1"]
-    except OSError:
-        return False
+    for rel, sha in entry["sources"].items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha1(f.read()).hexdigest() != sha:
+                    return False
+        except OSError:
+            return False
+    return True
 
 
 # Peaks of one MI355X: HBM bandwidth, dense matrix-core and vector rates.

@@ -268,21 +268,34 @@ void apply_saddle_prec(pe_context* c, int prec, const double* x, double* y) {
 // Potential (and field) of all particles for bead charges qb and ion charges qi.
 // phi (n_all), E (3 n_all or null).  Includes the self terms and removes
 // the k = 0 constant; optionally forms forces/energies.
+//
+// reuse_ion (single precision, ion charges those of the system): the ion
+// grid and the ion -> bead real-space sums kept by the right-hand side of
+// this configuration stand in for spreading the ions again and for the
+// ion sources of the bead targets' pair pass (the potential is linear in
+// the charges, and the kept parts were formed by the same kernels).
 template <typename T>
 void all_potential(pe_context* c, const double* qb, const double* qi, double* phi, double* E,
-                   double* f, double* u, const double* chg_all) {
+                   double* f, double* u, const double* chg_all, bool reuse_ion = false) {
   hipStream_t s = c->stream;
   const int64_t nb = c->n_bead, ni = c->n_ion, na = nb + ni;
+  reuse_ion = reuse_ion && sizeof(T) == 4 && ni > 0 && c->ion_parts_valid && E != nullptr;
   PE_HIP(hipMemsetAsync(phi, 0, sizeof(double) * na, s));
   if (E) PE_HIP(hipMemsetAsync(E, 0, sizeof(double) * 3 * na, s));
   launch_moments(s, qb, c->bead_sig.get(), 0.0, nb, ck_coef(c), c->red.get(), ck_bead(c), nullptr);
   if (ni) launch_moments(s, qi, c->ion_sig.get(), 0.0, ni, ck_coef(c), c->red.get(), ck_ion(c), nullptr);
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
+  if (reuse_ion) gA = reinterpret_cast<T*>(c->ion_grid32.get());
   {
-    ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8, (double)(nb + ni));
-    launch_spread<T>(s, c->B, qb, gA, c->gg, false);
-    if (ni) launch_spread<T>(s, c->I, qi, gA, c->gg, true);
+    ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8, (double)(reuse_ion ? nb : nb + ni));
+    if (reuse_ion) {
+      launch_spread<T>(s, c->B, qb, gA, c->gg, true);  // onto the kept ion grid
+      c->ion_parts_valid = false;
+    } else {
+      launch_spread<T>(s, c->B, qb, gA, c->gg, false);
+      if (ni) launch_spread<T>(s, c->I, qi, gA, c->gg, true);
+    }
   }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
   {
@@ -292,7 +305,13 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
   }
   ProfScope ps_pair(c->prof, s, PE_PROF_PAIR, sizeof(T) == 8);
   unsigned long long* npc = pair_counter<T>(c);
-  launch_pair_onfly<T>(s, c->B, &c->B, qb, &c->I, qi, c->rg, phi, E, false, npc);
+  if (reuse_ion) {
+    launch_pair_onfly<T>(s, c->B, &c->B, qb, nullptr, nullptr, c->rg, phi, E, false, npc);
+    launch_axpby(s, 1.0, c->ion_rs_phi.get(), 1.0, phi, nb);
+    launch_axpby(s, 1.0, c->ion_rs_E.get(), 1.0, E, 3 * nb);
+  } else {
+    launch_pair_onfly<T>(s, c->B, &c->B, qb, &c->I, qi, c->rg, phi, E, false, npc);
+  }
   launch_pair_onfly<T>(s, c->I, &c->B, qb, &c->I, qi, c->rg, phi + nb, E ? E + 3 * nb : nullptr, false, npc);
   // k = 0 constant, then forces and energies
   if (nb)
@@ -312,25 +331,48 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
 // in precision T: the wave part by one ion-only SE pass, plus the ion->bead
 // real-space pairs.  Mixed precision runs it in float like every other
 // real- and wave-space sum; the double path keeps it in double.
+//
+// In single precision with the field requested, the spread ion grid and the
+// real-space ion -> bead sums are kept for the force pass of the same
+// configuration (see all_potential).
 template <typename T>
 void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E) {
   hipStream_t s = c->stream;
   const bool dbl = sizeof(T) == 8;
+  const int64_t nb = c->n_bead;
+  const bool keep = sizeof(T) == 4 && E != nullptr;
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
+  if (keep) {
+    const int64_t G = (int64_t)c->gg.N[0] * c->gg.N[1] * c->gg.N[2];
+    c->ion_grid32.ensure((size_t)G);
+    gA = reinterpret_cast<T*>(c->ion_grid32.get());
+  }
   {
     ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)c->n_ion);
     launch_spread<T>(s, c->I, c->ion_q.get(), gA, c->gg, false);
   }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
   {
-    ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)c->n_bead);
+    ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb);
     launch_gather<T>(s, c->B, gB, c->gg, phi_ion, E, false);
   }
-  // the field only feeds the guess features: single precision
+  // double path: the field only feeds the guess features, single precision
   ProfScope ps(c->prof, s, PE_PROF_PAIR, dbl);
-  launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, phi_ion, E, true,
-                       pair_counter<T>(c));
+  if (keep) {
+    c->ion_rs_phi.ensure((size_t)std::max<int64_t>(nb, 1));
+    c->ion_rs_E.ensure(3 * (size_t)std::max<int64_t>(nb, 1));
+    PE_HIP(hipMemsetAsync(c->ion_rs_phi.get(), 0, sizeof(double) * nb, s));
+    PE_HIP(hipMemsetAsync(c->ion_rs_E.get(), 0, sizeof(double) * 3 * nb, s));
+    launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, c->ion_rs_phi.get(),
+                         c->ion_rs_E.get(), true, pair_counter<T>(c));
+    launch_axpby(s, 1.0, c->ion_rs_phi.get(), 1.0, phi_ion, nb);
+    launch_axpby(s, 1.0, c->ion_rs_E.get(), 1.0, E, 3 * nb);
+    c->ion_parts_valid = true;
+  } else {
+    launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, phi_ion, E, true,
+                         pair_counter<T>(c));
+  }
 }
 
 // Right-hand side b = [-r.E0 + phi_ion(beads); Q].
@@ -342,8 +384,9 @@ void build_rhs(pe_context* c, double* b) {
     phi_ion = c->phi_w.get();
     launch_moments(s, c->ion_q.get(), c->ion_sig.get(), 0.0, ni, ck_coef(c), c->red.get(), ck_ion(c), nullptr);
     // with the learned guess active, the same pass also yields the ion field at the beads
+    // (in single precision the field is formed anyway, for the force pass)
     double* E = nullptr;
-    if (c->guess) {
+    if (c->guess || c->p.precision == PE_MIXED) {
       c->E_ion.ensure(3 * std::max<int64_t>(nb, 1));
       E = c->E_ion.get();
     }
@@ -679,6 +722,7 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   c->have_solution = false;
   c->have_forces = false;
   c->have_eion = false;
+  c->ion_parts_valid = false;
   require(n_body >= 0 && n_ion >= 0, "negative sizes");
   require(n_body == 0 || body_offsets != nullptr, "body_offsets is null");
   require(E0 != nullptr, "E0 is null");
@@ -1020,7 +1064,7 @@ pe_status pe_forces_torques(pe_context* c, double* body_force, double* body_torq
   dcopy(s, c->ion_q.get(), chg + nb, ni);
   double* f = c->forces.get();
   if (c->p.precision == PE_MIXED)
-    all_potential<float>(c, chg, chg + nb, c->phi_all.get(), c->E_all.get(), f, u, chg);
+    all_potential<float>(c, chg, chg + nb, c->phi_all.get(), c->E_all.get(), f, u, chg, true);
   else
     all_potential<double>(c, chg, chg + nb, c->phi_all.get(), c->E_all.get(), f, u, chg);
   c->bodyF.ensure(3 * std::max<int64_t>(c->n_body, 1));

@@ -338,6 +338,12 @@ struct pe_context {
   pe::DevBuf<double> bodyF, bodyL;  // n_body x 3 from the last force pass
   pe::DevBuf<double> bd_R;     // per-body rotation of the last BD step
   pe::DevBuf<double> E_ion;    // n_bead x 3, field of the ions at the beads (learned-guess features)
+  // single-precision ion parts kept from the right-hand side for the force
+  // pass of the same configuration: the spread ion grid (before the
+  // convolution) and the real-space ion -> bead potential and field
+  pe::DevBuf<float> ion_grid32;
+  pe::DevBuf<double> ion_rs_phi, ion_rs_E;
+  bool ion_parts_valid = false;
   bool have_eion = false;
   pe::DevBuf<double> host_pin; // unused placeholder
 
