@@ -45,8 +45,9 @@ SPLIT_TOL = {"cfg2": 1e-8, "cfg3": 1e-6, "cfg4": 1e-6, "cfg5": 1e-6}
 # run of this script (the class's dispatches of five steps, averaged;
 # FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the ratios a plain 256 MiB
 # device copy reads on those counters).  Each entry
-# records the source file the kernels live in and its sha1 at measurement;
-# once that file changes the figure is stale and `traffic` is reported null.
+# records the source files of the kernels and of their launches with their
+# sha1 at measurement; once one changes the figure is stale and `traffic` is
+# reported null.
 TRAFFIC = {}
 
 
