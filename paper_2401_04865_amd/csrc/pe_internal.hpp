@@ -265,6 +265,7 @@ struct Precond {
   std::deque<BodyType> types;
   DevBuf<int> assigned;            // per body: type index
   DevBuf<unsigned char> dense;     // per body: intra-body pairs held by a dense block
+  std::vector<unsigned char> dense_h;  // host copy
   DevBuf<double> gemm_ws;          // partial tiles of the split per-shape products
 };
 
@@ -312,6 +313,18 @@ struct pe_context {
   int64_t nnz = 0;
   pe::DevBuf<int64_t> row_ptr;
   pe::DevBuf<int64_t> scan_tmp;    // prefix-sum workspace
+  // The pair structure is built with the cutoff r_c + skin and kept while no
+  // bead has moved more than skin/2 since (rigid bodies in Brownian steps
+  // move little); every configuration recomputes the values from the current
+  // positions with the exact cutoff r_c, so the operator is the truncated
+  // one either way.
+  bool csr_valid = false;
+  double csr_rc = 0, csr_skin = 0;
+  std::vector<int64_t> csr_off;
+  std::vector<unsigned char> csr_dense;
+  pe::DevBuf<double> csr_x0;       // bead positions (caller order) at the build
+  pe::DevBuf<int> csr_row;         // caller bead index of every row
+  pe::DevBuf<double> csr_part;     // displacement reduction partials
   pe::DevBuf<int> cnt;
   pe::DevBuf<int> col;
   pe::DevBuf<double> val64;

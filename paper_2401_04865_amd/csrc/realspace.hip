@@ -338,18 +338,20 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     }
     const double s2 = p.w * p.w + qp.w * qp.w;
     if constexpr (MODE == MODE_FILL) {
-      double R;
-      if (r2 == 0.0) {
-        R = self_value<double>(s2, g);
-      } else {
-        double dR;
-        pair_kernel<double>(sqrt(r2), s2, g, R, dR, false);
-      }
       // the row was sized by the count pass; never write past it
       if (o < o_end) {
         out.col[o] = s0.idx[sidx];
-        out.v64[o] = R;
-        if (out.v32) out.v32[o] = (float)R;
+        if (out.v64) {  // values here, or later from the structure
+          double R;
+          if (r2 == 0.0) {
+            R = self_value<double>(s2, g);
+          } else {
+            double dR;
+            pair_kernel<double>(sqrt(r2), s2, g, R, dR, false);
+          }
+          out.v64[o] = R;
+          if (out.v32) out.v32[o] = (float)R;
+        }
         ++o;
       }
       return;
@@ -598,11 +600,14 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   if (MODE == MODE_COUNT) {
     out.cnt[t] = cnt;
   } else if (MODE == MODE_FILL) {
-    // a pair counted but not found again (rounding at the cutoff) adds nothing
+    // a pair counted but not found again (rounding at the cutoff) adds
+    // nothing: column -1 - own index, value zero
     for (; o < o_end; ++o) {
-      out.col[o] = tidx[t];
-      out.v64[o] = 0.0;
-      if (out.v32) out.v32[o] = 0.0f;
+      out.col[o] = -1 - tidx[t];
+      if (out.v64) {
+        out.v64[o] = 0.0;
+        if (out.v32) out.v32[o] = 0.0f;
+      }
     }
   } else if (MODE == MODE_POT || MODE == MODE_FIELD) {
     const int oi = tidx[t];
@@ -622,7 +627,7 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
 template <typename T>
 __global__ void __launch_bounds__(256) spmv_assemble_kernel(
     const int64_t* __restrict__ row_ptr, const int* __restrict__ col, const T* __restrict__ val,
-    const int* __restrict__ idx, const double4* __restrict__ pos, int64_t n,
+    const int* __restrict__ row_bead, const double* __restrict__ sig, int64_t n,
     const double* __restrict__ q, const double* __restrict__ phi_wave, const double* __restrict__ ck,
     const double* __restrict__ dpsi, const int* __restrict__ body_of, double* __restrict__ y) {
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
@@ -630,15 +635,74 @@ __global__ void __launch_bounds__(256) spmv_assemble_kernel(
   T acc = 0;
   if (i < n) {
     const int64_t e = row_ptr[i + 1];
-    for (int64_t o = row_ptr[i] + sub; o < e; o += 16) acc += val[o] * (T)q[col[o]];
+    for (int64_t o = row_ptr[i] + sub; o < e; o += 16) {
+      const int j = col[o];  // a negative column is a zero entry
+      acc += val[o] * (T)q[j < 0 ? -1 - j : j];
+    }
   }
 #pragma unroll
   for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
   if (i < n && sub == 0) {
-    const int b = idx[i];
-    const double sg = pos[i].w;
+    const int b = row_bead[i];
+    const double sg = sig[b];
     const double phi = (double)acc + phi_wave[b] - (ck[0] - ck[1] * sg * sg);
     y[b] = -phi + (dpsi ? dpsi[body_of[b]] : 0.0);
+  }
+}
+
+// Values of the stored bead-bead pairs from the current positions (caller
+// order, minimum image) with the exact cutoff: R(r) inside r_c, the self
+// value at r = 0, zero outside r_c and for the zero entries (negative
+// column).  One thread per row.
+__global__ void csr_refresh_kernel(const int64_t* __restrict__ row_ptr, const int* __restrict__ col,
+                                   const int* __restrict__ row_bead, int64_t n, const double* __restrict__ x,
+                                   const double* __restrict__ sig, RealGeom g, double* __restrict__ v64,
+                                   float* __restrict__ v32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = row_bead[i];
+  const double xb = x[3 * b], yb = x[3 * b + 1], zb = x[3 * b + 2], sb = sig[b];
+  for (int64_t o = row_ptr[i]; o < row_ptr[i + 1]; ++o) {
+    const int j = col[o];
+    double R = 0.0;
+    if (j >= 0) {
+      const double dx = min_img(xb - x[3 * j], g.L[0], g.inv_L[0]);
+      const double dy = min_img(yb - x[3 * j + 1], g.L[1], g.inv_L[1]);
+      const double dz = min_img(zb - x[3 * j + 2], g.L[2], g.inv_L[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double s2 = sb * sb + sig[j] * sig[j];
+      if (r2 == 0.0) {
+        R = self_value<double>(s2, g);
+      } else if (r2 < g.rc2) {
+        double dR;
+        pair_kernel<double>(sqrt(r2), s2, g, R, dR, false);
+      }
+    }
+    v64[o] = R;
+    if (v32) v32[o] = (float)R;
+  }
+}
+
+// Per-block maximum of |x - x0|^2 over the beads (caller order, unwrapped).
+__global__ void __launch_bounds__(256) max_disp_kernel(const double* __restrict__ x, const double* __restrict__ x0,
+                                                       int64_t n, double* __restrict__ part) {
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double dx = x[3 * i] - x0[3 * i], dy = x[3 * i + 1] - x0[3 * i + 1], dz = x[3 * i + 2] - x0[3 * i + 2];
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    m = d2 > m || d2 != d2 ? d2 : m;  // a NaN wins, so it forces a rebuild
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v = __shfl_xor(m, o, 64);
+    m = v > m || v != v ? v : m;
+  }
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+    for (int w = 1; w < 4; ++w) t = sh[w] > t || sh[w] != sh[w] ? sh[w] : t;
+    part[blockIdx.x] = t;
   }
 }
 
@@ -741,32 +805,80 @@ void build_bead_matrix(pe_context* c) {
   const int64_t n = c->n_bead;
   ParticleSet& B = c->B;
   require(n < (int64_t(1) << kSetBit), "too many particles in one set for the pair traversal");
-  c->cnt.ensure(n);
-  const SrcSet sb = src_of(B, nullptr);
-  PairOut out{};
-  out.cnt = c->cnt.get();
-  if (c->n_body > 0) {
-    out.body_of = c->body_of.get();
-    out.dense = c->pc.dense.get();
-  }
-  if (n > 0) launch_queue<MODE_COUNT, double, double>(s, B, sb, sb, 1, c->rg, out);
-  // row offsets on the device; only the total comes back to size the arrays
-  c->row_ptr.ensure(n + 1);
-  c->scan_tmp.ensure((size_t)scan_workspace(n));
-  launch_exclusive_scan(s, c->cnt.get(), n, c->row_ptr.get(), c->scan_tmp.get());
-  int64_t nnz = 0;
-  PE_HIP(hipMemcpyAsync(&nnz, c->row_ptr.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  PE_HIP(hipStreamSynchronize(s));
-  c->nnz = nnz;
-  c->col.ensure(c->nnz);
-  c->val64.ensure(c->nnz);
   c->have_val32 = c->p.precision == PE_MIXED;
-  if (c->have_val32) c->val32.ensure(c->nnz);
-  out.row_ptr = c->row_ptr.get();
-  out.col = c->col.get();
-  out.v64 = c->val64.get();
-  out.v32 = c->have_val32 ? c->val32.get() : nullptr;
-  if (n > 0) launch_queue<MODE_FILL, double, double>(s, B, sb, sb, 1, c->rg, out);
+  // skin: what the cells allow beyond r_c (the 27-cell stencil must still
+  // hold every pair within r_c + skin), at most r_c / 10; none when an axis
+  // has fewer than three cells
+  const double rc = std::sqrt(c->rg.rc2);
+  double skin = 0.1 * rc;
+  for (int d = 0; d < 3; ++d) {
+    if (c->rg.nc[d] < 3) skin = 0.0;
+    else skin = std::min(skin, c->rg.L[d] / c->rg.nc[d] - rc);
+  }
+  if (skin < 1e-3 * rc) skin = 0.0;
+  bool rebuild = !(c->csr_valid && skin > 0 && c->csr_skin == skin && c->csr_rc == rc && c->csr_off == c->h_off &&
+                   c->csr_dense == c->pc.dense_h);
+  if (!rebuild && n > 0) {
+    const unsigned nbk = std::min<unsigned>(256, nblk(n, 256));
+    c->csr_part.ensure(256);
+    hipLaunchKernelGGL(max_disp_kernel, dim3(nbk), dim3(256), 0, s, c->bead_x.get(), c->csr_x0.get(), n,
+                       c->csr_part.get());
+    PE_CHECK_LAUNCH();
+    std::vector<double> part(nbk);
+    PE_HIP(hipMemcpyAsync(part.data(), c->csr_part.get(), sizeof(double) * nbk, hipMemcpyDeviceToHost, s));
+    PE_HIP(hipStreamSynchronize(s));
+    double mx = 0;
+    for (double v : part) mx = (v > mx || v != v) ? v : mx;
+    rebuild = !(mx <= 0.25 * skin * skin);
+  }
+  if (rebuild) {
+    c->cnt.ensure(n);
+    RealGeom rgb = c->rg;
+    rgb.rc2 = (rc + skin) * (rc + skin);
+    const SrcSet sb = src_of(B, nullptr);
+    PairOut out{};
+    out.cnt = c->cnt.get();
+    if (c->n_body > 0) {
+      out.body_of = c->body_of.get();
+      out.dense = c->pc.dense.get();
+    }
+    if (n > 0) launch_queue<MODE_COUNT, double, double>(s, B, sb, sb, 1, rgb, out);
+    // row offsets on the device; only the total comes back to size the arrays
+    c->row_ptr.ensure(n + 1);
+    c->scan_tmp.ensure((size_t)scan_workspace(n));
+    launch_exclusive_scan(s, c->cnt.get(), n, c->row_ptr.get(), c->scan_tmp.get());
+    int64_t nnz = 0;
+    PE_HIP(hipMemcpyAsync(&nnz, c->row_ptr.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PE_HIP(hipStreamSynchronize(s));
+    c->nnz = nnz;
+    c->col.ensure(c->nnz);
+    c->val64.ensure(c->nnz);
+    if (c->have_val32) c->val32.ensure(c->nnz);
+    out.row_ptr = c->row_ptr.get();
+    out.col = c->col.get();
+    // with a skin the values come from the refresh below (exact cutoff)
+    out.v64 = skin > 0 ? nullptr : c->val64.get();
+    out.v32 = skin > 0 || !c->have_val32 ? nullptr : c->val32.get();
+    if (n > 0) launch_queue<MODE_FILL, double, double>(s, B, sb, sb, 1, rgb, out);
+    c->csr_row.ensure((size_t)std::max<int64_t>(n, 1));
+    if (n > 0) PE_HIP(hipMemcpyAsync(c->csr_row.get(), B.idx.get(), sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+    c->csr_valid = skin > 0;
+    c->csr_skin = skin;
+    c->csr_rc = rc;
+    c->csr_off = c->h_off;
+    c->csr_dense = c->pc.dense_h;
+    if (skin > 0) {
+      c->csr_x0.ensure(3 * (size_t)std::max<int64_t>(n, 1));
+      if (n > 0)
+        PE_HIP(hipMemcpyAsync(c->csr_x0.get(), c->bead_x.get(), sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  if (skin > 0 && n > 0) {
+    hipLaunchKernelGGL(csr_refresh_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, c->row_ptr.get(), c->col.get(),
+                       c->csr_row.get(), n, c->bead_x.get(), c->bead_sig.get(), c->rg, c->val64.get(),
+                       c->have_val32 ? c->val32.get() : nullptr);
+    PE_CHECK_LAUNCH();
+  }
 }
 
 namespace {
@@ -821,7 +933,7 @@ void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const d
     val = c->val32.get();
   }
   hipLaunchKernelGGL(spmv_assemble_kernel<T>, dim3(nblk(16 * n, 256)), dim3(256), 0, s, c->row_ptr.get(),
-                     c->col.get(), val, c->B.idx.get(), c->B.pos.get(), n, q, phi_wave, ck0, dpsi,
+                     c->col.get(), val, c->csr_row.get(), c->bead_sig.get(), n, q, phi_wave, ck0, dpsi,
                      c->body_of.get(), y_top);
   PE_CHECK_LAUNCH();
 }

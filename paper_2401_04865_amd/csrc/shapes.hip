@@ -339,6 +339,7 @@ void shape_setup(pe_context* c) {
   pc.gemm_ws.ensure(ws);
   PE_HIP(hipMemcpyAsync(pc.dense.get(), dense.data(), nbody, hipMemcpyHostToDevice, s));
   PE_HIP(hipStreamSynchronize(s));
+  pc.dense_h = dense;
 }
 
 int body_gemm_splits(int N, int nbt, bool bordered) {
