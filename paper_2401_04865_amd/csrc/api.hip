@@ -464,9 +464,13 @@ double precond_madds(const pe_context* c) {
 
 // r0 (optional, with its norm r0n): the residual b - A x at the starting x,
 // already formed by the caller, so the first cycle does not recompute it.
+//
+// final_check = false (inner solves of the mixed refinement, whose caller
+// forms the true residual in double right after): a cycle that ends on the
+// residual estimate returns without recomputing b - A x.
 GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero, double bnorm, double tol,
                int max_iters, pe_solve_info* info, int* mv64, int* mv32, const double* r0 = nullptr,
-               double r0n = 0.0) {
+               double r0n = 0.0, bool final_check = true) {
   hipStream_t s = c->stream;
   const int64_t n = c->n_bead + c->n_body;
   const int m = std::max(1, std::min(c->p.gmres_restart, kMaxK - 1));
@@ -504,6 +508,7 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
     launch_scale(s, k.r, k.nrm, k.V, n);
     launch_init_g(s, k.st, m, k.nrm);
     int jend = 0;
+    double last_est = beta;
     const bool pre = c->p.precond != 0 && !c->pc.types.empty();
     for (int j = 0; j < m; ++j) {
       double* vj = k.V + (size_t)j * n;
@@ -533,10 +538,16 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
       if (info && info->n_hist < 1024) info->hist[info->n_hist++] = est / bnorm;
       jend = j + 1;
       if (!std::isfinite(est)) throw Error(PE_ERR_NUMERIC, "non-finite residual estimate in GMRES");
+      last_est = est;
       if (est <= tol * bnorm || out.iters >= max_iters) break;
     }
     launch_backsolve(s, k.st, m, jend, k.y);
     launch_maxpy(s, pre ? k.Z : k.V, n, jend, k.y, x, n, -1.0);  // x += Z y (flexible) or V y
+    if (!final_check && (last_est <= tol * bnorm || out.iters >= max_iters)) {
+      out.rel = last_est / bnorm;
+      out.converged = last_est <= tol * bnorm;
+      return out;
+    }
   }
 }
 
@@ -966,7 +977,7 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
         PE_HIP(hipMemsetAsync(d, 0, sizeof(double) * n, s));
         const double itol = std::max(c->p.inner_tol, 0.5 * tol / std::max(rel, 1e-300));
         GmresOut o = gmres(c, PE_MIXED, r, d, true, rn, std::min(itol, 0.5), c->p.max_iters - total, inf,
-                           &mv64, &mv32);
+                           &mv64, &mv32, nullptr, 0.0, false);
         total += o.iters;
         launch_axpby(s, 1.0, d, 1.0, x, n);
       }
