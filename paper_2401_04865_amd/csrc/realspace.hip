@@ -501,6 +501,19 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   // oy a1 from the target column's origin in the target's image.
   const float px = (float)(p.x - cx * a0), py = (float)(p.y - cy * a1), pz = (float)p.z;
   const float a0f = (float)a0, a1f = (float)a1, Lz = Lf2;
+  // bounding box of the wavefront's targets (same frame as the candidates)
+  float bx0 = active ? px : INFINITY, bx1 = active ? px : -INFINITY;
+  float by0 = active ? py : INFINITY, by1 = active ? py : -INFINITY;
+  float bz0 = active ? pz : INFINITY, bz1 = active ? pz : -INFINITY;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    bx0 = fminf(bx0, __shfl_xor(bx0, off, 64));
+    bx1 = fmaxf(bx1, __shfl_xor(bx1, off, 64));
+    by0 = fminf(by0, __shfl_xor(by0, off, 64));
+    by1 = fmaxf(by1, __shfl_xor(by1, off, 64));
+    bz0 = fminf(bz0, __shfl_xor(bz0, off, 64));
+    bz1 = fmaxf(bz1, __shfl_xor(bz1, off, 64));
+  }
   int next = 0, pbase = 0;  // next stream position to stage and (next S) mod M
   int nbat = 0, k0 = 0;
   const float nanf_ = __int_as_float(0x7fc00000);
@@ -510,6 +523,7 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
       if (next < M) {
         float4 v = make_float4(nanf_, nanf_, nanf_, nanf_);
         int own = -1;
+        bool keep = false;
         if (next + lane < M) {
           int pos = pbase + lane_pos;
           if (pos >= M) pos -= M;
@@ -529,14 +543,29 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
           const float4 sp = (set ? s1.posf : s0.posf)[sidx];
           v = make_float4(sp.x + ofx, sp.y + ofy, sp.z + ofz, __int_as_float(sidx | set << kSetBit));
           own = __float_as_int(sp.w);
+          keep = true;
+          if (!per_pair_image) {
+            // farther than the cutoff from the targets' bounding box: no lane can hit it
+            const float ex = fmaxf(fmaxf(bx0 - v.x, v.x - bx1), 0.0f);
+            const float ey = fmaxf(fmaxf(by0 - v.y, v.y - by1), 0.0f);
+            const float ez = fmaxf(fmaxf(bz0 - v.z, v.z - bz1), 0.0f);
+            keep = ex * ex + ey * ey + ez * ez < rc2f;
+          }
         }
-        cb[lane] = v;
-        if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) cown[lane] = own;
+        // the kept candidates first, in stream order; NaN points after them
+        const unsigned long long km = __ballot(keep);
+        const int nkeep = __popcll(km);
+        if (keep) {
+          const int slot = __popcll(km & ((1ull << lane) - 1ull));
+          cb[slot] = v;
+          if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) cown[slot] = own;
+        }
+        if (lane >= nkeep) cb[lane] = make_float4(nanf_, nanf_, nanf_, nanf_);  // slots past the kept ones
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        nbat = min(64, M - next);
-        next += nbat;
+        nbat = nkeep;
+        next += min(64, M - next);
         pbase += step64;
         if (pbase >= M) pbase -= M;
         k0 = 0;
