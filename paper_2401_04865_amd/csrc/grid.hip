@@ -594,56 +594,58 @@ __global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restr
 void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
   const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];
   ps.tile_start.ensure(nt + 1);
-  ps.tile_count.ensure(nt);
-  PE_HIP(hipMemsetAsync(ps.tile_count.get(), 0, sizeof(int) * nt, s));
+  ps.tile_count.ensure(2 * (size_t)nt);
+  int* tcount = ps.tile_count.get();  // spreading lists: counts, then cursors
+  int* hcount = tcount + nt;          // home lists: counts, then cursors
+  PE_HIP(hipMemsetAsync(tcount, 0, sizeof(int) * 2 * nt, s));
   const unsigned nb = (unsigned)((ps.n + 255) / 256);
   if (ps.n > 0) {
-    hipLaunchKernelGGL(tile_list_kernel<false>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g,
-                       ps.tile_count.get(), (int*)nullptr);
+    hipLaunchKernelGGL(tile_list_kernel<false>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, tcount,
+                       (int*)nullptr);
+    PE_CHECK_LAUNCH();
+    hipLaunchKernelGGL(home_count_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, hcount);
     PE_CHECK_LAUNCH();
   }
-  std::vector<int> cnt(nt), start(nt + 1, 0);
-  PE_HIP(hipMemcpyAsync(cnt.data(), ps.tile_count.get(), sizeof(int) * nt, hipMemcpyDeviceToHost, s));
+  // both counts in one round trip; the host arrays live in the set, so the
+  // copies below need no wait before this function returns
+  std::vector<int>& cnt = ps.h_tcnt;
+  cnt.resize(2 * (size_t)nt);
+  PE_HIP(hipMemcpyAsync(cnt.data(), tcount, sizeof(int) * 2 * nt, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
-  for (int t = 0; t < nt; ++t) start[t + 1] = start[t] + cnt[t];
+  std::vector<int>& start = ps.h_tstart;
+  std::vector<int>& hstart = ps.h_hstart;
+  std::vector<int>& htiles = ps.h_htiles;
+  start.assign(nt + 1, 0);
+  hstart.assign(nt + 1, 0);
+  htiles.clear();
+  for (int t = 0; t < nt; ++t) {
+    start[t + 1] = start[t] + cnt[t];
+    hstart[t + 1] = hstart[t] + cnt[nt + t];
+    if (cnt[nt + t]) htiles.push_back(t);
+  }
   ps.n_entries = start[nt];
   ps.tile_entries.ensure(ps.n_entries);
+  ps.home_start.ensure(nt + 1);
+  ps.home_entries.ensure(std::max<int64_t>(ps.n, 1));
+  ps.n_home_tiles = (int)htiles.size();
+  ps.home_tiles.ensure(std::max<size_t>(htiles.size(), 1));
   PE_HIP(hipMemcpyAsync(ps.tile_start.get(), start.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
-  PE_HIP(hipMemcpyAsync(ps.tile_count.get(), start.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(tcount, start.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(ps.home_start.get(), hstart.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(hcount, hstart.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  if (!htiles.empty())
+    PE_HIP(hipMemcpyAsync(ps.home_tiles.get(), htiles.data(), sizeof(int) * htiles.size(), hipMemcpyHostToDevice, s));
   if (ps.n > 0) {
-    hipLaunchKernelGGL(tile_list_kernel<true>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get(),
+    hipLaunchKernelGGL(tile_list_kernel<true>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, tcount,
                        ps.tile_entries.get());
     PE_CHECK_LAUNCH();
     // sort each tile's list so the accumulation order is the same on every run
     launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get());
-  }
-  // home lists (each particle once; order within a tile does not matter)
-  ps.home_start.ensure(nt + 1);
-  ps.home_entries.ensure(std::max<int64_t>(ps.n, 1));
-  PE_HIP(hipMemsetAsync(ps.tile_count.get(), 0, sizeof(int) * nt, s));
-  if (ps.n > 0) {
-    hipLaunchKernelGGL(home_count_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get());
-    PE_CHECK_LAUNCH();
-  }
-  PE_HIP(hipMemcpyAsync(cnt.data(), ps.tile_count.get(), sizeof(int) * nt, hipMemcpyDeviceToHost, s));
-  PE_HIP(hipStreamSynchronize(s));
-  std::vector<int> hstart(nt + 1, 0), htiles;
-  for (int t = 0; t < nt; ++t) {
-    hstart[t + 1] = hstart[t] + cnt[t];
-    if (cnt[t]) htiles.push_back(t);
-  }
-  ps.n_home_tiles = (int)htiles.size();
-  ps.home_tiles.ensure(std::max<size_t>(htiles.size(), 1));
-  PE_HIP(hipMemcpyAsync(ps.home_start.get(), hstart.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
-  if (!htiles.empty())
-    PE_HIP(hipMemcpyAsync(ps.home_tiles.get(), htiles.data(), sizeof(int) * htiles.size(), hipMemcpyHostToDevice, s));
-  PE_HIP(hipMemcpyAsync(ps.tile_count.get(), hstart.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
-  if (ps.n > 0) {
-    hipLaunchKernelGGL(home_fill_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, ps.tile_count.get(),
+    // home lists (each particle once; order within a tile does not matter)
+    hipLaunchKernelGGL(home_fill_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, hcount,
                        ps.home_entries.get());
     PE_CHECK_LAUNCH();
   }
-  PE_HIP(hipStreamSynchronize(s));
 }
 
 template <typename T>

@@ -136,7 +136,11 @@ struct ParticleSet {
   int n_chunks = 0;
   // grid tiles overlapped by each particle's support (spreading lists)
   DevBuf<int> tile_start;   // ntile + 1
-  DevBuf<int> tile_count;   // ntile (scratch)
+  DevBuf<int> tile_count;   // 2 ntile (scratch: counts and cursors of both list kinds)
+  // host copies of the counts and offsets (kept so the copies to the device
+  // need no wait before the builders return)
+  std::vector<int> h_tcnt, h_tstart, h_hstart, h_htiles, h_ccnt, h_cstart;
+  std::vector<int4> h_chunks;
   DevBuf<int> tile_entries; // sorted-particle indices, grouped by tile
   int64_t n_entries = 0;
   // home tile of each particle (the tile holding its first support point):

@@ -767,7 +767,10 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
                        sig_const, n, rg, ps.tmp.get(), ps.cell_of.get(), ps.cell_count.get());
     PE_CHECK_LAUNCH();
   }
-  std::vector<int> cnt(ncell), start(ncell + 1, 0);
+  std::vector<int>& cnt = ps.h_ccnt;
+  std::vector<int>& start = ps.h_cstart;
+  cnt.resize(ncell);
+  start.assign(ncell + 1, 0);
   PE_HIP(hipMemcpyAsync(cnt.data(), ps.cell_count.get(), sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
   for (int c = 0; c < ncell; ++c) start[c + 1] = start[c] + cnt[c];
@@ -775,7 +778,8 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   // and two neighbouring cells of one z column with 64 or fewer together
   // share a unit (when the column has room for the wider stencil), so sparse
   // cells do not leave most lanes of a wavefront idle
-  std::vector<int4> chunks;
+  std::vector<int4>& chunks = ps.h_chunks;
+  chunks.clear();
   const bool merge = rg.nc[2] >= 6;
   for (int c = 0; c < ncell;) {
     const int n0 = cnt[c];
@@ -807,8 +811,7 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
                        ps.idx.get(), owner, n, rg, ps.pos.get(), ps.posf.get());
     PE_CHECK_LAUNCH();
   }
-  // the host vectors go out of scope after the copies above complete
-  PE_HIP(hipStreamSynchronize(s));
+  // the host arrays live in the set: no wait here
 }
 
 namespace {
