@@ -16,6 +16,7 @@
 // m0-P/2+1 .. m0+P/2 with m0 = floor(x/h); odd P is centred on rint(x/h).
 // Index and displacement are computed in double for both precisions, so
 // the float and double paths use the same support.
+#include <algorithm>
 #include <climits>
 #include <vector>
 
@@ -640,7 +641,8 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
                        ps.tile_entries.get());
     PE_CHECK_LAUNCH();
     // sort each tile's list so the accumulation order is the same on every run
-    launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get());
+    launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get(),
+                        nt ? *std::max_element(cnt.begin(), cnt.begin() + nt) : 0);
     // home lists (each particle once; order within a tile does not matter)
     hipLaunchKernelGGL(home_fill_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, hcount,
                        ps.home_entries.get());

@@ -682,16 +682,19 @@ __global__ void __launch_bounds__(256) spmv_assemble_kernel(
 // Values of the stored bead-bead pairs from the current positions (caller
 // order, minimum image) with the exact cutoff: R(r) inside r_c, the self
 // value at r = 0, zero outside r_c and for the zero entries (negative
-// column).  One thread per row.
-__global__ void csr_refresh_kernel(const int64_t* __restrict__ row_ptr, const int* __restrict__ col,
-                                   const int* __restrict__ row_bead, int64_t n, const double* __restrict__ x,
-                                   const double* __restrict__ sig, RealGeom g, double* __restrict__ v64,
-                                   float* __restrict__ v32) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// column).  16 lanes per row, each taking every 16th entry.
+__global__ void __launch_bounds__(256) csr_refresh_kernel(const int64_t* __restrict__ row_ptr,
+                                                          const int* __restrict__ col,
+                                                          const int* __restrict__ row_bead, int64_t n,
+                                                          const double* __restrict__ x,
+                                                          const double* __restrict__ sig, RealGeom g,
+                                                          double* __restrict__ v64, float* __restrict__ v32) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int sub = threadIdx.x & 15;
   if (i >= n) return;
   const int b = row_bead[i];
   const double xb = x[3 * b], yb = x[3 * b + 1], zb = x[3 * b + 2], sb = sig[b];
-  for (int64_t o = row_ptr[i]; o < row_ptr[i + 1]; ++o) {
+  for (int64_t o = row_ptr[i] + sub; o < row_ptr[i + 1]; o += 16) {
     const int j = col[o];
     double R = 0.0;
     if (j >= 0) {
@@ -806,7 +809,8 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
     PE_CHECK_LAUNCH();
     // sort each cell's slice by caller index so the order (and every sum over
     // it) is the same on every run
-    launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get());
+    launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get(),
+                        ncell ? *std::max_element(cnt.begin(), cnt.end()) : 0);
     hipLaunchKernelGGL(gather_sorted_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.tmp.get(),
                        ps.idx.get(), owner, n, rg, ps.pos.get(), ps.posf.get());
     PE_CHECK_LAUNCH();
@@ -906,7 +910,7 @@ void build_bead_matrix(pe_context* c) {
     }
   }
   if (skin > 0 && n > 0) {
-    hipLaunchKernelGGL(csr_refresh_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, c->row_ptr.get(), c->col.get(),
+    hipLaunchKernelGGL(csr_refresh_kernel, dim3(nblk(16 * n, 256)), dim3(256), 0, s, c->row_ptr.get(), c->col.get(),
                        c->csr_row.get(), n, c->bead_x.get(), c->bead_sig.get(), c->rg, c->val64.get(),
                        c->have_val32 ? c->val32.get() : nullptr);
     PE_CHECK_LAUNCH();

@@ -266,7 +266,7 @@ inline unsigned nred(int64_t n) {
 constexpr int kSortMax = 4096;
 
 __global__ void __launch_bounds__(256) segment_sort_kernel(const int* __restrict__ start, int* __restrict__ keys) {
-  __shared__ int key[kSortMax];
+  extern __shared__ int key[];  // next power of two of the longest segment (at most kSortMax)
   const int b = start[blockIdx.x], e = start[blockIdx.x + 1];
   const int n = e - b;
   if (n <= 1) return;
@@ -386,9 +386,11 @@ void launch_backsolve(hipStream_t s, const double* st, int m, int k, double* y) 
   PE_CHECK_LAUNCH();
 }
 
-void launch_segment_sort(hipStream_t s, const int* start, int nseg, int* keys) {
-  if (nseg <= 0) return;
-  hipLaunchKernelGGL(segment_sort_kernel, dim3((unsigned)nseg), dim3(256), 0, s, start, keys);
+void launch_segment_sort(hipStream_t s, const int* start, int nseg, int* keys, int max_len) {
+  if (nseg <= 0 || max_len <= 1) return;
+  int m = 1;
+  while (m < std::min(max_len, kSortMax)) m <<= 1;
+  hipLaunchKernelGGL(segment_sort_kernel, dim3((unsigned)nseg), dim3(256), sizeof(int) * (size_t)m, s, start, keys);
   PE_CHECK_LAUNCH();
 }
 

@@ -33,7 +33,9 @@ void launch_init_g(hipStream_t s, double* st, int m, const double* beta);
 void launch_backsolve(hipStream_t s, const double* st, int m, int k, double* y);
 
 // Sort every segment [start[k], start[k+1]) of keys ascending, in place.
-void launch_segment_sort(hipStream_t s, const int* start, int nseg, int* keys);
+// Sorts keys[start[k] .. start[k+1]) ascending for every k; max_len bounds
+// the segment lengths (it sizes the LDS of each workgroup).
+void launch_segment_sort(hipStream_t s, const int* start, int nseg, int* keys, int max_len);
 // out[0] = 0, out[i+1] = in[0] + ... + in[i] (i < n), summed in 64 bits;
 // tmp holds scan_workspace(n) values.
 int64_t scan_workspace(int64_t n);
