@@ -439,11 +439,10 @@ KWork kwork(pe_context* c, int64_t n, int m) {
 }
 
 double fetch(pe_context* c, const double* d) {
-  double h;
-  PE_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  PE_HIP(hipMemcpyAsync(c->pinned, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   PE_HIP(hipStreamSynchronize(c->stream));
   c->prof.flush();
-  return h;
+  return c->pinned[0];
 }
 
 struct GmresOut {
@@ -700,6 +699,7 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
   c->rg.erfcx = c->erfcx_tab.get();
   c->sums.ensure(64);
   c->red.ensure((size_t)kMaxK * 1024 + 8192);
+  PE_HIP(hipHostMalloc((void**)&c->pinned, 512 * sizeof(double), hipHostMallocDefault));
   *out = c;
   c = nullptr;
   PE_API_END(c)
@@ -708,6 +708,7 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
 pe_status pe_destroy(pe_context* ctx) {
   if (!ctx) return PE_OK;
   if (ctx->guess) guess_destroy(ctx);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return PE_OK;
 }

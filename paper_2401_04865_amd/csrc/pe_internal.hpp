@@ -362,7 +362,7 @@ struct pe_context {
   pe::DevBuf<double> ion_rs_phi, ion_rs_E;
   bool ion_parts_valid = false;
   bool have_eion = false;
-  pe::DevBuf<double> host_pin; // unused placeholder
+  double* pinned = nullptr;    // 512 doubles of pinned host memory for small reads (hipHostMalloc)
 
   // learned guess
   pe::LearnedGuess* guess = nullptr;

@@ -33,6 +33,7 @@
 // matrix-vector product.  One-off passes (ion -> bead for the right-hand
 // side, all pairs with fields for the forces) are evaluated on the fly.
 #include <algorithm>
+#include <cstring>
 #include <numeric>
 
 #include "pe_internal.hpp"
@@ -860,11 +861,10 @@ void build_bead_matrix(pe_context* c) {
     hipLaunchKernelGGL(max_disp_kernel, dim3(nbk), dim3(256), 0, s, c->bead_x.get(), c->csr_x0.get(), n,
                        c->csr_part.get());
     PE_CHECK_LAUNCH();
-    std::vector<double> part(nbk);
-    PE_HIP(hipMemcpyAsync(part.data(), c->csr_part.get(), sizeof(double) * nbk, hipMemcpyDeviceToHost, s));
+    PE_HIP(hipMemcpyAsync(c->pinned, c->csr_part.get(), sizeof(double) * nbk, hipMemcpyDeviceToHost, s));
     PE_HIP(hipStreamSynchronize(s));
     double mx = 0;
-    for (double v : part) mx = (v > mx || v != v) ? v : mx;
+    for (unsigned k = 0; k < nbk; ++k) mx = (c->pinned[k] > mx || c->pinned[k] != c->pinned[k]) ? c->pinned[k] : mx;
     rebuild = !(mx <= 0.25 * skin * skin);
   }
   if (rebuild) {
@@ -883,9 +883,10 @@ void build_bead_matrix(pe_context* c) {
     c->row_ptr.ensure(n + 1);
     c->scan_tmp.ensure((size_t)scan_workspace(n));
     launch_exclusive_scan(s, c->cnt.get(), n, c->row_ptr.get(), c->scan_tmp.get());
-    int64_t nnz = 0;
-    PE_HIP(hipMemcpyAsync(&nnz, c->row_ptr.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PE_HIP(hipMemcpyAsync(c->pinned, c->row_ptr.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PE_HIP(hipStreamSynchronize(s));
+    int64_t nnz;
+    std::memcpy(&nnz, c->pinned, sizeof(int64_t));
     c->nnz = nnz;
     c->col.ensure(c->nnz);
     c->val64.ensure(c->nnz);
