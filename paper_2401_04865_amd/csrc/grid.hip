@@ -522,21 +522,30 @@ __global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restr
     const bool valid = e < e1;
     const int i = home_entries[valid ? e : e1 - 1];
     const double4 p = pos[i];
-    // window factors and displacements of the three axes
+    // support of the three axes (placed in double), then the window factors
+    // and displacements; in single precision the factors are formed in
+    // float, the displacement (j + delta) h being below P h
+    double dlx, dly, dlz;
+    const int mx = support_start(p.x, g.inv_h[0], P, dlx);
+    const int my = support_start(p.y, g.inv_h[1], P, dly);
+    const int mz = support_start(p.z, g.inv_h[2], P, dlz);
     for (int k = s; k < 3 * P; k += 16) {
       const int ax = k / P;
       const int j = k - ax * P;
-      const double x = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
-      double delta;
-      support_start(x, g.inv_h[ax], P, delta);
-      w_s[slot][k] = window<T>(g, ax, j, delta);
-      if (FIELD) d_s[slot][k] = (T)(((double)j + delta) * g.h[ax]);
+      const double delta = ax == 0 ? dlx : (ax == 1 ? dly : dlz);
+      if constexpr (sizeof(T) == 4) {
+        const float d = ((float)j + (float)delta) * (float)g.h[ax];
+        w_s[slot][k] = (float)g.wnorm * __expf(-(float)g.wexp * d * d);
+        if (FIELD) d_s[slot][k] = d;
+      } else {
+        w_s[slot][k] = window<T>(g, ax, j, delta);
+        if (FIELD) d_s[slot][k] = (T)(((double)j + delta) * g.h[ax]);
+      }
     }
     // first support point relative to the region origin, per axis
-    double dl;
-    const int ox = wrap_idx(support_start(p.x, g.inv_h[0], P, dl), g.N[0]) - kTile * ux;
-    const int oy = wrap_idx(support_start(p.y, g.inv_h[1], P, dl), g.N[1]) - kTile * uy;
-    const int oz = wrap_idx(support_start(p.z, g.inv_h[2], P, dl), g.N[2]) - kTile * uz;
+    const int ox = wrap_idx(mx, g.N[0]) - kTile * ux;
+    const int oy = wrap_idx(my, g.N[1]) - kTile * uy;
+    const int oz = wrap_idx(mz, g.N[2]) - kTile * uz;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
