@@ -843,8 +843,10 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   PE_CHECK_LAUNCH();
   build_cells(s, c->B, c->bead_x.get(), c->bead_sig.get(), 0.0, c->body_of.get(), nb, rg);
   build_cells(s, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, nullptr, n_ion, rg);
-  build_tiles(s, c->B, c->gg);
-  build_tiles(s, c->I, c->gg);
+  // beads are spread by every Krylov product: tile lists; ions once per
+  // configuration in single precision: their sorted home lists serve
+  build_tiles(s, c->B, c->gg, false);
+  build_tiles(s, c->I, c->gg, c->p.precision == PE_MIXED);
   shape_setup(c);
   build_bead_matrix(c);
   ensure_grids(c);

@@ -204,7 +204,11 @@ __global__ void sorted_charges_kernel(const int* __restrict__ idx, const double*
 // every run.
 constexpr int kWaveChunk = 16;
 
-template <typename T>
+// HOME: the particle list of a tile is the concatenation of the sorted home
+// lists of the tiles (ux - dx, uy - dy, uz - dz), d in {0, 1}^3 (tile_start /
+// entries are then the home lists); particles whose support misses the tile
+// get zero factors.
+template <typename T, bool HOME>
 __global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restrict__ pos,
                                                           const double* __restrict__ qs,
                                                           const int* __restrict__ tile_start,
@@ -225,8 +229,38 @@ __global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restr
 #pragma unroll
   for (int c = 0; c < kTile; ++c) acc[c] = 0;
   if (uz < g.ntile[2]) {
-    const int tid = (ux * g.ntile[1] + uy) * g.ntile[2] + uz;
-    const int e0 = tile_start[tid], e1 = tile_start[tid + 1];
+    int e0, e1;
+    // HOME: segment d of the virtual list starts at hb[d] in the home lists
+    // and at hp[d] in the list; lane d < 8 computes it, every lane keeps all
+    int hb[8], hp[9];
+    if constexpr (HOME) {
+      int my_b = 0, my_n = 0;
+      if (lane < 8) {
+        const int dx = lane >> 2, dy = (lane >> 1) & 1, dz = lane & 1;
+        // a neighbour index that wraps onto the tile itself is not a second source
+        const bool dup = (dx && g.ntile[0] < 2) || (dy && g.ntile[1] < 2) || (dz && g.ntile[2] < 2);
+        if (!dup) {
+          const int tx = ux - dx < 0 ? ux - dx + g.ntile[0] : ux - dx;
+          const int ty = uy - dy < 0 ? uy - dy + g.ntile[1] : uy - dy;
+          const int tz = uz - dz < 0 ? uz - dz + g.ntile[2] : uz - dz;
+          const int t = (tx * g.ntile[1] + ty) * g.ntile[2] + tz;
+          my_b = tile_start[t];
+          my_n = tile_start[t + 1] - my_b;
+        }
+      }
+      hp[0] = 0;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        hb[d] = __shfl(my_b, d, 64);
+        hp[d + 1] = hp[d] + __shfl(my_n, d, 64);
+      }
+      e0 = 0;
+      e1 = hp[8];
+    } else {
+      const int tid = (ux * g.ntile[1] + uy) * g.ntile[2] + uz;
+      e0 = tile_start[tid];
+      e1 = tile_start[tid + 1];
+    }
     T (*fw)[3][kTile] = f_s[wv];
     // staging lane: particle c3 of the round, axis ax3.  Loads run ahead of
     // use: the entries two rounds ahead, the coordinate and charge one round
@@ -235,7 +269,22 @@ __global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restr
     const bool stager = lane < 3 * kWaveChunk;
     const int N = g.N[ax3];
     const int u = ax3 == 0 ? ux : (ax3 == 1 ? uy : uz);
-    auto entry_at = [&](int c0) { return (stager && c0 + c3 < e1) ? entries[c0 + c3] : -1; };
+    auto entry_at = [&](int c0) {
+      const int k = c0 + c3;
+      if (!stager || k >= e1) return -1;
+      if constexpr (HOME) {
+        int d = 0;
+#pragma unroll
+        for (int m = 1; m < 8; ++m) d += k >= hp[m] ? 1 : 0;
+        int b = hb[0], p0 = hp[0];
+#pragma unroll
+        for (int m = 1; m < 8; ++m)
+          if (d == m) { b = hb[m]; p0 = hp[m]; }
+        return entries[b + (k - p0)];
+      } else {
+        return entries[k];
+      }
+    };
     int i1 = entry_at(e0), i2 = entry_at(e0 + kWaveChunk);
     double x1 = 0, q1 = 1;
     if (i1 >= 0) {
@@ -601,61 +650,95 @@ __global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restr
 
 }  // namespace
 
-void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
+namespace {
+
+// Spreading lists of a set (particles overlapping each tile), sorted within
+// each tile so the accumulation order is the same on every run.
+void build_tile_lists(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
   const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];
   ps.tile_start.ensure(nt + 1);
   ps.tile_count.ensure(2 * (size_t)nt);
-  int* tcount = ps.tile_count.get();  // spreading lists: counts, then cursors
-  int* hcount = tcount + nt;          // home lists: counts, then cursors
-  PE_HIP(hipMemsetAsync(tcount, 0, sizeof(int) * 2 * nt, s));
+  int* tcount = ps.tile_count.get();
+  PE_HIP(hipMemsetAsync(tcount, 0, sizeof(int) * nt, s));
   const unsigned nb = (unsigned)((ps.n + 255) / 256);
   if (ps.n > 0) {
     hipLaunchKernelGGL(tile_list_kernel<false>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, tcount,
                        (int*)nullptr);
     PE_CHECK_LAUNCH();
+  }
+  std::vector<int>& cnt = ps.h_tcnt;
+  cnt.resize(nt);
+  PE_HIP(hipMemcpyAsync(cnt.data(), tcount, sizeof(int) * nt, hipMemcpyDeviceToHost, s));
+  PE_HIP(hipStreamSynchronize(s));
+  std::vector<int>& start = ps.h_tstart;
+  start.assign(nt + 1, 0);
+  for (int t = 0; t < nt; ++t) start[t + 1] = start[t] + cnt[t];
+  ps.n_entries = start[nt];
+  ps.tile_entries.ensure(std::max<int64_t>(ps.n_entries, 1));
+  PE_HIP(hipMemcpyAsync(ps.tile_start.get(), start.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(tcount, start.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  if (ps.n > 0) {
+    hipLaunchKernelGGL(tile_list_kernel<true>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, tcount,
+                       ps.tile_entries.get());
+    PE_CHECK_LAUNCH();
+    launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get(),
+                        nt ? *std::max_element(cnt.begin(), cnt.end()) : 0);
+  }
+  ps.have_tile_lists = true;
+}
+
+}  // namespace
+
+// Home lists of a set (each particle once, under the tile of its first
+// support point).  With spread_by_home the lists are sorted and serve the
+// single-precision spreading too (a tile's particles are those of the home
+// lists of the tile and of its lower neighbours), and the tile lists are
+// built only if a double spread asks for them; otherwise the tile lists are
+// built here.  A support spans at most two tiles per axis only when P <= 8 and
+// every tile is full: a short last tile lets a support run from its lower
+// neighbour across it into tile 0, so such meshes keep the tile lists.
+void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g, bool spread_by_home) {
+  const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];
+  spread_by_home = spread_by_home && g.P <= kTile && g.N[0] % kTile == 0 && g.N[1] % kTile == 0 &&
+                   g.N[2] % kTile == 0;
+  ps.have_tile_lists = false;
+  ps.spread_by_home = spread_by_home;
+  if (!spread_by_home) build_tile_lists(s, ps, g);
+  ps.tile_count.ensure(2 * (size_t)nt);
+  int* hcount = ps.tile_count.get() + nt;
+  PE_HIP(hipMemsetAsync(hcount, 0, sizeof(int) * nt, s));
+  const unsigned nb = (unsigned)((ps.n + 255) / 256);
+  if (ps.n > 0) {
     hipLaunchKernelGGL(home_count_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, hcount);
     PE_CHECK_LAUNCH();
   }
-  // both counts in one round trip; the host arrays live in the set, so the
-  // copies below need no wait before this function returns
-  std::vector<int>& cnt = ps.h_tcnt;
-  cnt.resize(2 * (size_t)nt);
-  PE_HIP(hipMemcpyAsync(cnt.data(), tcount, sizeof(int) * 2 * nt, hipMemcpyDeviceToHost, s));
+  std::vector<int>& cnt = ps.h_hcnt;
+  cnt.resize(nt);
+  PE_HIP(hipMemcpyAsync(cnt.data(), hcount, sizeof(int) * nt, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
-  std::vector<int>& start = ps.h_tstart;
   std::vector<int>& hstart = ps.h_hstart;
   std::vector<int>& htiles = ps.h_htiles;
-  start.assign(nt + 1, 0);
   hstart.assign(nt + 1, 0);
   htiles.clear();
+  int hmax = 0;
   for (int t = 0; t < nt; ++t) {
-    start[t + 1] = start[t] + cnt[t];
-    hstart[t + 1] = hstart[t] + cnt[nt + t];
-    if (cnt[nt + t]) htiles.push_back(t);
+    hstart[t + 1] = hstart[t] + cnt[t];
+    hmax = std::max(hmax, cnt[t]);
+    if (cnt[t]) htiles.push_back(t);
   }
-  ps.n_entries = start[nt];
-  ps.tile_entries.ensure(ps.n_entries);
   ps.home_start.ensure(nt + 1);
   ps.home_entries.ensure(std::max<int64_t>(ps.n, 1));
   ps.n_home_tiles = (int)htiles.size();
   ps.home_tiles.ensure(std::max<size_t>(htiles.size(), 1));
-  PE_HIP(hipMemcpyAsync(ps.tile_start.get(), start.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
-  PE_HIP(hipMemcpyAsync(tcount, start.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
   PE_HIP(hipMemcpyAsync(ps.home_start.get(), hstart.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
   PE_HIP(hipMemcpyAsync(hcount, hstart.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
   if (!htiles.empty())
     PE_HIP(hipMemcpyAsync(ps.home_tiles.get(), htiles.data(), sizeof(int) * htiles.size(), hipMemcpyHostToDevice, s));
   if (ps.n > 0) {
-    hipLaunchKernelGGL(tile_list_kernel<true>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, tcount,
-                       ps.tile_entries.get());
-    PE_CHECK_LAUNCH();
-    // sort each tile's list so the accumulation order is the same on every run
-    launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get(),
-                        nt ? *std::max_element(cnt.begin(), cnt.begin() + nt) : 0);
-    // home lists (each particle once; order within a tile does not matter)
     hipLaunchKernelGGL(home_fill_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, hcount,
                        ps.home_entries.get());
     PE_CHECK_LAUNCH();
+    if (spread_by_home) launch_segment_sort(s, ps.home_start.get(), nt, ps.home_entries.get(), hmax);
   }
 }
 
@@ -664,8 +747,8 @@ void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* gri
                    bool accumulate) {
   if (ps.n == 0 && accumulate) return;
   require(g.P <= kMaxP, "support P must be <= 16");
+  ParticleSet& m = const_cast<ParticleSet&>(ps);
   if constexpr (sizeof(T) == 4) {
-    ParticleSet& m = const_cast<ParticleSet&>(ps);
     m.qspread.ensure((size_t)std::max<int64_t>(ps.n, 1));
     if (ps.n > 0) {
       hipLaunchKernelGGL(sorted_charges_kernel, dim3((unsigned)((ps.n + 255) / 256)), dim3(256), 0, s, ps.idx.get(),
@@ -674,9 +757,14 @@ void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* gri
     }
     const int nbz = (g.ntile[2] + kWaves - 1) / kWaves;
     const int nt = g.ntile[0] * g.ntile[1] * nbz;
-    hipLaunchKernelGGL(spread_tile_kernel<T>, dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(), m.qspread.get(),
-                       ps.tile_start.get(), ps.tile_entries.get(), grid, g, accumulate ? 1 : 0);
+    if (ps.spread_by_home)
+      hipLaunchKernelGGL((spread_tile_kernel<T, true>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
+                         m.qspread.get(), ps.home_start.get(), ps.home_entries.get(), grid, g, accumulate ? 1 : 0);
+    else
+      hipLaunchKernelGGL((spread_tile_kernel<T, false>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
+                         m.qspread.get(), ps.tile_start.get(), ps.tile_entries.get(), grid, g, accumulate ? 1 : 0);
   } else {
+    if (!ps.have_tile_lists) build_tile_lists(s, m, g);
     // double: the window exponentials dominate, and spreading them over the
     // whole workgroup (one staging pass per 64 particles) measured faster
     const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];

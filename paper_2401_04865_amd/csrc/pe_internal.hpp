@@ -139,7 +139,9 @@ struct ParticleSet {
   DevBuf<int> tile_count;   // 2 ntile (scratch: counts and cursors of both list kinds)
   // host copies of the counts and offsets (kept so the copies to the device
   // need no wait before the builders return)
-  std::vector<int> h_tcnt, h_tstart, h_hstart, h_htiles, h_ccnt, h_cstart;
+  std::vector<int> h_tcnt, h_tstart, h_hcnt, h_hstart, h_htiles, h_ccnt, h_cstart;
+  bool have_tile_lists = false;   // tile lists built for the current configuration
+  bool spread_by_home = false;    // single-precision spreading walks the sorted home lists
   std::vector<int4> h_chunks;
   DevBuf<int> tile_entries; // sorted-particle indices, grouped by tile
   int64_t n_entries = 0;
@@ -378,7 +380,7 @@ namespace pe {
 // (each enqueues on the given stream; geometry passed by value)
 
 // grid: spread charges q (indexed by caller index through idx) into grid (accumulate)
-void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g);
+void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g, bool spread_by_home);
 template <typename T>
 void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* grid, const GridGeom& g,
                    bool accumulate);
