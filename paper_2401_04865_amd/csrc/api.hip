@@ -305,14 +305,17 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
   }
   ProfScope ps_pair(c->prof, s, PE_PROF_PAIR, sizeof(T) == 8);
   unsigned long long* npc = pair_counter<T>(c);
+  const PairTables& pt = c->pair_tabs;
   if (reuse_ion) {
-    launch_pair_onfly<T>(s, c->B, &c->B, qb, nullptr, nullptr, c->rg, phi, E, false, npc);
+    launch_pair_onfly<T>(s, c->B, &c->B, qb, nullptr, nullptr, c->rg, phi, E, false, npc, pt.get(false, false));
     launch_axpby(s, 1.0, c->ion_rs_phi.get(), 1.0, phi, nb);
     launch_axpby(s, 1.0, c->ion_rs_E.get(), 1.0, E, 3 * nb);
   } else {
-    launch_pair_onfly<T>(s, c->B, &c->B, qb, &c->I, qi, c->rg, phi, E, false, npc);
+    launch_pair_onfly<T>(s, c->B, &c->B, qb, &c->I, qi, c->rg, phi, E, false, npc, pt.get(false, false),
+                         pt.get(false, true));
   }
-  launch_pair_onfly<T>(s, c->I, &c->B, qb, &c->I, qi, c->rg, phi + nb, E ? E + 3 * nb : nullptr, false, npc);
+  launch_pair_onfly<T>(s, c->I, &c->B, qb, &c->I, qi, c->rg, phi + nb, E ? E + 3 * nb : nullptr, false, npc,
+                       pt.get(true, false), pt.get(true, true));
   // k = 0 constant, then forces and energies
   if (nb)
     hipLaunchKernelGGL(finish_particles_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, chg_all,
@@ -365,13 +368,13 @@ void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E) {
     PE_HIP(hipMemsetAsync(c->ion_rs_phi.get(), 0, sizeof(double) * nb, s));
     PE_HIP(hipMemsetAsync(c->ion_rs_E.get(), 0, sizeof(double) * 3 * nb, s));
     launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, c->ion_rs_phi.get(),
-                         c->ion_rs_E.get(), true, pair_counter<T>(c));
+                         c->ion_rs_E.get(), true, pair_counter<T>(c), c->pair_tabs.get(false, true));
     launch_axpby(s, 1.0, c->ion_rs_phi.get(), 1.0, phi_ion, nb);
     launch_axpby(s, 1.0, c->ion_rs_E.get(), 1.0, E, 3 * nb);
     c->ion_parts_valid = true;
   } else {
     launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, phi_ion, E, true,
-                         pair_counter<T>(c));
+                         pair_counter<T>(c), c->pair_tabs.get(false, true));
   }
 }
 
@@ -843,6 +846,7 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   PE_CHECK_LAUNCH();
   build_cells(s, c->B, c->bead_x.get(), c->bead_sig.get(), 0.0, c->body_of.get(), nb, rg);
   build_cells(s, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, nullptr, n_ion, rg);
+  update_pair_tables(s, c->pair_tabs, rg, c->B, c->I);
   // beads are spread by every Krylov product: tile lists; ions once per
   // configuration in single precision: their sorted home lists serve
   build_tiles(s, c->B, c->gg, false);

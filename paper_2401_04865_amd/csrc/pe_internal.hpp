@@ -120,6 +120,20 @@ constexpr int kErfcxDeg = 7;
 constexpr float kErfcxInvWidth = 4.0f;
 void build_erfcx_table(hipStream_t s, DevBuf<float>& tab);
 
+// Single-precision table of the Gaussian-regularized real-space kernel R(r)
+// for one class of pairs (one value of s2 = sigma_t^2 + sigma_s^2): r in
+// [0, r_c] cut into kPairTabPieces pieces of width h; on piece k,
+// R(r) = sum_j a_j t^j with t = 2 (r - (k + 1/2) h) / h in [-1, 1], degree 7
+// (8 floats per piece, interpolation at the Chebyshev points of the piece).
+// dR/dr = (2 / h) sum_j j a_j t^(j-1) comes from the same coefficients.
+// build_pair_table fits the pieces in double, rounds them to float and checks
+// value and slope against the closed form at 18 points per piece; it returns
+// false (and the caller keeps the general kernel) if either misses by more
+// than 1e-7 of its largest magnitude on [0, r_c].
+constexpr int kPairTabPieces = 32;
+constexpr int kPairTabFloats = 8 * kPairTabPieces;
+bool build_pair_table(const RealGeom& rg, double s2, float* out);
+
 // A particle set sorted by real-space cell.
 struct ParticleSet {
   int64_t n = 0;
@@ -151,6 +165,24 @@ struct ParticleSet {
   DevBuf<int> home_entries; // sorted-particle indices, grouped by home tile
   DevBuf<int> home_tiles;   // tiles with at least one home particle
   int n_home_tiles = 0;
+  // width check of the set: [0] nonzero if the widths differ, [1] the first
+  // width's bits; sig_uniform is the width when all are equal, else 0
+  DevBuf<unsigned long long> sig_check;
+  unsigned long long h_sig_check[2] = {0, 0};
+  double sig_uniform = 0.0;
+};
+
+// Pair tables of the classes (target set, source set) of one context's
+// traversals whose sets both have uniform widths (see build_pair_table).
+struct PairTables {
+  DevBuf<float> buf;              // slots x kPairTabFloats
+  double key[6] = {};             // xi, eps, rc2, reg and the two widths the tables were built for
+  bool built = false;
+  int slot[2][2] = {{-1, -1}, {-1, -1}};  // [target is ions][source is ions]; -1: no table
+  const float4* get(bool tgt_ion, bool src_ion) const {
+    const int k = slot[tgt_ion ? 1 : 0][src_ion ? 1 : 0];
+    return k < 0 ? nullptr : reinterpret_cast<const float4*>(buf.get() + (size_t)k * kPairTabFloats);
+  }
 };
 
 // 1-D FFT factorization (radices 8, 4, 2, 3, 5).
@@ -297,6 +329,7 @@ struct pe_context {
   pe::DevBuf<float2> tw32[3];
   pe::DevBuf<double> gtab;   // separable Green's-function tables (exp factors, k_d^2)
   pe::DevBuf<float> erfcx_tab;  // scaled erfc pieces for the single-precision pair kernel
+  pe::PairTables pair_tabs;     // per-class pair tables (uniform widths)
 
   // system
   bool have_system = false;
@@ -407,10 +440,18 @@ void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const d
                           const double* phi_wave, const double* ck0, double* y_top);
 // Adds the real-space potential (and field, if E) at the targets from up to
 // two source sets; field_single evaluates the field in single precision.
+// tab0 / tab1 (may be null): pair tables of the classes (tgt, src0) and
+// (tgt, src1), used by the single-precision Gaussian passes when every
+// source set has one.
 template <typename T>
 void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet* src0, const double* q0,
                        const ParticleSet* src1, const double* q1, const RealGeom& rg, double* phi, double* E,
-                       bool field_single = false, unsigned long long* npairs = nullptr);
+                       bool field_single = false, unsigned long long* npairs = nullptr,
+                       const float4* tab0 = nullptr, const float4* tab1 = nullptr);
+// (Re)builds the tables of the bead / ion classes when the geometry or the
+// widths changed (after build_cells of both sets).
+void update_pair_tables(hipStream_t s, PairTables& pt, const RealGeom& rg, const ParticleSet& beads,
+                        const ParticleSet& ions);
 
 // body shapes (shapes.hip): group bodies into shape types (device-side
 // matching, types cached across configurations), build the per-shape blocks

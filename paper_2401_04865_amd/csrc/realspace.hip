@@ -178,24 +178,34 @@ __device__ __forceinline__ void pair_kernel_fast(float r2, float s2, float xi, f
 
 __global__ void assign_cells_kernel(const double* __restrict__ pos, const double* __restrict__ sig,
                                     double sig_const, int64_t n, RealGeom g, double4* __restrict__ tmp,
-                                    int* __restrict__ cell_of, int* __restrict__ count) {
+                                    int* __restrict__ cell_of, int* __restrict__ count,
+                                    unsigned long long* __restrict__ sig_check) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
-  x -= g.L[0] * floor(x * g.inv_L[0]);
-  y -= g.L[1] * floor(y * g.inv_L[1]);
-  z -= g.L[2] * floor(z * g.inv_L[2]);
-  if (x >= g.L[0]) x -= g.L[0];
-  if (y >= g.L[1]) y -= g.L[1];
-  if (z >= g.L[2]) z -= g.L[2];
-  const double s = sig ? sig[i] : sig_const;
-  tmp[i] = make_double4(x, y, z, s);
-  const int cx = cell_coord(x, g.cell_inv[0], g.nc[0]);
-  const int cy = cell_coord(y, g.cell_inv[1], g.nc[1]);
-  const int cz = cell_coord(z, g.cell_inv[2], g.nc[2]);
-  const int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
-  cell_of[i] = c;
-  atomicAdd(&count[c], 1);
+  // uniform widths: sig_check[1] = the first width; a wavefront that sees
+  // another value sets sig_check[0] (a plain store of 1, no atomics, so the
+  // common uniform case costs nothing)
+  const double s_ref = sig ? sig[0] : sig_const;
+  bool differs = false;
+  if (i < n) {
+    double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    x -= g.L[0] * floor(x * g.inv_L[0]);
+    y -= g.L[1] * floor(y * g.inv_L[1]);
+    z -= g.L[2] * floor(z * g.inv_L[2]);
+    if (x >= g.L[0]) x -= g.L[0];
+    if (y >= g.L[1]) y -= g.L[1];
+    if (z >= g.L[2]) z -= g.L[2];
+    const double s = sig ? sig[i] : sig_const;
+    tmp[i] = make_double4(x, y, z, s);
+    const int cx = cell_coord(x, g.cell_inv[0], g.nc[0]);
+    const int cy = cell_coord(y, g.cell_inv[1], g.nc[1]);
+    const int cz = cell_coord(z, g.cell_inv[2], g.nc[2]);
+    const int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+    cell_of[i] = c;
+    atomicAdd(&count[c], 1);
+    differs = !(s == s_ref);
+  }
+  if (i == 0) sig_check[1] = (unsigned long long)__double_as_longlong(s_ref);
+  if (__ballot(differs) != 0ull && (threadIdx.x & 63) == 0) sig_check[0] = 1ull;
 }
 
 __global__ void scatter_cells_kernel(const int* __restrict__ cell_of, int64_t n,
@@ -239,6 +249,7 @@ struct SrcSet {
   const int* idx;       // sorted slot -> caller index
   const int* start;     // cell_start
   const double* q;      // charges in sorted order (potential passes)
+  const float4* tab;    // pair table of the class (targets, this set), or null
 };
 
 // Outputs of a traversal; which ones are used depends on the mode.
@@ -263,24 +274,36 @@ constexpr int kSetBit = 30;     // queue entry: sorted source index | set << kSe
 constexpr int kMaxRuns = 36;    // stencil runs: 2 source sets x 9 columns x 2 runs
 
 
-template <int MODE, typename T, typename TF>
+// EV selects the pair evaluation: EV_GENERAL (any precision and
+// regularization), EV_ERFCX (single precision, Gaussian: erfc from the
+// scaled-erfc table, per-pair widths) or EV_TABLE (single precision,
+// Gaussian, uniform widths per set: R and R' from the class tables).
+enum { EV_GENERAL = 0, EV_ERFCX = 1, EV_TABLE = 2 };
+
+template <int MODE, typename T, typename TF, int EV>
 __global__ void __launch_bounds__(256) pair_queue_kernel(
     const double4* __restrict__ tpos, const int* __restrict__ tidx, const int* __restrict__ tstart,
     const int4* __restrict__ chunks, int nchunk, SrcSet s0, SrcSet s1, int nsrc, RealGeom g, float rc2f,
     PairOut out) {
+  static_assert(EV == EV_GENERAL || (sizeof(T) == 4 && sizeof(TF) == 4 && (MODE == MODE_POT || MODE == MODE_FIELD)),
+                "table evaluations are single-precision potential / field passes");
+  constexpr bool kOwn = MODE == MODE_COUNT || MODE == MODE_FILL;
+  constexpr int kTabF4 = EV == EV_TABLE ? 4 * kPairTabPieces : (EV == EV_ERFCX ? 2 * kErfcxPieces : 1);
   __shared__ int qbuf[kWaves][kQ][64];
   __shared__ float4 cbuf[kWaves][64];
-  __shared__ float4 etab[2 * kErfcxPieces];
-  __shared__ int cownb[kWaves][64];          // owner tags of the staged candidates (count / fill)
+  __shared__ float4 etab[kTabF4];
+  __shared__ int cownb[kOwn ? kWaves : 1][64];  // owner tags of the staged candidates (count / fill)
   __shared__ int rstart[kWaves][kMaxRuns + 1];
   __shared__ int rbase[kWaves][kMaxRuns];
   __shared__ int rcode[kWaves][kMaxRuns];    // per run: set | (ox+1) << 1 | (oy+1) << 3 | z image << 5
-  // single-precision Gaussian passes use the table-driven pair kernel
-  constexpr bool kFastT = sizeof(T) == 4 && (MODE == MODE_POT || MODE == MODE_FIELD);
-  const bool fast = kFastT && g.reg == PE_REG_GAUSSIAN && g.erfcx != nullptr;
-  if (fast) {
+  if constexpr (EV == EV_ERFCX) {
     if (threadIdx.x < 2 * kErfcxPieces) etab[threadIdx.x] = reinterpret_cast<const float4*>(g.erfcx)[threadIdx.x];
     __syncthreads();  // before any wavefront leaves
+  } else if constexpr (EV == EV_TABLE) {
+    // the class tables of source sets 0 and 1 (2 float4 per piece)
+    for (int i = threadIdx.x; i < 4 * kPairTabPieces; i += blockDim.x)
+      etab[i] = i < 2 * kPairTabPieces ? s0.tab[i] : s1.tab[i - 2 * kPairTabPieces];
+    __syncthreads();
   }
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -419,6 +442,51 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     }
   };
 
+  // class tables: r = 0 (the self pair) reads R(0) at the table's first
+  // point and gets no field (inv_r = 0)
+  const float tab_w = (float)(kPairTabPieces / sqrt(g.rc2));  // pieces per unit length
+  const float tab_d = -2.0f * tab_w;                          // -dt/dr
+  auto evaluate_tab = [&](int e) {
+    const int set = e >> kSetBit;
+    const int sidx = e & ((1 << kSetBit) - 1);
+    const double4 qp = set ? s1.pos[sidx] : s0.pos[sidx];
+    const float dx = (float)min_img(p.x - qp.x, g.L[0], g.inv_L[0]);
+    const float dy = (float)min_img(p.y - qp.y, g.L[1], g.inv_L[1]);
+    const float dz = (float)min_img(p.z - qp.z, g.L[2], g.inv_L[2]);
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (!(r2 < rc2e)) return;
+    ++nev;
+    const float qf = (float)(set ? s1.q[sidx] : s0.q[sidx]);
+    const float inv_r = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+    const float w = r2 * inv_r * tab_w;
+    const int k = min((int)w, kPairTabPieces - 1);
+    const float t = fmaf(2.0f, w - (float)k, -1.0f);
+    const float4* tb = etab + 2 * (set * kPairTabPieces + k);
+    const float4 lo = tb[0], hi = tb[1];
+    // value v and slope d = dv/dt in one Horner pass
+    float v = hi.w, d = hi.w;
+    v = fmaf(v, t, hi.z);
+    d = fmaf(d, t, v);
+    v = fmaf(v, t, hi.y);
+    d = fmaf(d, t, v);
+    v = fmaf(v, t, hi.x);
+    d = fmaf(d, t, v);
+    v = fmaf(v, t, lo.w);
+    d = fmaf(d, t, v);
+    v = fmaf(v, t, lo.z);
+    d = fmaf(d, t, v);
+    v = fmaf(v, t, lo.y);
+    d = fmaf(d, t, v);
+    v = fmaf(v, t, lo.x);
+    acc += v * qf;
+    if constexpr (MODE == MODE_FIELD) {
+      const float fq = d * tab_d * inv_r * qf;  // -R'(r) / r q
+      ex += fq * dx;
+      ey += fq * dy;
+      ez += fq * dz;
+    }
+  };
+
   // The candidate stream.  The stencil is a list of runs: for each source
   // set and each (x, y) column, the cells along z (contiguous in the sorted
   // order; a second run holds the cell reached through the periodic wrap in
@@ -436,7 +504,7 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   // more pushes cannot overflow any queue; after the last group, everything
   // left.  (One drain site, so the pair evaluation is emitted once.)
   float4* cb = cbuf[wv];
-  int* cown = cownb[wv];
+  int* cown = cownb[kOwn ? wv : 0];
   int* rs = rstart[wv];
   int* rb = rbase[wv];
   int* rc = rcode[wv];
@@ -610,12 +678,9 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
       if (popped < pushed) {
         const int e = qb[popped & (kQ - 1)][lane];
         ++popped;
-        if constexpr (kFastT) {
-          if (fast) evaluate_fast(e);
-          else evaluate(e);
-        } else {
-          evaluate(e);
-        }
+        if constexpr (EV == EV_TABLE) evaluate_tab(e);
+        else if constexpr (EV == EV_ERFCX) evaluate_fast(e);
+        else evaluate(e);
       }
     }
     if (finished) break;
@@ -766,9 +831,12 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   ps.cell_start.ensure(ncell + 1);
   ps.cell_count.ensure(ncell);
   PE_HIP(hipMemsetAsync(ps.cell_count.get(), 0, sizeof(int) * ncell, s));
+  ps.sig_check.ensure(2);
+  PE_HIP(hipMemsetAsync(ps.sig_check.get(), 0, sizeof(unsigned long long), s));
   if (n > 0) {
     hipLaunchKernelGGL(assign_cells_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, pos_caller, sig_caller,
-                       sig_const, n, rg, ps.tmp.get(), ps.cell_of.get(), ps.cell_count.get());
+                       sig_const, n, rg, ps.tmp.get(), ps.cell_of.get(), ps.cell_count.get(),
+                       ps.sig_check.get());
     PE_CHECK_LAUNCH();
   }
   std::vector<int>& cnt = ps.h_ccnt;
@@ -776,7 +844,14 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   cnt.resize(ncell);
   start.assign(ncell + 1, 0);
   PE_HIP(hipMemcpyAsync(cnt.data(), ps.cell_count.get(), sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
+  if (n > 0)
+    PE_HIP(hipMemcpyAsync(ps.h_sig_check, ps.sig_check.get(), sizeof(ps.h_sig_check), hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
+  {
+    double w;
+    std::memcpy(&w, &ps.h_sig_check[1], sizeof(double));
+    ps.sig_uniform = n > 0 && ps.h_sig_check[0] == 0 && w > 0 && w < INFINITY ? w : 0.0;
+  }
   for (int c = 0; c < ncell; ++c) start[c + 1] = start[c] + cnt[c];
   // traversal work units: at most 64 particles; a cell with more is split,
   // and two neighbouring cells of one z column with 64 or fewer together
@@ -821,18 +896,32 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
 
 namespace {
 
-SrcSet src_of(const ParticleSet& ps, const double* qsorted) {
-  return SrcSet{ps.pos.get(), ps.posf.get(), ps.idx.get(), ps.cell_start.get(), qsorted};
+SrcSet src_of(const ParticleSet& ps, const double* qsorted, const float4* tab = nullptr) {
+  return SrcSet{ps.pos.get(), ps.posf.get(), ps.idx.get(), ps.cell_start.get(), qsorted, tab};
 }
 
+template <int MODE, typename T, typename TF, int EV>
+void launch_queue_ev(hipStream_t s, const ParticleSet& tgt, const SrcSet& s0, const SrcSet& s1, int nsrc,
+                     const RealGeom& rg, const PairOut& out) {
+  hipLaunchKernelGGL((pair_queue_kernel<MODE, T, TF, EV>), dim3(nblk(tgt.n_chunks, kWaves)), dim3(64 * kWaves), 0,
+                     s, tgt.pos.get(), tgt.idx.get(), tgt.cell_start.get(), tgt.chunks.get(), tgt.n_chunks, s0, s1,
+                     nsrc, rg, candidate_rc2(rg), out);
+  PE_CHECK_LAUNCH();
+}
+
+// Single-precision Gaussian passes take the class tables when every source
+// set has one, else the scaled-erfc kernel; everything else the general one.
 template <int MODE, typename T, typename TF>
 void launch_queue(hipStream_t s, const ParticleSet& tgt, const SrcSet& s0, const SrcSet& s1, int nsrc,
                   const RealGeom& rg, const PairOut& out) {
   if (tgt.n_chunks == 0) return;
-  hipLaunchKernelGGL((pair_queue_kernel<MODE, T, TF>), dim3(nblk(tgt.n_chunks, kWaves)), dim3(64 * kWaves), 0, s,
-                     tgt.pos.get(), tgt.idx.get(), tgt.cell_start.get(), tgt.chunks.get(), tgt.n_chunks, s0, s1,
-                     nsrc, rg, candidate_rc2(rg), out);
-  PE_CHECK_LAUNCH();
+  if constexpr (sizeof(T) == 4 && sizeof(TF) == 4 && (MODE == MODE_POT || MODE == MODE_FIELD)) {
+    if (rg.reg == PE_REG_GAUSSIAN && s0.tab && s1.tab)
+      return launch_queue_ev<MODE, T, TF, EV_TABLE>(s, tgt, s0, s1, nsrc, rg, out);
+    if (rg.reg == PE_REG_GAUSSIAN && rg.erfcx)
+      return launch_queue_ev<MODE, T, TF, EV_ERFCX>(s, tgt, s0, s1, nsrc, rg, out);
+  }
+  launch_queue_ev<MODE, T, TF, EV_GENERAL>(s, tgt, s0, s1, nsrc, rg, out);
 }
 
 }  // namespace
@@ -978,12 +1067,13 @@ void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const d
 template <typename T>
 void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet* src0, const double* q0,
                        const ParticleSet* src1, const double* q1, const RealGeom& rg, double* phi, double* E,
-                       bool field_single, unsigned long long* npairs) {
+                       bool field_single, unsigned long long* npairs, const float4* tab0, const float4* tab1) {
   if (tgt.n == 0) return;
   if (src1 && src1->n == 0) src1 = nullptr;
   if (src0 && src0->n == 0) {
     src0 = src1;
     q0 = q1;
+    tab0 = tab1;
     src1 = nullptr;
   }
   if (!src0) return;
@@ -997,8 +1087,8 @@ void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet*
     PE_CHECK_LAUNCH();
     return m.qsorted.get();
   };
-  const SrcSet a = src_of(*src0, sorted_q(*src0, q0));
-  const SrcSet b = src1 ? src_of(*src1, sorted_q(*src1, q1)) : a;
+  const SrcSet a = src_of(*src0, sorted_q(*src0, q0), tab0);
+  const SrcSet b = src1 ? src_of(*src1, sorted_q(*src1, q1), tab1) : a;
   const int nsrc = src1 ? 2 : 1;
   PairOut out{};
   out.phi = phi;
@@ -1033,13 +1123,118 @@ void build_erfcx_table(hipStream_t s, DevBuf<float>& tab) {
   PE_HIP(hipStreamSynchronize(s));
 }
 
+namespace {
+
+// R(r) and dR/dr of the Gaussian-regularized split, in double (r >= 0;
+// R(0) is the limit c (2/sqrt pi)(b - xi), where the slope is zero).
+void gauss_pair(double r, double b, double xi, double c, double& R, double& dR) {
+  if (r < 1e-300) {
+    R = c * kTwoOverSqrtPi * (b - xi);
+    dR = 0.0;
+    return;
+  }
+  const double D = std::erf(b * r) - std::erf(xi * r);
+  const double Dp = kTwoOverSqrtPi * (b * std::exp(-b * b * r * r) - xi * std::exp(-xi * xi * r * r));
+  R = c * D / r;
+  dR = c * (Dp * r - D) / (r * r);
+}
+
+}  // namespace
+
+bool build_pair_table(const RealGeom& rg, double s2, float* out) {
+  if (rg.reg != PE_REG_GAUSSIAN || !(s2 > 0.0) || !(rg.rc2 > 0.0)) return false;
+  constexpr int K = kPairTabPieces, N = 8;
+  const double rc = std::sqrt(rg.rc2), h = rc / K;
+  const double b = 1.0 / std::sqrt(2.0 * s2), xi = rg.xi, c = kInv4Pi / rg.eps;
+  double err_v = 0.0, err_d = 0.0, max_v = 0.0, max_d = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double mid = (k + 0.5) * h;
+    // interpolation at the N Chebyshev points of the piece: Chebyshev
+    // coefficients, then the same polynomial in powers of t
+    double f[N], cc[N], mono[N] = {};
+    for (int i = 0; i < N; ++i) {
+      double dR;
+      gauss_pair(mid + 0.5 * h * std::cos(kPi * (i + 0.5) / N), b, xi, c, f[i], dR);
+    }
+    for (int m = 0; m < N; ++m) {
+      double a = 0.0;
+      for (int i = 0; i < N; ++i) a += f[i] * std::cos(kPi * m * (i + 0.5) / N);
+      cc[m] = a * (m == 0 ? 1.0 : 2.0) / N;
+    }
+    // T_0 = 1, T_1 = t, T_(m+1) = 2 t T_m - T_(m-1), as coefficient vectors
+    double Tp[N] = {}, Tc[N] = {}, Tn[N];
+    Tp[0] = 1.0;
+    Tc[1] = 1.0;
+    for (int j = 0; j < N; ++j) mono[j] = cc[0] * Tp[j] + cc[1] * Tc[j];
+    for (int m = 2; m < N; ++m) {
+      for (int j = 0; j < N; ++j) Tn[j] = (j > 0 ? 2.0 * Tc[j - 1] : 0.0) - Tp[j];
+      for (int j = 0; j < N; ++j) {
+        mono[j] += cc[m] * Tn[j];
+        Tp[j] = Tc[j];
+        Tc[j] = Tn[j];
+      }
+    }
+    float* o = out + (size_t)N * k;
+    for (int j = 0; j < N; ++j) o[j] = (float)mono[j];
+    // the rounded coefficients against the closed form, ends of the piece included
+    for (int i = 0; i <= 17; ++i) {
+      const double t = -1.0 + 2.0 * i / 17.0;
+      double v = o[N - 1], d = 0.0;
+      for (int j = N - 2; j >= 0; --j) {
+        d = d * t + v;
+        v = v * t + o[j];
+      }
+      double R, dR;
+      gauss_pair(mid + 0.5 * h * t, b, xi, c, R, dR);
+      err_v = std::max(err_v, std::fabs(v - R));
+      err_d = std::max(err_d, std::fabs(d * 2.0 / h - dR));
+      max_v = std::max(max_v, std::fabs(R));
+      max_d = std::max(max_d, std::fabs(dR));
+    }
+  }
+  return err_v <= 1e-7 * max_v && err_d <= 1e-7 * max_d;
+}
+
+void update_pair_tables(hipStream_t s, PairTables& pt, const RealGeom& rg, const ParticleSet& beads,
+                        const ParticleSet& ions) {
+  const double key[6] = {rg.xi, rg.eps, rg.rc2, (double)rg.reg, beads.sig_uniform, ions.sig_uniform};
+  if (pt.built && std::equal(key, key + 6, pt.key)) return;
+  std::copy(key, key + 6, pt.key);
+  pt.built = true;
+  const double sg[2] = {beads.sig_uniform, ions.sig_uniform};
+  std::vector<float> h;
+  std::vector<double> s2_of;  // per slot
+  for (int t = 0; t < 2; ++t)
+    for (int u = 0; u < 2; ++u) {
+      pt.slot[t][u] = -1;
+      if (!(sg[t] > 0.0 && sg[u] > 0.0)) continue;
+      const double s2 = sg[t] * sg[t] + sg[u] * sg[u];
+      const auto it = std::find(s2_of.begin(), s2_of.end(), s2);
+      if (it != s2_of.end()) {
+        pt.slot[t][u] = (int)(it - s2_of.begin());
+        continue;
+      }
+      h.resize(h.size() + kPairTabFloats);
+      if (build_pair_table(rg, s2, h.data() + h.size() - kPairTabFloats)) {
+        pt.slot[t][u] = (int)s2_of.size();
+        s2_of.push_back(s2);
+      } else {
+        h.resize(h.size() - kPairTabFloats);
+      }
+    }
+  if (h.empty()) return;
+  pt.buf.ensure(h.size());
+  PE_HIP(hipMemcpyAsync(pt.buf.get(), h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, s));
+  PE_HIP(hipStreamSynchronize(s));
+}
+
 template void launch_spmv_assemble<float>(hipStream_t, pe_context*, const double*, const double*, const double*, const double*, double*);
 template void launch_spmv_assemble<double>(hipStream_t, pe_context*, const double*, const double*, const double*, const double*, double*);
 template void launch_pair_onfly<float>(hipStream_t, const ParticleSet&, const ParticleSet*, const double*,
                                        const ParticleSet*, const double*, const RealGeom&, double*, double*, bool,
-                                       unsigned long long*);
+                                       unsigned long long*, const float4*, const float4*);
 template void launch_pair_onfly<double>(hipStream_t, const ParticleSet&, const ParticleSet*, const double*,
                                         const ParticleSet*, const double*, const RealGeom&, double*, double*, bool,
-                                        unsigned long long*);
+                                        unsigned long long*, const float4*, const float4*);
 
 }  // namespace pe

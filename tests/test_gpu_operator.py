@@ -73,6 +73,26 @@ def test_apply_fp32_matches_modeB(gpu_lib, case):
     p = gpu_lib.make_params(s.box, mesh, P=P, split_tol=tol, precision=gpu_lib.PE_MIXED)
     psi, E, d = _gpu_apply(gpu_lib, s, p, chg, precision=gpu_lib.PE_MIXED)
     pb, Eb = _modeB(s, chg, d, P)
+    print(np.abs(psi - pb).max() / np.abs(pb).max(), np.abs(E - Eb).max() / np.abs(Eb).max())
+    assert np.abs(psi - pb).max() <= 2e-6 * np.abs(pb).max()
+    assert np.abs(E - Eb).max() <= 2e-5 * np.abs(Eb).max()
+
+
+def test_apply_fp32_varied_widths_matches_modeB(gpu_lib):
+    """Widths that differ from particle to particle: the single-precision
+    pair passes take the per-pair kernel (scaled-erfc table) instead of the
+    per-class tables that uniform widths allow (the cases above)."""
+    seed, nbody, level, nion, box, mesh, P, tol = CASES[0]
+    s = inputs.small_random_system(seed, n_body=nbody, level=level, n_ion=nion, L=box[0], sigma=0.16,
+                                   mesh=mesh)
+    rng = np.random.default_rng(44)
+    s.bead_sigma = rng.uniform(0.12, 0.2, s.n_bead)
+    s.ion_sigma = rng.uniform(0.08, 0.14, s.n_ion)
+    chg = _charges(s, seed)
+    p = gpu_lib.make_params(s.box, mesh, P=P, split_tol=tol, precision=gpu_lib.PE_MIXED)
+    psi, E, d = _gpu_apply(gpu_lib, s, p, chg, precision=gpu_lib.PE_MIXED)
+    pb, Eb = _modeB(s, chg, d, P)
+    print(np.abs(psi - pb).max() / np.abs(pb).max(), np.abs(E - Eb).max() / np.abs(Eb).max())
     assert np.abs(psi - pb).max() <= 2e-6 * np.abs(pb).max()
     assert np.abs(E - Eb).max() <= 2e-5 * np.abs(Eb).max()
 
