@@ -230,11 +230,13 @@ __global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restr
   for (int c = 0; c < kTile; ++c) acc[c] = 0;
   if (uz < g.ntile[2]) {
     int e0, e1;
-    // HOME: segment d of the virtual list starts at hb[d] in the home lists
-    // and at hp[d] in the list; lane d < 8 computes it, every lane keeps all
-    int hb[8], hp[9];
+    // HOME: segment d of the virtual list starts at my_b in the home lists
+    // and at my_p in the list on lane d < 8; every lane keeps the list
+    // offsets hp[d] to find a position's segment
+    int hp[9];
+    int my_b = 0, my_p = 0;
     if constexpr (HOME) {
-      int my_b = 0, my_n = 0;
+      int my_n = 0;
       if (lane < 8) {
         const int dx = lane >> 2, dy = (lane >> 1) & 1, dz = lane & 1;
         // a neighbour index that wraps onto the tile itself is not a second source
@@ -251,8 +253,8 @@ __global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restr
       hp[0] = 0;
 #pragma unroll
       for (int d = 0; d < 8; ++d) {
-        hb[d] = __shfl(my_b, d, 64);
         hp[d + 1] = hp[d] + __shfl(my_n, d, 64);
+        if (lane == d) my_p = hp[d];
       }
       e0 = 0;
       e1 = hp[8];
@@ -269,19 +271,18 @@ __global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restr
     const bool stager = lane < 3 * kWaveChunk;
     const int N = g.N[ax3];
     const int u = ax3 == 0 ? ux : (ax3 == 1 ? uy : uz);
+    // (called with every lane of the wavefront active)
     auto entry_at = [&](int c0) {
       const int k = c0 + c3;
-      if (!stager || k >= e1) return -1;
       if constexpr (HOME) {
         int d = 0;
 #pragma unroll
         for (int m = 1; m < 8; ++m) d += k >= hp[m] ? 1 : 0;
-        int b = hb[0], p0 = hp[0];
-#pragma unroll
-        for (int m = 1; m < 8; ++m)
-          if (d == m) { b = hb[m]; p0 = hp[m]; }
+        const int b = __shfl(my_b, d, 64), p0 = __shfl(my_p, d, 64);
+        if (!stager || k >= e1) return -1;
         return entries[b + (k - p0)];
       } else {
+        if (!stager || k >= e1) return -1;
         return entries[k];
       }
     };
@@ -504,10 +505,12 @@ __global__ void __launch_bounds__(256) gather_kernel(const double4* __restrict__
 // lanes contracts one particle from LDS (four per wavefront), lane s taking
 // the (y, z) lines s, s + 16, ... of the support and looping over x, and the
 // group reduces with lane shuffles.  The result is the same sum as the
-// per-particle kernel, in another order.
+// per-particle kernel, in another order.  PP > 0 fixes P at compile time
+// (the common support): the lines are unrolled, their P loads issued
+// together, and the x factors held in registers.
 constexpr int kGatherLDS = 48 * 1024;
 
-template <typename T, bool FIELD>
+template <typename T, bool FIELD, int PP>
 __global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restrict__ pos,
                                                           const int* __restrict__ idx,
                                                           const int* __restrict__ home_start,
@@ -521,11 +524,12 @@ __global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restr
   __shared__ T w_s[16][3 * kMaxP];
   __shared__ T d_s[16][3 * kMaxP];
   __shared__ int gidx[3][kTile + kMaxP];  // wrapped grid index of each region plane, per axis
+  static_assert(PP == 0 || (PP * PP) % 16 == 0, "lines of the support shared by 16 lanes");
   const int tile = home_tiles[xcd_remap(blockIdx.x, gridDim.x)];
   const int uz = tile % g.ntile[2];
   const int uy = (tile / g.ntile[2]) % g.ntile[1];
   const int ux = tile / (g.ntile[2] * g.ntile[1]);
-  const int P = g.P;
+  const int P = PP > 0 ? PP : g.P;
   const int Hs = kTile + P - 1;
   const int Hs2 = Hs * Hs;
   if ((int)threadIdx.x < 3 * Hs) {
@@ -601,6 +605,38 @@ __global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restr
     const T* wsl = w_s[slot];
     const T* dsl = d_s[slot];
     T acc = 0, axf = 0, ayf = 0, azf = 0;
+    if constexpr (PP > 0) {
+      T wx[PP], dxv[PP];
+#pragma unroll
+      for (int j = 0; j < PP; ++j) {
+        wx[j] = wsl[j];
+        if (FIELD) dxv[j] = dsl[j];
+      }
+#pragma unroll
+      for (int k = 0; k < PP * PP / 16; ++k) {
+        const int t = s + 16 * k;
+        const int jy = t / PP;
+        const int jz = t - jy * PP;
+        const T wyz = wsl[PP + jy] * wsl[2 * PP + jz];
+        const T* col = H + (ox * Hs + oy + jy) * Hs + oz + jz;
+        T v[PP];
+#pragma unroll
+        for (int jx = 0; jx < PP; ++jx) v[jx] = col[jx * Hs2];
+        T lacc = 0, lx = 0;
+#pragma unroll
+        for (int jx = 0; jx < PP; ++jx) {
+          const T u = v[jx] * wx[jx];
+          lacc += u;
+          if (FIELD) lx += u * dxv[jx];
+        }
+        acc += lacc * wyz;
+        if (FIELD) {
+          axf += lx * wyz;
+          ayf += lacc * wyz * dsl[PP + jy];
+          azf += lacc * wyz * dsl[2 * PP + jz];
+        }
+      }
+    } else {
     for (int t = s; t < P * P; t += 16) {
       const int jy = t / P;
       const int jz = t - jy * P;
@@ -618,6 +654,7 @@ __global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restr
         ayf += lacc * wyz * dsl[P + jy];
         azf += lacc * wyz * dsl[2 * P + jz];
       }
+    }
     }
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) {
@@ -786,14 +823,17 @@ void launch_gather(hipStream_t s, const ParticleSet& ps, const T* grid, const Gr
   if (sizeof(T) == 4 && region <= (size_t)kGatherLDS) {
     if (ps.n_home_tiles == 0) return;
     const dim3 blocks((unsigned)ps.n_home_tiles);
-    if (E)
-      hipLaunchKernelGGL((gather_tile_kernel<T, true>), blocks, dim3(256), region, s, ps.pos.get(), ps.idx.get(),
-                         ps.home_start.get(), ps.home_entries.get(), ps.home_tiles.get(), grid, g, phi, E,
-                         accumulate ? 1 : 0);
-    else
-      hipLaunchKernelGGL((gather_tile_kernel<T, false>), blocks, dim3(256), region, s, ps.pos.get(), ps.idx.get(),
-                         ps.home_start.get(), ps.home_entries.get(), ps.home_tiles.get(), grid, g, phi, E,
-                         accumulate ? 1 : 0);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, blocks, dim3(256), region, s, ps.pos.get(), ps.idx.get(), ps.home_start.get(),
+                         ps.home_entries.get(), ps.home_tiles.get(), grid, g, phi, E, accumulate ? 1 : 0);
+    };
+    if (g.P == 8) {
+      if (E) go(gather_tile_kernel<T, true, 8>);
+      else go(gather_tile_kernel<T, false, 8>);
+    } else {
+      if (E) go(gather_tile_kernel<T, true, 0>);
+      else go(gather_tile_kernel<T, false, 0>);
+    }
     PE_CHECK_LAUNCH();
     return;
   }
