@@ -268,8 +268,8 @@ struct PairOut {
 
 enum { MODE_COUNT = 0, MODE_FILL = 1, MODE_POT = 2, MODE_FIELD = 3 };
 
-constexpr int kQ = 32;          // queue entries per lane
-constexpr int kQFlush = 16;     // candidates between flushes (kQ - kQFlush entries stay free)
+constexpr int kQ = 16;          // queue entries per lane
+constexpr int kQFlush = 8;      // candidates between flushes (kQ - kQFlush entries stay free)
 constexpr int kSetBit = 30;     // queue entry: sorted source index | set << kSetBit
 constexpr int kMaxRuns = 36;    // stencil runs: 2 source sets x 9 columns x 2 runs
 
