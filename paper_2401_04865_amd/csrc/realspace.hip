@@ -417,18 +417,37 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   const float pw2 = (float)p.w * (float)p.w;
   const float rc2e = (float)g.rc2;
   const float xif = (float)g.xi, cf = (float)(kInv4Pi / g.eps);
-  auto evaluate_fast = [&](int e) {
-    const int set = e >> kSetBit;
+  // Single-precision evaluations are split into a fetch (the source's
+  // position, width and charge) and the arithmetic: the drain takes two
+  // queued sources of a lane per round, issuing both fetches before the
+  // first evaluation, so the second source's loads overlap the first's
+  // arithmetic.
+  struct Src {
+    double x, y, z, w;  // sorted position and width
+    double q;           // charge
+    int set;
+  };
+  auto fetch = [&](int e) {
+    Src o;
+    o.set = e >> kSetBit;
     const int sidx = e & ((1 << kSetBit) - 1);
-    const double4 qp = set ? s1.pos[sidx] : s0.pos[sidx];
-    const float dx = (float)min_img(p.x - qp.x, g.L[0], g.inv_L[0]);
-    const float dy = (float)min_img(p.y - qp.y, g.L[1], g.inv_L[1]);
-    const float dz = (float)min_img(p.z - qp.z, g.L[2], g.inv_L[2]);
+    const double4 qp = o.set ? s1.pos[sidx] : s0.pos[sidx];
+    o.x = qp.x;
+    o.y = qp.y;
+    o.z = qp.z;
+    o.w = qp.w;
+    o.q = o.set ? s1.q[sidx] : s0.q[sidx];
+    return o;
+  };
+  auto evaluate_fast = [&](const Src& sc) {
+    const float dx = (float)min_img(p.x - sc.x, g.L[0], g.inv_L[0]);
+    const float dy = (float)min_img(p.y - sc.y, g.L[1], g.inv_L[1]);
+    const float dz = (float)min_img(p.z - sc.z, g.L[2], g.inv_L[2]);
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     if (!(r2 < rc2e)) return;
     ++nev;
-    const float qf = (float)(set ? s1.q[sidx] : s0.q[sidx]);
-    const float sw = (float)qp.w;
+    const float qf = (float)sc.q;
+    const float sw = (float)sc.w;
     const float s2 = fmaf(sw, sw, pw2);
     float R, F = 0.0f;
     if (r2 == 0.0f) R = self_value<float>(s2, g);
@@ -446,22 +465,22 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   // point and gets no field (inv_r = 0)
   const float tab_w = (float)(kPairTabPieces / sqrt(g.rc2));  // pieces per unit length
   const float tab_d = -2.0f * tab_w;                          // -dt/dr
-  auto evaluate_tab = [&](int e) {
-    const int set = e >> kSetBit;
-    const int sidx = e & ((1 << kSetBit) - 1);
-    const double4 qp = set ? s1.pos[sidx] : s0.pos[sidx];
-    const float dx = (float)min_img(p.x - qp.x, g.L[0], g.inv_L[0]);
-    const float dy = (float)min_img(p.y - qp.y, g.L[1], g.inv_L[1]);
-    const float dz = (float)min_img(p.z - qp.z, g.L[2], g.inv_L[2]);
+  // branch-free: every lane runs the arithmetic and a lane whose source is
+  // not a pair (none queued, or outside r_c in double) adds nothing, so the
+  // loads of both sources of a pass are needed, and issued, up front
+  auto evaluate_tab = [&](const Src& sc, bool valid) {
+    const float dx = (float)min_img(p.x - sc.x, g.L[0], g.inv_L[0]);
+    const float dy = (float)min_img(p.y - sc.y, g.L[1], g.inv_L[1]);
+    const float dz = (float)min_img(p.z - sc.z, g.L[2], g.inv_L[2]);
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    if (!(r2 < rc2e)) return;
-    ++nev;
-    const float qf = (float)(set ? s1.q[sidx] : s0.q[sidx]);
+    const bool ok = valid && r2 < rc2e;
+    nev += ok ? 1 : 0;
+    const float qf = ok ? (float)sc.q : 0.0f;
     const float inv_r = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
     const float w = r2 * inv_r * tab_w;
     const int k = min((int)w, kPairTabPieces - 1);
     const float t = fmaf(2.0f, w - (float)k, -1.0f);
-    const float4* tb = etab + 2 * (set * kPairTabPieces + k);
+    const float4* tb = etab + 2 * (sc.set * kPairTabPieces + k);
     const float4 lo = tb[0], hi = tb[1];
     // value v and slope d = dv/dt in one Horner pass
     float v = hi.w, d = hi.w;
@@ -478,9 +497,9 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     v = fmaf(v, t, lo.y);
     d = fmaf(d, t, v);
     v = fmaf(v, t, lo.x);
-    acc += v * qf;
+    acc += ok ? v * qf : 0.0f;
     if constexpr (MODE == MODE_FIELD) {
-      const float fq = d * tab_d * inv_r * qf;  // -R'(r) / r q
+      const float fq = ok ? d * tab_d * inv_r * qf : 0.0f;  // -R'(r) / r q
       ex += fq * dx;
       ey += fq * dy;
       ez += fq * dz;
@@ -583,6 +602,14 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     bz0 = fminf(bz0, __shfl_xor(bz0, off, 64));
     bz1 = fmaxf(bz1, __shfl_xor(bz1, off, 64));
   }
+  // uniform after the reduction: scalar registers
+  auto uniform_f = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+  bx0 = uniform_f(bx0);
+  bx1 = uniform_f(bx1);
+  by0 = uniform_f(by0);
+  by1 = uniform_f(by1);
+  bz0 = uniform_f(bz0);
+  bz1 = uniform_f(bz1);
   int next = 0, pbase = 0;  // next stream position to stage and (next S) mod M
   int nbat = 0, k0 = 0;
   const float nanf_ = __int_as_float(0x7fc00000);
@@ -674,13 +701,33 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
       mx = max(mx, __shfl_xor(mx, off, 64));
     }
     const int rounds = finished ? mx : max(mn, mx - (kQ - kQFlush));
-    for (int r = 0; r < rounds; ++r) {
-      if (popped < pushed) {
-        const int e = qb[popped & (kQ - 1)][lane];
-        ++popped;
-        if constexpr (EV == EV_TABLE) evaluate_tab(e);
-        else if constexpr (EV == EV_ERFCX) evaluate_fast(e);
-        else evaluate(e);
+    if constexpr (EV == EV_GENERAL) {
+      for (int r = 0; r < rounds; ++r) {
+        if (popped < pushed) {
+          const int e = qb[popped & (kQ - 1)][lane];
+          ++popped;
+          evaluate(e);
+        }
+      }
+    } else {
+      // two rounds per pass: both sources fetched first
+      for (int r = 0; r < rounds; r += 2) {
+        const int avail = min(pushed - popped, min(2, rounds - r));
+        // both fetches unconditional (a lane without a second source re-reads
+        // its first, or source 0 of set 0), so the loads are issued back to
+        // back and the first evaluation waits for its own loads only
+        const int ea = avail > 0 ? qb[popped & (kQ - 1)][lane] : 0;
+        const int eb = avail > 1 ? qb[(popped + 1) & (kQ - 1)][lane] : ea;
+        const Src a = fetch(ea);
+        const Src b = fetch(eb);
+        popped += max(avail, 0);
+        if constexpr (EV == EV_TABLE) {
+          evaluate_tab(a, avail > 0);
+          evaluate_tab(b, avail > 1);
+        } else {
+          if (avail > 0) evaluate_fast(a);
+          if (avail > 1) evaluate_fast(b);
+        }
       }
     }
     if (finished) break;
@@ -853,24 +900,30 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
     ps.sig_uniform = n > 0 && ps.h_sig_check[0] == 0 && w > 0 && w < INFINITY ? w : 0.0;
   }
   for (int c = 0; c < ncell; ++c) start[c + 1] = start[c] + cnt[c];
-  // traversal work units: at most 64 particles; a cell with more is split,
-  // and two neighbouring cells of one z column with 64 or fewer together
-  // share a unit (when the column has room for the wider stencil), so sparse
-  // cells do not leave most lanes of a wavefront idle
+  // traversal work units: runs of up to 64 consecutive particles of one
+  // (x, y) column, so a wavefront's lanes are all busy however the cells are
+  // filled; a unit spans at most nz_max cells along z (the stencil reaches
+  // one cell beyond each end, and with nz <= nc_z - 2 the cell reached
+  // through the periodic wrap is never also a cell of the run)
   std::vector<int4>& chunks = ps.h_chunks;
   chunks.clear();
-  const bool merge = rg.nc[2] >= 6;
-  for (int c = 0; c < ncell;) {
-    const int n0 = cnt[c];
-    if (n0 == 0) { ++c; continue; }
-    const int z = c % rg.nc[2];
-    if (merge && n0 < 64 && z + 1 < rg.nc[2] && n0 + cnt[c + 1] <= 64 && cnt[c + 1] > 0) {
-      chunks.push_back(make_int4(start[c], start[c + 2], c, 2));
-      c += 2;
-      continue;
+  const int nc2 = rg.nc[2];
+  const int nz_max = nc2 >= 3 ? std::min(nc2 - 2, 2) : 1;
+  for (int col = 0; col < ncell / nc2; ++col) {
+    const int c0 = col * nc2;
+    int cur = start[c0];
+    const int col_end = start[c0 + nc2];
+    int z = 0;
+    while (cur < col_end) {
+      while (start[c0 + z + 1] <= cur) ++z;  // cell of the unit's first particle
+      int end = std::min(cur + 64, col_end);
+      const int zlim = std::min(z + nz_max, nc2);
+      end = std::min(end, start[c0 + zlim]);
+      int zl = z;
+      while (start[c0 + zl + 1] < end) ++zl;  // cell of the unit's last particle
+      chunks.push_back(make_int4(cur, end, c0 + z, zl - z + 1));
+      cur = end;
     }
-    for (int b = start[c]; b < start[c + 1]; b += 64) chunks.push_back(make_int4(b, std::min(b + 64, start[c + 1]), c, 1));
-    ++c;
   }
   ps.n_chunks = (int)chunks.size();
   ps.chunks.ensure(std::max<int64_t>(ps.n_chunks, 1));
