@@ -308,6 +308,63 @@ __global__ void __launch_bounds__(256) segment_sort_kernel(const int* __restrict
   for (int i = threadIdx.x; i < n; i += blockDim.x) keys[b + i] = key[i];
 }
 
+// One wavefront per segment (segments of at most kWaveSortMax keys): up to
+// 64 keys sit one per lane and are sorted by the same network with lane
+// shuffles; longer ones in the wavefront's LDS slice, with wavefront-level
+// ordering only.  Many short segments (cells, tiles) then cost a few dozen
+// instructions each instead of a workgroup with a barrier per stage.
+constexpr int kWaveSortMax = 1024;
+
+__global__ void __launch_bounds__(256) segment_sort_wave_kernel(const int* __restrict__ start, int nseg,
+                                                                int* __restrict__ keys) {
+  __shared__ int buf[4][kWaveSortMax];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sg = blockIdx.x * 4 + wv;
+  if (sg >= nseg) return;
+  const int b = start[sg], e = start[sg + 1];
+  const int n = e - b;
+  if (n <= 1) return;
+  if (n <= 64) {
+    int v = lane < n ? keys[b + lane] : 0x7fffffff;
+    for (int k = 2; k <= 64; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int mask = (j == (k >> 1)) ? k - 1 : j;
+        const int p = lane ^ mask;
+        const int o = __shfl(v, p, 64);
+        v = lane < p ? min(v, o) : max(v, o);  // the lower lane keeps the smaller key
+      }
+    }
+    if (lane < n) keys[b + lane] = v;
+    return;
+  }
+  int m = 1;
+  while (m < n) m <<= 1;
+  int* key = buf[wv];
+  for (int i = lane; i < m; i += 64) key[i] = i < n ? keys[b + i] : 0x7fffffff;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int mask = (j == (k >> 1)) ? k - 1 : j;
+      for (int i = lane; i < m; i += 64) {
+        if ((i & j) == 0) {
+          const int p = i ^ mask;
+          const int a = key[i], c = key[p];
+          if (a > c) {
+            key[i] = c;
+            key[p] = a;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  for (int i = lane; i < n; i += 64) keys[b + i] = key[i];
+}
+
 }  // namespace
 
 void launch_moments(hipStream_t s, const double* q, const double* sig, double sig_const, int64_t n,
@@ -388,6 +445,12 @@ void launch_backsolve(hipStream_t s, const double* st, int m, int k, double* y) 
 
 void launch_segment_sort(hipStream_t s, const int* start, int nseg, int* keys, int max_len) {
   if (nseg <= 0 || max_len <= 1) return;
+  if (max_len <= kWaveSortMax) {
+    hipLaunchKernelGGL(segment_sort_wave_kernel, dim3((unsigned)((nseg + 3) / 4)), dim3(256), 0, s, start, nseg,
+                       keys);
+    PE_CHECK_LAUNCH();
+    return;
+  }
   int m = 1;
   while (m < std::min(max_len, kSortMax)) m <<= 1;
   hipLaunchKernelGGL(segment_sort_kernel, dim3((unsigned)nseg), dim3(256), sizeof(int) * (size_t)m, s, start, keys);
