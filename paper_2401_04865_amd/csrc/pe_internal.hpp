@@ -157,6 +157,8 @@ struct ParticleSet {
   bool have_tile_lists = false;   // tile lists built for the current configuration
   bool spread_by_home = false;    // single-precision spreading walks the sorted home lists
   std::vector<int4> h_chunks;
+  std::vector<int4> h_colchunks;             // traversal units in column order (scratch)
+  std::vector<int> h_colfirst, h_colcursor;  // per column: first unit, and a cursor (scratch)
   DevBuf<int> tile_entries; // sorted-particle indices, grouped by tile
   int64_t n_entries = 0;
   // home tile of each particle (the tile holding its first support point):

@@ -905,11 +905,15 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   // filled; a unit spans at most nz_max cells along z (the stencil reaches
   // one cell beyond each end, and with nz <= nc_z - 2 the cell reached
   // through the periodic wrap is never also a cell of the run)
-  std::vector<int4>& chunks = ps.h_chunks;
-  chunks.clear();
-  const int nc2 = rg.nc[2];
+  const int nc0 = rg.nc[0], nc1 = rg.nc[1], nc2 = rg.nc[2];
   const int nz_max = nc2 >= 3 ? std::min(nc2 - 2, 2) : 1;
-  for (int col = 0; col < ncell / nc2; ++col) {
+  const int ncol = nc0 * nc1;
+  std::vector<int4>& colchunks = ps.h_colchunks;
+  std::vector<int>& col_first = ps.h_colfirst;
+  colchunks.clear();
+  col_first.assign(ncol + 1, 0);
+  for (int col = 0; col < ncol; ++col) {
+    col_first[col] = (int)colchunks.size();
     const int c0 = col * nc2;
     int cur = start[c0];
     const int col_end = start[c0 + nc2];
@@ -921,10 +925,28 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
       end = std::min(end, start[c0 + zlim]);
       int zl = z;
       while (start[c0 + zl + 1] < end) ++zl;  // cell of the unit's last particle
-      chunks.push_back(make_int4(cur, end, c0 + z, zl - z + 1));
+      colchunks.push_back(make_int4(cur, end, c0 + z, zl - z + 1));
       cur = end;
     }
   }
+  col_first[ncol] = (int)colchunks.size();
+  // work order: bricks of kBrick^3 cells, so the units in flight on one XCD
+  // (a contiguous range, see xcd_remap) read their sources from a compact
+  // region that its L2 can hold, rather than from a slab of whole planes
+  constexpr int kBrick = 8;
+  std::vector<int4>& chunks = ps.h_chunks;
+  chunks.clear();
+  std::vector<int>& cursor = ps.h_colcursor;
+  cursor.assign(col_first.begin(), col_first.end() - 1);
+  for (int bx = 0; bx < nc0; bx += kBrick)
+    for (int by = 0; by < nc1; by += kBrick)
+      for (int bz = 0; bz < nc2; bz += kBrick)
+        for (int x = bx; x < std::min(bx + kBrick, nc0); ++x)
+          for (int y = by; y < std::min(by + kBrick, nc1); ++y) {
+            const int col = x * nc1 + y;
+            while (cursor[col] < col_first[col + 1] && colchunks[cursor[col]].z % nc2 < bz + kBrick)
+              chunks.push_back(colchunks[cursor[col]++]);
+          }
   ps.n_chunks = (int)chunks.size();
   ps.chunks.ensure(std::max<int64_t>(ps.n_chunks, 1));
   if (ps.n_chunks)
