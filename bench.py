@@ -48,7 +48,14 @@ SPLIT_TOL = {"cfg2": 1e-8, "cfg3": 1e-6, "cfg4": 1e-6, "cfg5": 1e-6}
 # records the source files of the kernels and of their launches with their
 # sha1 at measurement; once one changes the figure is stale and `traffic` is
 # reported null.
-TRAFFIC = {}
+TRAFFIC = {
+    # two rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 after a
+    # 256 MiB copy calibration) of the 512-sphere workload; one launch is one
+    # profiler scope (right-hand side: 401 MB; force pass: 2371 MB)
+    "pair_f32": {"bytes_per_launch": 1.386e9,
+                 "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "c6d162a708d7a204523a33b7086c50585ea2cd67",
+                             "paper_2401_04865_amd/csrc/api.hip": "784794249a7586cc579034cb875da02712b009ec"}},
+}
 
 
 def traffic_current(entry):
@@ -68,7 +75,7 @@ def traffic_current(entry):
 # Peaks of one MI355X: HBM bandwidth, dense matrix-core and vector rates.
 MFMA_PEAK_TFLOPS = {False: 157.3, True: 78.6}     # fp32, fp64 dense matrix
 VALU_PEAK_TFLOPS = {False: 157.3, True: 78.6}     # fp32, fp64 vector
-PAIR_FLOP = 40   # arithmetic of one pair evaluation inside the cutoff
+PAIR_FLOP = 40   # one pair inside the cutoff: minimum image, r^2, kernel value and slope, field, sums
 
 
 def kernel_model(cls, dbl, cnt, work, nb, G, Gc):
