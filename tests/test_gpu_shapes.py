@@ -126,3 +126,55 @@ def test_pair_structure_kept_across_small_moves(gpu_lib):
             print(prec, step, err, d["nnz"])
             assert err <= tol
         ctx.close()
+
+
+def test_saddle_operator_full_size_sampled_sources(gpu_lib):
+    """The Krylov operator at full size (512 bodies of 642 beads, the
+    per-shape near-field product over all of them on the matrix cores, split
+    over K): with bead charges on 40 beads of four bodies and no potential
+    offsets, the bead rows at 40 other beads of the same bodies equal minus
+    the oracle's potential from those sources, and the body rows equal the
+    bodies' charge sums.  A body's dense block keeps all of its own pairs
+    (the sphere is wider than r_c), so the reference adds, per body, the
+    oracle's real-space sum over the same pairs beyond r_c."""
+    import torch
+    B = gpu_lib
+    s = inputs.config(5)
+    pos, sig, _ = saddle.all_particles(s, np.zeros(s.n_bead))
+    rng = np.random.default_rng(53)
+    bodies = rng.choice(s.n_body, 4, replace=False)
+    src, tgt = [], []
+    for b in bodies:
+        beads = np.arange(s.body_offsets[b], s.body_offsets[b + 1])
+        pick = rng.choice(beads, 20, replace=False)
+        src += list(pick[:10])
+        tgt += list(pick[10:])
+    src, tgt = np.array(src), np.array(tgt)
+    q = rng.standard_normal(len(src))
+    n = s.n_bead + s.n_body
+    x = np.zeros(n)
+    x[src] = q
+    ref = None
+    for prec, tol in ((B.PE_FP64, 1e-10), (B.PE_MIXED, 3e-6)):
+        p = B.make_params(s.box, s.mesh, P=8, split_tol=1e-6, precision=prec)
+        ctx = B.Context(p).load(s)
+        d = ctx.pe_get_derived()
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.pe_apply_saddle(torch.as_tensor(x, device="cuda"), y, prec)
+        y = y.cpu().numpy()
+        ctx.close()
+        if ref is None:
+            ref, _ = se.apply(pos[tgt], sig[tgt], pos[src], sig[src], q, s.box, s.mesh, 8, d["xi"], d["eta"],
+                              d["r_cut"], want_field=False, same=False)
+            for k in range(len(bodies)):
+                t, sr = slice(10 * k, 10 * k + 10), slice(10 * k, 10 * k + 10)
+                far, _ = se.real_potential(pos[tgt[t]], sig[tgt[t]], pos[src[sr]], sig[src[sr]], q[sr], s.box,
+                                           d["xi"], 0.49 * min(s.box))
+                near, _ = se.real_potential(pos[tgt[t]], sig[tgt[t]], pos[src[sr]], sig[src[sr]], q[sr], s.box,
+                                            d["xi"], d["r_cut"])
+                ref[t] += far - near
+        err = np.abs(-y[tgt] - ref).max() / np.abs(ref).max()
+        print(prec, err)
+        assert err <= tol
+        sums = np.array([x[s.body_offsets[b]:s.body_offsets[b + 1]].sum() for b in range(s.n_body)])
+        np.testing.assert_allclose(y[s.n_bead:], sums, rtol=0, atol=1e-12)
