@@ -274,6 +274,18 @@ void apply_saddle_prec(pe_context* c, int prec, const double* x, double* y) {
 // this configuration stand in for spreading the ions again and for the
 // ion sources of the bead targets' pair pass (the potential is linear in
 // the charges, and the kept parts were formed by the same kernels).
+// Work enqueued on c->aux after fork() starts after everything enqueued on
+// c->stream so far; work on c->stream after join() starts after everything
+// enqueued on c->aux so far.
+void fork_aux(pe_context* c) {
+  PE_HIP(hipEventRecord(c->ev_fork, c->stream));
+  PE_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+}
+void join_aux(pe_context* c) {
+  PE_HIP(hipEventRecord(c->ev_join, c->aux));
+  PE_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+}
+
 template <typename T>
 void all_potential(pe_context* c, const double* qb, const double* qi, double* phi, double* E,
                    double* f, double* u, const double* chg_all, bool reuse_ion = false) {
@@ -287,6 +299,31 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
   if (reuse_ion) gA = reinterpret_cast<T*>(c->ion_grid32.get());
+  // real space on the auxiliary stream, into its own buffers
+  c->phi_pair.ensure((size_t)std::max<int64_t>(na, 1));
+  if (E) c->E_pair.ensure(3 * (size_t)std::max<int64_t>(na, 1));
+  double* phi_p = c->phi_pair.get();
+  double* E_p = E ? c->E_pair.get() : nullptr;
+  fork_aux(c);
+  {
+    hipStream_t sa = c->aux;
+    PE_HIP(hipMemsetAsync(phi_p, 0, sizeof(double) * na, sa));
+    if (E) PE_HIP(hipMemsetAsync(E_p, 0, sizeof(double) * 3 * na, sa));
+    ProfScope ps_pair(c->prof, sa, PE_PROF_PAIR, sizeof(T) == 8);
+    unsigned long long* npc = pair_counter<T>(c);
+    const PairTables& pt = c->pair_tabs;
+    if (reuse_ion) {
+      launch_pair_onfly<T>(sa, c->B, &c->B, qb, nullptr, nullptr, c->rg, phi_p, E_p, false, npc,
+                           pt.get(false, false));
+      launch_axpby(sa, 1.0, c->ion_rs_phi.get(), 1.0, phi_p, nb);
+      launch_axpby(sa, 1.0, c->ion_rs_E.get(), 1.0, E_p, 3 * nb);
+    } else {
+      launch_pair_onfly<T>(sa, c->B, &c->B, qb, &c->I, qi, c->rg, phi_p, E_p, false, npc, pt.get(false, false),
+                           pt.get(false, true));
+    }
+    launch_pair_onfly<T>(sa, c->I, &c->B, qb, &c->I, qi, c->rg, phi_p + nb, E_p ? E_p + 3 * nb : nullptr, false,
+                         npc, pt.get(true, false), pt.get(true, true));
+  }
   {
     ProfScope ps(c->prof, s, PE_PROF_SPREAD, sizeof(T) == 8, (double)(reuse_ion ? nb : nb + ni));
     if (reuse_ion) {
@@ -303,19 +340,9 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
     launch_gather<T>(s, c->B, gB, c->gg, phi, E, true);
     if (ni) launch_gather<T>(s, c->I, gB, c->gg, phi + nb, E ? E + 3 * nb : nullptr, true);
   }
-  ProfScope ps_pair(c->prof, s, PE_PROF_PAIR, sizeof(T) == 8);
-  unsigned long long* npc = pair_counter<T>(c);
-  const PairTables& pt = c->pair_tabs;
-  if (reuse_ion) {
-    launch_pair_onfly<T>(s, c->B, &c->B, qb, nullptr, nullptr, c->rg, phi, E, false, npc, pt.get(false, false));
-    launch_axpby(s, 1.0, c->ion_rs_phi.get(), 1.0, phi, nb);
-    launch_axpby(s, 1.0, c->ion_rs_E.get(), 1.0, E, 3 * nb);
-  } else {
-    launch_pair_onfly<T>(s, c->B, &c->B, qb, &c->I, qi, c->rg, phi, E, false, npc, pt.get(false, false),
-                         pt.get(false, true));
-  }
-  launch_pair_onfly<T>(s, c->I, &c->B, qb, &c->I, qi, c->rg, phi + nb, E ? E + 3 * nb : nullptr, false, npc,
-                       pt.get(true, false), pt.get(true, true));
+  join_aux(c);
+  launch_axpby(s, 1.0, phi_p, 1.0, phi, na);
+  if (E) launch_axpby(s, 1.0, E_p, 1.0, E, 3 * na);
   // k = 0 constant, then forces and energies
   if (nb)
     hipLaunchKernelGGL(finish_particles_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, chg_all,
@@ -351,6 +378,33 @@ void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E) {
     c->ion_grid32.ensure((size_t)G);
     gA = reinterpret_cast<T*>(c->ion_grid32.get());
   }
+  // ion -> bead real space on the auxiliary stream, into its own buffers
+  // (kept for the force pass in single precision with the field)
+  double* rs_phi;
+  double* rs_E = nullptr;
+  if (keep) {
+    c->ion_rs_phi.ensure((size_t)std::max<int64_t>(nb, 1));
+    c->ion_rs_E.ensure(3 * (size_t)std::max<int64_t>(nb, 1));
+    rs_phi = c->ion_rs_phi.get();
+    rs_E = c->ion_rs_E.get();
+  } else {
+    c->phi_pair.ensure((size_t)std::max<int64_t>(nb, 1));
+    rs_phi = c->phi_pair.get();
+    if (E) {
+      c->E_pair.ensure(3 * (size_t)std::max<int64_t>(nb, 1));
+      rs_E = c->E_pair.get();
+    }
+  }
+  fork_aux(c);
+  {
+    hipStream_t sa = c->aux;
+    PE_HIP(hipMemsetAsync(rs_phi, 0, sizeof(double) * nb, sa));
+    if (rs_E) PE_HIP(hipMemsetAsync(rs_E, 0, sizeof(double) * 3 * nb, sa));
+    // double path: the field only feeds the guess features, single precision
+    ProfScope ps(c->prof, sa, PE_PROF_PAIR, dbl);
+    launch_pair_onfly<T>(sa, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, rs_phi, rs_E, true,
+                         pair_counter<T>(c), c->pair_tabs.get(false, true));
+  }
   {
     ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)c->n_ion);
     launch_spread<T>(s, c->I, c->ion_q.get(), gA, c->gg, false);
@@ -360,22 +414,10 @@ void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E) {
     ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb);
     launch_gather<T>(s, c->B, gB, c->gg, phi_ion, E, false);
   }
-  // double path: the field only feeds the guess features, single precision
-  ProfScope ps(c->prof, s, PE_PROF_PAIR, dbl);
-  if (keep) {
-    c->ion_rs_phi.ensure((size_t)std::max<int64_t>(nb, 1));
-    c->ion_rs_E.ensure(3 * (size_t)std::max<int64_t>(nb, 1));
-    PE_HIP(hipMemsetAsync(c->ion_rs_phi.get(), 0, sizeof(double) * nb, s));
-    PE_HIP(hipMemsetAsync(c->ion_rs_E.get(), 0, sizeof(double) * 3 * nb, s));
-    launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, c->ion_rs_phi.get(),
-                         c->ion_rs_E.get(), true, pair_counter<T>(c), c->pair_tabs.get(false, true));
-    launch_axpby(s, 1.0, c->ion_rs_phi.get(), 1.0, phi_ion, nb);
-    launch_axpby(s, 1.0, c->ion_rs_E.get(), 1.0, E, 3 * nb);
-    c->ion_parts_valid = true;
-  } else {
-    launch_pair_onfly<T>(s, c->B, &c->I, c->ion_q.get(), nullptr, nullptr, c->rg, phi_ion, E, true,
-                         pair_counter<T>(c), c->pair_tabs.get(false, true));
-  }
+  join_aux(c);
+  launch_axpby(s, 1.0, rs_phi, 1.0, phi_ion, nb);
+  if (E) launch_axpby(s, 1.0, rs_E, 1.0, E, 3 * nb);
+  if (keep) c->ion_parts_valid = true;
 }
 
 // Right-hand side b = [-r.E0 + phi_ion(beads); Q].
@@ -686,6 +728,9 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
   if (c->p.inner_tol <= 0) c->p.inner_tol = 1e-4;
   if (c->p.max_refine <= 0) c->p.max_refine = 8;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  PE_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+  PE_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  PE_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   {
     int dev = 0, lds = 0;
     PE_HIP(hipGetDevice(&dev));
@@ -712,6 +757,12 @@ pe_status pe_destroy(pe_context* ctx) {
   if (!ctx) return PE_OK;
   if (ctx->guess) guess_destroy(ctx);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   delete ctx;
   return PE_OK;
 }

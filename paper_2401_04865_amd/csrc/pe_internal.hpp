@@ -318,6 +318,12 @@ struct LearnedGuess;  // defined in the guess translation unit
 struct pe_context {
   pe_params p;
   hipStream_t stream = nullptr;
+  // second stream (default priority) for the real-space pair passes of the
+  // one-off potentials, forked from and joined back into `stream` by events,
+  // so they overlap the spread / FFT / gather of the same pass
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  pe::DevBuf<double> phi_pair, E_pair;  // the pair passes' own outputs (summed after the join)
   std::string err;
 
   int lds_per_block = 65536;  // device limit on LDS per workgroup (bytes)
