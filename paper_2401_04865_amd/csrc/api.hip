@@ -230,6 +230,18 @@ unsigned long long* pair_counter(pe_context* c) {
 
 // M q for the beads with bead charges q (caller order), assembled into the
 // saddle operator: y[0:nb] = -(M q) + Sigma^T dpsi, y[nb:] = Sigma q.
+// Work enqueued on c->aux after fork() starts after everything enqueued on
+// c->stream so far; work on c->stream after join() starts after everything
+// enqueued on c->aux so far.
+void fork_aux(pe_context* c) {
+  PE_HIP(hipEventRecord(c->ev_fork, c->stream));
+  PE_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+}
+void join_aux(pe_context* c) {
+  PE_HIP(hipEventRecord(c->ev_join, c->aux));
+  PE_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+}
+
 template <typename T>
 void apply_saddle(pe_context* c, const double* x, double* y) {
   hipStream_t s = c->stream;
@@ -241,22 +253,35 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
   const bool dbl = sizeof(T) == 8;
+  // dense intra-body blocks per shape on the auxiliary stream, into their own
+  // buffer, while the mesh part runs; the sparse pairs and the assembly after
+  // the join
+  bool any_near = false;
+  for (auto& t : c->pc.types) any_near = any_near || (t.near && !t.bodies.empty());
+  double* phi_near = nullptr;
+  if (any_near) {
+    c->phi_near.ensure((size_t)std::max<int64_t>(nb, 1));
+    phi_near = c->phi_near.get();
+    fork_aux(c);
+    hipStream_t sa = c->aux;
+    PE_HIP(hipMemsetAsync(phi_near, 0, sizeof(double) * nb, sa));
+    for (auto& t : c->pc.types) {
+      if (!t.near || t.bodies.empty()) continue;
+      const T* R;
+      if constexpr (sizeof(T) == 8) R = t.R64.get();
+      else R = t.R32.get();
+      ProfScope ps(c->prof, sa, PE_PROF_NEAR, dbl, (double)t.N * t.N * (double)t.bodies.size());
+      launch_body_gemm<T>(sa, R, t.N, false, true, t.dbodies.get(), (int)t.bodies.size(), c->off.get(), nb,
+                          q, phi_near, c->pc.gemm_ws.get());
+    }
+  }
   { ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)nb); launch_spread<T>(s, c->B, q, gA, c->gg, false); }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
   { ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
-  // real space: dense intra-body blocks per shape, then the sparse pairs
-  for (auto& t : c->pc.types) {
-    if (!t.near || t.bodies.empty()) continue;
-    const T* R;
-    if constexpr (sizeof(T) == 8) R = t.R64.get();
-    else R = t.R32.get();
-    ProfScope ps(c->prof, s, PE_PROF_NEAR, dbl, (double)t.N * t.N * (double)t.bodies.size());
-    launch_body_gemm<T>(s, R, t.N, false, true, t.dbodies.get(), (int)t.bodies.size(), c->off.get(), nb,
-                        q, c->phi_w.get(), c->pc.gemm_ws.get());
-  }
+  if (any_near) join_aux(c);
   {
     ProfScope ps(c->prof, s, PE_PROF_SPMV, dbl, (double)c->nnz);
-    launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), ck_bead(c), y);
+    launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), phi_near, ck_bead(c), y);
   }
 }
 
@@ -274,18 +299,6 @@ void apply_saddle_prec(pe_context* c, int prec, const double* x, double* y) {
 // this configuration stand in for spreading the ions again and for the
 // ion sources of the bead targets' pair pass (the potential is linear in
 // the charges, and the kept parts were formed by the same kernels).
-// Work enqueued on c->aux after fork() starts after everything enqueued on
-// c->stream so far; work on c->stream after join() starts after everything
-// enqueued on c->aux so far.
-void fork_aux(pe_context* c) {
-  PE_HIP(hipEventRecord(c->ev_fork, c->stream));
-  PE_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-}
-void join_aux(pe_context* c) {
-  PE_HIP(hipEventRecord(c->ev_join, c->aux));
-  PE_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
-}
-
 template <typename T>
 void all_potential(pe_context* c, const double* qb, const double* qi, double* phi, double* E,
                    double* f, double* u, const double* chg_all, bool reuse_ion = false) {

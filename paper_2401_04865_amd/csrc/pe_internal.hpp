@@ -324,6 +324,7 @@ struct pe_context {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   pe::DevBuf<double> phi_pair, E_pair;  // the pair passes' own outputs (summed after the join)
+  pe::DevBuf<double> phi_near;          // the near-field blocks' output of a Krylov product
   std::string err;
 
   int lds_per_block = 65536;  // device limit on LDS per workgroup (bytes)
@@ -445,7 +446,7 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
 void build_bead_matrix(pe_context* c);
 template <typename T>
 void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const double* dpsi,
-                          const double* phi_wave, const double* ck0, double* y_top);
+                          const double* phi_wave, const double* phi_near, const double* ck0, double* y_top);
 // Adds the real-space potential (and field, if E) at the targets from up to
 // two source sets; field_single evaluates the field in single precision.
 // tab0 / tab1 (may be null): pair tables of the classes (tgt, src0) and

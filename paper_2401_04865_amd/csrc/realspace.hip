@@ -762,7 +762,8 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   }
 }
 
-// y_top[b] = -(phi_wave[b] + sum_j R_bj q_j - ck0_b) + dpsi[body(b)] for every bead b.
+// y_top[b] = -(phi_wave[b] + phi_near[b] + sum_j R_bj q_j - ck0_b) + dpsi[body(b)]
+// for every bead b (phi_near may be null).
 // ck0_b = ck[0] - ck[1] * sigma_b^2 (the k = 0 constant of the split).
 // CSR rows in cell order; 16 lanes per row read the row's entries
 // contiguously and reduce with lane shuffles (4 rows per wavefront).
@@ -770,8 +771,9 @@ template <typename T>
 __global__ void __launch_bounds__(256) spmv_assemble_kernel(
     const int64_t* __restrict__ row_ptr, const int* __restrict__ col, const T* __restrict__ val,
     const int* __restrict__ row_bead, const double* __restrict__ sig, int64_t n,
-    const double* __restrict__ q, const double* __restrict__ phi_wave, const double* __restrict__ ck,
-    const double* __restrict__ dpsi, const int* __restrict__ body_of, double* __restrict__ y) {
+    const double* __restrict__ q, const double* __restrict__ phi_wave, const double* __restrict__ phi_near,
+    const double* __restrict__ ck, const double* __restrict__ dpsi, const int* __restrict__ body_of,
+    double* __restrict__ y) {
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int sub = threadIdx.x & 15;
   T acc = 0;
@@ -787,7 +789,7 @@ __global__ void __launch_bounds__(256) spmv_assemble_kernel(
   if (i < n && sub == 0) {
     const int b = row_bead[i];
     const double sg = sig[b];
-    const double phi = (double)acc + phi_wave[b] - (ck[0] - ck[1] * sg * sg);
+    const double phi = (double)acc + phi_wave[b] + (phi_near ? phi_near[b] : 0.0) - (ck[0] - ck[1] * sg * sg);
     y[b] = -phi + (dpsi ? dpsi[body_of[b]] : 0.0);
   }
 }
@@ -1124,7 +1126,7 @@ void build_near_block(hipStream_t s, const BodyType& t, const RealGeom& rg, doub
 
 template <typename T>
 void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const double* dpsi,
-                          const double* phi_wave, const double* ck0, double* y_top) {
+                          const double* phi_wave, const double* phi_near, const double* ck0, double* y_top) {
   const int64_t n = c->n_bead;
   if (n == 0) return;
   const T* val;
@@ -1134,7 +1136,7 @@ void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const d
     val = c->val32.get();
   }
   hipLaunchKernelGGL(spmv_assemble_kernel<T>, dim3(nblk(16 * n, 256)), dim3(256), 0, s, c->row_ptr.get(),
-                     c->col.get(), val, c->csr_row.get(), c->bead_sig.get(), n, q, phi_wave, ck0, dpsi,
+                     c->col.get(), val, c->csr_row.get(), c->bead_sig.get(), n, q, phi_wave, phi_near, ck0, dpsi,
                      c->body_of.get(), y_top);
   PE_CHECK_LAUNCH();
 }
@@ -1303,8 +1305,10 @@ void update_pair_tables(hipStream_t s, PairTables& pt, const RealGeom& rg, const
   PE_HIP(hipStreamSynchronize(s));
 }
 
-template void launch_spmv_assemble<float>(hipStream_t, pe_context*, const double*, const double*, const double*, const double*, double*);
-template void launch_spmv_assemble<double>(hipStream_t, pe_context*, const double*, const double*, const double*, const double*, double*);
+template void launch_spmv_assemble<float>(hipStream_t, pe_context*, const double*, const double*, const double*,
+                                          const double*, const double*, double*);
+template void launch_spmv_assemble<double>(hipStream_t, pe_context*, const double*, const double*, const double*,
+                                           const double*, const double*, double*);
 template void launch_pair_onfly<float>(hipStream_t, const ParticleSet&, const ParticleSet*, const double*,
                                        const ParticleSet*, const double*, const RealGeom&, double*, double*, bool,
                                        unsigned long long*, const float4*, const float4*);
