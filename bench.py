@@ -51,10 +51,10 @@ SPLIT_TOL = {"cfg2": 1e-8, "cfg3": 1e-6, "cfg4": 1e-6, "cfg5": 1e-6}
 TRAFFIC = {
     # two rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 after a
     # 256 MiB copy calibration) of the 512-sphere workload; one launch is one
-    # profiler scope (right-hand side: 401 MB; force pass: 2371 MB)
-    "pair_f32": {"bytes_per_launch": 1.386e9,
-                 "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "c6d162a708d7a204523a33b7086c50585ea2cd67",
-                             "paper_2401_04865_amd/csrc/api.hip": "784794249a7586cc579034cb875da02712b009ec"}},
+    # profiler scope (right-hand side: 399 MB; force pass: 2351 MB)
+    "pair_f32": {"bytes_per_launch": 1.375e9,
+                 "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "2b16859b43b3ff03ebd098f432a4936de7aa29f7",
+                             "paper_2401_04865_amd/csrc/api.hip": "276ecc3011deaaae6a342c777efee31edd16e5d4"}},
 }
 
 
