@@ -818,9 +818,10 @@ void launch_gather(hipStream_t s, const ParticleSet& ps, const T* grid, const Gr
   require(g.P <= kMaxP, "support P must be <= 16");
   const int Hs = kTile + g.P - 1;
   const size_t region = (size_t)Hs * Hs * Hs * sizeof(T);
-  // single precision: tile-staged; double: per particle (measured faster for
-  // double, whose region halves the workgroups an LDS can hold)
-  if (sizeof(T) == 4 && region <= (size_t)kGatherLDS) {
+  // tile-staged in single precision, and in double for P = 8 (the unrolled
+  // contraction: 187 -> 148 us per bead pass at cfg5); double with other
+  // supports per particle (its region halves the workgroups an LDS holds)
+  if ((sizeof(T) == 4 || g.P == 8) && region <= (size_t)kGatherLDS) {
     if (ps.n_home_tiles == 0) return;
     const dim3 blocks((unsigned)ps.n_home_tiles);
     auto go = [&](auto kern) {
