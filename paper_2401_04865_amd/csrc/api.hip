@@ -908,13 +908,17 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
     hipLaunchKernelGGL(rel_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, c->bead_x.get(), body_center,
                        c->body_of.get(), nb, c->rel.get());
   PE_CHECK_LAUNCH();
+  // the two sets' cells and lists: ions on the auxiliary stream, so their
+  // kernels run while the host waits on the beads' counts and vice versa
+  fork_aux(c);
   build_cells(s, c->B, c->bead_x.get(), c->bead_sig.get(), 0.0, c->body_of.get(), nb, rg);
-  build_cells(s, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, nullptr, n_ion, rg);
-  update_pair_tables(s, c->pair_tabs, rg, c->B, c->I);
+  build_cells(c->aux, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, nullptr, n_ion, rg);
   // beads are spread by every Krylov product: tile lists; ions once per
   // configuration in single precision: their sorted home lists serve
   build_tiles(s, c->B, c->gg, false);
-  build_tiles(s, c->I, c->gg, c->p.precision == PE_MIXED);
+  build_tiles(c->aux, c->I, c->gg, c->p.precision == PE_MIXED);
+  join_aux(c);
+  update_pair_tables(s, c->pair_tabs, rg, c->B, c->I);
   shape_setup(c);
   build_bead_matrix(c);
   ensure_grids(c);
