@@ -917,10 +917,11 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   // configuration in single precision: their sorted home lists serve
   build_tiles(s, c->B, c->gg, false);
   build_tiles(c->aux, c->I, c->gg, c->p.precision == PE_MIXED);
-  join_aux(c);
-  update_pair_tables(s, c->pair_tabs, rg, c->B, c->I);
+  update_pair_tables(s, c->pair_tabs, rg, c->B, c->I);  // the widths are known on the host by now
+  // bead-only set-up still overlaps the ions' lists
   shape_setup(c);
   build_bead_matrix(c);
+  join_aux(c);
   ensure_grids(c);
   c->phi_w.ensure(nb + n_ion + 1);
   c->phi_all.ensure(nb + n_ion + 1);
