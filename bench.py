@@ -54,7 +54,7 @@ TRAFFIC = {
     # profiler scope (right-hand side: 399 MB; force pass: 2351 MB)
     "pair_f32": {"bytes_per_launch": 1.375e9,
                  "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "2b16859b43b3ff03ebd098f432a4936de7aa29f7",
-                             "paper_2401_04865_amd/csrc/api.hip": "276ecc3011deaaae6a342c777efee31edd16e5d4"}},
+                             "paper_2401_04865_amd/csrc/api.hip": "db2cf28a122a3411da773082a60831037809cb40"}},
 }
 
 
