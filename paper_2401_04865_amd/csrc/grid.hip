@@ -207,9 +207,12 @@ constexpr int kWaveChunk = 16;
 // HOME: the particle list of a tile is the concatenation of the sorted home
 // lists of the tiles (ux - dx, uy - dy, uz - dz), d in {0, 1}^3 (tile_start /
 // entries are then the home lists); particles whose support misses the tile
-// get zero factors.
+// get zero factors.  Eight wavefronts per SIMD (at most 64 VGPRs, no spills;
+// 14 KB of LDS per workgroup leaves room for eight workgroups per CU): the
+// loop waits on its list and position loads, and more resident wavefronts hide
+// them (bead spread 198 -> 189 us on the 256^3 mesh).
 template <typename T, bool HOME>
-__global__ void __launch_bounds__(256) spread_tile_kernel(const double4* __restrict__ pos,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) spread_tile_kernel(const double4* __restrict__ pos,
                                                           const double* __restrict__ qs,
                                                           const int* __restrict__ tile_start,
                                                           const int* __restrict__ entries,
