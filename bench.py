@@ -53,7 +53,7 @@ TRAFFIC = {
     # 256 MiB copy calibration) of the 512-sphere workload; one launch is one
     # profiler scope (right-hand side: 399 MB; force pass: 2351 MB)
     "pair_f32": {"bytes_per_launch": 1.375e9,
-                 "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "2b16859b43b3ff03ebd098f432a4936de7aa29f7",
+                 "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "83ae5a528fd52d9ce40bfb5e8fe773457299762d",
                              "paper_2401_04865_amd/csrc/api.hip": "db2cf28a122a3411da773082a60831037809cb40"}},
 }
 

@@ -766,7 +766,10 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
 // for every bead b (phi_near may be null).
 // ck0_b = ck[0] - ck[1] * sigma_b^2 (the k = 0 constant of the split).
 // CSR rows in cell order; 16 lanes per row read the row's entries
-// contiguously and reduce with lane shuffles (4 rows per wavefront).
+// contiguously and reduce with lane shuffles (4 rows per wavefront).  Rows
+// hold about ten entries, so most lanes take one; that entry and the bead's
+// own terms are loaded before either is used, which overlaps the two chains
+// of dependent loads (row -> column -> charge, row -> bead -> body -> dpsi).
 template <typename T>
 __global__ void __launch_bounds__(256) spmv_assemble_kernel(
     const int64_t* __restrict__ row_ptr, const int* __restrict__ col, const T* __restrict__ val,
@@ -777,20 +780,33 @@ __global__ void __launch_bounds__(256) spmv_assemble_kernel(
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int sub = threadIdx.x & 15;
   T acc = 0;
+  int b = 0;
+  double sg = 0.0, pw = 0.0, pn = 0.0, dp = 0.0;
   if (i < n) {
-    const int64_t e = row_ptr[i + 1];
-    for (int64_t o = row_ptr[i] + sub; o < e; o += 16) {
-      const int j = col[o];  // a negative column is a zero entry
-      acc += val[o] * (T)q[j < 0 ? -1 - j : j];
+    const int64_t o0 = row_ptr[i] + sub, e = row_ptr[i + 1];
+    b = row_bead[i];
+    int j = 0;
+    T v = 0;
+    if (o0 < e) {
+      j = col[o0];  // a negative column is a zero entry
+      v = val[o0];
+    }
+    sg = sig[b];
+    pw = phi_wave[b];
+    if (phi_near) pn = phi_near[b];
+    const int bo = dpsi ? body_of[b] : 0;
+    if (o0 < e) acc = v * (T)q[j < 0 ? -1 - j : j];
+    if (dpsi) dp = dpsi[bo];
+    for (int64_t o = o0 + 16; o < e; o += 16) {
+      const int jj = col[o];
+      acc += val[o] * (T)q[jj < 0 ? -1 - jj : jj];
     }
   }
 #pragma unroll
   for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
   if (i < n && sub == 0) {
-    const int b = row_bead[i];
-    const double sg = sig[b];
-    const double phi = (double)acc + phi_wave[b] + (phi_near ? phi_near[b] : 0.0) - (ck[0] - ck[1] * sg * sg);
-    y[b] = -phi + (dpsi ? dpsi[body_of[b]] : 0.0);
+    const double phi = (double)acc + pw + (phi_near ? pn : 0.0) - (ck[0] - ck[1] * sg * sg);
+    y[b] = -phi + (dpsi ? dp : 0.0);
   }
 }
 
