@@ -513,8 +513,11 @@ __global__ void __launch_bounds__(256) gather_kernel(const double4* __restrict__
 // together, and the x factors held in registers.
 constexpr int kGatherLDS = 48 * 1024;
 
+// Single precision is held to 64 VGPRs (the field variant needs 65 unforced),
+// eight wavefronts per SIMD; its LDS region of 15^3 floats still lets eight
+// workgroups share a CU.  Double keeps the compiler's choice.
 template <typename T, bool FIELD, int PP>
-__global__ void __launch_bounds__(256) gather_tile_kernel(const double4* __restrict__ pos,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1))) gather_tile_kernel(const double4* __restrict__ pos,
                                                           const int* __restrict__ idx,
                                                           const int* __restrict__ home_start,
                                                           const int* __restrict__ home_entries,
