@@ -485,20 +485,34 @@ __global__ void __launch_bounds__(256) fft256_z_c2r_kernel(const typename C2<T>:
   const int64_t la = 2 * ((int64_t)blockIdx.x * 16 + c), lb = la + 1;
   const bool va = la < nlines, vb = lb < nlines;
   C v[16];
-  // z_k = A_k + i B_k over the full spectrum (Hermitian extension above N/2)
+  // z_k = A_k + i B_k over the full spectrum.  Only k <= N/2 is read (j1 <= 8);
+  // above it z_k = conj(A_{N-k}) + i conj(B_{N-k}), and N - k = g' + 16 j1'
+  // sits in lane (c, 16 - g) at j1' = 15 - j1, or for g = 0 in the lane itself
+  // at j1' = 16 - j1: that lane forms the mirrored value and a shuffle brings it.
+  C m[9];
 #pragma unroll
-  for (int j1 = 0; j1 < 16; ++j1) {
+  for (int j1 = 0; j1 <= 8; ++j1) {
     const int k = 16 * j1 + g;
-    const bool lo = k <= Nz / 2;
-    const int kk = lo ? k : Nz - k;
     C A = {0, 0}, Bv = {0, 0};
-    if (va) A = cplx[la * Nzs + kk];
-    if (vb) Bv = cplx[lb * Nzs + kk];
-    if (!lo) {
-      A.y = -A.y;
-      Bv.y = -Bv.y;
+    if (k <= Nz / 2) {
+      if (va) A = cplx[la * Nzs + k];
+      if (vb) Bv = cplx[lb * Nzs + k];
     }
     v[j1] = {A.x - Bv.y, A.y + Bv.x};
+    m[j1] = {A.x + Bv.y, Bv.x - A.y};
+  }
+  {
+    const int lane = threadIdx.x & 63;
+    const int partner = (lane & 48) | ((16 - g) & 15);
+#pragma unroll
+    for (int j1 = 8; j1 < 16; ++j1) {
+      C p;
+      p.x = __shfl(m[15 - j1].x, partner, 64);
+      p.y = __shfl(m[15 - j1].y, partner, 64);
+      if (g == 0) p = m[(16 - j1) & 15];
+      // k = 16 j1 + g is above N/2 except k = N/2 itself (j1 = 8, g = 0)
+      if (j1 > 8 || g > 0) v[j1] = p;
+    }
   }
   __syncthreads();  // twiddles
   dft16<T, C>(v, -1);
