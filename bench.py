@@ -47,12 +47,12 @@ SPLIT_TOL = {"cfg2": 1e-8, "cfg3": 1e-6, "cfg4": 1e-6, "cfg5": 1e-6}
 # device copy reads on those counters).  Each entry
 # records the source files of the kernels and of their launches with their
 # sha1 at measurement; once one changes the figure is stale and `traffic` is
-# reported null.
+# reported null, as it is on any other workload.
 TRAFFIC = {
     # two rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 after a
     # 256 MiB copy calibration) of the 512-sphere workload; one launch is one
     # profiler scope (right-hand side: 399 MB; force pass: 2351 MB)
-    "pair_f32": {"bytes_per_launch": 1.375e9,
+    "pair_f32": {"workload": "cfg5", "bytes_per_launch": 1.375e9,
                  "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "83ae5a528fd52d9ce40bfb5e8fe773457299762d",
                              "paper_2401_04865_amd/csrc/api.hip": "db2cf28a122a3411da773082a60831037809cb40"}},
 }
@@ -351,7 +351,9 @@ def main():
         achieved = amount / (ms * 1e-3) / (1e9 if unit == "GB/s" else 1e12)
         key = f"{name}_{'f64' if dbl else 'f32'}"
         tr = TRAFFIC.get(key)
-        traffic = tr["bytes_per_launch"] if tr and traffic_current(tr) else None
+        # a figure holds only for the workload it was counted on
+        traffic = (tr["bytes_per_launch"] if tr and tr["workload"] == args.workload and traffic_current(tr)
+                   else None)
         share = per_class[(name, dbl)][1] / total_ms
         return {"kernel": key, "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": traffic,
