@@ -149,12 +149,15 @@ def test_apply_linear_and_symmetric(gpu_lib):
     ctx.close()
 
 
-@pytest.mark.parametrize("box,mesh", [((8.0, 8.0, 1.0), (256, 256, 32)), ((1.0, 1.0, 8.0), (32, 32, 256))])
+@pytest.mark.parametrize("box,mesh", [((8.0, 8.0, 1.0), (256, 256, 32)), ((1.0, 1.0, 8.0), (32, 32, 256)),
+                                      ((1.0, 1.08, 8.0), (25, 27, 256))])
 def test_apply_256_point_lines_match_modeB(gpu_lib, box, mesh):
     """Lines of 256 points (the two-stage transforms: strided x and y, and
     the packed real z passes) and half-spectrum rows of 17 values padded to
     32, against mode B, in double to rounding and in float to the float
-    bound."""
+    bound.  The (25, 27, 256) mesh has ragged last tiles in x and y (1 and 3
+    planes of 8) and an odd number (675) of z lines, so the packed z passes
+    end on a line pair with its second line missing."""
     rng = np.random.default_rng(17)
     body = inputs.icosphere(0, 0.12)
     n_ion = 48
