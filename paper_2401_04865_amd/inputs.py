@@ -253,7 +253,7 @@ def place_ions(rng, box, n_pos, n_neg, centers, exclusion, sigma=0.1,
         cand = cand[ok][: need - have]
         out.append(cand)
         have += len(cand)
-    pos = np.concatenate(out, 0)
+    pos = np.concatenate(out, 0) if out else np.zeros((0, 3))
     q = np.concatenate([np.ones(n_pos), -np.ones(n_neg)])
     return pos, q, np.full(need, float(sigma))
 

@@ -167,6 +167,39 @@ def test_mixed_precision_solve(gpu_lib):
     assert np.abs(F32 - F64).max() <= 1e-4 * rms
 
 
+def test_no_ions_solve_and_forces(gpu_lib):
+    """Charged bodies with no ions (empty ion sets): in double the charges,
+    body forces, torques and energy equal the dense discrete-operator oracle;
+    the mixed path reaches its residual target and agrees to the float bound."""
+    s = inputs.small_random_system(31, n_body=3, level=1, n_ion=0, L=7.0, sigma=0.16, mesh=(32, 32, 32),
+                                   charges=[0.6, -0.2, 0.0])
+    assert s.n_ion == 0
+    res = {}
+    for prec, tol in ((gpu_lib.PE_FP64, 1e-13), (gpu_lib.PE_MIXED, 1e-10)):
+        p = gpu_lib.make_params(s.box, s.mesh, P=8, split_tol=1e-8, rel_tol=tol, precision=prec)
+        ctx = gpu_lib.Context(p).load(s)
+        d = ctx.pe_get_derived()
+        out = ctx.solve()
+        f = ctx.forces()
+        res[prec] = (out["q"].cpu().numpy(), out["info"], f["body_force"].cpu().numpy(),
+                     f["body_torque"].cpu().numpy(), f["total_energy"], d)
+        ctx.close()
+    q64, i64, F64, L64, U64, d = res[gpu_lib.PE_FP64]
+    assert i64["rel_residual"] < 1e-12
+    qb, _, _ = _modeB_dense_solve(s, d, 8)
+    assert np.abs(q64 - qb).max() <= 1e-9 * np.abs(qb).max()
+    F, L, fi, U = _modeB_forces(s, qb, d, 8)
+    assert fi.shape == (0, 3)
+    assert np.abs(F64 - F).max() <= 1e-8 * np.abs(F).max()
+    assert np.abs(L64 - L).max() <= 1e-8 * np.abs(L).max()
+    assert abs(U64 - U) <= 1e-9 * abs(U)
+    q32, i32, F32, _, _, _ = res[gpu_lib.PE_MIXED]
+    print(i64["iters"], i32["iters"], i32["rel_residual"])
+    assert i32["rel_residual"] <= 1e-10
+    assert np.linalg.norm(q32 - q64) <= 1e-6 * np.linalg.norm(q64)
+    assert np.abs(F32 - F).max() <= 1e-4 * np.sqrt((F ** 2).mean())
+
+
 def test_saddle_operator_matches_discrete_matrix(gpu_lib):
     """pe_apply_saddle equals the dense discrete saddle matrix times x."""
     import torch
