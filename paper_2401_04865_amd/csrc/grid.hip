@@ -191,8 +191,8 @@ __global__ void sorted_charges_kernel(const int* __restrict__ idx, const double*
 }
 
 // One workgroup per column of four tiles along z; wavefront w owns tile
-// (ux, uy, 4 bz + w) and walks that tile's particle list on its own, 16
-// particles at a time: lanes 0..47, one per (particle, axis), stage the eight
+// (ux, uy, 4 bz + w) and walks that tile's particle list on its own, 21
+// particles at a time: lanes 0..62, one per (particle, axis), stage the eight
 // tile-local window factors (f_x[a] q, f_y[b], f_z[c], zero where the support
 // misses the tile) in the wavefront's LDS slice; then lane (a, b) adds
 // q f_x[a] f_y[b] f_z[c] into the z-pencil (a, b, 0..7) it holds in
@@ -202,7 +202,7 @@ __global__ void sorted_charges_kernel(const int* __restrict__ idx, const double*
 // written (empty ones with zeros), so the grid needs no clearing between
 // products.  The lists are sorted, so the result is the same bit for bit on
 // every run.
-constexpr int kWaveChunk = 16;
+constexpr int kWaveChunk = 21;
 
 // HOME: the particle list of a tile is the concatenation of the sorted home
 // lists of the tiles (ux - dx, uy - dy, uz - dz), d in {0, 1}^3 (tile_start /
