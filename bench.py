@@ -157,7 +157,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (the solve is not sharded across GPUs); "
+        print("bench.py: the solve runs on one GPU only (it is not sharded across GPUs); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
