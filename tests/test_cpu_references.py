@@ -64,3 +64,91 @@ def test_rigid_body_step_keeps_shape_and_charge_free_translation():
     np.testing.assert_allclose(d1, d0, atol=1e-12)
     np.testing.assert_allclose(X[0] - s.body_center[0], F[0] * 0.01 / 42, atol=1e-15)
     np.testing.assert_allclose(np.linalg.norm(Q[0]), 1.0, atol=1e-14)
+
+
+# ------------------------------------------------------------------------
+# Rotation of a free-draining rigid body (section "Brownian dynamics
+# simulations ...": overdamped motion with Stokes drag gamma per bead and no
+# hydrodynamic coupling).  A body of six beads at (+-a,0,0), (0,+-b,0),
+# (0,0,+-c) about its centroid has, by the definition of the rotational drag
+# K = gamma sum_j (|r_j|^2 I - r_j r_j^T), the principal values
+# 2 gamma (b^2 + c^2), 2 gamma (a^2 + c^2), 2 gamma (a^2 + b^2) in its own
+# frame; the checks below compare the oracle's step with those values.
+
+def _axis_rotation(k, t):
+    """Rotation matrix by angle t about the unit axis k (Rodrigues)."""
+    k = np.asarray(k, dtype=np.float64)
+    Kx = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + np.sin(t) * Kx + (1 - np.cos(t)) * (Kx @ Kx)
+
+
+class _Body:
+    """One rigid six-bead body, frame rotated by R0, no ions."""
+
+    def __init__(self, a, b, c, R0, centre):
+        r = np.array([[a, 0, 0], [-a, 0, 0], [0, b, 0], [0, -b, 0], [0, 0, c], [0, 0, -c]], dtype=np.float64)
+        self.bead_pos = centre + r @ R0.T
+        self.body_center = np.array([centre], dtype=np.float64)
+        self.body_quat = np.array([[1.0, 0, 0, 0]])
+        self.body_offsets = np.array([0, 6])
+        self.n_body, self.n_bead, self.n_ion = 1, 6, 0
+        self.ion_pos = np.zeros((0, 3))
+
+
+_ABC = (0.5, 1.0, 2.0)
+_R0 = _axis_rotation(np.array([1.0, 2.0, 2.0]) / 3.0, 0.7)
+
+
+def _principal_drag(gamma):
+    a, b, c = _ABC
+    return 2 * gamma * np.array([b * b + c * c, a * a + c * c, a * a + b * b])
+
+
+def _rotvec_from_quat(q):
+    w, v = q[0], q[1:]
+    s = np.linalg.norm(v)
+    return np.zeros(3) if s == 0 else 2 * np.arctan2(s, w) * v / s
+
+
+def test_rigid_body_rotational_drift_closed_form():
+    """At kT = 0 the body turns by Omega dt with Omega = K^{-1} L: in the
+    body's principal frame each component of the torque divided by its
+    principal drag.  Checked on the quaternion and on every bead."""
+    gamma, dt = 1.7, 0.02
+    body = _Body(*_ABC, _R0, np.array([3.0, 4.0, 5.0]))
+    Lt = np.array([[0.4, -0.9, 1.3]])
+    pos, X, Q, _ = bd.step(body, np.zeros((1, 3)), Lt, np.zeros((0, 3)), dt, 0.0, gamma, 11, 3)
+    omega_body = (_R0.T @ Lt[0]) / _principal_drag(gamma)
+    theta = _R0 @ omega_body * dt
+    np.testing.assert_allclose(_rotvec_from_quat(Q[0]), theta, rtol=1e-12, atol=1e-15)
+    ang = np.linalg.norm(theta)
+    Rt = _axis_rotation(theta / ang, ang)
+    np.testing.assert_allclose(pos, X[0] + (body.bead_pos - body.body_center[0]) @ Rt.T, atol=1e-13)
+    np.testing.assert_allclose(X[0], body.body_center[0], atol=0)
+
+
+def test_rigid_body_brownian_covariances():
+    """With no force or torque, the rotation vector of one step has mean 0
+    and covariance 2 kT dt K^{-1} (fluctuation-dissipation), and the centre's
+    displacement 2 kT dt / (N gamma) I.  The body is rotated off its
+    principal axes so K^{-1} is a full matrix (a transposed Cholesky factor
+    would show in the off-diagonal terms).  Sampled over 12000 steps: the
+    statistical error of each entry is about 1.5 % of the diagonal."""
+    gamma, dt, kT = 1.3, 0.01, 0.8
+    body = _Body(*_ABC, _R0, np.array([1.0, 1.0, 1.0]))
+    n = 12000
+    th = np.zeros((n, 3))
+    dx = np.zeros((n, 3))
+    zero3 = np.zeros((1, 3))
+    for k in range(n):
+        _, X, Q, _ = bd.step(body, zero3, zero3, np.zeros((0, 3)), dt, kT, gamma, 2024, k)
+        th[k] = _rotvec_from_quat(Q[0])
+        dx[k] = X[0] - body.body_center[0]
+    Kinv = _R0 @ np.diag(1.0 / _principal_drag(gamma)) @ _R0.T
+    C_rot = 2 * kT * dt * Kinv
+    C_tr = 2 * kT * dt / (6 * gamma) * np.eye(3)
+    for C_ref, samp in ((C_rot, th), (C_tr, dx)):
+        d = np.sqrt(np.diag(C_ref))
+        assert np.all(np.abs(samp.mean(0)) < 4 * d / np.sqrt(n))
+        C = np.cov(samp.T)
+        assert np.abs(C - C_ref).max() < 0.06 * d.max() ** 2, (C, C_ref)

@@ -57,6 +57,16 @@ def test_guess_gradient_matches_reference_backprop(gpu_lib, n_rows):
     for a, b in ((0, mlp.ob1), (mlp.ob1, mlp.oW2), (mlp.oW2, mlp.ob2), (mlp.ob2, mlp.oW3), (mlp.oW3, mlp.ob3),
                  (mlp.ob3, mlp.NPAR)):
         assert np.abs(g[a:b] - gr[a:b]).max() <= 1e-4 * np.abs(gr[a:b]).max() + 1e-12
+    # against the plain double-precision backprop (no operand rounding): the
+    # matrix-core products round their operands to bfloat16 (unit roundoff
+    # 2^-9 = 2e-3), so each block may differ by a few units of it; 1.5e-2 is
+    # about eight (the bf16 reference itself differs from double by at most
+    # 5e-3 per block on these inputs)
+    L64, g64 = mlp.loss_grad(P.astype(np.float64), rows.astype(np.float64), bf=False)
+    assert abs(loss - L64) <= 5e-3 * L64
+    for a, b in ((0, mlp.ob1), (mlp.ob1, mlp.oW2), (mlp.oW2, mlp.ob2), (mlp.ob2, mlp.oW3), (mlp.oW3, mlp.ob3),
+                 (mlp.ob3, mlp.NPAR)):
+        assert np.abs(g[a:b] - g64[a:b]).max() <= 1.5e-2 * np.abs(g64[a:b]).max()
     ctx.close()
 
 

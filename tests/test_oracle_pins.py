@@ -361,6 +361,41 @@ def test_modeB_converges_to_ewald_with_support():
     assert errs[1] < 1e-4 and errs[2] < 1e-6
 
 
+def test_modeB_field_converges_to_ewald_with_support():
+    """The discrete spectral-Ewald field (the gathered gradient of the
+    window, section "Spectral Ewald implementation", plus the real-space
+    pair field) approaches the exact field of the potential tensor as the
+    support P grows.  Checked per component: a sign slip in the gathered
+    gradient or a wrong prefactor of it leaves an O(1) error at every P."""
+    rng = np.random.default_rng(2)
+    L = 6.0
+    box = np.full(3, L)
+    pos = rng.random((12, 3)) * L
+    sig = np.full(12, 0.25)
+    q = rng.standard_normal(12)
+    q -= q.mean()
+    N = 24
+    h = L / N
+    xi = math.pi * (N - 1) / L / (2 * math.sqrt(math.log(1e10)))
+    r_c = math.sqrt(math.log(1e14)) * max(1 / xi, 2 * 0.25)
+    r_c = min(r_c, L / 2)
+    _, Ee = ewald.potential_field(pos, sig, pos, sig, q, box, 1.0)
+    scale = np.abs(Ee).max()
+    errs = []
+    for P in (4, 8, 12):
+        eta = se.eta_of(h, xi, P)
+        _, E = se.apply(pos, sig, pos, sig, q, box, (N, N, N), P, xi, eta, r_c, want_field=True, same=True)
+        errs.append(np.abs(E - Ee).max() / scale)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] < 2e-3 and errs[2] < 1e-5
+    # both parts carry a share of the field far above the bound, so a sign
+    # slip or a lost factor in either one fails the check above
+    eta = se.eta_of(h, xi, 12)
+    _, Ew = se.wave_potential(pos, pos, q, box, (N, N, N), 12, xi, eta, want_field=True)
+    _, Er = se.real_potential(pos, sig, pos, sig, q, box, xi, r_c, want_field=True, same=True)
+    assert np.abs(Ew).max() > 1e-2 * scale and np.abs(Er).max() > 1e-2 * scale
+
+
 def test_modeB_operator_symmetric():
     rng = np.random.default_rng(4)
     L = 5.0
