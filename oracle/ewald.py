@@ -148,6 +148,83 @@ class Shell:
         return 2.0 * self.a
 
 
+class ShellPaperSplit(Shell):
+    """Shells of radius ``a`` with the paper's own placement of the
+    regularization in the split (section "Spectrally-accurate Ewald
+    summation", the splitting equation): the form factor j0^2(ka) multiplies
+    both parts, so the wave part is h(k) j0^2(ka) / k^2 and the real-space
+    part the inverse transform of (1 - h(k)) j0^2(ka) / k^2, for which the
+    section "Real-space sum" prints a closed form.  The printed Heaviside term
+    is read with the sign of its second part flipped,
+    -(1/(4 pi r) - (4a - r)/(16 pi a^2)) H(2a - r): only with that sign does the
+    closed form equal the inverse transform (and M stay continuous at r = 2a).
+    The potential tensor M itself is the same as with the other split."""
+
+    name = "shell_paper"
+
+    def __init__(self, a):
+        super().__init__(a)
+        self.real_shift = 2.0 * self.a   # the real part decays like erfc(xi (r - 2a))
+
+    def real(self, r, s2, xi, eps=1.0):
+        a = self.a
+        r = np.asarray(r, dtype=np.float64)
+        sp, sm = r + 2 * a, r - 2 * a
+        pi32 = math.pi ** 1.5
+        out = (-sp / (32 * pi32 * a * a * xi * r) * np.exp(-(sp * xi) ** 2)
+               - sm / (32 * pi32 * a * a * xi * r) * np.exp(-(sm * xi) ** 2)
+               + 1.0 / (16 * pi32 * a * a * xi) * np.exp(-(r * xi) ** 2)
+               + (2 * xi * xi * sp * sp + 1) / (64 * math.pi * a * a * xi * xi * r) * erfc(sp * xi)
+               + (2 * xi * xi * sm * sm + 1) / (64 * math.pi * a * a * xi * xi * r) * erfc(sm * xi)
+               - (2 * xi * xi * r * r + 1) / (32 * math.pi * a * a * xi * xi * r) * erfc(r * xi))
+        heav = np.where(r < 2 * a, 1.0 / (FOUR_PI * r) - (4 * a - r) / (16 * math.pi * a * a), 0.0)
+        return (out - heav) / eps
+
+    @staticmethod
+    def _g1(s, xi):
+        """d/ds of g(s) = (2 xi^2 s^2 + 1) erfc(xi s) / (64 pi xi^2)
+        - s exp(-xi^2 s^2) / (32 pi^1.5 xi), the function whose second
+        difference (g(r+2a) + g(r-2a) - 2 g(r)) / (a^2 r) is the printed sum of
+        erfc and exponential terms: g'(s) = (s erfc(xi s) - exp(-xi^2 s^2) /
+        (sqrt(pi) xi)) / (16 pi)."""
+        return (s * erfc(xi * s) - np.exp(-(xi * s) ** 2) / (SQRT_PI * xi)) / (16 * math.pi)
+
+    @staticmethod
+    def _g(s, xi):
+        return ((2 * xi * xi * s * s + 1) * erfc(xi * s) / (64 * math.pi * xi * xi)
+                - s * np.exp(-(xi * s) ** 2) / (32 * math.pi ** 1.5 * xi))
+
+    def real_deriv(self, r, s2, xi, eps=1.0):
+        a = self.a
+        r = np.asarray(r, dtype=np.float64)
+        G = self._g(r + 2 * a, xi) + self._g(r - 2 * a, xi) - 2 * self._g(r, xi)
+        G1 = self._g1(r + 2 * a, xi) + self._g1(r - 2 * a, xi) - 2 * self._g1(r, xi)
+        d = G1 / (a * a * r) - G / (a * a * r * r)
+        dheav = np.where(r < 2 * a, -1.0 / (FOUR_PI * r * r) + 1.0 / (16 * math.pi * a * a), 0.0)
+        return (d - dheav) / eps
+
+    def real_self(self, s2, xi, eps=1.0):
+        a = self.a
+        v = (1 - math.exp(-4 * a * a * xi * xi)) / (8 * math.pi ** 1.5 * a * a * xi) + \
+            math.erfc(2 * a * xi) / (FOUR_PI * a)
+        return v / eps + 0.0 * s2
+
+    def rhat0(self, s2, xi):
+        return 1.0 / (4.0 * xi * xi) + 0.0 * s2
+
+    def wave_form(self, kk):
+        ka = np.sqrt(kk) * self.a
+        j0 = np.where(ka == 0, 1.0, np.sin(ka) / np.where(ka == 0, 1.0, ka))
+        return j0 * j0
+
+
+def _wave_form(profile, kk):
+    """Extra factor of the wave-space Green's function: 1 when the whole
+    regularization sits in the real-space kernel."""
+    f = getattr(profile, "wave_form", None)
+    return 1.0 if f is None else f(kk)
+
+
 def _profile(profile):
     return Gaussian() if profile is None else profile
 
@@ -193,7 +270,7 @@ def k_half_space(box, k_max):
 def default_cutoffs(xi, s2_max, profile, tol=1e-16):
     """Real- and wave-space cutoffs that make each truncated tail < tol."""
     lt = math.sqrt(math.log(1.0 / tol))
-    r_o = max(lt / xi, profile.reach(s2_max)) * 1.05
+    r_o = max(lt / xi + getattr(profile, "real_shift", 0.0), profile.reach(s2_max)) * 1.05
     k_o = 2.0 * xi * lt * 1.05
     return r_o, k_o
 
@@ -291,7 +368,7 @@ def potential_matrix(pos, sig, box, xi, eps=1.0, profile=None, tol=1e-16):
         Mr, _ = _real_block(pos[t0:t1], sig[t0:t1], pos, sig, box, xi, eps, profile, r_o)
         M[t0:t1] = Mr
     k, kk = k_half_space(box, k_o)
-    g = np.exp(-kk / (4 * xi * xi)) / kk
+    g = np.exp(-kk / (4 * xi * xi)) / kk * _wave_form(profile, kk)
     for c0 in range(0, len(k), 8192):
         ph = pos @ k[c0:c0 + 8192].T
         C, S = np.cos(ph), np.sin(ph)
@@ -328,7 +405,7 @@ def potential_field(pos_t, sig_t, pos_s, sig_s, q_s, box, xi, eps=1.0, profile=N
         if want_field:
             E[t0:t1] += e
     k, kk = k_half_space(box, k_o)
-    g = np.exp(-kk / (4 * xi * xi)) / kk
+    g = np.exp(-kk / (4 * xi * xi)) / kk * _wave_form(profile, kk)
     for c0 in range(0, len(k), 4096):
         kc, gc = k[c0:c0 + 4096], g[c0:c0 + 4096]
         Cs = np.zeros(len(kc))

@@ -87,17 +87,19 @@ def signed_index(N):
     return np.where(n < (N + 1) // 2, n, n - N) if N % 2 else np.where(n < N // 2, n, n - N)
 
 
-def greens(box, mesh, xi, eta):
+def greens(box, mesh, xi, eta, profile=None):
+    """G_k, times the profile's wave-space form factor when the split puts
+    part of the regularization there (the paper's shell split: j0^2(ka))."""
     box = np.asarray(box, dtype=np.float64)
     ks = [2 * math.pi * signed_index(N) / L for N, L in zip(mesh, box)]
     kk = ks[0][:, None, None] ** 2 + ks[1][None, :, None] ** 2 + ks[2][None, None, :] ** 2
     with np.errstate(divide="ignore", invalid="ignore"):
-        G = np.exp(-(1.0 - eta) * kk / (4 * xi * xi)) / kk
+        G = np.exp(-(1.0 - eta) * kk / (4 * xi * xi)) / kk * ewald._wave_form(profile, kk)
     G[0, 0, 0] = 0.0
     return G
 
 
-def scaled_grid(H, box, mesh, xi, eta):
+def scaled_grid(H, box, mesh, xi, eta, profile=None):
     """Ht_m from H_m through the explicit forward DFT, scaling and inverse."""
     box = np.asarray(box, dtype=np.float64)
     h = box / np.asarray(mesh)
@@ -105,7 +107,7 @@ def scaled_grid(H, box, mesh, xi, eta):
     V = float(np.prod(box))
     Fx, Fy, Fz = (dft_matrix(N, -1) for N in mesh)
     Hh = h3 * np.einsum("ai,bj,ck,ijk->abc", Fx, Fy, Fz, H, optimize=True)
-    Ht_hat = greens(box, mesh, xi, eta) * Hh
+    Ht_hat = greens(box, mesh, xi, eta, profile) * Hh
     Bx, By, Bz = (dft_matrix(N, +1) for N in mesh)
     Ht = np.einsum("ia,jb,kc,abc->ijk", Bx, By, Bz, Ht_hat, optimize=True) / V
     return Ht.real
@@ -133,9 +135,9 @@ def gather(Ht, pos, box, mesh, P, xi, eta, eps=1.0, want_field=False):
     return phi, E
 
 
-def wave_potential(pos_t, pos_s, q_s, box, mesh, P, xi, eta, eps=1.0, want_field=False):
+def wave_potential(pos_t, pos_s, q_s, box, mesh, P, xi, eta, eps=1.0, want_field=False, profile=None):
     H = spread(pos_s, q_s, box, mesh, P, xi, eta)
-    Ht = scaled_grid(H, box, mesh, xi, eta)
+    Ht = scaled_grid(H, box, mesh, xi, eta, profile)
     return gather(Ht, pos_t, box, mesh, P, xi, eta, eps, want_field)
 
 
@@ -176,7 +178,7 @@ def k0_constant(sig_t, sig_s, q_s, box, xi, eps=1.0, profile=None):
 def apply(pos_t, sig_t, pos_s, sig_s, q_s, box, mesh, P, xi, eta, r_c, eps=1.0,
           profile=None, want_field=False, same=False):
     """Full discrete operator: potential (and field) at the targets."""
-    pw, Ew = wave_potential(pos_t, pos_s, q_s, box, mesh, P, xi, eta, eps, want_field)
+    pw, Ew = wave_potential(pos_t, pos_s, q_s, box, mesh, P, xi, eta, eps, want_field, profile)
     pr, Er = real_potential(pos_t, sig_t, pos_s, sig_s, q_s, box, xi, r_c, eps, profile,
                             want_field, same)
     c = k0_constant(sig_t, sig_s, q_s, box, xi, eps, profile)
