@@ -19,6 +19,24 @@ Counter (index, stream, step lo, step hi), key = seed; uniforms (u+1)/2^32;
 normals by Box-Muller: sqrt(-2 ln u0) (cos, sin)(2 pi u1) and
 sqrt(-2 ln u2) cos(2 pi u3).  Streams: 0 ions, 2 body translation,
 3 body rotation.
+
+Hard spheres (section "Brownian dynamics", the potential-free hard-sphere
+pair potential): every two particles closer than 2a -- ions, and beads of
+different bodies -- interact through U(r) = gamma / (4 dt) (r - 2a)^2, so the
+force on i from j is gamma / (2 dt) (2a - r) along (x_i - x_j) / r: under the
+free-draining mobility 1/gamma one step separates an isolated overlapping
+pair exactly to contact.  Beads of one rigid body never interact.
+
+Rigid bodies (appendix "Force and torques derivation"): the body velocities
+solve the saddle system of the bead mobility M^H and the rigid summation
+tensor S3 (6 rows per body: the bead forces summed, and their moments
+r x f): bead forces f with S3 f = (F, L) move the beads at
+M^H f = S3^T (U, Omega) = U + Omega x r.  The printed block reads
+[M^H, S3^T; S3, 0] [f_c; (U, Omega)] = [0; (F, L)]: with f_c the constraint
+forces, that is the same system with (U, Omega) of the opposite sign, the
+reading taken here.  With M^H = I / gamma it reduces per body to
+U = F / (N gamma) (r measured from the centroid) and Omega = K^-1 L, the
+free-draining update of ``step``.
 """
 from __future__ import annotations
 
@@ -74,9 +92,70 @@ def quat_matrix(q):
                      [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
 
 
-def step(sys, body_force, body_torque, ion_force, dt, kT, gamma, seed, step_no):
-    """Return new (bead_pos, body_center, body_quat, ion_pos)."""
+def _min_image(d, box):
+    return d - box * np.round(d / box)
+
+
+def hard_sphere_forces(sys, a, gamma, dt):
+    """(bead forces, ion forces) of the hard-sphere pair potential at the
+    current positions, by brute force over all pairs (minimum image)."""
+    box = np.asarray(sys.box, dtype=np.float64)
+    pos = np.concatenate([sys.bead_pos, sys.ion_pos], 0)
+    owner = np.concatenate([np.repeat(np.arange(sys.n_body), np.diff(sys.body_offsets)),
+                            -1 - np.arange(sys.n_ion)])
+    f = np.zeros_like(pos)
+    for i in range(len(pos)):
+        d = _min_image(pos[i] - pos, box)
+        r = np.sqrt(np.einsum("ij,ij->i", d, d))
+        m = (r < 2 * a) & (owner != owner[i])
+        if m.any():
+            f[i] += ((gamma / (2 * dt)) * (2 * a - r[m]) / r[m]) @ d[m]
+    return f[:sys.n_bead], f[sys.n_bead:]
+
+
+def rigid_summation(rel, body_offsets):
+    """The rigid summation tensor (6 n_body x 3 n_bead): rows 6i..6i+2 sum
+    body i's bead forces, rows 6i+3..6i+5 their moments r x f."""
+    off = np.asarray(body_offsets, dtype=np.int64)
+    nb = len(off) - 1
+    S = np.zeros((6 * nb, 3 * off[-1]))
+    for i in range(nb):
+        for j in range(off[i], off[i + 1]):
+            S[6 * i:6 * i + 3, 3 * j:3 * j + 3] = np.eye(3)
+            x, y, z = rel[j]
+            S[6 * i + 3:6 * i + 6, 3 * j:3 * j + 3] = np.array([[0, -z, y], [z, 0, -x], [-y, x, 0]])
+    return S
+
+
+def rigid_velocities(rel, body_offsets, body_force, body_torque, mobility):
+    """(U, Omega) per body from the dense saddle system of the bead mobility
+    (3 n_bead square) and the rigid summation tensor."""
+    S = rigid_summation(rel, body_offsets)
+    nb = S.shape[0] // 6
+    A = np.block([[mobility, -S.T], [S, np.zeros((6 * nb, 6 * nb))]])
+    FL = np.concatenate([np.concatenate([body_force[i], body_torque[i]]) for i in range(nb)])
+    x = np.linalg.solve(A, np.concatenate([np.zeros(S.shape[1]), FL]))
+    V = x[S.shape[1]:].reshape(nb, 6)
+    return V[:, :3], V[:, 3:]
+
+
+def step(sys, body_force, body_torque, ion_force, dt, kT, gamma, seed, step_no, hs_radius=0.0):
+    """Return new (bead_pos, body_center, body_quat, ion_pos).  With
+    hs_radius > 0 the hard-sphere forces at the current positions are added
+    to the given forces (their bead parts summed into each body's force and
+    its torque about the centre)."""
+    if hs_radius > 0:
+        fb, fi = hard_sphere_forces(sys, hs_radius, gamma, dt)
+        ion_force = np.asarray(ion_force, dtype=np.float64) + fi
+        body_force = np.array(body_force, dtype=np.float64)
+        body_torque = np.array(body_torque, dtype=np.float64)
+        for b in range(sys.n_body):
+            o0, o1 = sys.body_offsets[b], sys.body_offsets[b + 1]
+            r = sys.bead_pos[o0:o1] - sys.body_center[b]
+            body_force[b] += fb[o0:o1].sum(0)
+            body_torque[b] += np.cross(r, fb[o0:o1]).sum(0)
     ion = sys.ion_pos.copy()
+
     s = math.sqrt(2 * kT * dt / gamma)
     for i in range(sys.n_ion):
         ion[i] += ion_force[i] * dt / gamma + s * normals3(seed, step_no, i, 0)

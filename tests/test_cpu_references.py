@@ -152,3 +152,102 @@ def test_rigid_body_brownian_covariances():
         assert np.all(np.abs(samp.mean(0)) < 4 * d / np.sqrt(n))
         C = np.cov(samp.T)
         assert np.abs(C - C_ref).max() < 0.06 * d.max() ** 2, (C, C_ref)
+
+
+# ------------------------------------------------------------------------
+# Hard spheres and the rigid-body saddle (section "Brownian dynamics", the
+# potential-free hard-sphere potential; appendix "Force and torques
+# derivation", the rigid-body integrator).
+
+class _Ions:
+    def __init__(self, pos, box):
+        self.ion_pos = np.asarray(pos, dtype=np.float64)
+        self.ion_charge = np.zeros(len(pos))
+        self.box = np.asarray(box, dtype=np.float64)
+        self.bead_pos = np.zeros((0, 3))
+        self.body_center = np.zeros((0, 3))
+        self.body_quat = np.zeros((0, 4))
+        self.body_offsets = np.array([0])
+        self.n_body, self.n_bead, self.n_ion = 0, 0, len(pos)
+
+
+def test_hard_sphere_step_separates_an_overlapping_pair_to_contact():
+    """Two ions closer than 2a (across the periodic boundary), no other force
+    and kT = 0: one step puts them exactly at contact, each moving half the
+    overlap along the line of centres (the Heyes-Melrose property the
+    potential is built to have); pairs at or beyond 2a feel nothing."""
+    a, gamma, dt = 0.1, 2.0, 1e-3
+    s = _Ions([[0.05, 3.0, 3.0], [9.92, 3.04, 2.98], [5.0, 5.0, 5.0], [5.2, 5.0, 5.0]], [10.0, 10.0, 10.0])
+    _, _, _, ion = bd.step(s, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((4, 3)), dt, 0.0, gamma, 1, 0,
+                           hs_radius=a)
+    d = ion[0] - ion[1]
+    d -= 10.0 * np.round(d / 10.0)
+    assert abs(np.linalg.norm(d) - 2 * a) < 1e-12
+    d0 = s.ion_pos[0] - s.ion_pos[1]
+    d0 -= 10.0 * np.round(d0 / 10.0)
+    np.testing.assert_allclose(np.cross(d, d0), 0, atol=1e-14)   # along the line of centres
+    np.testing.assert_allclose(ion[0] + ion[1], s.ion_pos[0] + s.ion_pos[1], atol=1e-14)  # no net drift
+    np.testing.assert_array_equal(ion[2:], s.ion_pos[2:])       # exactly at contact: no force
+
+
+def test_hard_sphere_forces_are_the_potential_gradient():
+    """Forces = -grad of sum over pairs of gamma/(4 dt)(r - 2a)^2 (central
+    differences), they sum to zero, and beads of one body do not repel."""
+    from paper_2401_04865_amd import inputs
+    a, gamma, dt = 0.12, 1.3, 2e-3
+    s = inputs.small_random_system(9, n_body=2, level=1, n_ion=60, L=3.0, mesh=(32, 32, 32))
+
+    def energy(sys):
+        pos = np.concatenate([sys.bead_pos, sys.ion_pos], 0)
+        owner = np.concatenate([np.repeat(np.arange(sys.n_body), np.diff(sys.body_offsets)),
+                                -1 - np.arange(sys.n_ion)])
+        U = 0.0
+        for i in range(len(pos)):
+            d = pos[i] - pos[i + 1:]
+            d -= sys.box * np.round(d / sys.box)
+            r = np.linalg.norm(d, axis=1)
+            m = (r < 2 * a) & (owner[i + 1:] != owner[i])
+            U += gamma / (4 * dt) * np.sum((r[m] - 2 * a) ** 2)
+        return U
+    fb, fi = bd.hard_sphere_forces(s, a, gamma, dt)
+    assert np.abs(fi).max() > 0
+    np.testing.assert_allclose(fb.sum(0) + fi.sum(0), 0, atol=1e-9 * np.abs(fi).max())
+    h = 1e-6
+    for k in range(min(8, s.n_ion)):
+        for c in range(3):
+            s.ion_pos[k, c] += h
+            up = energy(s)
+            s.ion_pos[k, c] -= 2 * h
+            dn = energy(s)
+            s.ion_pos[k, c] += h
+            assert abs(-(up - dn) / (2 * h) - fi[k, c]) <= 1e-5 * max(1.0, abs(fi[k, c]))
+    # a lone body with overlapping beads (bead spacing < 2a) feels nothing
+    lone = inputs.small_random_system(9, n_body=1, level=1, n_ion=0, L=3.0, mesh=(32, 32, 32))
+    fb1, _ = bd.hard_sphere_forces(lone, 0.5, gamma, dt)
+    assert np.abs(fb1).max() == 0
+
+
+def test_rigid_saddle_reduces_to_free_draining_closed_form():
+    """With the free-draining bead mobility I/gamma the saddle system of the
+    rigid summation tensor gives U = F/(N gamma) and Omega = K^-1 L, the
+    update the step uses, for bodies rotated off their principal axes; with
+    a full mobility the bead velocities are a rigid motion and the bead
+    forces add up to (F, L)."""
+    gamma = 1.7
+    body = _Body(*_ABC, _R0, np.array([3.0, 4.0, 5.0]))
+    r = body.bead_pos - body.body_center[0]
+    F = np.array([[0.3, -0.5, 0.2]])
+    L = np.array([[0.4, -0.9, 1.3]])
+    U, W = bd.rigid_velocities(r, body.body_offsets, F, L, np.eye(18) / gamma)
+    np.testing.assert_allclose(U[0], F[0] / (6 * gamma), rtol=1e-12)
+    K = gamma * (np.sum(r * r) * np.eye(3) - r.T @ r)
+    np.testing.assert_allclose(W[0], np.linalg.solve(K, L[0]), rtol=1e-11)
+    # a dense SPD mobility (coupled beads): the defining equations hold
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((18, 18))
+    Mh = G @ G.T / 18 + np.eye(18) / gamma
+    U2, W2 = bd.rigid_velocities(r, body.body_offsets, F, L, Mh)
+    S = bd.rigid_summation(r, body.body_offsets)
+    u = U2[0] + np.cross(W2[0], r)
+    f = np.linalg.solve(Mh, u.reshape(-1))
+    np.testing.assert_allclose(S @ f, np.concatenate([F[0], L[0]]), atol=1e-12)
