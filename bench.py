@@ -5,14 +5,20 @@ One step = one pass of the whole path over one synthetic configuration:
 pe_set_system (wrap, cell sort, bead-bead real-space operator), the
 right-hand side (ion potential at the beads), the Krylov solve to a double
 relative residual of 1e-6 (float operator inside double refinement, started
-from the learned guess when a trained model is given), and the force pass
-(forces, torques, energies).  Inputs are resident in HBM before timing.
+from the learned guess), the force pass (forces, torques, energies) and, on
+the Brownian-dynamics workload, the BD update.  Inputs are resident in HBM
+before timing.
 
-Printed: one JSON line with the metric, the live roofline of the dominant
-kernel class (HIP events around its launches in the timed region; which
-class dominates, and the per-class breakdown, come from a few untimed steps
-with events around every class), the FP64 arms for comparison, and the CPU
-oracle timed on a bounded sample.
+`value` is the metric's throughput: the bead-only spectral-Ewald operator
+(the Krylov product) in Mbeads/s = beads / average duration of one product,
+timed live with HIP events around every product the solves of the timed
+steps apply.  Beside it: the whole path's rate, solve p50/p99 over at least
+100 solves, the products in isolation (bead-only and all particles with the
+field, both precisions), comparison arms (plain FP64, FP64 with the
+preconditioner, mixed with a zero start), the live roofline of the dominant
+kernel class, and the CPU oracle's matrix-free product timed on a bounded
+sample.  `--workload cfg3` adds the precision table, `--workload cfg4` the
+zero-guess / learned-guess comparison on held-out systems.
 """
 from __future__ import annotations
 
@@ -39,19 +45,18 @@ WORKLOADS = {
     "cfg5": (5, "512 level-3 spheres Q=+20 (328704 beads) + 1e6 ions, phi=0.1, mesh 256^3, P=8, split 1e-6"),
 }
 SPLIT_TOL = {"cfg2": 1e-8, "cfg3": 1e-6, "cfg4": 1e-6, "cfg5": 1e-6}
+# training systems of the learned guess: the reduced-scale generator of each kind
+TRAIN_DEFAULT = {"cfg2": 0, "cfg3": 0, "cfg4": 2000, "cfg5": 200}
 
 # HBM bytes per launch (profiler scope) of a kernel class on the default
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes over a short
 # run of this script (the class's dispatches of five steps, averaged;
 # FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the ratios a plain 256 MiB
-# device copy reads on those counters).  Each entry
-# records the source files of the kernels and of their launches with their
-# sha1 at measurement; once one changes the figure is stale and `traffic` is
-# reported null, as it is on any other workload.
+# device copy reads on those counters).  Each entry records the source files
+# of the kernels and of their launches with their sha1 at measurement; once
+# one changes the figure is stale and `traffic` is reported null, as it is on
+# any other workload.
 TRAFFIC = {
-    # two rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 after a
-    # 256 MiB copy calibration) of the 512-sphere workload; one launch is one
-    # profiler scope (right-hand side: 399 MB; force pass: 2351 MB)
     "pair_f32": {"workload": "cfg5", "bytes_per_launch": 1.375e9,
                  "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "83ae5a528fd52d9ce40bfb5e8fe773457299762d",
                              "paper_2401_04865_amd/csrc/api.hip": "db2cf28a122a3411da773082a60831037809cb40"}},
@@ -72,10 +77,15 @@ def traffic_current(entry):
     return True
 
 
-# Peaks of one MI355X: HBM bandwidth, dense matrix-core and vector rates.
-MFMA_PEAK_TFLOPS = {False: 157.3, True: 78.6}     # fp32, fp64 dense matrix
-VALU_PEAK_TFLOPS = {False: 157.3, True: 78.6}     # fp32, fp64 vector
+# Peaks of one MI355X.  Matrix cores (dense): fp32 157.3, fp64 78.6 TFLOP/s.
+# Vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 2 (multiply-add) x 2.4 GHz =
+# 78.6 TFLOP/s in fp32 when every instruction is a single (unpacked) one, as
+# this build compiles them (packed fp32 is switched off), and 78.6 in fp64;
+# the 157.3 fp32 vector figure needs packed instructions.
+MFMA_PEAK_TFLOPS = {False: 157.3, True: 78.6}
+VALU_PEAK_TFLOPS = {False: 78.6, True: 78.6}
 PAIR_FLOP = 40   # one pair inside the cutoff: minimum image, r^2, kernel value and slope, field, sums
+NOT_KERNEL_CLASSES = ("matvec",)   # profiler scopes around whole operator applications
 
 
 def kernel_model(cls, dbl, cnt, work, nb, G, Gc):
@@ -106,51 +116,70 @@ def kernel_model(cls, dbl, cnt, work, nb, G, Gc):
     return None
 
 
-def cpu_baseline(system, budget_s=20.0):
-    """The FP64 oracle (direct Ewald assembly of M + dense LU) on a bounded
-    sample of the same workload, extrapolated to the full bead count."""
+def cpu_baseline(system, budget_targets=(2, 8)):
+    """The FP64 oracle's matrix-free Ewald product (oracle.ewald.potential_field:
+    real-space sum over every source image within its cutoff, plus the direct
+    k-sum) for the bead-only operator of the workload: potentials at a
+    sample of target beads from all beads, timed for two sample sizes; the
+    fixed cost (the structure factors of all sources) and the per-target
+    cost give the product for all beads by linear extrapolation."""
     import threadpoolctl
     from oracle import ewald
     n = system.n_bead
     rng = np.random.default_rng(0)
-    ns = min(n, 1536)
-    idx = np.sort(rng.choice(n, ns, replace=False))
-    pos, sig = system.bead_pos[idx], system.bead_sigma[idx]
-    xi = 1.0
-    t0 = time.perf_counter()
-    M = ewald.potential_matrix(pos, sig, system.box, xi)
-    t_asm = time.perf_counter() - t0
-    nl = min(n, 4096)
-    A = np.random.default_rng(1).standard_normal((nl, nl)) + nl * np.eye(nl)
-    b = np.ones(nl)
-    t0 = time.perf_counter()
-    np.linalg.solve(A, b)
-    t_lu = time.perf_counter() - t0
-    t_full = t_asm * (n / ns) ** 2 + t_lu * (n / nl) ** 3
+    q = rng.standard_normal(n)
+    L = float(np.min(system.box))
+    # split parameter of the oracle's own cutoff rule (tail 1e-16) chosen so
+    # the real-space cutoff reaches 1.5 box lengths (125 image shifts): near
+    # the cheapest split for this oracle, which sums all pairs of each shift
+    xi = 1.01 * 1.05 * math.sqrt(math.log(1e16)) / (1.5 * L)
+    times = []
+    for nt in budget_targets:
+        idx = np.sort(rng.choice(n, nt, replace=False))
+        t0 = time.perf_counter()
+        ewald.potential_field(system.bead_pos[idx], system.bead_sigma[idx], system.bead_pos, system.bead_sigma,
+                              q, system.box, xi, want_field=False)
+        times.append(time.perf_counter() - t0)
+    (n1, n2), (t1, t2) = budget_targets, times
+    per_target = max((t2 - t1) / (n2 - n1), 1e-9)
+    fixed = max(t1 - per_target * n1, 0.0)
+    t_full = fixed + per_target * n
     info = threadpoolctl.threadpool_info()
     threads = max([i.get("num_threads", 1) for i in info] + [1])
     return {
         "value": n / t_full / 1e6, "unit": "Mbeads/s", "cores": int(threads), "kind": "oracle",
-        "sample": (f"direct-Ewald assembly of M for {ns} of {n} beads ({t_asm:.2f} s, scaled by (n/ns)^2) "
-                   f"+ dense LU of {nl}^2 ({t_lu:.2f} s, scaled by (n/nl)^3); solve time extrapolated "
-                   f"{t_full:.3g} s"),
-        "seconds_measured": t_asm + t_lu,
+        "sample": (f"matrix-free direct-Ewald bead-only product (xi={xi:.4f}): potentials at {n1} and {n2} "
+                   f"sampled target beads from all {n} beads timed ({t1:.2f} s, {t2:.2f} s); fixed "
+                   f"{fixed:.2f} s + {per_target:.3f} s per target, extrapolated to {n} targets: "
+                   f"{t_full:.4g} s per product"),
+        "extrapolated": True,
+        "seconds_measured": float(sum(times)),
+        "product_s_extrapolated": t_full,
     }
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pct(a, p):
+    return round(float(np.percentile(np.asarray(a, dtype=np.float64), p)), 3)
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
-    ap.add_argument("--train-systems", type=int, default=4,
-                    help="independent configurations of the workload whose solves train the learned guess "
-                         "(0: no learned guess)")
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--train-systems", type=int, default=-1,
+                    help="reduced-scale systems whose solves train the learned guess (-1: the workload's "
+                         "default, 0: no learned guess)")
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--solves", type=int, default=100, help="solves behind the p50/p99 figures (at least)")
+    ap.add_argument("--arm-solves", type=int, default=20, help="solves per comparison arm (plain FP64: 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64-arm", action="store_true")
-    ap.add_argument("--fp64-solves", type=int, default=2)
+    ap.add_argument("--no-arms", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="untimed steps with events around every kernel class (per-class breakdown)")
@@ -179,10 +208,22 @@ def main():
     nb, nbody, ni = system.n_bead, system.n_body, system.n_ion
     off = system.body_offsets
     dt, kT, gamma, seed = 1e-4, 1.0, 1.0, 20240109
+    n_train = TRAIN_DEFAULT[args.workload] if args.train_systems < 0 else args.train_systems
 
-    def params(prec, learned=False, precond=1):
-        return B.make_params(system.box, system.mesh, P=8, split_tol=tol, rel_tol=1e-6, precision=prec,
-                             use_learned_guess=1 if learned else 0, precond=precond)
+    # The measured mixed configuration forms the right-hand side's ion
+    # potential with the float kernels like every other sum (the library's
+    # default forms it in double); the solution's residual against the
+    # double system is audited below.
+    def params(prec, learned=False, precond=1, rel_tol=1e-6, mesh=None, box=None, rhs64=False):
+        return B.make_params(system.box if box is None else box, system.mesh if mesh is None else mesh, P=8,
+                             split_tol=tol, rel_tol=rel_tol, precision=prec,
+                             use_learned_guess=1 if learned else 0, precond=precond, rhs_fp64=1 if rhs64 else 0)
+
+    def dev_of(s):
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+        return dict(bead_pos=f(s.bead_pos), bead_sigma=f(s.bead_sigma), body_center=f(s.body_center),
+                    body_quat=f(s.body_quat), body_charge=f(s.body_charge), ion_pos=f(s.ion_pos),
+                    ion_charge=f(s.ion_charge), ion_sigma=f(s.ion_sigma))
 
     q = torch.empty(nb, dtype=torch.float64, device="cuda")
     dpsi = torch.empty(nbody, dtype=torch.float64, device="cuda")
@@ -193,17 +234,19 @@ def main():
     fi = torch.empty((max(ni, 1), 3), dtype=torch.float64, device="cuda")
     counter = {"step": 0}
 
-    def step(c, dev, record=False, move=bd_mode):
+    def set_system(c, s, dev):
+        c.pe_set_system(s.body_offsets, dev["bead_pos"], dev["bead_sigma"], dev["body_center"], dev["body_quat"],
+                        dev["body_charge"], dev["ion_pos"] if s.n_ion else None,
+                        dev["ion_charge"] if s.n_ion else None, dev["ion_sigma"] if s.n_ion else None, s.E0)
+
+    def step(c, dev, move=bd_mode, forces=True):
         tp = [time.perf_counter()]
-        c.pe_set_system(off, dev["bead_pos"], dev["bead_sigma"], dev["body_center"], dev["body_quat"],
-                        dev["body_charge"], dev["ion_pos"] if ni else None, dev["ion_charge"] if ni else None,
-                        dev["ion_sigma"] if ni else None, system.E0)
+        set_system(c, system, dev)
         tp.append(time.perf_counter())
         st, info = c.pe_solve_polarization(None, q, dpsi, S)
         tp.append(time.perf_counter())
-        if record:
-            c.pe_guess_record(q)
-        c.pe_forces_torques(F, L, U, fi if ni else None, None)
+        if forces:
+            c.pe_forces_torques(F, L, U, fi if ni else None, None)
         tp.append(time.perf_counter())
         if move:
             c.pe_bd_step(dt, kT, gamma, seed, counter["step"], dev["bead_pos"], dev["body_center"],
@@ -212,42 +255,57 @@ def main():
         tp.append(time.perf_counter())
         return info, np.diff(tp)
 
-    # ---- learned guess: train on solves of the method from untimed steps
-    learned = args.train_systems > 0
+    # ---- learned guess: trained on solves the method itself generates, on
+    # reduced-scale systems of the workload's kind (fresh seeds each)
     train_info = None
     wfile = os.path.join(tempfile.mkdtemp(), "guess.bin")
-    ctx = B.Context(params(B.PE_MIXED))
-    if learned:
-        ctx.pe_guess_init(1)
+    if n_train > 0:
+        gen = inputs.training_system if args.workload == "cfg4" else inputs.training_spheres
+        probe = gen(inputs.SEED_BASE + 100000)
+        tctx = B.Context(params(B.PE_MIXED, box=probe.box, mesh=probe.mesh))
+        tctx.pe_guess_init(1)
+        tq = torch.empty(probe.n_bead, dtype=torch.float64, device="cuda")
+        tdp = torch.empty(probe.n_body, dtype=torch.float64, device="cuda")
         ta = time.perf_counter()
-        for t in range(args.train_systems):
-            ts = inputs.config(k, seed=inputs.SEED_BASE + 1000 + t)
-            ctx.load(ts)
-            ctx.pe_guess_set_types(ts.body_type)
-            st, _ = ctx.pe_solve_polarization(None, q, dpsi, S)
-            ctx.pe_guess_record(q)
+        t_cpu = 0.0
+        iters = []
+        for t in range(n_train):
+            tc0 = time.perf_counter()
+            ts = gen(inputs.SEED_BASE + 100000 + t)
+            t_cpu += time.perf_counter() - tc0
+            if ts.n_bead != tq.numel():
+                tq = torch.empty(ts.n_bead, dtype=torch.float64, device="cuda")
+            if ts.n_body != tdp.numel():
+                tdp = torch.empty(ts.n_body, dtype=torch.float64, device="cuda")
+            tctx.load(ts)
+            tctx.pe_guess_set_types(ts.body_type)
+            st, inf = tctx.pe_solve_polarization(None, tq, tdp)
+            iters.append(inf.iters)
+            tctx.pe_guess_record(tq)
+            if (t + 1) % 100 == 0:
+                log(f"training solves: {t + 1}/{n_train}")
         tb = time.perf_counter()
-        loss0 = ctx.pe_guess_train(1, 4096, 1e-3, 1)
-        loss = ctx.pe_guess_train(args.epochs, 4096, 2e-3, 2)
+        loss0 = tctx.pe_guess_train(1, 4096, 1e-3, 1)
+        loss = tctx.pe_guess_train(args.epochs, 4096, 2e-3, 2)
         torch.cuda.synchronize()
         tc = time.perf_counter()
-        ctx.pe_guess_save(wfile)
-        train_info = {"solves": args.train_systems, "rows": args.train_systems * nb, "epochs": args.epochs + 1,
-                      "loss_first_epoch": loss0, "loss_last_epoch": loss, "generate_s": round(tb - ta, 2),
-                      "train_s": round(tc - tb, 2)}
+        tctx.pe_guess_save(wfile)
+        train_info = {"solves": n_train, "system": f"{probe.n_body} bodies, {probe.n_bead} beads, "
+                      f"{probe.n_ion} ions, mesh {probe.mesh[0]}^3 (fresh seeds)", "rows": n_train * probe.n_bead,
+                      "epochs": args.epochs + 1, "loss_first_epoch": loss0, "loss_last_epoch": loss,
+                      "generate_s": round(tb - ta, 2), "generate_cpu_s": round(t_cpu, 2),
+                      "train_s": round(tc - tb, 2), "iters_p50": float(np.median(iters))}
         log(f"learned guess: {train_info}")
-        ctx.close()
-        ctx = B.Context(params(B.PE_MIXED, learned=True))
+        tctx.close()
+
+    learned = n_train > 0
+    ctx = B.Context(params(B.PE_MIXED, learned=learned))
+    if learned:
         ctx.pe_guess_load(wfile)
-        ctx.load(system)
-        dev = ctx.sys_dev
-        ctx.pe_set_system(off, dev["bead_pos"], dev["bead_sigma"], dev["body_center"], dev["body_quat"],
-                          dev["body_charge"], dev["ion_pos"] if ni else None, dev["ion_charge"] if ni else None,
-                          dev["ion_sigma"] if ni else None, system.E0)
+    ctx.load(system)
+    dev = ctx.sys_dev
+    if learned:
         ctx.pe_guess_set_types(system.body_type)
-    else:
-        ctx.load(system)
-        dev = ctx.sys_dev
     d = ctx.pe_get_derived()
     for _ in range(args.warmup):
         step(ctx, dev)
@@ -270,16 +328,17 @@ def main():
     for _ in range(args.profile_steps):
         step(ctx, dev)
     torch.cuda.synchronize()
-    per_class = classes_of(ctx.pe_profile_read())
+    per_class = {kk: v for kk, v in classes_of(ctx.pe_profile_read()).items() if kk[0] not in NOT_KERNEL_CLASSES}
     ctx.pe_profile_enable(False)
     ranked = sorted(per_class, key=lambda kk: -per_class[kk][1])
     modeled = [kk for kk in ranked
                if kernel_model(kk[0], kk[1], per_class[kk][0], per_class[kk][2], nb, G, Gc) is not None]
     dominant = modeled[0] if modeled else None
 
-    # timed steps: events only around the dominant class's launches, so its
-    # roofline is measured live while the rest runs undisturbed
-    ctx.pe_profile_select([dominant[0]] if dominant else [])
+    # timed steps: events only around the dominant class's launches and
+    # around every Krylov product, so the product rate and the dominant
+    # class's roofline are measured live while the rest runs undisturbed
+    ctx.pe_profile_select(([dominant[0]] if dominant else []) + ["matvec"])
     ctx.pe_profile_enable(True)
     infos, phases = [], []
     torch.cuda.synchronize()
@@ -293,50 +352,90 @@ def main():
     timed_class = classes_of(ctx.pe_profile_read())
     ctx.pe_profile_enable(False)
     ctx.pe_profile_select(None)
-    solve_ms = [1e3 * i.t_total for i in infos]
-    ph = 1e3 * np.median(np.array(phases), axis=0)
-    log(f"timed {args.steps} steps: {elapsed:.3f} s; solve p50 {np.median(solve_ms):.2f} ms, iters "
-        f"{[i.iters for i in infos]}, guess residual {infos[-1].rel_residual_guess:.3f}")
+    mv_cnt, mv_ms, _ = timed_class.get(("matvec", False), (0, 0.0, 0.0))
+    mv64_cnt, mv64_ms, _ = timed_class.get(("matvec", True), (0, 0.0, 0.0))
+    live_matvec_ms = mv_ms / mv_cnt if mv_cnt else float("nan")
+    value = nb / (live_matvec_ms * 1e-3) / 1e6
+    log(f"timed {args.steps} steps: {elapsed:.3f} s; {mv_cnt} float products, {live_matvec_ms * 1e3:.1f} us each "
+        f"({value:.1f} Mbeads/s); iters {[i.iters for i in infos]}")
 
-    # bead-only PME matvec throughput (the Krylov operator), both precisions, on the current configuration
-    ctx.pe_set_system(off, dev["bead_pos"], dev["bead_sigma"], dev["body_center"], dev["body_quat"],
-                      dev["body_charge"], dev["ion_pos"] if ni else None, dev["ion_charge"] if ni else None,
-                      dev["ion_sigma"] if ni else None, system.E0)
+    # solve-time distribution over at least `solves` solves (the timed steps
+    # and further untimed steps of the same run)
+    solve_ms = [1e3 * i.t_total for i in infos]
+    iters_all = [int(i.iters) for i in infos]
+    while len(solve_ms) < args.solves:
+        info, ph = step(ctx, dev)
+        solve_ms.append(1e3 * info.t_total)
+        iters_all.append(int(info.iters))
+        phases.append(ph)
+    ph = 1e3 * np.median(np.array(phases), axis=0)
+
+    # audit: the residual of a measured solve against the double system
+    # (the right-hand side and the operator both in double)
+    set_system(ctx, system, dev)
+    ctx.pe_solve_polarization(None, q, dpsi, S)
+    audit = fp64_residual(B, torch, system, dev, q, dpsi, params(B.PE_FP64))
+    log(f"residual of the mixed solve against the double system: {audit:.3e}")
+
+    # the products in isolation, on the current configuration: the bead-only
+    # Krylov operator and the all-particle potential with the field (the
+    # force pass's operator), both precisions
+    set_system(ctx, system, dev)
     x = torch.randn(nb + nbody, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
+    na = nb + ni
+    chg = torch.randn(na, dtype=torch.float64, device="cuda")
+    psi = torch.empty(na, dtype=torch.float64, device="cuda")
+    Ef = torch.empty((na, 3), dtype=torch.float64, device="cuda")
     matvec = {}
     for name, prec in (("fp32", B.PE_MIXED), ("fp64", B.PE_FP64)):
-        for _ in range(3):
-            ctx.pe_apply_saddle(x, y, prec)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(args.matvec_reps):
-            ctx.pe_apply_saddle(x, y, prec)
-        torch.cuda.synchronize()
-        tm = (time.perf_counter() - ta) / args.matvec_reps
-        matvec[name] = {"ms": round(1e3 * tm, 4), "mbeads_s": round(nb / tm / 1e6, 2)}
+        for label, fn, count in (("bead_only", lambda: ctx.pe_apply_saddle(x, y, prec), nb),
+                                 ("all_particles_with_field",
+                                  lambda: ctx.pe_apply_potential(chg, psi, Ef, prec), na)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(args.matvec_reps):
+                fn()
+            torch.cuda.synchronize()
+            tm = (time.perf_counter() - ta) / args.matvec_reps
+            matvec[f"{label}_{name}"] = {"ms": round(1e3 * tm, 4), "particles": count,
+                                         "mbeads_s": round(count / tm / 1e6, 2)}
 
-    # comparison arms on the same configuration, zero initial guess: the method as stated (double,
-    # unpreconditioned GMRES), double with the block preconditioner, and mixed precision with the
-    # preconditioner but without the learned guess
-    fp64 = None
-    if not args.no_fp64_arm:
+    # comparison arms on the same configuration, same residual target
+    # (1e-6, double operator): the method as stated (plain FP64:
+    # unpreconditioned double GMRES, zero start), FP64 with the block
+    # preconditioner, mixed with the preconditioner from a zero start, and
+    # the measured configuration (mixed, preconditioner, learned start)
+    arms = None
+    if not args.no_arms:
         arms = {}
-        for name, prec, pre in (("plain_fp64", B.PE_FP64, 0), ("fp64_precond", B.PE_FP64, 1),
-                                ("mixed_precond_zero_guess", B.PE_MIXED, 1)):
-            p = params(prec, precond=pre)
+        arm_list = [("plain_fp64", B.PE_FP64, 0, False, False), ("fp64_precond", B.PE_FP64, 1, False, False),
+                    ("mixed_precond_zero_guess", B.PE_MIXED, 1, False, False)]
+        if learned:
+            arm_list.append(("mixed_precond_learned", B.PE_MIXED, 1, True, False))
+            arm_list.append(("mixed_precond_learned_rhs_fp64", B.PE_MIXED, 1, True, True))
+        for name, prec, pre, lg, r64 in arm_list:
+            p = params(prec, precond=pre, learned=lg, rhs64=r64)
             p.max_iters = 4000
-            c64 = B.Context(p)
-            c64.sys_dev = dev
-            ms, its = [], []
-            for _ in range(args.fp64_solves):
-                info, _ = step(c64, dev, move=False)
+            c2 = B.Context(p)
+            if lg:
+                c2.pe_guess_load(wfile)
+                set_system(c2, system, dev)
+                c2.pe_guess_set_types(system.body_type)
+            ms, its, res = [], [], []
+            nsolve = 2 if name == "plain_fp64" else args.arm_solves
+            for _ in range(nsolve):
+                info, _ = step(c2, dev, move=False, forces=False)
                 ms.append(1e3 * info.t_total)
-                its.append(info.iters)
-            arms[name] = {"solve_ms_p50": round(float(np.median(ms)), 3), "iters": its,
-                          "rel_residual": float(info.rel_residual)}
-            c64.close()
-        fp64 = arms
+                its.append(int(info.iters))
+                res.append(float(info.rel_residual))
+            arms[name] = {"solves": nsolve, "solve_ms_p50": pct(ms, 50), "solve_ms_p99": pct(ms, 99),
+                          "iters": sorted(set(its)), "rel_residual_max": max(res),
+                          "rel_residual_guess": float(info.rel_residual_guess)}
+            c2.close()
+            log(f"arm {name}: {arms[name]}")
 
     # roofline of the dominant kernel class: live HIP-event timing of its
     # launches in the timed region; the other classes from the profiled steps
@@ -369,16 +468,27 @@ def main():
                                                    "avg_us": round(1e3 * m / c, 2), "work": w}
                  for (n, db), (c, m, w) in sorted(per_class.items(), key=lambda kv: -kv[1][1])}
 
+    extra = {}
+    if args.workload == "cfg3":
+        extra["precision_table"] = precision_table(B, system, params, set_system, dev, q, dpsi, S, F, L, U, fi)
+    if args.workload == "cfg4" and learned:
+        extra["guess_ablation_held_out"] = guess_ablation(B, inputs, k, params, set_system, wfile, args)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         cpu = cpu_baseline(system)
+        if arms:
+            its = arms["plain_fp64"]["iters"][-1]
+            cpu["solve_s_extrapolated"] = cpu["product_s_extrapolated"] * its
+            cpu["solve_note"] = (f"plain FP64 method: {its} GMRES iterations (as on the GPU) x the "
+                                 "extrapolated oracle product; labelled extrapolated")
 
     ms_per_step = 1e3 * elapsed / args.steps
-    value = nb * args.steps / elapsed / 1e6
+    best = float(np.median(solve_ms))
     out = {
         "metric": METRIC,
-        "value": round(value, 4),
+        "value": round(value, 2),
         "unit": "Mbeads/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -393,35 +503,169 @@ def main():
                    "n_bead": nb, "n_body": nbody, "n_ion": ni, "mesh": list(system.mesh), "P": 8,
                    "xi": round(d["xi"], 5), "r_cut": round(d["r_cut"], 5), "eta": round(d["eta"], 5),
                    "bead_pairs_stored": d["nnz"], "rel_tol": 1e-6, "learned_guess": learned,
-                   "precond": "block-Jacobi", "parallelism": "single GPU"},
+                   "precond": "block-Jacobi", "rhs": "float kernels, residual audited against the double system",
+                   "parallelism": "single GPU"},
+        "value_is": ("bead-only spectral-Ewald Krylov product, float kernels: beads / mean live duration of the "
+                     "products the timed steps' solves applied (HIP events around each product)"),
+        "live_matvec_us": round(1e3 * live_matvec_ms, 2),
+        "live_matvecs": int(mv_cnt),
+        "live_matvec_fp64_us": round(1e3 * mv64_ms / mv64_cnt, 2) if mv64_cnt else None,
+        "whole_path_mbeads_s": round(nb * args.steps / elapsed / 1e6, 3),
+        "steps_per_s": round(args.steps / elapsed, 3),
         "step_phases_ms_p50": {"set_system": round(ph[0], 3), "solve": round(ph[1], 3), "forces": round(ph[2], 3),
                                "bd_update": round(ph[3], 3)},
-        "steps_per_s": round(args.steps / elapsed, 3),
-        "solve_ms_p50": round(float(np.median(solve_ms)), 3),
-        "solve_ms_p99": round(float(np.percentile(solve_ms, 99)), 3),
-        "iters": [int(i.iters) for i in infos],
+        "solves": len(solve_ms),
+        "solve_ms_p50": pct(solve_ms, 50),
+        "solve_ms_p99": pct(solve_ms, 99),
+        "iters": sorted(set(iters_all)),
         "outer_refinements": int(infos[-1].outer_refinements),
         "matvecs_fp32": int(infos[-1].matvecs_fp32),
         "matvecs_fp64": int(infos[-1].matvecs_fp64),
         "rel_residual": float(infos[-1].rel_residual),
+        "rel_residual_double_system": audit,
         "rel_residual_guess": float(infos[-1].rel_residual_guess),
         "learned_guess_training": train_info,
         "matvec": matvec,
-        "fp64_arms": fp64,
-        "speedup_solve_vs_plain_fp64": (round(fp64["plain_fp64"]["solve_ms_p50"] / float(np.median(solve_ms)), 2)
-                                        if fp64 else None),
+        "arms": arms,
+        "solve_speedup": ({"vs_plain_fp64": round(arms["plain_fp64"]["solve_ms_p50"] / best, 2),
+                           "vs_fp64_precond": round(arms["fp64_precond"]["solve_ms_p50"] / best, 3),
+                           "vs_mixed_zero_guess": round(arms["mixed_precond_zero_guess"]["solve_ms_p50"] / best, 3)}
+                          if arms else None),
         "roofline": roof,
         "roofline_by_class": roofs[1:6],
         "kernels": breakdown,
         "kernels_from": f"{args.profile_steps} profiled steps after the warmup (events around every class)",
         "cpu_baseline": cpu,
     }
+    out.update(extra)
     ctx.close()
     print(json.dumps(out), flush=True)
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+def fp64_residual(B, torch, system, dev, q, dpsi, p64):
+    """||b - A x|| / ||b|| of x = [q; dpsi] for the system of `dev` with the
+    right-hand side b = [-r.E0 + M_bead,ion q_ion; Q] and the saddle operator
+    A both from the double kernels (through the public entry points)."""
+    c = B.Context(p64)
+    n_ion = system.n_ion
+    c.pe_set_system(system.body_offsets, dev["bead_pos"], dev["bead_sigma"], dev["body_center"], dev["body_quat"],
+                    dev["body_charge"], dev["ion_pos"] if n_ion else None, dev["ion_charge"] if n_ion else None,
+                    dev["ion_sigma"] if n_ion else None, system.E0)
+    nb = system.n_bead
+    chg = torch.zeros(nb + n_ion, dtype=torch.float64, device="cuda")
+    if n_ion:
+        chg[nb:] = dev["ion_charge"]
+    psi, _ = c.apply(chg, field=False, precision=B.PE_FP64)
+    bi = torch.as_tensor(np.repeat(np.arange(system.n_body), np.diff(system.body_offsets)), device="cuda")
+    rel = dev["bead_pos"] - dev["body_center"][bi]
+    E0 = torch.as_tensor(np.asarray(system.E0, dtype=np.float64), device="cuda")
+    b = torch.cat([-(rel @ E0) + psi[:nb], dev["body_charge"]])
+    x = torch.cat([q, dpsi])
+    y = torch.empty_like(x)
+    c.pe_apply_saddle(x, y, B.PE_FP64)
+    out = float(torch.linalg.norm(b - y) / torch.linalg.norm(b))
+    c.close()
+    return out
+
+
+def precision_table(B, system, params, set_system, dev, q, dpsi, S, F, L, U, fi):
+    """FP64 at residual 1e-12 (the reference), mixed at 1e-6 and FP64 at 1e-6
+    on the same configuration: per-body dipole, force and torque deviations
+    and the total-energy deviation, against the FP32 bounds (dipoles 1e-5
+    relative, forces and torques 1e-4 of their RMS over bodies, energy 1e-6
+    relative) and the calibration rule (the mixed deviation at most ten times
+    that of FP64 at the same residual, or inside the bound)."""
+    import torch
+    runs = {}
+    for name, prec, rt in (("fp64_1e-12", B.PE_FP64, 1e-12), ("mixed_1e-6", B.PE_MIXED, 1e-6),
+                           ("fp64_1e-6", B.PE_FP64, 1e-6)):
+        p = params(prec, rel_tol=rt)
+        p.max_iters = 4000
+        c = B.Context(p)
+        set_system(c, system, dev)
+        st, info = c.pe_solve_polarization(None, q, dpsi, S)
+        tot = c.pe_forces_torques(F, L, U, fi if system.n_ion else None, None)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(5):
+            set_system(c, system, dev)
+            c.pe_solve_polarization(None, q, dpsi, S)
+        torch.cuda.synchronize()
+        runs[name] = dict(q=q.cpu().numpy().copy(), S=S.cpu().numpy().copy(), F=F.cpu().numpy().copy(),
+                          L=L.cpu().numpy().copy(), U=tot, iters=int(info.iters),
+                          rel_residual=float(info.rel_residual),
+                          set_and_solve_ms=round(1e3 * (time.perf_counter() - ta) / 5, 3))
+        c.close()
+    ref = runs["fp64_1e-12"]
+    rmsF = float(np.sqrt((ref["F"] ** 2).sum(1).mean()))
+    rmsL = float(np.sqrt((ref["L"] ** 2).sum(1).mean()))
+    out = {"reference": "FP64 solve at residual 1e-12, same discretization",
+           "bounds": {"q": 1e-5, "dipole_rel": 1e-5, "force_rel_rms": 1e-4, "torque_rel_rms": 1e-4,
+                      "energy_rel": 1e-6}}
+    for name in ("mixed_1e-6", "fp64_1e-6"):
+        r = runs[name]
+        dS = np.linalg.norm(r["S"] - ref["S"], axis=1) / np.linalg.norm(ref["S"], axis=1)
+        dF = np.linalg.norm(r["F"] - ref["F"], axis=1) / rmsF
+        dL = np.linalg.norm(r["L"] - ref["L"], axis=1) / rmsL
+        out[name] = {"iters": r["iters"], "rel_residual": r["rel_residual"], "set_and_solve_ms": r["set_and_solve_ms"],
+                     "q_rel": float(np.linalg.norm(r["q"] - ref["q"]) / np.linalg.norm(ref["q"])),
+                     "dipole_rel_per_body": [float(v) for v in dS],
+                     "force_rel_rms_per_body": [float(v) for v in dF],
+                     "torque_rel_rms_per_body": [float(v) for v in dL],
+                     "dipole_rel_max": float(dS.max()), "force_rel_rms_max": float(dF.max()),
+                     "torque_rel_rms_max": float(dL.max()),
+                     "energy_rel": float(abs(r["U"] - ref["U"]) / abs(ref["U"]))}
+    m, f = out["mixed_1e-6"], out["fp64_1e-6"]
+    checks = {}
+    for key, b in (("dipole_rel_max", 1e-5), ("force_rel_rms_max", 1e-4), ("torque_rel_rms_max", 1e-4),
+                   ("energy_rel", 1e-6)):
+        checks[key] = {"mixed": m[key], "fp64_same_residual": f[key], "bound": b,
+                       "within_bound": m[key] <= b, "within_10x_fp64": m[key] <= 10 * f[key]}
+    out["checks"] = checks
+    out["reference_iters"] = ref["iters"]
+    return out
+
+
+def guess_ablation(B, inputs, k, params, set_system, wfile, args, n_held_out=3, reps=5):
+    """Zero start vs learned start (mixed precision, the same block
+    preconditioner, residual 1e-6) on full-size held-out systems of the
+    workload (seeds never used for training)."""
+    import torch
+    rows = []
+    for h in range(n_held_out):
+        s = inputs.config(k, seed=inputs.SEED_BASE + 900000 + h)
+        dev = {kk: torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64), device="cuda")
+               for kk, v in dict(bead_pos=s.bead_pos, bead_sigma=s.bead_sigma, body_center=s.body_center,
+                                 body_quat=s.body_quat, body_charge=s.body_charge, ion_pos=s.ion_pos,
+                                 ion_charge=s.ion_charge, ion_sigma=s.ion_sigma).items()}
+        qq = torch.empty(s.n_bead, dtype=torch.float64, device="cuda")
+        dp = torch.empty(s.n_body, dtype=torch.float64, device="cuda")
+        row = {"seed_offset": 900000 + h, "n_bead": s.n_bead}
+        for name, lg in (("zero_guess", False), ("learned_guess", True)):
+            p = params(B.PE_MIXED, learned=lg, box=s.box, mesh=s.mesh)
+            c = B.Context(p)
+            if lg:
+                c.pe_guess_load(wfile)
+            set_system(c, s, dev)
+            if lg:
+                c.pe_guess_set_types(s.body_type)
+            ms = []
+            for _ in range(reps):
+                set_system(c, s, dev)
+                st, info = c.pe_solve_polarization(None, qq, dp)
+                ms.append(1e3 * info.t_total)
+            row[name] = {"iters": int(info.iters), "solve_ms_p50": pct(ms, 50),
+                         "rel_residual": float(info.rel_residual),
+                         "rel_residual_start": float(info.rel_residual_guess),
+                         "matvecs_fp32": int(info.matvecs_fp32), "matvecs_fp64": int(info.matvecs_fp64)}
+            c.close()
+        rows.append(row)
+        log(f"held-out {h}: {row}")
+    return {"systems": rows,
+            "iters_zero": [r["zero_guess"]["iters"] for r in rows],
+            "iters_learned": [r["learned_guess"]["iters"] for r in rows],
+            "solve_ms_zero": [r["zero_guess"]["solve_ms_p50"] for r in rows],
+            "solve_ms_learned": [r["learned_guess"]["solve_ms_p50"] for r in rows]}
 
 
 if __name__ == "__main__":

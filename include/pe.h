@@ -30,8 +30,11 @@
  * - Work is enqueued on the HIP stream given to pe_create.  Entry points that
  *   return host data (solve, forces, apply) synchronize that stream before
  *   returning; pe_set_system synchronizes once (to size the neighbour data).
- * - The library allocates its own device workspace with hipMalloc, grows it
- *   on demand and frees it in pe_destroy.
+ * - The library never allocates device memory.  All of a context's device
+ *   buffers lie in one region the caller owns and registers with
+ *   pe_set_workspace (pe_workspace_size says how large); a call that needs
+ *   more returns PE_ERR_NOMEM and can be repeated with the same arguments
+ *   after a larger region is registered.
  * - A context is not thread safe; use one context per host thread.
  */
 #ifndef PE_H
@@ -65,7 +68,15 @@ typedef enum {
 
 typedef enum {
   PE_REG_GAUSSIAN = 0, /* Gaussian charges of per-particle standard deviation sigma */
-  PE_REG_SHELL = 1     /* uniformly charged shells of one radius (the paper's own) */
+  PE_REG_SHELL = 1,    /* uniformly charged shells of one radius (the paper's own), with the
+                          whole regularization in the real-space kernel and the wave space
+                          of point charges */
+  PE_REG_SHELL_PAPER = 2 /* the same shells with the paper's own split (section
+                          "Spectrally-accurate Ewald summation"): j0^2(ka) multiplies the
+                          Green's function of the wave space, the real-space kernel is the
+                          closed form of section "Real-space sum" (its Heaviside term read
+                          as -(1/(4 pi r) - (4a - r)/(16 pi a^2)) H(2a - r)) with the printed
+                          self term; the same potential tensor M */
 } pe_reg;
 
 /*
@@ -78,8 +89,10 @@ typedef enum {
  * Derived when xi <= 0 / r_cut <= 0 (tolerance tau = split_tol):
  *   k_c = pi min_d (mesh[d]-1)/box[d]  (the paper's N_g = 1 + L k_c / pi),
  *   xi = k_c / (2 sqrt(ln 1/tau)),
- *   r_cut = sqrt(ln 1/tau) * max(1/xi, 2 sigma_max) for Gaussians, or
- *           max(sqrt(ln 1/tau)/xi, 2 a) for shells.
+ *   r_cut = sqrt(ln 1/tau) * max(1/xi, 2 sigma_max) for Gaussians,
+ *           max(sqrt(ln 1/tau)/xi, 2 a) for shells, and
+ *           2 a + sqrt(ln 1/tau)/xi for shells with the paper's split (its
+ *           real-space kernel decays like erfc(xi (r - 2a))).
  */
 typedef struct pe_params {
   double box[3];          /* periodic box lengths */
@@ -101,6 +114,13 @@ typedef struct pe_params {
   int32_t use_learned_guess; /* 1: start from the network's prediction (needs a loaded model) */
   int32_t precond;        /* 1 (default): block-Jacobi preconditioner (inverse of each body's
                              free-space saddle block) inside flexible GMRES; 0: none */
+  int32_t rhs_fp64;       /* PE_MIXED: 1 (default) forms the ion potential of the right-hand
+                             side in double, so the double residual is that of the system the
+                             PE_FP64 path solves; 0 forms it with the float kernels */
+  double hs_radius;       /* pe_bd_step: hard-sphere radius a of every particle (ions and beads;
+                             beads of one body never interact), section "Brownian dynamics":
+                             the potential-free pair potential gamma/(4 dt) (r - 2a)^2 for
+                             r < 2a.  0 (default): none.  2a must not exceed a third of the box */
 } pe_params;
 
 typedef struct pe_solve_info {
@@ -124,6 +144,35 @@ pe_status pe_default_params(pe_params* p);
 pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out);
 pe_status pe_destroy(pe_context* ctx);
 const char* pe_last_error(const pe_context* ctx);
+
+/*
+ * Device workspace (the library's only device memory, owned by the caller).
+ *
+ * pe_workspace_size  bytes (host size_t) a system of n_bead beads, n_body
+ *                    bodies and n_ion ions needs: every buffer at its size
+ *                    for these counts, the data-dependent ones (stored bead
+ *                    pairs, spreading lists, body-shape blocks, one recorded
+ *                    training solve) estimated from the mean densities; after
+ *                    a call failed with PE_ERR_NOMEM it returns at least what
+ *                    that call needed.  PE_ERR_ARG for a null pointer or a
+ *                    negative count.
+ * pe_set_workspace   registers [dev_ptr, dev_ptr + bytes) (device memory,
+ *                    256-byte aligned, e.g. a torch uint8 tensor) as the
+ *                    region.  Buffers already live (tables, the last
+ *                    system, shapes, the network) are copied into it, so the
+ *                    previous region may be released once this returns; it
+ *                    must not overlap the new one unless it is the same base
+ *                    address.  Waits for the context's streams first.
+ *                    PE_ERR_NOMEM if the live buffers do not fit.  The caller
+ *                    keeps the region alive and unused by others until
+ *                    pe_destroy or the next pe_set_workspace.
+ * pe_workspace_info  out[0] registered bytes, out[1] bytes in live buffers,
+ *                    out[2] the most ever live, out[3] the size the last
+ *                    failed request needed (0 if none failed).
+ */
+pe_status pe_workspace_size(const pe_context* ctx, int64_t n_bead, int64_t n_body, int64_t n_ion, size_t* bytes);
+pe_status pe_set_workspace(pe_context* ctx, void* dev_ptr, size_t bytes);
+pe_status pe_workspace_info(const pe_context* ctx, size_t out[4]);
 
 /* The split parameters in use (valid after pe_set_system):
  * out[0]=xi, out[1]=r_cut, out[2]=eta, out[3]=h (largest spacing),
@@ -172,10 +221,14 @@ pe_status pe_apply_potential(pe_context* ctx, const double* charges, double* psi
  *   [ -M     Sigma^T ] [ q    ]   [ -r.E0 + M_bead,ion q_ion ]
  *   [ Sigma  0       ] [ dPsi ] = [  Q                       ]
  * for the bead charges q and dPsi = Psi - Psi_0 (ions are eliminated into the
- * right-hand side).  Unpreconditioned restarted GMRES with classical
- * Gram-Schmidt applied twice, Givens rotations and back substitution in
- * double on the device; with PE_MIXED the inner solves use the float operator
- * inside a double iterative refinement.
+ * right-hand side).  Restarted flexible GMRES with classical Gram-Schmidt
+ * applied twice, Givens rotations and back substitution in double on the
+ * device, preconditioned (precond = 1, the default) by the block-Jacobi
+ * inverse of each body's free-space saddle block, or unpreconditioned
+ * (precond = 0).  With PE_MIXED the inner solves use the float operator
+ * inside a double iterative refinement whose residuals b - A x are formed
+ * with the double operator (and, with rhs_fp64, a double b); convergence is
+ * only ever declared on such a double residual, also for a warm start.
  *   q_init   dev n_bead or NULL (zero guess, or the network's when enabled)
  *   q_out    dev n_bead;  dpsi_out dev n_body;  dipole_out dev n_body x 3 or NULL
  *            (S_i = sum_j r_ij q_ij, eq. "rigid_dipole")
@@ -198,6 +251,29 @@ pe_status pe_solve_polarization(pe_context* ctx, const double* q_init, double* q
 pe_status pe_forces_torques(pe_context* ctx, double* body_force, double* body_torque,
                             double* body_energy, double* ion_force, double* bead_force,
                             double* total_energy);
+
+/*
+ * Grand capacitance tensor and effective permittivity of the loaded
+ * configuration (section "Induced Surface Charge Distribution of Polarizable
+ * Bodies", the rigid-body moment equation [Q; S] = C [Psi - Psi_0; E0] with
+ * C = Sigma' M^-1 Sigma'^T; section "Cubic array of spheres in an electric
+ * field" for the permittivity).  Ions do not enter (M is the bead-bead
+ * potential tensor).  Rows and columns: body i's charge is index i, its
+ * dipole components d = x, y, z are n_body + 3 i + d.
+ *   C_out    dev (4 n_body) x (4 n_body), row-major, or NULL
+ *   eps_eff  host 3 x 3, row-major, or NULL: for neutral bodies in the mean
+ *            field, eps I + (1/V) sum_ij [C_SE - C_SPsi C_qPsi^-1 C_qE]_ij
+ *   info     host or NULL: iters = most conjugate-gradient iterations of any
+ *            column, matvecs_fp64 = operator applications, rel_residual =
+ *            largest final ||b - M x|| / ||b|| over the columns
+ * The 4 n_body systems M x = (column of Sigma'^T) are solved with the double
+ * operator whatever the context precision, by conjugate gradients (block
+ * Jacobi over the bodies' free-space self blocks when precond = 1) to
+ * rel_tol, blocks of up to 32 columns sharing each step's launches.
+ * PE_ERR_STATE before pe_set_system; PE_ERR_ARG without bodies;
+ * PE_ERR_NOT_CONVERGED if a column misses rel_tol within max_iters.
+ */
+pe_status pe_grand_capacitance(pe_context* ctx, double* C_out, double* eps_eff, pe_solve_info* info);
 
 /*
  * The saddle-point operator itself (the matrix of eq. "saddle", ions
@@ -234,6 +310,9 @@ typedef enum {
   PE_PROF_KRYLOV,
   PE_PROF_PRECOND,
   PE_PROF_NEAR,
+  PE_PROF_MATVEC,   /* one whole Krylov operator application (pe_apply_saddle and every
+                       product inside a solve), around all of its kernels; work = beads.
+                       It encloses launches of the other classes, so it is not a kernel class */
   PE_PROF_NCLASS
 } pe_prof_class;
 pe_status pe_profile_enable(pe_context* ctx, int32_t on);
@@ -297,7 +376,9 @@ pe_status pe_guess_add_rows(pe_context* ctx, const float* rows, int64_t n_rows);
  * ions x += f dt / gamma + sqrt(2 kT dt / gamma) N(0,1);
  * bodies move rigidly: U_i = F_i / (N_i gamma) + Brownian term,
  * Omega_i = K_i^{-1} L_i + Brownian term, K_i = gamma sum_j (|r|^2 I - r r^T),
- * beads follow x_ij = X_i + R_i r'_ij.  Gaussian noise comes from a
+ * beads follow x_ij = X_i + R_i r'_ij.  With hs_radius > 0 the forces of the
+ * potential-free hard-sphere pair potential at the current positions are
+ * added first (bead parts into each body's force and torque).  Gaussian noise comes from a
  * counter-based Philox-4x32-10 generator keyed by (seed, step, particle).
  * Updates the caller's arrays in place (same layouts as pe_set_system):
  *   bead_pos dev n_bead x 3 (rebuilt from the body frame), body_center,

@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libpe.so")
 
 PE_OK, PE_ERR_ARG, PE_ERR_STATE, PE_ERR_DEVICE, PE_ERR_NOMEM, PE_ERR_NOT_CONVERGED, PE_ERR_NUMERIC = range(7)
 PE_FP64, PE_MIXED = 0, 1
-PE_REG_GAUSSIAN, PE_REG_SHELL = 0, 1
+PE_REG_GAUSSIAN, PE_REG_SHELL, PE_REG_SHELL_PAPER = 0, 1, 2
 PROF_CLASSES = ["spread", "fft_z_r2c", "fft_y_fwd", "fft_x_scale", "fft_y_inv", "fft_z_c2r", "gather",
-                "spmv", "pair", "krylov", "precond", "near"]
+                "spmv", "pair", "krylov", "precond", "near", "matvec"]
 STATUS_NAMES = {0: "PE_OK", 1: "PE_ERR_ARG", 2: "PE_ERR_STATE", 3: "PE_ERR_DEVICE", 4: "PE_ERR_NOMEM",
                 5: "PE_ERR_NOT_CONVERGED", 6: "PE_ERR_NUMERIC"}
 
@@ -44,6 +44,8 @@ class pe_params(ctypes.Structure):
         ("max_refine", ctypes.c_int32),
         ("use_learned_guess", ctypes.c_int32),
         ("precond", ctypes.c_int32),
+        ("rhs_fp64", ctypes.c_int32),
+        ("hs_radius", ctypes.c_double),
     ]
 
 
@@ -109,6 +111,10 @@ SIGNATURES = {
     "pe_guess_debug": [_vp, _vp, _i32, _i64, _vp, ctypes.POINTER(_dbl)],
     "pe_guess_rows": [_vp, _vp, _i64],
     "pe_guess_add_rows": [_vp, _vp, _i64],
+    "pe_grand_capacitance": [_vp, _vp, ctypes.POINTER(_dbl), ctypes.POINTER(pe_solve_info)],
+    "pe_workspace_size": [_vp, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+    "pe_set_workspace": [_vp, _vp, ctypes.c_size_t],
+    "pe_workspace_info": [_vp, ctypes.POINTER(ctypes.c_size_t)],
 }
 
 
@@ -188,11 +194,53 @@ class Context:
         _check(_lib.pe_create(ctypes.byref(params), _stream_handle(self.stream), ctypes.byref(h)))
         self.h = h
         self.n_body = self.n_bead = self.n_ion = 0
+        self.workspace = None   # the context's device memory: a torch uint8 tensor
 
     def close(self):
         if getattr(self, "h", None):
             _lib.pe_destroy(self.h)
             self.h = None
+        self.workspace = None
+
+    # ---- device workspace (torch owns the memory; the library carves it)
+    def pe_workspace_size(self, n_bead, n_body, n_ion):
+        out = ctypes.c_size_t()
+        self._chk(_lib.pe_workspace_size(self.h, int(n_bead), int(n_body), int(n_ion), ctypes.byref(out)))
+        return out.value
+
+    def pe_set_workspace(self, tensor):
+        self._chk(_lib.pe_set_workspace(self.h, ctypes.c_void_p(tensor.data_ptr()), tensor.numel()))
+        self.workspace = tensor
+
+    def pe_workspace_info(self):
+        out = (ctypes.c_size_t * 4)()
+        self._chk(_lib.pe_workspace_info(self.h, out))
+        return dict(size=out[0], in_use=out[1], peak=out[2], need=out[3])
+
+    def reserve(self, n_bead=None, n_body=None, n_ion=None, grow=1.0):
+        """Registers a workspace of at least pe_workspace_size bytes (a new
+        torch tensor when the current one is smaller; live buffers move)."""
+        t = self.torch
+        need = self.pe_workspace_size(self.n_bead if n_bead is None else n_bead,
+                                      self.n_body if n_body is None else n_body,
+                                      self.n_ion if n_ion is None else n_ion)
+        have = 0 if self.workspace is None else self.workspace.numel()
+        if need <= have and grow <= 1.0:
+            return
+        size = max(need, int(have * grow))
+        size = (size + (1 << 20) - 1) >> 20 << 20
+        self.pe_set_workspace(t.empty(size, dtype=t.uint8, device="cuda"))
+
+    def _run(self, name, *args):
+        """Calls an entry point; on PE_ERR_NOMEM registers a larger workspace
+        and calls again (the entry points are repeatable)."""
+        fn = getattr(_lib, name)
+        for _ in range(8):
+            st = fn(self.h, *args)
+            if st != PE_ERR_NOMEM:
+                return st
+            self.reserve(grow=1.5)
+        return st
 
     def __del__(self):
         try:
@@ -216,20 +264,21 @@ class Context:
         n_ion = 0 if ion_charge is None else int(ion_charge.numel())
         e0 = (ctypes.c_double * 3)(*[float(v) for v in np.asarray(E0, dtype=np.float64)])
         self._keep = (bead_pos, bead_sigma, body_center, body_quat, body_charge, ion_pos, ion_charge, ion_sigma)
-        self._chk(_lib.pe_set_system(
-            self.h, n_body, off.ctypes.data_as(ctypes.POINTER(_i64)), _ptr(bead_pos), _ptr(bead_sigma),
+        self.reserve(int(off[-1]), n_body, n_ion)
+        self._chk(self._run(
+            "pe_set_system", n_body, off.ctypes.data_as(ctypes.POINTER(_i64)), _ptr(bead_pos), _ptr(bead_sigma),
             _ptr(body_center), _ptr(body_quat), _ptr(body_charge), n_ion, _ptr(ion_pos), _ptr(ion_charge),
             _ptr(ion_sigma), e0))
         self.n_body, self.n_bead, self.n_ion = n_body, int(off[-1]), n_ion
 
     def pe_apply_potential(self, charges, psi_out, field_out=None, precision=PE_FP64):
-        self._chk(_lib.pe_apply_potential(self.h, _ptr(charges), _ptr(psi_out), _ptr(field_out), int(precision)))
+        self._chk(self._run("pe_apply_potential", _ptr(charges), _ptr(psi_out), _ptr(field_out), int(precision)))
 
     def pe_apply_saddle(self, x, y, precision=PE_FP64):
-        self._chk(_lib.pe_apply_saddle(self.h, _ptr(x), _ptr(y), int(precision)))
+        self._chk(self._run("pe_apply_saddle", _ptr(x), _ptr(y), int(precision)))
 
     def pe_profile_enable(self, on=True):
-        self._chk(_lib.pe_profile_enable(self.h, 1 if on else 0))
+        self._chk(self._run("pe_profile_enable", 1 if on else 0))
 
     def pe_profile_select(self, classes=None):
         """Record events only for the named classes (None: all)."""
@@ -248,8 +297,8 @@ class Context:
 
     def pe_solve_polarization(self, q_init, q_out, dpsi_out, dipole_out=None, check=True):
         info = pe_solve_info()
-        st = _lib.pe_solve_polarization(self.h, _ptr(q_init), _ptr(q_out), _ptr(dpsi_out), _ptr(dipole_out),
-                                        ctypes.byref(info))
+        st = self._run("pe_solve_polarization", _ptr(q_init), _ptr(q_out), _ptr(dpsi_out), _ptr(dipole_out),
+                       ctypes.byref(info))
         if check and st != PE_OK:
             self._chk(st)
         return st, info
@@ -257,36 +306,36 @@ class Context:
     def pe_forces_torques(self, body_force=None, body_torque=None, body_energy=None, ion_force=None,
                           bead_force=None):
         tot = ctypes.c_double()
-        self._chk(_lib.pe_forces_torques(self.h, _ptr(body_force), _ptr(body_torque), _ptr(body_energy),
+        self._chk(self._run("pe_forces_torques", _ptr(body_force), _ptr(body_torque), _ptr(body_energy),
                                          _ptr(ion_force), _ptr(bead_force), ctypes.byref(tot)))
         return tot.value
 
     def pe_guess_init(self, seed):
-        self._chk(_lib.pe_guess_init(self.h, int(seed)))
+        self._chk(self._run("pe_guess_init", int(seed)))
 
     def pe_guess_set_types(self, body_type):
         t = np.ascontiguousarray(np.asarray(body_type, dtype=np.int32))
-        self._chk(_lib.pe_guess_set_types(self.h, t.ctypes.data_as(ctypes.POINTER(_i32))))
+        self._chk(self._run("pe_guess_set_types", t.ctypes.data_as(ctypes.POINTER(_i32))))
 
     def pe_guess_record(self, q_solved):
-        self._chk(_lib.pe_guess_record(self.h, _ptr(q_solved)))
+        self._chk(self._run("pe_guess_record", _ptr(q_solved)))
 
     def pe_guess_clear(self):
-        self._chk(_lib.pe_guess_clear(self.h))
+        self._chk(self._run("pe_guess_clear"))
 
     def pe_guess_train(self, epochs, batch, lr, seed):
         loss = ctypes.c_double()
-        self._chk(_lib.pe_guess_train(self.h, int(epochs), int(batch), float(lr), int(seed), ctypes.byref(loss)))
+        self._chk(self._run("pe_guess_train", int(epochs), int(batch), float(lr), int(seed), ctypes.byref(loss)))
         return loss.value
 
     def pe_guess_predict(self, q_out):
-        self._chk(_lib.pe_guess_predict(self.h, _ptr(q_out)))
+        self._chk(self._run("pe_guess_predict", _ptr(q_out)))
 
     def pe_guess_save(self, path):
         self._chk(_lib.pe_guess_save(self.h, str(path).encode()))
 
     def pe_guess_load(self, path):
-        self._chk(_lib.pe_guess_load(self.h, str(path).encode()))
+        self._chk(self._run("pe_guess_load", str(path).encode()))
 
     def pe_guess_debug(self, params=None, n_rows=0):
         """(params, grad, loss): read (params None) or set the parameters; gradient over n_rows."""
@@ -294,22 +343,22 @@ class Context:
         p = np.zeros(NP, dtype=np.float32) if params is None else np.ascontiguousarray(params, dtype=np.float32)
         g = np.zeros(NP, dtype=np.float32)
         loss = ctypes.c_double()
-        self._chk(_lib.pe_guess_debug(self.h, p.ctypes.data_as(ctypes.c_void_p), 0 if params is None else 1,
+        self._chk(self._run("pe_guess_debug", p.ctypes.data_as(ctypes.c_void_p), 0 if params is None else 1,
                                       int(n_rows), g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
         return p, g, loss.value
 
     def pe_guess_rows(self, n_rows):
         out = np.zeros((int(n_rows), 11), dtype=np.float32)
-        self._chk(_lib.pe_guess_rows(self.h, out.ctypes.data_as(ctypes.c_void_p), int(n_rows)))
+        self._chk(self._run("pe_guess_rows", out.ctypes.data_as(ctypes.c_void_p), int(n_rows)))
         return out
 
     def pe_guess_add_rows(self, rows):
         r = np.ascontiguousarray(rows, dtype=np.float32)
         assert r.ndim == 2 and r.shape[1] == 11
-        self._chk(_lib.pe_guess_add_rows(self.h, r.ctypes.data_as(ctypes.c_void_p), int(r.shape[0])))
+        self._chk(self._run("pe_guess_add_rows", r.ctypes.data_as(ctypes.c_void_p), int(r.shape[0])))
 
     def pe_bd_step(self, dt, kT, gamma, seed, step, bead_pos, body_center, body_quat, ion_pos):
-        self._chk(_lib.pe_bd_step(self.h, float(dt), float(kT), float(gamma), int(seed), int(step),
+        self._chk(self._run("pe_bd_step", float(dt), float(kT), float(gamma), int(seed), int(step),
                                   _ptr(bead_pos), _ptr(body_center), _ptr(body_quat), _ptr(ion_pos)))
 
     # ---- conveniences on a synthetic System (inputs module)
@@ -343,6 +392,16 @@ class Context:
         fi, fb = z(self.n_ion, 3), z(self.n_bead, 3)
         tot = self.pe_forces_torques(F, L, U, fi if self.n_ion else None, fb)
         return dict(body_force=F, body_torque=L, body_energy=U, ion_force=fi, bead_force=fb, total_energy=tot)
+
+    def capacitance(self, want_C=True):
+        """(C (4 n_body)^2 device tensor or None, eps_eff 3x3 numpy, info dict)."""
+        t = self.torch
+        nc = 4 * self.n_body
+        C = t.empty((nc, nc), dtype=t.float64, device="cuda") if want_C else None
+        eps = (ctypes.c_double * 9)()
+        info = pe_solve_info()
+        self._chk(self._run("pe_grand_capacitance", _ptr(C), eps, ctypes.byref(info)))
+        return C, np.array(eps[:], dtype=np.float64).reshape(3, 3), info.as_dict()
 
     def apply(self, charges, field=False, precision=PE_FP64):
         t = self.torch

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PE_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "grid.hip", "fft.hip", "realspace.hip", "vector.hip", "shapes.hip", "precond.hip", "guess.hip",
-           "bd.hip"]
+           "bd.hip", "capacitance.hip"]
 
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

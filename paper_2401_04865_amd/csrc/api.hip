@@ -12,6 +12,110 @@
 #include "guess.hpp"
 #include "precond.hpp"
 
+namespace pe {
+
+thread_local Arena* tl_arena = nullptr;
+
+void* Arena::alloc(size_t bytes, void** owner) {
+  const size_t len = (std::max<size_t>(bytes, 1) + kAlign - 1) / kAlign * kAlign;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < len) continue;
+    const size_t off = it->first, rest = it->second - len;
+    free_.erase(it);
+    if (rest) free_[off + len] = rest;
+    live_[off] = Blk{len, owner};
+    in_use += len;
+    peak = std::max(peak, in_use);
+    return base + off;
+  }
+  // does not fit: the region would need at least the live bytes plus this
+  // request, and more than it has now
+  need = std::max(need, std::max(in_use + len, size + len));
+  throw Error(PE_ERR_NOMEM, "workspace too small: " + std::to_string(len) + " more bytes requested with " +
+                                std::to_string(in_use) + " of " + std::to_string(size) +
+                                " in use; register a region of at least pe_workspace_size() bytes "
+                                "with pe_set_workspace and call again");
+}
+
+void Arena::release(void* p) {
+  if (!p) return;
+  const size_t off = static_cast<char*>(p) - base;
+  auto it = live_.find(off);
+  if (it == live_.end()) return;
+  size_t o = off, len = it->second.len;
+  in_use -= len;
+  live_.erase(it);
+  auto nx = free_.lower_bound(o);
+  if (nx != free_.end() && nx->first == o + len) {
+    len += nx->second;
+    nx = free_.erase(nx);
+  }
+  if (nx != free_.begin()) {
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == o) {
+      o = pv->first;
+      len += pv->second;
+      free_.erase(pv);
+    }
+  }
+  free_[o] = len;
+}
+
+void Arena::reown(void* p, void** owner) {
+  auto it = live_.find(static_cast<char*>(p) - base);
+  if (it != live_.end()) it->second.owner = owner;
+}
+
+void Arena::migrate(char* nb, size_t nsize, hipStream_t s) {
+  size_t total = 0, end = 0;
+  for (auto& kv : live_) {
+    total += kv.second.len;
+    end = kv.first + kv.second.len;
+  }
+  if (nb == base) {
+    // the same region, resized: blocks stay where they are
+    if (end > nsize) {
+      need = std::max(need, end);
+      throw Error(PE_ERR_NOMEM, "the resized workspace cuts through live blocks");
+    }
+    if (nsize > size) free_[size] = nsize - size;  // merged by later releases
+    else if (nsize < size) {
+      auto it = free_.rbegin();
+      require(it != free_.rend() && it->first + it->second == size, "cannot shrink the workspace");
+      const size_t o = it->first;
+      free_.erase(o);
+      if (nsize > o) free_[o] = nsize - o;
+    }
+    size = nsize;
+    need = 0;
+    return;
+  }
+  require(nb + nsize <= base || base + size <= nb, "the new workspace overlaps the old one");
+  if (total > nsize) {
+    need = std::max(need, total);
+    throw Error(PE_ERR_NOMEM, "the new workspace cannot hold the " + std::to_string(total) + " live bytes");
+  }
+  // live blocks packed from the start of the new region, in address order
+  std::map<size_t, Blk> nl;
+  size_t o = 0;
+  for (auto& kv : live_) {
+    if (nb + o != base + kv.first)
+      PE_HIP(hipMemcpyAsync(nb + o, base + kv.first, kv.second.len, hipMemcpyDeviceToDevice, s));
+    nl[o] = kv.second;
+    o += kv.second.len;
+  }
+  PE_HIP(hipStreamSynchronize(s));
+  for (auto& kv : nl) *kv.second.owner = nb + kv.first;
+  live_.swap(nl);
+  free_.clear();
+  if (nsize > o) free_[o] = nsize - o;
+  base = nb;
+  size = nsize;
+  need = 0;
+}
+
+}  // namespace pe
+
 using namespace pe;
 
 namespace {
@@ -114,6 +218,11 @@ __global__ void stats_kernel(const double* __restrict__ a, int64_t n, int stride
     part[3 * blockIdx.x + 1] = m2;
     part[3 * blockIdx.x + 2] = n2;
   }
+}
+
+__global__ void to_float_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
 }
 
 __global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
@@ -246,6 +355,7 @@ template <typename T>
 void apply_saddle(pe_context* c, const double* x, double* y) {
   hipStream_t s = c->stream;
   const int64_t nb = c->n_bead;
+  ProfScope ps_all(c->prof, s, PE_PROF_MATVEC, sizeof(T) == 8, (double)nb);
   const double* q = x;
   const double* dpsi = x + nb;
   launch_moments(s, q, c->bead_sig.get(), 0.0, nb, ck_coef(c), c->red.get(), ck_bead(c), nullptr);
@@ -378,18 +488,22 @@ void all_potential(pe_context* c, const double* qb, const double* qi, double* ph
 // In single precision with the field requested, the spread ion grid and the
 // real-space ion -> bead sums are kept for the force pass of the same
 // configuration (see all_potential).
+//
+// keep32 (mixed precision, field requested): the parts are kept for the
+// single-precision force pass; a double pass keeps a float copy of its ion
+// grid.
 template <typename T>
-void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E) {
+void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E, bool keep32) {
   hipStream_t s = c->stream;
   const bool dbl = sizeof(T) == 8;
   const int64_t nb = c->n_bead;
-  const bool keep = sizeof(T) == 4 && E != nullptr;
+  const bool keep = keep32 && E != nullptr;
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
+  const int64_t G = (int64_t)c->gg.N[0] * c->gg.N[1] * c->gg.N[2];
   if (keep) {
-    const int64_t G = (int64_t)c->gg.N[0] * c->gg.N[1] * c->gg.N[2];
     c->ion_grid32.ensure((size_t)G);
-    gA = reinterpret_cast<T*>(c->ion_grid32.get());
+    if constexpr (sizeof(T) == 4) gA = reinterpret_cast<T*>(c->ion_grid32.get());
   }
   // ion -> bead real space on the auxiliary stream, into its own buffers
   // (kept for the force pass in single precision with the field)
@@ -422,6 +536,11 @@ void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E) {
     ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)c->n_ion);
     launch_spread<T>(s, c->I, c->ion_q.get(), gA, c->gg, false);
   }
+  if (keep && dbl) {
+    hipLaunchKernelGGL(to_float_kernel, dim3(nblk(G, 256)), dim3(256), 0, s,
+                       reinterpret_cast<const double*>(gA), c->ion_grid32.get(), G);
+    PE_CHECK_LAUNCH();
+  }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
   {
     ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb);
@@ -433,7 +552,10 @@ void ion_potential_at_beads(pe_context* c, double* phi_ion, double* E) {
   if (keep) c->ion_parts_valid = true;
 }
 
-// Right-hand side b = [-r.E0 + phi_ion(beads); Q].
+// Right-hand side b = [-r.E0 + phi_ion(beads); Q].  The ion potential is
+// formed in double unless the parameters ask for the float kernels in mixed
+// precision (rhs_fp64 = 0): the double residuals of the refinement are then
+// residuals of the same system the double path solves.
 void build_rhs(pe_context* c, double* b) {
   hipStream_t s = c->stream;
   const int64_t nb = c->n_bead, ni = c->n_ion;
@@ -448,8 +570,9 @@ void build_rhs(pe_context* c, double* b) {
       c->E_ion.ensure(3 * std::max<int64_t>(nb, 1));
       E = c->E_ion.get();
     }
-    if (c->p.precision == PE_MIXED) ion_potential_at_beads<float>(c, phi_ion, E);
-    else ion_potential_at_beads<double>(c, phi_ion, E);
+    const bool mixed = c->p.precision == PE_MIXED;
+    if (mixed && !c->p.rhs_fp64) ion_potential_at_beads<float>(c, phi_ion, E, true);
+    else ion_potential_at_beads<double>(c, phi_ion, E, mixed);
   }
   c->have_eion = c->guess != nullptr;
   if (nb)
@@ -659,6 +782,75 @@ void build_twiddles(pe_context* c) {
   }
 }
 
+// Tables that depend on the parameters only (twiddles, Green's-function
+// factors, the scaled-erfc table) and the small reduction buffers, built
+// in the workspace once per context.
+void prepare_constants(pe_context* c) {
+  if (c->consts_ready) return;
+  build_twiddles(c);
+  build_green_tables(c);
+  build_erfcx_table(c->stream, c->erfcx_tab);
+  c->rg.erfcx = c->erfcx_tab.get();
+  c->sums.ensure(64);
+  c->red.ensure((size_t)kMaxK * 1024 + 8192);
+  c->consts_ready = true;
+}
+
+// Device bytes a system of these sizes needs: every buffer of the context
+// at its size for this system, with the data-dependent ones (the stored
+// bead pairs, spreading-list entries, body-shape blocks, one recorded
+// training solve) estimated: bead pairs from the mean bead density inside
+// 1.1 r_c, every particle on 8 spreading tiles, two body shapes of the mean
+// body size.  A configuration denser than that asks for more; the entry
+// point then fails with PE_ERR_NOMEM and this call returns what it needed.
+size_t estimate_workspace(const pe_context* c, int64_t nb, int64_t nbody, int64_t ni) {
+  const pe_params& p = c->p;
+  auto up = [](double b) { return (size_t)((b + Arena::kAlign - 1) / Arena::kAlign) * Arena::kAlign; };
+  const double Nx = p.mesh[0], Ny = p.mesh[1], Nz = p.mesh[2];
+  const double G = Nx * Ny * Nz;
+  const double Nzs = std::ceil((Nz / 2 + 1) / 16.0) * 16.0;
+  const double Gc = Nx * Ny * Nzs;
+  const double n = (double)(nb + nbody), na = (double)(nb + ni);
+  size_t b = 0;
+  // parameter tables and reduction buffers
+  b += up(24.0 * (Nx + Ny + Nz)) * 2 + up(16.0 * (Nx + Ny + Nz)) + up(64 * 1024);
+  b += up(8.0 * (64 + nbody)) + up(8.0 * ((double)kMaxK * 1024 + 8192));
+  // grids: two real double grids, the half spectrum, the kept float ion grid
+  b += 2 * up(8 * G) + up(16 * Gc) + up(4 * G);
+  // the system's copies
+  b += up(8.0 * (nbody + 1)) + up(4.0 * nb) + 2 * up(24.0 * nb) + up(8.0 * nb) + up(24.0 * ni) + 2 * up(8.0 * ni) +
+       up(8.0 * nbody) + up(32.0 * nbody) + up(4.0 * nbody);
+  // the two particle sets (sorted records, lists, charges) and their cells
+  const double lt = std::sqrt(std::log(1.0 / p.split_tol));
+  const double rc_min = c->xi > 0 ? lt / c->xi : 0.0;
+  double ncell = 1;
+  for (int d = 0; d < 3; ++d) ncell *= rc_min > 0 ? std::min(512.0, std::max(1.0, std::floor(p.box[d] / rc_min))) : 1;
+  const double ntile = std::ceil(Nx / 8) * std::ceil(Ny / 8) * std::ceil(Nz / 8);
+  for (double m : {(double)nb, (double)ni})
+    b += up(156.0 * m + 1) + up(12.0 * (ncell + 1)) + up(16.0 * (ntile + 1)) + 4 * Arena::kAlign;
+  // per-particle outputs and scratch in caller order
+  b += up(8 * na) * 3 + up(24 * na) * 3 + up(8 * std::max(n, na)) + up(8 * std::max(3 * na, n)) + up(8 * n) * 2 +
+       up(8.0 * nb) * 2 + up(24.0 * nb) * 2 + up(8 * std::max(3 * n, 2 * na)) + up(72.0 * nbody) * 2;
+  // Krylov basis and flexible directions
+  const double m = std::max(1, std::min(p.gmres_restart, kMaxK - 1));
+  b += up(8 * (m + 1) * n) + up(8 * m * n) + up(8 * ((m + 1) * (m + 4) + 8));
+  // stored bead pairs (column, double and float value) and their rows
+  const double V = p.box[0] * p.box[1] * p.box[2];
+  const double rc = 1.1 * std::max(rc_min, 1e-12);
+  const double nnz = (double)nb * (1.0 + (double)nb / V * 4.18879 * rc * rc * rc) * 1.5;
+  b += up(16 * nnz) + up(8.0 * nb) * 3 + up(28.0 * nb) + up(4096);
+  // body shapes: two shapes of the mean size (blocks in both precisions) and
+  // the split-product partials
+  if (nbody) {
+    const double N = (double)nb / nbody;
+    b += 2 * (up(12 * (N + 1) * (N + 1)) + up(12 * N * N) + up(48 * N)) + up(8 * 8 * (N + 1) * nbody) +
+         up(8.0 * nbody) + up(2.0 * nbody);
+  }
+  // learned guess: features, one recorded solve, parameters and partials
+  b += up(36.0 * nb) + up(44.0 * nb) + up(4.0 * nb) + up(4.0 * 256 * 4 * 5000) + up(4 * 4 * 5000);
+  return b + (16u << 20);
+}
+
 void ensure_grids(pe_context* c) {
   const int64_t G = (int64_t)c->p.mesh[0] * c->p.mesh[1] * c->p.mesh[2];
   const int64_t Gc = (int64_t)c->p.mesh[0] * c->p.mesh[1] * c->gg.Nzs;
@@ -669,9 +861,13 @@ void ensure_grids(pe_context* c) {
 
 }  // namespace
 
+namespace pe {
+void saddle_product(pe_context* c, int prec, const double* x, double* y) { apply_saddle_prec(c, prec, x, y); }
+}  // namespace pe
+
 // =============================================================== C ABI
 
-#define PE_API_BEGIN try {
+#define PE_API_BEGIN(ctx) ::pe::ArenaScope arena_scope_((ctx) ? &(ctx)->arena : nullptr); try {
 #define PE_API_END(ctx)                                   \
   }                                                       \
   catch (const pe::Error& e) {                            \
@@ -707,6 +903,7 @@ pe_status pe_default_params(pe_params* p) {
   p->max_refine = 8;
   p->use_learned_guess = 0;
   p->precond = 1;
+  p->rhs_fp64 = 1;
   return PE_OK;
 }
 
@@ -716,7 +913,7 @@ const char* pe_last_error(const pe_context* ctx) {
 
 pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out) {
   pe_context* c = nullptr;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   require(params != nullptr && out != nullptr, "null argument");
   const pe_params& p = *params;
   for (int d = 0; d < 3; ++d) {
@@ -731,8 +928,9 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
   require(p.eta_c > 0, "eta_c must be positive");
   require(p.split_tol > 0 && p.split_tol < 1, "split_tol must be in (0,1)");
   require(p.precision == PE_FP64 || p.precision == PE_MIXED, "unknown precision");
-  require(p.reg == PE_REG_GAUSSIAN || p.reg == PE_REG_SHELL, "unknown regularization");
-  if (p.reg == PE_REG_SHELL) require(p.shell_radius > 0, "shell_radius must be positive");
+  require(p.reg == PE_REG_GAUSSIAN || p.reg == PE_REG_SHELL || p.reg == PE_REG_SHELL_PAPER,
+          "unknown regularization");
+  if (p.reg != PE_REG_GAUSSIAN) require(p.shell_radius > 0, "shell_radius must be positive");
   require(p.gmres_restart >= 1, "gmres_restart must be >= 1");
   require(p.max_iters >= 1, "max_iters must be >= 1");
   require(p.rel_tol > 0, "rel_tol must be positive");
@@ -749,17 +947,14 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
     PE_HIP(hipGetDevice(&dev));
     PE_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     c->lds_per_block = lds;
+    c->device = dev;
   }
   pe::FFTPlan1D tmp;
   for (int d = 0; d < 3; ++d) make_fft_plan(p.mesh[d], tmp);
   compute_params(c);
   require(c->eta > 0 && c->eta < 1, "eta = (h xi)^2 P/(pi c^2) must lie in (0, 1); refine the mesh or lower xi");
-  build_twiddles(c);
-  build_green_tables(c);
-  build_erfcx_table(c->stream, c->erfcx_tab);
-  c->rg.erfcx = c->erfcx_tab.get();
-  c->sums.ensure(64);
-  c->red.ensure((size_t)kMaxK * 1024 + 8192);
+  // no device memory yet: the constant tables are built in the workspace
+  // by the first pe_set_system
   PE_HIP(hipHostMalloc((void**)&c->pinned, 512 * sizeof(double), hipHostMallocDefault));
   *out = c;
   c = nullptr;
@@ -791,12 +986,42 @@ pe_status pe_get_derived(const pe_context* ctx, double out[6]) {
   return PE_OK;
 }
 
+pe_status pe_workspace_size(const pe_context* c, int64_t n_bead, int64_t n_body, int64_t n_ion, size_t* bytes) {
+  if (!c || !bytes || n_bead < 0 || n_body < 0 || n_ion < 0) return PE_ERR_ARG;
+  const size_t est = estimate_workspace(c, n_bead, n_body, n_ion);
+  *bytes = std::max({est, c->arena.need, c->arena.peak});
+  *bytes = (*bytes + Arena::kAlign - 1) / Arena::kAlign * Arena::kAlign;
+  return PE_OK;
+}
+
+pe_status pe_set_workspace(pe_context* c, void* dev_ptr, size_t bytes) {
+  if (!c) return PE_ERR_ARG;
+  PE_API_BEGIN(c)
+  require(dev_ptr != nullptr || bytes == 0, "null workspace");
+  require(reinterpret_cast<uintptr_t>(dev_ptr) % Arena::kAlign == 0, "workspace must be 256-byte aligned");
+  // work in flight may still use the current region
+  PE_HIP(hipStreamSynchronize(c->stream));
+  PE_HIP(hipStreamSynchronize(c->aux));
+  c->arena.migrate(static_cast<char*>(dev_ptr), bytes, c->stream);
+  c->rg.erfcx = c->erfcx_tab.get();  // the one device address kept outside a buffer
+  PE_API_END(c)
+}
+
+pe_status pe_workspace_info(const pe_context* c, size_t out[4]) {
+  if (!c || !out) return PE_ERR_ARG;
+  out[0] = c->arena.size;
+  out[1] = c->arena.in_use;
+  out[2] = c->arena.peak;
+  out[3] = c->arena.need;
+  return PE_OK;
+}
+
 pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offsets, const double* bead_pos,
                         const double* bead_sigma, const double* body_center, const double* body_quat,
                         const double* body_charge, int64_t n_ion, const double* ion_pos, const double* ion_charge,
                         const double* ion_sigma, const double E0[3]) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   c->have_system = false;
   c->have_solution = false;
   c->have_forces = false;
@@ -815,6 +1040,7 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   require(nb == 0 || (bead_pos && bead_sigma), "bead arrays are null");
   require(n_body == 0 || (body_center && body_charge), "body arrays are null");
   require(n_ion == 0 || (ion_pos && ion_charge && ion_sigma), "ion arrays are null");
+  prepare_constants(c);
   hipStream_t s = c->stream;
   c->n_body = n_body;
   c->n_bead = nb;
@@ -884,6 +1110,7 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   const double lt = std::sqrt(std::log(1.0 / c->p.split_tol));
   if (c->p.r_cut > 0) c->rc = c->p.r_cut;
   else if (c->p.reg == PE_REG_GAUSSIAN) c->rc = lt * std::max(1.0 / c->xi, 2.0 * sig_max);
+  else if (c->p.reg == PE_REG_SHELL_PAPER) c->rc = 2.0 * c->p.shell_radius + lt / c->xi;
   else c->rc = std::max(lt / c->xi, 2.0 * c->p.shell_radius);
   const double Lmin = std::min(c->p.box[0], std::min(c->p.box[1], c->p.box[2]));
   require(c->rc <= 0.5 * Lmin * (1 + 1e-12),
@@ -939,7 +1166,7 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
 pe_status pe_apply_potential(pe_context* c, const double* charges, double* psi_out, double* field_out,
                              int32_t precision) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
   require(charges && psi_out, "null charges or output");
   require(precision == PE_FP64 || precision == PE_MIXED, "unknown precision");
@@ -957,7 +1184,7 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
                                 double* dipole_out, pe_solve_info* info) {
   if (!c) return PE_ERR_ARG;
   pe_status status = PE_OK;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
   require(q_out && dpsi_out, "null output");
   pe_solve_info local;
@@ -1047,7 +1274,11 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
         }
         if (!std::isfinite(rn)) throw Error(PE_ERR_NUMERIC, "non-finite residual in refinement");
         rel = rn / bnorm;
-        if (rel <= tol) { conv = true; break; }
+        // the residual of a guess was formed with the float operator:
+        // convergence is only accepted on a double residual
+        const bool r_is_fp64 = outer > 0 || x_zero;
+        if (rel <= tol && r_is_fp64) { conv = true; break; }
+        if (rel <= tol) continue;
         if (outer == c->p.max_refine || total >= c->p.max_iters) break;
         inf->outer_refinements++;
         PE_HIP(hipMemsetAsync(d, 0, sizeof(double) * n, s));
@@ -1084,9 +1315,19 @@ pe_status pe_solve_polarization(pe_context* c, const double* q_init, double* q_o
   PE_API_END(c)
 }
 
+pe_status pe_grand_capacitance(pe_context* c, double* C_out, double* eps_eff, pe_solve_info* info) {
+  if (!c) return PE_ERR_ARG;
+  PE_API_BEGIN(c)
+  if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
+  require(c->n_body > 0, "the capacitance needs at least one body");
+  if (info) std::memset(info, 0, sizeof(*info));
+  grand_capacitance(c, C_out, eps_eff, info);
+  PE_API_END(c)
+}
+
 pe_status pe_apply_saddle(pe_context* c, const double* x, double* y, int32_t precision) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
   require(x && y, "null vector");
   require(precision == PE_FP64 || precision == PE_MIXED, "unknown precision");
@@ -1098,7 +1339,7 @@ pe_status pe_apply_saddle(pe_context* c, const double* x, double* y, int32_t pre
 
 pe_status pe_profile_enable(pe_context* c, int32_t on) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   PE_HIP(hipStreamSynchronize(c->stream));
   c->prof.reset();
   c->prof.on = on != 0;
@@ -1116,7 +1357,7 @@ pe_status pe_profile_select(pe_context* c, uint32_t class_mask) {
 
 pe_status pe_profile_read(pe_context* c, double* out) {
   if (!c || !out) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   PE_HIP(hipStreamSynchronize(c->stream));
   c->prof.flush();
   unsigned long long np[2] = {0, 0};
@@ -1136,7 +1377,7 @@ pe_status pe_profile_read(pe_context* c, double* out) {
 pe_status pe_forces_torques(pe_context* c, double* body_force, double* body_torque, double* body_energy,
                             double* ion_force, double* bead_force, double* total_energy) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   if (!c->have_solution) throw Error(PE_ERR_STATE, "pe_solve_polarization has not been called");
   require(total_energy != nullptr, "total_energy is null");
   hipStream_t s = c->stream;

@@ -15,8 +15,11 @@
 // normal by the Box-Muller transform.  Ions use streams 0/1, bodies 2/3
 // (translation / rotation), so every number is fixed by (seed, step, index).
 #include <cmath>
+#include <string>
+#include <vector>
 
 #include "pe_internal.hpp"
+#include "vector.hpp"
 
 namespace pe {
 
@@ -178,7 +181,251 @@ __global__ void bd_beads_kernel(int64_t n, const int* __restrict__ body_of, cons
   for (int a = 0; a < 3; ++a) x[3 * j + a] = X[3 * b + a] + R[3 * a] * r0 + R[3 * a + 1] * r1 + R[3 * a + 2] * r2;
 }
 
+// ---- hard spheres (section "Brownian dynamics", the potential-free pair
+// potential U(r) = gamma / (4 dt) (r - 2a)^2 for r < 2a): every two particles
+// closer than 2a, ions and beads of different bodies, push each other apart
+// with gamma / (2 dt) (2a - r) along the line of centres, which under the
+// free-draining mobility separates an isolated pair to contact in one step.
+// The pairs are found on a cell grid of edge >= 2a over all particles,
+// counting-sorted and sorted by index within each cell, so every force is
+// summed in a fixed order.
+
+struct HsGeom {
+  double L[3], inv_L[3];
+  int nc[3];
+  double cell_inv[3];
+  double a2;      // (2a)^2
+  double twoa;
+  double coef;    // gamma / (2 dt)
+};
+
+// particle k of the combined list: beads 0..nb-1, then ions
+__device__ __forceinline__ const double* hs_pos(int64_t k, int64_t nb, const double* bx, const double* ix) {
+  return k < nb ? bx + 3 * k : ix + 3 * (k - nb);
+}
+
+__device__ __forceinline__ int hs_cell_index(double v, double inv_L, double cinv, int nc) {
+  double w = v - floor(v * inv_L) / inv_L;  // wrapped into [0, L)
+  int c = (int)(w * cinv);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__global__ void hs_count_kernel(int64_t n, int64_t nb, const double* __restrict__ bx, const double* __restrict__ ix,
+                                HsGeom g, int* __restrict__ cell_of, int* __restrict__ count) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double* p = hs_pos(k, nb, bx, ix);
+  const int c = (hs_cell_index(p[0], g.inv_L[0], g.cell_inv[0], g.nc[0]) * g.nc[1] +
+                 hs_cell_index(p[1], g.inv_L[1], g.cell_inv[1], g.nc[1])) * g.nc[2] +
+                hs_cell_index(p[2], g.inv_L[2], g.cell_inv[2], g.nc[2]);
+  cell_of[k] = c;
+  atomicAdd(count + c, 1);
+}
+
+__global__ void hs_start_kernel(const int64_t* __restrict__ s64, int64_t m, int* __restrict__ s32,
+                                int* __restrict__ cursor, int* __restrict__ maxlen) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > m) return;
+  s32[c] = (int)s64[c];
+  if (c < m) {
+    cursor[c] = (int)s64[c];
+    atomicMax(maxlen, (int)(s64[c + 1] - s64[c]));
+  }
+}
+
+__global__ void hs_scatter_kernel(int64_t n, const int* __restrict__ cell_of, int* __restrict__ cursor,
+                                  int* __restrict__ entries) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  entries[atomicAdd(cursor + cell_of[k], 1)] = (int)k;
+}
+
+// f[k] = sum over partners j of coef (2a - r) (x_k - x_j) / r, 27 cells, fixed order
+__global__ void hs_force_kernel(int64_t n, int64_t nb, const double* __restrict__ bx, const double* __restrict__ ix,
+                                const int* __restrict__ body_of, HsGeom g, const int* __restrict__ start,
+                                const int* __restrict__ entries, const int* __restrict__ cell_of,
+                                double* __restrict__ f) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double* p = hs_pos(k, nb, bx, ix);
+  const int own = k < nb ? body_of[k] : -1;
+  const int c = cell_of[k];
+  const int cz = c % g.nc[2], cy = (c / g.nc[2]) % g.nc[1], cx = c / (g.nc[1] * g.nc[2]);
+  double fx = 0, fy = 0, fz = 0;
+  for (int ox = -1; ox <= 1; ++ox) {
+    const int x = (cx + ox + g.nc[0]) % g.nc[0];
+    for (int oy = -1; oy <= 1; ++oy) {
+      const int y = (cy + oy + g.nc[1]) % g.nc[1];
+      for (int oz = -1; oz <= 1; ++oz) {
+        const int z = (cz + oz + g.nc[2]) % g.nc[2];
+        const int cc = (x * g.nc[1] + y) * g.nc[2] + z;
+        for (int e = start[cc]; e < start[cc + 1]; ++e) {
+          const int j = entries[e];
+          if (j == k) continue;
+          if (own >= 0 && j < nb && body_of[j] == own) continue;  // beads of one body
+          const double* q = hs_pos(j, nb, bx, ix);
+          double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+          dx -= g.L[0] * rint(dx * g.inv_L[0]);
+          dy -= g.L[1] * rint(dy * g.inv_L[1]);
+          dz -= g.L[2] * rint(dz * g.inv_L[2]);
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (!(r2 < g.a2) || r2 == 0.0) continue;
+          const double r = sqrt(r2);
+          const double s = g.coef * (g.twoa - r) / r;
+          fx += s * dx;
+          fy += s * dy;
+          fz += s * dz;
+        }
+      }
+    }
+  }
+  f[3 * k] = fx;
+  f[3 * k + 1] = fy;
+  f[3 * k + 2] = fz;
+}
+
+// per body: F += sum_j f_j, L += sum_j r_j x f_j (one block per body, fixed order)
+__global__ void __launch_bounds__(256) hs_body_kernel(const int64_t* __restrict__ off, const double* __restrict__ rel,
+                                                      const double* __restrict__ f, const double* __restrict__ F0,
+                                                      const double* __restrict__ L0, double* __restrict__ Fo,
+                                                      double* __restrict__ Lo) {
+  const int64_t b = blockIdx.x;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = off[b] + threadIdx.x; i < off[b + 1]; i += blockDim.x) {
+    const double rx = rel[3 * i], ry = rel[3 * i + 1], rz = rel[3 * i + 2];
+    const double fx = f[3 * i], fy = f[3 * i + 1], fz = f[3 * i + 2];
+    v[0] += fx; v[1] += fy; v[2] += fz;
+    v[3] += ry * fz - rz * fy; v[4] += rz * fx - rx * fz; v[5] += rx * fy - ry * fx;
+  }
+  __shared__ double sh[6][4];
+  for (int m = 0; m < 6; ++m)
+    for (int o = 32; o > 0; o >>= 1) v[m] += __shfl_xor(v[m], o, 64);
+  if ((threadIdx.x & 63) == 0)
+    for (int m = 0; m < 6; ++m) sh[m][threadIdx.x >> 6] = v[m];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int m = 0; m < 6; ++m) {
+      double t = 0;
+      for (int w = 0; w < 4; ++w) t += sh[m][w];
+      // F and L of the electrostatic pass plus the hard-sphere parts
+      if (m < 3) Fo[3 * b + m] = F0[3 * b + m] + t;
+      else Lo[3 * b + m - 3] = L0[3 * b + m - 3] + t;
+    }
+  }
+}
+
+__global__ void hs_ion_kernel(int64_t ni, const double* __restrict__ f0, const double* __restrict__ fh,
+                              double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * ni) out[i] = f0[i] + fh[i];
+}
+
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Hard-sphere forces of every particle of the loaded configuration (beads,
+// then ions; 3 doubles each) in the workspace, followed by room for the
+// summed ion forces (3 per ion) and body forces and torques (3 + 3 per body).
+double* hard_sphere_forces(pe_context* c, double gamma, double dt) {
+  hipStream_t s = c->stream;
+  const int64_t nb = c->n_bead, ni = c->n_ion, n = nb + ni, nbody = c->n_body;
+  const double a = c->p.hs_radius;
+  HsGeom g{};
+  int64_t ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    g.L[d] = c->p.box[d];
+    g.inv_L[d] = 1.0 / c->p.box[d];
+    g.nc[d] = (int)std::min(1024.0, std::floor(c->p.box[d] / (2.0 * a)));
+    require(g.nc[d] >= 3, "hard-sphere diameter above a third of the box");
+  }
+  // at most 2^26 cells: coarser cells (edges still >= 2a) beyond that
+  while ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] > ((int64_t)1 << 26)) {
+    const int d = g.nc[0] >= g.nc[1] ? (g.nc[0] >= g.nc[2] ? 0 : 2) : (g.nc[1] >= g.nc[2] ? 1 : 2);
+    g.nc[d] = std::max(3, g.nc[d] / 2);
+  }
+  for (int d = 0; d < 3; ++d) {
+    g.cell_inv[d] = g.nc[d] / c->p.box[d];
+    ncell *= g.nc[d];
+  }
+  g.twoa = 2.0 * a;
+  g.a2 = 4.0 * a * a;
+  g.coef = gamma / (2.0 * dt);
+  c->hs_f.ensure(3 * (size_t)n + 3 * (size_t)ni + 6 * (size_t)nbody + 1);
+  c->hs_cell.ensure((size_t)n);
+  c->hs_entries.ensure((size_t)n);
+  c->hs_count.ensure((size_t)ncell + 1);
+  c->hs_start.ensure((size_t)ncell + 1);
+  c->hs_start64.ensure((size_t)ncell + 1);
+  c->hs_scan.ensure((size_t)scan_workspace(ncell));
+  int* count = c->hs_count.get();
+  PE_HIP(hipMemsetAsync(count, 0, sizeof(int) * (ncell + 1), s));
+  hipLaunchKernelGGL(hs_count_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, n, nb, c->bead_x.get(), c->ion_x.get(), g,
+                     c->hs_cell.get(), count);
+  PE_CHECK_LAUNCH();
+  launch_exclusive_scan(s, count, ncell, c->hs_start64.get(), c->hs_scan.get());
+  // counts become cursors; count[ncell] holds the longest cell
+  PE_HIP(hipMemsetAsync(count + ncell, 0, sizeof(int), s));
+  hipLaunchKernelGGL(hs_start_kernel, dim3(nblk(ncell + 1, 256)), dim3(256), 0, s, c->hs_start64.get(), ncell,
+                     c->hs_start.get(), count, count + ncell);
+  hipLaunchKernelGGL(hs_scatter_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, n, c->hs_cell.get(), count,
+                     c->hs_entries.get());
+  PE_CHECK_LAUNCH();
+  int maxlen = 0;
+  PE_HIP(hipMemcpyAsync(&maxlen, count + ncell, sizeof(int), hipMemcpyDeviceToHost, s));
+  PE_HIP(hipStreamSynchronize(s));
+  launch_segment_sort(s, c->hs_start.get(), (int)ncell, c->hs_entries.get(), maxlen);
+  hipLaunchKernelGGL(hs_force_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, n, nb, c->bead_x.get(), c->ion_x.get(),
+                     c->body_of.get(), g, c->hs_start.get(), c->hs_entries.get(), c->hs_cell.get(), c->hs_f.get());
+  PE_CHECK_LAUNCH();
+  return c->hs_f.get();
+}
+
+// The step's kernels; R: 9 doubles per body of scratch (the rotation of each
+// body, written by the body kernel and read by the bead kernel).
+void bd_launch(pe_context* c, double dt, double kT, double gamma, uint64_t seed, uint64_t step, double* bead_pos,
+               double* body_center, double* body_quat, double* ion_pos, double* R) {
+  if (!c->have_forces) throw Error(PE_ERR_STATE, "pe_forces_torques has not been called");
+  require(dt > 0 && kT >= 0 && gamma > 0, "dt, gamma must be positive and kT non-negative");
+  require((c->n_bead == 0 || bead_pos) && (c->n_body == 0 || (body_center && body_quat)) &&
+              (c->n_ion == 0 || ion_pos),
+          "null state array");
+  hipStream_t s = c->stream;
+  const int64_t nb = c->n_bead, nbody = c->n_body, ni = c->n_ion;
+  const double* fion = c->forces.get() + 3 * nb;
+  const double* Fb = c->bodyF.get();
+  const double* Lb = c->bodyL.get();
+  if (c->p.hs_radius > 0 && nb + ni > 1) {
+    // hard-sphere forces of the current configuration added to the electrostatic ones
+    double* hs = hard_sphere_forces(c, gamma, dt);
+    double* ftot = hs + 3 * (nb + ni);   // ions: electrostatic + hard sphere
+    double* Ft = ftot + 3 * ni;          // bodies
+    double* Lt = Ft + 3 * nbody;
+    if (ni) {
+      hipLaunchKernelGGL(hs_ion_kernel, dim3(nblk(3 * ni, 256)), dim3(256), 0, s, ni, fion, hs + 3 * nb, ftot);
+      fion = ftot;
+    }
+    if (nbody) {
+      hipLaunchKernelGGL(hs_body_kernel, dim3((unsigned)nbody), dim3(256), 0, s, c->off.get(), c->rel.get(), hs, Fb,
+                         Lb, Ft, Lt);
+      Fb = Ft;
+      Lb = Lt;
+    }
+    PE_CHECK_LAUNCH();
+  }
+  if (ni)
+    hipLaunchKernelGGL(bd_ions_kernel, dim3(nblk(ni, 256)), dim3(256), 0, s, ni, fion, dt, kT, gamma, seed, step,
+                       ion_pos);
+  if (nbody) {
+    hipLaunchKernelGGL(bd_bodies_kernel, dim3((unsigned)nbody), dim3(64), 0, s, nbody, c->off.get(), c->rel.get(),
+                       Fb, Lb, dt, kT, gamma, seed, step, body_center, body_quat, R);
+    hipLaunchKernelGGL(bd_beads_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, c->body_of.get(), c->rel.get(),
+                       body_center, R, bead_pos);
+  }
+  PE_CHECK_LAUNCH();
+  PE_HIP(hipStreamSynchronize(s));
+  c->have_system = false;  // positions moved: pe_set_system must run again
+  c->have_solution = false;
+  c->have_forces = false;
+}
 
 }  // namespace
 
@@ -189,30 +436,10 @@ using namespace pe;
 extern "C" pe_status pe_bd_step(pe_context* c, double dt, double kT, double gamma, uint64_t seed, uint64_t step,
                                 double* bead_pos, double* body_center, double* body_quat, double* ion_pos) {
   if (!c) return PE_ERR_ARG;
+  ArenaScope arena_scope(&c->arena);
   try {
-    if (!c->have_forces) throw Error(PE_ERR_STATE, "pe_forces_torques has not been called");
-    require(dt > 0 && kT >= 0 && gamma > 0, "dt, gamma must be positive and kT non-negative");
-    require((c->n_bead == 0 || bead_pos) && (c->n_body == 0 || (body_center && body_quat)) &&
-                (c->n_ion == 0 || ion_pos),
-            "null state array");
-    hipStream_t s = c->stream;
-    const int64_t nb = c->n_bead, nbody = c->n_body, ni = c->n_ion;
-    if (ni)
-      hipLaunchKernelGGL(bd_ions_kernel, dim3(nblk(ni, 256)), dim3(256), 0, s, ni, c->forces.get() + 3 * nb, dt, kT,
-                         gamma, seed, step, ion_pos);
-    c->bd_R.ensure(9 * std::max<int64_t>(nbody, 1));
-    if (nbody) {
-      hipLaunchKernelGGL(bd_bodies_kernel, dim3((unsigned)nbody), dim3(64), 0, s, nbody, c->off.get(), c->rel.get(),
-                         c->bodyF.get(), c->bodyL.get(), dt, kT, gamma, seed, step, body_center, body_quat,
-                         c->bd_R.get());
-      hipLaunchKernelGGL(bd_beads_kernel, dim3(nblk(nb, 256)), dim3(256), 0, s, nb, c->body_of.get(), c->rel.get(),
-                         body_center, c->bd_R.get(), bead_pos);
-    }
-    PE_CHECK_LAUNCH();
-    PE_HIP(hipStreamSynchronize(s));
-    c->have_system = false;  // positions moved: pe_set_system must run again
-    c->have_solution = false;
-    c->have_forces = false;
+    c->bd_R.ensure(9 * std::max<int64_t>(c->n_body, 1));
+    bd_launch(c, dt, kT, gamma, seed, step, bead_pos, body_center, body_quat, ion_pos, c->bd_R.get());
   } catch (const Error& e) {
     c->err = e.what();
     return e.code;

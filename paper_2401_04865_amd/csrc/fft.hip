@@ -208,7 +208,18 @@ struct ScaleArgs {
   const double* ky2;  // Ny
   const double* kz2;  // Nzc
   double norm;        // 1 / (Nx Ny Nz)
+  double shell_a;     // > 0: the Green's function also carries j0^2(|k| a) (the paper's shell split)
 };
+
+// j0(|k| a)^2 from k^2 (the paper's split puts the shells' form factor in the
+// wave space too); below |k| a = 1e-3 the series 1 - x^2/3.
+template <typename T>
+__device__ __forceinline__ T j0_squared(T k2, T a) {
+  const T x = sqrt(k2) * a;
+  if (x < (T)1e-3) return (T)1 - x * x / (T)3;
+  const T j = sin(x) / x;
+  return j * j;
+}
 
 // Lines along a strided axis: line L (0..nlines-1), element j at
 // base(L) + j*stride, base(L) = (L / inner) * outer + (L % inner); a line
@@ -258,7 +269,8 @@ __global__ void __launch_bounds__(512) fft_lines_kernel(typename C2<T>::type* __
       const int j = t - c * n;
       if (lbase[c] < 0) continue;
       const T k2 = (T)sa.kx2[j] + lksq[c];
-      const T gk = k2 > (T)0 ? (T)sa.ex[j] * lfac[c] / k2 : (T)0;
+      T gk = k2 > (T)0 ? (T)sa.ex[j] * lfac[c] / k2 : (T)0;
+      if (sa.shell_a > 0.0) gk *= j0_squared<T>(k2, (T)sa.shell_a);
       C v = res[ll.at(c, j)];
       res[ll.at(c, j)] = {v.x * gk, v.y * gk};
     }
@@ -388,7 +400,8 @@ __global__ void __launch_bounds__(256) fft256_lines_kernel(typename C2<T>::type*
       for (int k2 = 0; k2 < 16; ++k2) {
         const int kx = g + 16 * k2;
         const T k2s = (T)sa.kx2[kx] + lksq[c];
-        const T gk = k2s > (T)0 ? (T)sa.ex[kx] * lfac[c] / k2s : (T)0;
+        T gk = k2s > (T)0 ? (T)sa.ex[kx] * lfac[c] / k2s : (T)0;
+        if (sa.shell_a > 0.0) gk *= j0_squared<T>(k2s, (T)sa.shell_a);
         v[k2] = {v[k2].x * gk, v[k2].y * gk};
       }
     }
@@ -729,6 +742,7 @@ void launch_wave_pipeline(hipStream_t s, pe_context* c, T* gA, T* gB, void* gCv)
   sa.ky2 = sa.kx2 + Nx;
   sa.kz2 = sa.ky2 + Ny;
   sa.norm = 1.0 / ((double)Nx * Ny * Nz);
+  sa.shell_a = c->p.reg == PE_REG_SHELL_PAPER ? c->p.shell_radius : 0.0;
   // 2. y forward: lines (x, kz), element y
   auto ypass = [&](int fwd) {
     ProfScope ps(c->prof, s, fwd > 0 ? PE_PROF_FFT_Y_FWD : PE_PROF_FFT_Y_INV, sizeof(T) == 8, 1.0);

@@ -211,8 +211,11 @@ constexpr int kWaveChunk = 21;
 // 14 KB of LDS per workgroup leaves room for eight workgroups per CU): the
 // loop waits on its list and position loads, and more resident wavefronts hide
 // them (bead spread 198 -> 189 us on the 256^3 mesh).
+// Double precision (used for the ions' home lists when a double pass spreads
+// them) takes the window factors in double and holds four wavefronts per
+// SIMD (the z-pencil is twice as wide in registers).
 template <typename T, bool HOME>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) spread_tile_kernel(const double4* __restrict__ pos,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) spread_tile_kernel(const double4* __restrict__ pos,
                                                           const double* __restrict__ qs,
                                                           const int* __restrict__ tile_start,
                                                           const int* __restrict__ entries,
@@ -310,16 +313,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) s
         int s0 = wrap_idx(m0, N) - kTile * u;
         if (s0 > kTile - 1) s0 -= N;
         if (s0 < 1 - P) s0 += N;
-        // single precision once the support is placed: the displacement
-        // (j + delta) h is below P h, so float keeps it to rounding and the
-        // exponential to a few ulp
-        const float hf = (float)g.h[ax3], df = (float)delta, we = (float)g.wexp;
-        const float wn = (float)g.wnorm * (float)q1;
+        if constexpr (sizeof(T) == 4) {
+          // single precision once the support is placed: the displacement
+          // (j + delta) h is below P h, so float keeps it to rounding and the
+          // exponential to a few ulp
+          const float hf = (float)g.h[ax3], df = (float)delta, we = (float)g.wexp;
+          const float wn = (float)g.wnorm * (float)q1;
 #pragma unroll
-        for (int loc = 0; loc < kTile; ++loc) {
-          const int j = loc - s0;
-          const float d = ((float)j + df) * hf;
-          fw[c3][ax3][loc] = (j >= 0 && j < P) ? (T)(wn * __expf(-we * d * d)) : (T)0;
+          for (int loc = 0; loc < kTile; ++loc) {
+            const int j = loc - s0;
+            const float d = ((float)j + df) * hf;
+            fw[c3][ax3][loc] = (j >= 0 && j < P) ? (T)(wn * __expf(-we * d * d)) : (T)0;
+          }
+        } else {
+          const double wn = g.wnorm * q1;
+#pragma unroll
+          for (int loc = 0; loc < kTile; ++loc) {
+            const int j = loc - s0;
+            const double d = ((double)j + delta) * g.h[ax3];
+            fw[c3][ax3][loc] = (j >= 0 && j < P) ? (T)(wn * exp(-g.wexp * d * d)) : (T)0;
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -806,6 +819,19 @@ void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* gri
     else
       hipLaunchKernelGGL((spread_tile_kernel<T, false>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
                          m.qspread.get(), ps.tile_start.get(), ps.tile_entries.get(), grid, g, accumulate ? 1 : 0);
+  } else if (ps.spread_by_home) {
+    // a set spread from its sorted home lists (the ions in mixed precision,
+    // whose double pass forms the right-hand side): no tile lists needed
+    m.qspread.ensure((size_t)std::max<int64_t>(ps.n, 1));
+    if (ps.n > 0) {
+      hipLaunchKernelGGL(sorted_charges_kernel, dim3((unsigned)((ps.n + 255) / 256)), dim3(256), 0, s, ps.idx.get(),
+                         q, ps.n, m.qspread.get());
+      PE_CHECK_LAUNCH();
+    }
+    const int nbz = (g.ntile[2] + kWaves - 1) / kWaves;
+    const int nt = g.ntile[0] * g.ntile[1] * nbz;
+    hipLaunchKernelGGL((spread_tile_kernel<T, true>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
+                       m.qspread.get(), ps.home_start.get(), ps.home_entries.get(), grid, g, accumulate ? 1 : 0);
   } else {
     if (!ps.have_tile_lists) build_tile_lists(s, m, g);
     // double: the window exponentials dominate, and spreading them over the

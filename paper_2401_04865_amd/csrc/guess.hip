@@ -382,8 +382,7 @@ void ensure_data(LearnedGuess* gs, int64_t rows) {
   DevBuf<float> nd;
   nd.ensure(cap);
   if (gs->n_rec) PE_HIP(hipMemcpy(nd.get(), gs->data.get(), sizeof(float) * gs->n_rec * kRec, hipMemcpyDeviceToDevice));
-  std::swap(nd.ptr, gs->data.ptr);
-  std::swap(nd.cap, gs->data.cap);
+  nd.swap(gs->data);
 }
 
 LearnedGuess* get(pe_context* c) {
@@ -487,7 +486,7 @@ void guess_gradient(pe_context* c, int64_t nb, float* host_grad, double* host_lo
 
 using namespace pe;
 
-#define PE_API_BEGIN try {
+#define PE_API_BEGIN(ctx) ::pe::ArenaScope arena_scope_((ctx) ? &(ctx)->arena : nullptr); try {
 #define PE_API_END(ctx)                 \
   }                                     \
   catch (const pe::Error& e) {          \
@@ -504,14 +503,14 @@ extern "C" {
 
 pe_status pe_guess_init(pe_context* c, uint64_t seed) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   init_weights(get(c), seed, c->stream);
   PE_API_END(c)
 }
 
 pe_status pe_guess_set_types(pe_context* c, const int32_t* body_type) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
   LearnedGuess* g = get(c);
   g->types.assign(body_type, body_type + c->n_body);
@@ -521,7 +520,7 @@ pe_status pe_guess_set_types(pe_context* c, const int32_t* body_type) {
 
 pe_status pe_guess_record(pe_context* c, const double* q_solved) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   if (!c->have_solution) throw Error(PE_ERR_STATE, "pe_solve_polarization has not been called");
   require(q_solved != nullptr, "null charges");
   LearnedGuess* g = get(c);
@@ -545,7 +544,7 @@ pe_status pe_guess_clear(pe_context* c) {
 
 pe_status pe_guess_train(pe_context* c, int32_t epochs, int32_t batch, double lr, uint64_t seed, double* loss) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   LearnedGuess* g = get(c);
   require(g->init, "pe_guess_init or pe_guess_load first");
   require(g->n_rec > 0, "no recorded samples");
@@ -594,7 +593,7 @@ pe_status pe_guess_train(pe_context* c, int32_t epochs, int32_t batch, double lr
 
 pe_status pe_guess_predict(pe_context* c, double* q_out) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   if (!c->have_system) throw Error(PE_ERR_STATE, "pe_set_system has not been called");
   require(q_out != nullptr, "null output");
   guess_predict(c, q_out);
@@ -605,7 +604,7 @@ pe_status pe_guess_predict(pe_context* c, double* q_out) {
 pe_status pe_guess_save(const pe_context* cc, const char* path) {
   pe_context* c = const_cast<pe_context*>(cc);
   if (!c || !path) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   require(c->guess && c->guess->init, "no weights to save");
   std::vector<float> P(kNPar);
   PE_HIP(hipMemcpy(P.data(), c->guess->P.get(), sizeof(float) * kNPar, hipMemcpyDeviceToHost));
@@ -622,7 +621,7 @@ pe_status pe_guess_save(const pe_context* cc, const char* path) {
 
 pe_status pe_guess_load(pe_context* c, const char* path) {
   if (!c || !path) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   FILE* f = std::fopen(path, "rb");
   require(f != nullptr, std::string("cannot open ") + path);
   char magic[8];
@@ -645,7 +644,7 @@ pe_status pe_guess_load(pe_context* c, const char* path) {
 pe_status pe_guess_debug(pe_context* c, float* params_inout, int32_t set_params, int64_t n_rows, float* grad,
                          double* loss) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   LearnedGuess* g = get(c);
   if (!g->init) init_weights(g, 0, c->stream);
   if (set_params) PE_HIP(hipMemcpy(g->P.get(), params_inout, sizeof(float) * kNPar, hipMemcpyHostToDevice));
@@ -659,7 +658,7 @@ pe_status pe_guess_debug(pe_context* c, float* params_inout, int32_t set_params,
 
 pe_status pe_guess_add_rows(pe_context* c, const float* rows, int64_t n_rows) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   require(rows != nullptr && n_rows >= 0, "bad rows");
   LearnedGuess* g = get(c);
   ensure_data(g, g->n_rec + n_rows);
@@ -671,7 +670,7 @@ pe_status pe_guess_add_rows(pe_context* c, const float* rows, int64_t n_rows) {
 
 pe_status pe_guess_rows(pe_context* c, float* rows, int64_t n_rows) {
   if (!c) return PE_ERR_ARG;
-  PE_API_BEGIN
+  PE_API_BEGIN(c)
   LearnedGuess* g = get(c);
   require(n_rows <= g->n_rec, "not enough recorded rows");
   PE_HIP(hipMemcpy(rows, g->data.get(), sizeof(float) * kRec * n_rows, hipMemcpyDeviceToHost));

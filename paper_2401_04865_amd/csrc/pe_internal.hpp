@@ -8,6 +8,7 @@
 #include <stdexcept>
 #include <string>
 #include <deque>
+#include <map>
 #include <vector>
 
 #include "../../include/pe.h"
@@ -34,33 +35,85 @@ inline void require(bool ok, const std::string& msg) {
   if (!ok) throw Error(PE_ERR_ARG, msg);
 }
 
-// ----------------------------------------------------------- device buffer
+// -------------------------------------------------------- device workspace
 
-// Device allocation owned by the context; grows on demand, never shrinks.
+// All device memory of a context lies in one region the caller registers
+// with pe_set_workspace (a torch tensor, say); the library itself never
+// allocates device memory.  Buffers are carved from the region first fit in
+// 256-byte granules, freed blocks coalesce with their neighbours, and every
+// live block records the address of the pointer that owns it, so that
+// pe_set_workspace can move all live blocks into a new, larger region and
+// repoint their owners.  A request that does not fit throws PE_ERR_NOMEM and
+// records how large the region would have to be (`need`), which
+// pe_workspace_size then reports.
+class Arena {
+ public:
+  static constexpr size_t kAlign = 256;
+  char* base = nullptr;
+  size_t size = 0;
+  size_t in_use = 0;   // bytes in live blocks
+  size_t peak = 0;     // largest in_use seen
+  size_t need = 0;     // region size a failed request would have needed (0: none failed)
+
+  void* alloc(size_t bytes, void** owner);
+  void release(void* p);
+  void reown(void* p, void** owner);
+  // Moves every live block into [nb, nb + nsize) (copies on stream s, then
+  // waits) and makes it the region.  Throws PE_ERR_NOMEM if they do not fit.
+  void migrate(char* nb, size_t nsize, hipStream_t s);
+  size_t live_blocks() const { return live_.size(); }
+
+ private:
+  struct Blk {
+    size_t len;
+    void** owner;
+  };
+  std::map<size_t, size_t> free_;   // offset -> length
+  std::map<size_t, Blk> live_;      // offset -> block
+};
+
+// The arena of the context whose entry point is running on this thread (set
+// by every entry point); buffers remember the arena they came from.
+extern thread_local Arena* tl_arena;
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena* a) : prev(tl_arena) { tl_arena = a; }
+  ~ArenaScope() { tl_arena = prev; }
+};
+
+// A buffer in the context's workspace; grows on demand, never shrinks.
 template <typename T>
 struct DevBuf {
   T* ptr = nullptr;
   size_t cap = 0;  // elements
+  Arena* arena = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr && arena) arena->release(ptr);
     ptr = nullptr;
     cap = 0;
   }
   T* ensure(size_t n) {
     if (n <= cap && ptr) return ptr;
     release();
-    size_t bytes = (n ? n : 1) * sizeof(T);
-    hipError_t e = hipMalloc(&ptr, bytes);
-    if (e != hipSuccess) {
-      ptr = nullptr;
-      throw Error(PE_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-    }
+    Arena* a = tl_arena;
+    if (!a) throw Error(PE_ERR_STATE, "device buffer requested outside an entry point");
+    const size_t bytes = (n ? n : 1) * sizeof(T);
+    ptr = static_cast<T*>(a->alloc(bytes, reinterpret_cast<void**>(&ptr)));
+    arena = a;
     cap = n ? n : 1;
     return ptr;
+  }
+  // exchange storage with o (the owners recorded in the arena follow)
+  void swap(DevBuf& o) {
+    std::swap(ptr, o.ptr);
+    std::swap(cap, o.cap);
+    std::swap(arena, o.arena);
+    if (ptr) arena->reown(ptr, reinterpret_cast<void**>(&ptr));
+    if (o.ptr) o.arena->reown(o.ptr, reinterpret_cast<void**>(&o.ptr));
   }
   T* get() const { return ptr; }
   operator T*() const { return ptr; }
@@ -294,6 +347,7 @@ struct BodyType {
   bool have_inv = false;
   DevBuf<double> Ainv;
   DevBuf<float> Ainv32;
+  DevBuf<double> Minv;             // inverse of the free-space self block alone (N x N)
   bool near = false;               // intra-body real-space block stored densely
   DevBuf<double> R64;
   DevBuf<float> R32;
@@ -316,6 +370,8 @@ struct LearnedGuess;  // defined in the guess translation unit
 }  // namespace pe
 
 struct pe_context {
+  // declared first so that it is destroyed after every buffer carved from it
+  pe::Arena arena;
   pe_params p;
   hipStream_t stream = nullptr;
   // second stream (default priority) for the real-space pair passes of the
@@ -328,7 +384,9 @@ struct pe_context {
   std::string err;
 
   int lds_per_block = 65536;  // device limit on LDS per workgroup (bytes)
+  int device = 0;             // the GPU current at pe_create (the context's device)
 
+  bool consts_ready = false;  // parameter tables built in the workspace
   // derived parameters
   double xi = 0, rc = 0, eta = 0, hmax = 0, V = 0;
   pe::GridGeom gg{};
@@ -398,6 +456,10 @@ struct pe_context {
   pe::DevBuf<double> forces;   // f per particle (n_bead+n_ion) x 3
   pe::DevBuf<double> bodyF, bodyL;  // n_body x 3 from the last force pass
   pe::DevBuf<double> bd_R;     // per-body rotation of the last BD step
+  // hard spheres of the BD step: cells over all particles, forces
+  pe::DevBuf<int> hs_cell, hs_entries, hs_count, hs_start;
+  pe::DevBuf<int64_t> hs_start64, hs_scan;
+  pe::DevBuf<double> hs_f;
   pe::DevBuf<double> E_ion;    // n_bead x 3, field of the ions at the beads (learned-guess features)
   // single-precision ion parts kept from the right-hand side for the force
   // pass of the same configuration: the spread ion grid (before the
@@ -475,6 +537,13 @@ void launch_body_gemm(hipStream_t s, const T* A, int N, bool bordered, bool accu
 size_t body_gemm_workspace(int N, int nbt, bool bordered);
 // dense intra-body real-space block of one shape (realspace.hip)
 void build_near_block(hipStream_t s, const BodyType& t, const RealGeom& rg, double* R64, float* R32);
+
+// The saddle-point operator y = [-M q + Sigma^T dpsi; Sigma q] of the loaded
+// configuration for x = [q; dpsi] (prec: PE_FP64 or PE_MIXED kernels).
+void saddle_product(pe_context* c, int prec, const double* x, double* y);
+// Grand capacitance C (device, row-major (4 n_body)^2) and the effective
+// permittivity (host 3 x 3, may be null) of the loaded configuration.
+void grand_capacitance(pe_context* c, double* C_out, double* eps_out, pe_solve_info* info);
 
 // body / vector kernels
 void launch_body_sums(hipStream_t s, pe_context* c, const double* q, double* out_sum, double* out_sig2);

@@ -122,6 +122,10 @@ void build_type_inverse(pe_context* c, BodyType& t) {
     hipLaunchKernelGGL(gj_update_kernel, dim3(nb), dim3(256), 0, s, M.get(), N, k, f.get(), rowk.get());
   }
   PE_CHECK_LAUNCH();
+  // keep M_ii^-1 itself (block-Jacobi preconditioner of M alone, e.g. for
+  // the capacitance solves)
+  t.Minv.ensure((size_t)NN);
+  PE_HIP(hipMemcpyAsync(t.Minv.get(), M.get(), sizeof(double) * NN, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(rowsum_kernel, dim3((N + 255) / 256), dim3(256), 0, s, M.get(), N, u.get());
   PE_CHECK_LAUNCH();
   std::vector<double> hu(N);

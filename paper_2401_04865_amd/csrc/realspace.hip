@@ -70,12 +70,52 @@ __device__ __forceinline__ T erf_diff(T b, T xi, T r) {
   return erfc(xi * r) - erfc(br);
 }
 
+// The paper's split for shells of radius a (j0^2(ka) in both parts): the
+// real-space kernel is the inverse transform of (1 - h(k)) j0^2(ka) / k^2,
+// whose printed closed form (its Heaviside term read as
+// -(1/(4 pi r) - (4a - r)/(16 pi a^2)) H(2a - r)) regroups as a second
+// difference,
+//   R(r) = [g(r + 2a) + g(r - 2a) - 2 g(r)] / (a^2 r) - Heaviside term,
+//   g(s) = (2 xi^2 s^2 + 1) erfc(xi s) / (64 pi xi^2) - s exp(-xi^2 s^2) / (32 pi^1.5 xi),
+//   g'(s) = (s erfc(xi s) - exp(-xi^2 s^2) / (sqrt(pi) xi)) / (16 pi).
+// The difference cancels about (a xi)^-2 of the leading digits, so it is
+// formed in double whatever the caller's precision.
+__device__ __forceinline__ void shell_paper_g(double s, double xi, double& gv, double& g1) {
+  const double ec = erfc(xi * s), ex = exp(-xi * xi * s * s);
+  gv = (2.0 * xi * xi * s * s + 1.0) * ec * (1.0 / (64.0 * kPi)) / (xi * xi) - s * ex / (32.0 * kPi * sqrt(kPi) * xi);
+  g1 = (s * ec - ex / (sqrt(kPi) * xi)) * (1.0 / (16.0 * kPi));
+}
+
+__device__ __forceinline__ void shell_paper_kernel(double r, const RealGeom& g, double& R, double& dR) {
+  const double a = g.a, xi = g.xi, c = 1.0 / g.eps;
+  double gp, g1p, gm, g1m, g0, g10;
+  shell_paper_g(r + 2.0 * a, xi, gp, g1p);
+  shell_paper_g(r - 2.0 * a, xi, gm, g1m);
+  shell_paper_g(r, xi, g0, g10);
+  const double G = gp + gm - 2.0 * g0, G1 = g1p + g1m - 2.0 * g10;
+  const double ia2 = 1.0 / (a * a);
+  double v = G * ia2 / r, d = G1 * ia2 / r - G * ia2 / (r * r);
+  if (r < 2.0 * a) {
+    v -= kInv4Pi / r - (4.0 * a - r) * ia2 * (1.0 / (16.0 * kPi));
+    d -= -kInv4Pi / (r * r) + ia2 * (1.0 / (16.0 * kPi));
+  }
+  R = c * v;
+  dR = c * d;
+}
+
 // R(r) and dR/dr for one pair (r > 0).
 template <typename T>
 __device__ __forceinline__ void pair_kernel(T r, T s2, const RealGeom& g, T& R, T& dR, bool want_d) {
   const T xi = (T)g.xi;
   const T c = (T)(kInv4Pi / g.eps);
   const T inv_r = (T)1 / r;
+  if (g.reg == PE_REG_SHELL_PAPER) {
+    double Rd, dRd;
+    shell_paper_kernel((double)r, g, Rd, dRd);
+    R = (T)Rd;
+    if (want_d) dR = (T)dRd;
+    return;
+  }
   if (g.reg == PE_REG_GAUSSIAN) {
     const T b = rsqrt((T)2 * s2);
     const T D = erf_diff<T>(b, xi, r);
@@ -114,6 +154,12 @@ template <typename T>
 __device__ __forceinline__ T self_value(T s2, const RealGeom& g) {
   const T c = (T)(kInv4Pi / g.eps);
   if (g.reg == PE_REG_GAUSSIAN) return c * (T)kTwoOverSqrtPi * (rsqrt((T)2 * s2) - (T)g.xi);
+  if (g.reg == PE_REG_SHELL_PAPER) {
+    // the printed self term of the paper's split (the kernel's r -> 0 limit)
+    const double a = g.a, xi = g.xi;
+    return (T)(((1.0 - exp(-4.0 * a * a * xi * xi)) / (8.0 * kPi * sqrt(kPi) * a * a * xi) +
+                erfc(2.0 * a * xi) * kInv4Pi / a) / g.eps);
+  }
   return c * ((T)1 / (T)g.a - (T)2 * (T)g.xi / (T)sqrt(kPi));
 }
 

@@ -77,6 +77,10 @@ __global__ void moments_final_kernel(const double* __restrict__ partial, int nb,
     if (cc.reg == PE_REG_GAUSSIAN) {
       ck[0] = cc.inv_epsV * (Sq * cc.inv4xi2 - 0.5 * Ssq);
       ck[1] = cc.inv_epsV * 0.5 * Sq;
+    } else if (cc.reg == PE_REG_SHELL_PAPER) {
+      // (1 - h) j0^2 / k^2 -> 1 / (4 xi^2) as k -> 0
+      ck[0] = cc.inv_epsV * cc.inv4xi2 * Sq;
+      ck[1] = 0.0;
     } else {
       ck[0] = cc.inv_epsV * (cc.inv4xi2 - cc.a * cc.a / 3.0) * Sq;
       ck[1] = 0.0;

@@ -244,11 +244,13 @@ def place_ions(rng, box, n_pos, n_neg, centers, exclusion, sigma=0.1,
     while have < need:
         cand = rng.random((batch, 3)) * box
         ok = np.ones(batch, dtype=bool)
+        # only whether a neighbour lies within the exclusion matters, so the
+        # searches stop there (a candidate with none gets d = inf)
         if ctree is not None:
-            d, _ = ctree.query(cand, k=1)
+            d, _ = ctree.query(cand, k=1, distance_upper_bound=exclusion)
             ok &= d >= exclusion
         if btree is not None:
-            d, _ = btree.query(cand, k=1)
+            d, _ = btree.query(cand, k=1, distance_upper_bound=bead_exclusion)
             ok &= d >= bead_exclusion
         cand = cand[ok][: need - have]
         out.append(cand)
@@ -362,7 +364,8 @@ def config(k: int, seed: int | None = None, **over) -> System:
                         mesh=over.get("mesh", (192, 192, 192)))
         n_ion = over.get("n_ion", 100000)
         ip, iq, isg = place_ions(rng, [L] * 3, n_ion // 2, n_ion // 2, np.zeros((0, 3)), 0.0,
-                                 bead_pos=sysb.bead_pos, bead_exclusion=0.2)
+                                 bead_pos=sysb.bead_pos, bead_exclusion=0.2,
+                                 batch=over.get("ion_batch", 200_000))
         E0 = random_unit_vector(rng)
         return assemble(L, shapes, c, quats, np.zeros(len(radii)), types, over.get("sigma", 0.05),
                         ip, iq, isg, E0=E0, mesh=over.get("mesh", (192, 192, 192)), name="cfg4")
@@ -388,7 +391,15 @@ def training_system(seed: int, n_body: int = 32, n_ion: int = 12500, L: float = 
     """Reduced-scale system of the cfg4 kind (rods and cubes at the same
     density): the source of training solves for the learned initial guess."""
     return config(4, seed=seed, L=L, n_rod=n_body // 2, n_cube=n_body - n_body // 2,
-                  n_ion=n_ion, mesh=mesh)
+                  n_ion=n_ion, mesh=mesh, ion_batch=2 * n_ion)
+
+
+def training_spheres(seed: int, n_body: int = 64, mesh=(128, 128, 128)) -> System:
+    """Reduced-scale system of the 512-sphere kind (charged level-3 spheres,
+    volume fraction 0.1, the same ion density and grid spacing): training
+    solves for the learned warm start of the Brownian-dynamics workload."""
+    n_ion = int(round(1_000_000 * n_body / 512))
+    return config(5, seed=seed, n_body=n_body, n_ion=n_ion, mesh=mesh)
 
 
 def small_random_system(seed: int, n_body: int = 2, level: int = 1, n_ion: int = 20,

@@ -80,3 +80,17 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(out[st]) == ctypes.sizeof(cls)
         for f in fields[st]:
             assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
+
+
+def test_library_allocates_no_device_memory():
+    """Every device buffer comes from the caller's workspace: no source of
+    the library calls a device allocator."""
+    import glob
+    srcs = glob.glob(os.path.join(ROOT, "paper_2401_04865_amd", "csrc", "*.hip")) + \
+        glob.glob(os.path.join(ROOT, "paper_2401_04865_amd", "csrc", "*.hpp"))
+    assert srcs
+    pat = re.compile(r"\b(hipMalloc|hipMallocAsync|hipMallocManaged|hipMallocPitch|hipMalloc3D|hipExtMallocWithFlags|"
+                     r"hipMallocFromPoolAsync|hipFree|hipFreeAsync)\s*\(")
+    for f in srcs:
+        text = re.sub(r"//[^\n]*", "", open(f).read())
+        assert not pat.search(text), f

@@ -198,3 +198,32 @@ def test_bd_step_matches_oracle(gpu_lib):
         ctx.pe_solve_polarization(None, torch.empty(s.n_bead, dtype=torch.float64, device="cuda"),
                                   torch.empty(s.n_body, dtype=torch.float64, device="cuda"))
     ctx.close()
+
+
+def test_bd_step_with_hard_spheres_matches_oracle(gpu_lib):
+    """The step with the potential-free hard-sphere forces (ions against ions
+    and against beads of the bodies) against the oracle's step with its own
+    brute-force hard-sphere forces, driven by the oracle's electrostatic
+    forces; noise and all."""
+    B = gpu_lib
+    s = inputs.small_random_system(8, n_body=2, level=1, n_ion=80, L=6.0, sigma=0.16, mesh=(48, 48, 48),
+                                   charges=[0.4, -0.1])
+    a = 0.2
+    fb_hs, fi_hs = bd.hard_sphere_forces(s, a, 1.0, 1e-3)
+    assert np.abs(fb_hs).max() > 0 and np.abs(fi_hs).max() > 0   # both kinds of contact occur
+    p = B.make_params(s.box, s.mesh, P=14, eta_c=0.95, split_tol=1e-12, rel_tol=1e-13, hs_radius=a)
+    ctx = B.Context(p).load(s)
+    ctx.solve()
+    ctx.forces()
+    d = ctx.sys_dev
+    dt, kT, gamma, seed, step_no = 1e-3, 1.0, 1.0, 777, 3
+    ctx.pe_bd_step(dt, kT, gamma, seed, step_no, d["bead_pos"], d["body_center"], d["body_quat"], d["ion_pos"])
+    qe, dpe, M, b = saddle.solve(s, xi=1.1)
+    ref = saddle.forces_torques(s, qe, 1.1)
+    pos, X, Q, ion = bd.step(s, ref["body_force"], ref["body_torque"], ref["ion_force"], dt, kT, gamma, seed,
+                             step_no, hs_radius=a)
+    np.testing.assert_allclose(d["ion_pos"].cpu().numpy(), ion, atol=1e-9)
+    np.testing.assert_allclose(d["body_center"].cpu().numpy(), X, atol=1e-9)
+    np.testing.assert_allclose(d["body_quat"].cpu().numpy(), Q, atol=1e-9)
+    np.testing.assert_allclose(d["bead_pos"].cpu().numpy(), pos, atol=1e-9)
+    ctx.close()
