@@ -388,6 +388,21 @@ pe_status pe_bd_step(pe_context* ctx, double dt, double kT, double gamma, uint64
                      uint64_t step, double* bead_pos, double* body_center, double* body_quat,
                      double* ion_pos);
 
+/*
+ * pe_bd_step without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid it): the same step and the same kernels as
+ * pe_bd_step, bit for bit, with the per-body rotations kept in a static
+ * device array of the library (one per GPU, 9 doubles for each of at most
+ * 65536 bodies, held until the process ends) instead of the workspace.
+ * Arguments and state requirements as pe_bd_step; PE_ERR_ARG for more than
+ * 65536 bodies.  Every call on one GPU uses that GPU's array: calls that
+ * overlap on one GPU (several contexts or threads) race.
+ */
+pe_status pe_bd_step_noalloc(pe_context* ctx, double dt, double kT, double gamma, uint64_t seed,
+                             uint64_t step, double* bead_pos, double* body_center, double* body_quat,
+                             double* ion_pos);
+
 #ifdef __cplusplus
 }
 #endif

@@ -111,6 +111,7 @@ SIGNATURES = {
     "pe_guess_debug": [_vp, _vp, _i32, _i64, _vp, ctypes.POINTER(_dbl)],
     "pe_guess_rows": [_vp, _vp, _i64],
     "pe_guess_add_rows": [_vp, _vp, _i64],
+    "pe_bd_step_noalloc": [_vp, _dbl, _dbl, _dbl, _u64, _u64, _vp, _vp, _vp, _vp],
     "pe_grand_capacitance": [_vp, _vp, ctypes.POINTER(_dbl), ctypes.POINTER(pe_solve_info)],
     "pe_workspace_size": [_vp, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
     "pe_set_workspace": [_vp, _vp, ctypes.c_size_t],

@@ -948,6 +948,9 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
     PE_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     c->lds_per_block = lds;
     c->device = dev;
+    // the allocation-free BD step's scratch array: its device address on
+    // this GPU, looked up here (the library's init call) with the device current
+    bd_static_scratch(dev);
   }
   pe::FFTPlan1D tmp;
   for (int d = 0; d < 3; ++d) make_fft_plan(p.mesh[d], tmp);

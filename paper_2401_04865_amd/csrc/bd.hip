@@ -15,6 +15,7 @@
 // normal by the Box-Muller transform.  Ions use streams 0/1, bodies 2/3
 // (translation / rotation), so every number is fixed by (seed, step, index).
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -427,11 +428,61 @@ void bd_launch(pe_context* c, double dt, double kT, double gamma, uint64_t seed,
   c->have_forces = false;
 }
 
+// Scratch of the allocation-free step: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code uses only the device
+// address looked up for each GPU (the array's name is a host-side stand-in).
+constexpr int64_t kMaxStaticBodies = 65536;   // 4.5 MiB of rotations
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // per device; null until looked up
+
 }  // namespace
+
+static __device__ __align__(256) double scratch[9 * kMaxStaticBodies];
+
+// Looks up (once per device, with that device current) the address of that
+// device's copy of the scratch array.
+double* bd_static_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev >= (int)g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    PE_HIP(hipGetDevice(&cur));
+    if (cur != dev) PE_HIP(hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) PE_HIP(hipSetDevice(cur));
+    if (e != hipSuccess)
+      throw Error(PE_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
 
 }  // namespace pe
 
 using namespace pe;
+
+extern "C" pe_status pe_bd_step_noalloc(pe_context* c, double dt, double kT, double gamma, uint64_t seed,
+                                        uint64_t step, double* bead_pos, double* body_center, double* body_quat,
+                                        double* ion_pos) {
+  if (!c) return PE_ERR_ARG;
+  try {
+    require(!(c->p.hs_radius > 0), "pe_bd_step_noalloc: hard spheres need workspace buffers (hs_radius must be 0)");
+    if (c->n_body > kMaxStaticBodies)
+      throw Error(PE_ERR_ARG, "pe_bd_step_noalloc: more than " + std::to_string(kMaxStaticBodies) +
+                                  " bodies (the static scratch holds that many)");
+    double* R = bd_static_scratch(c->device);
+    bd_launch(c, dt, kT, gamma, seed, step, bead_pos, body_center, body_quat, ion_pos, R);
+  } catch (const Error& e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return PE_ERR_DEVICE;
+  }
+  return PE_OK;
+}
 
 extern "C" pe_status pe_bd_step(pe_context* c, double dt, double kT, double gamma, uint64_t seed, uint64_t step,
                                 double* bead_pos, double* body_center, double* body_quat, double* ion_pos) {

@@ -545,6 +545,10 @@ void saddle_product(pe_context* c, int prec, const double* x, double* y);
 // permittivity (host 3 x 3, may be null) of the loaded configuration.
 void grand_capacitance(pe_context* c, double* C_out, double* eps_out, pe_solve_info* info);
 
+// Device address of this GPU's copy of the allocation-free BD step's static
+// scratch array (looked up once per device, with that device current).
+double* bd_static_scratch(int dev);
+
 // body / vector kernels
 void launch_body_sums(hipStream_t s, pe_context* c, const double* q, double* out_sum, double* out_sig2);
 void launch_seg_totals(hipStream_t s, int64_t n_body, const double* body_sum, const double* body_sig2,
