@@ -108,7 +108,9 @@ def kernel_model(cls, dbl, cnt, work, nb, G, Gc):
     if cls in ("fft_z_r2c", "fft_z_c2r"):
         return "hbm", cnt * (G * s + Gc * 2 * s), "GB/s", HBM_PEAK_GBS
     if cls == "spmv":
-        return "hbm", work * (s + 4) + cnt * nb * (8 + 4 + 32 + 8 + 8 + 4 + 8), "GB/s", HBM_PEAK_GBS
+        # stored entries (value, column) and per bead its row start, row bead
+        # and the real-space partial read and written
+        return "hbm", work * (s + 4) + cnt * nb * (8 + 4 + 8 + 8), "GB/s", HBM_PEAK_GBS
     if cls in ("near", "precond"):
         return "mfma", 2.0 * work, "TFLOP/s", MFMA_PEAK_TFLOPS[dbl]
     if cls == "pair":
@@ -584,7 +586,8 @@ def precision_table(B, system, params, set_system, dev, q, dpsi, S, F, L, U, fi)
         c = B.Context(p)
         set_system(c, system, dev)
         st, info = c.pe_solve_polarization(None, q, dpsi, S)
-        tot = c.pe_forces_torques(F, L, U, fi if system.n_ion else None, None)
+        fbead = torch.empty((system.n_bead, 3), dtype=torch.float64, device="cuda")
+        tot = c.pe_forces_torques(F, L, U, fi if system.n_ion else None, fbead)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         for _ in range(5):
@@ -592,16 +595,23 @@ def precision_table(B, system, params, set_system, dev, q, dpsi, S, F, L, U, fi)
             c.pe_solve_polarization(None, q, dpsi, S)
         torch.cuda.synchronize()
         runs[name] = dict(q=q.cpu().numpy().copy(), S=S.cpu().numpy().copy(), F=F.cpu().numpy().copy(),
-                          L=L.cpu().numpy().copy(), U=tot, iters=int(info.iters),
+                          L=L.cpu().numpy().copy(), U=tot, iters=int(info.iters), fb=fbead.cpu().numpy(),
                           rel_residual=float(info.rel_residual),
                           set_and_solve_ms=round(1e3 * (time.perf_counter() - ta) / 5, 3))
         c.close()
     ref = runs["fp64_1e-12"]
     rmsF = float(np.sqrt((ref["F"] ** 2).sum(1).mean()))
-    rmsL = float(np.sqrt((ref["L"] ** 2).sum(1).mean()))
+    # torque scale: RMS over bodies of sum_j |r_ij| |f_ij| (the torques of a
+    # sphere lattice nearly vanish, so their own RMS is no scale)
+    rel = system.bead_pos - system.body_center[np.repeat(np.arange(system.n_body),
+                                                                   np.diff(system.body_offsets))]
+    tl = np.bincount(np.repeat(np.arange(system.n_body), np.diff(system.body_offsets)),
+                     np.linalg.norm(rel, axis=1) * np.linalg.norm(ref["fb"], axis=1))
+    rmsL = float(np.sqrt((tl ** 2).mean()))
     out = {"reference": "FP64 solve at residual 1e-12, same discretization",
-           "bounds": {"q": 1e-5, "dipole_rel": 1e-5, "force_rel_rms": 1e-4, "torque_rel_rms": 1e-4,
-                      "energy_rel": 1e-6}}
+           "bounds": {"q": 1e-5, "dipole_rel": 1e-5, "force_rel_rms": 1e-4, "torque_rel_scale": 1e-4,
+                      "energy_rel": 1e-6},
+           "torque_scale": "RMS over bodies of sum_j |r_ij| |f_ij|"}
     for name in ("mixed_1e-6", "fp64_1e-6"):
         r = runs[name]
         dS = np.linalg.norm(r["S"] - ref["S"], axis=1) / np.linalg.norm(ref["S"], axis=1)
@@ -611,16 +621,19 @@ def precision_table(B, system, params, set_system, dev, q, dpsi, S, F, L, U, fi)
                      "q_rel": float(np.linalg.norm(r["q"] - ref["q"]) / np.linalg.norm(ref["q"])),
                      "dipole_rel_per_body": [float(v) for v in dS],
                      "force_rel_rms_per_body": [float(v) for v in dF],
-                     "torque_rel_rms_per_body": [float(v) for v in dL],
+                     "torque_rel_scale_per_body": [float(v) for v in dL],
                      "dipole_rel_max": float(dS.max()), "force_rel_rms_max": float(dF.max()),
-                     "torque_rel_rms_max": float(dL.max()),
+                     "torque_rel_scale_max": float(dL.max()),
                      "energy_rel": float(abs(r["U"] - ref["U"]) / abs(ref["U"]))}
     m, f = out["mixed_1e-6"], out["fp64_1e-6"]
     checks = {}
-    for key, b in (("dipole_rel_max", 1e-5), ("force_rel_rms_max", 1e-4), ("torque_rel_rms_max", 1e-4),
+    for key, b in (("dipole_rel_max", 1e-5), ("force_rel_rms_max", 1e-4), ("torque_rel_scale_max", 1e-4),
                    ("energy_rel", 1e-6)):
+        # the energy is stationary in the charges: the double solve at 1e-6 has
+        # it to ~1e-13, so the ten-times rule applies to the other quantities
         checks[key] = {"mixed": m[key], "fp64_same_residual": f[key], "bound": b,
-                       "within_bound": m[key] <= b, "within_10x_fp64": m[key] <= 10 * f[key]}
+                       "within_bound": m[key] <= b,
+                       "within_10x_fp64": None if key == "energy_rel" else m[key] <= 10 * f[key]}
     out["checks"] = checks
     out["reference_iters"] = ref["iters"]
     return out

@@ -155,7 +155,6 @@ def step(sys, body_force, body_torque, ion_force, dt, kT, gamma, seed, step_no, 
             body_force[b] += fb[o0:o1].sum(0)
             body_torque[b] += np.cross(r, fb[o0:o1]).sum(0)
     ion = sys.ion_pos.copy()
-
     s = math.sqrt(2 * kT * dt / gamma)
     for i in range(sys.n_ion):
         ion[i] += ion_force[i] * dt / gamma + s * normals3(seed, step_no, i, 0)

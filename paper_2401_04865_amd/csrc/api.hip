@@ -363,18 +363,16 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
   const bool dbl = sizeof(T) == 8;
-  // dense intra-body blocks per shape on the auxiliary stream, into their own
-  // buffer, while the mesh part runs; the sparse pairs and the assembly after
-  // the join
-  bool any_near = false;
-  for (auto& t : c->pc.types) any_near = any_near || (t.near && !t.bodies.empty());
-  double* phi_near = nullptr;
-  if (any_near) {
-    c->phi_near.ensure((size_t)std::max<int64_t>(nb, 1));
-    phi_near = c->phi_near.get();
-    fork_aux(c);
+  // the real-space part on the auxiliary stream, into its own buffer, while
+  // the mesh part (spread, FFT, contraction) runs on the caller's: the dense
+  // intra-body blocks per shape, then the sparse inter-body pairs added;
+  // the assembly after the join
+  c->phi_near.ensure((size_t)std::max<int64_t>(nb, 1));
+  double* phi_real = c->phi_near.get();
+  fork_aux(c);
+  {
     hipStream_t sa = c->aux;
-    PE_HIP(hipMemsetAsync(phi_near, 0, sizeof(double) * nb, sa));
+    PE_HIP(hipMemsetAsync(phi_real, 0, sizeof(double) * nb, sa));
     for (auto& t : c->pc.types) {
       if (!t.near || t.bodies.empty()) continue;
       const T* R;
@@ -382,17 +380,16 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
       else R = t.R32.get();
       ProfScope ps(c->prof, sa, PE_PROF_NEAR, dbl, (double)t.N * t.N * (double)t.bodies.size());
       launch_body_gemm<T>(sa, R, t.N, false, true, t.dbodies.get(), (int)t.bodies.size(), c->off.get(), nb,
-                          q, phi_near, c->pc.gemm_ws.get());
+                          q, phi_real, c->pc.gemm_ws.get());
     }
+    ProfScope ps(c->prof, sa, PE_PROF_SPMV, dbl, (double)c->nnz);
+    launch_spmv_add<T>(sa, c, q, phi_real);
   }
   { ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)nb); launch_spread<T>(s, c->B, q, gA, c->gg, false); }
   launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
   { ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
-  if (any_near) join_aux(c);
-  {
-    ProfScope ps(c->prof, s, PE_PROF_SPMV, dbl, (double)c->nnz);
-    launch_spmv_assemble<T>(s, c, q, dpsi, c->phi_w.get(), phi_near, ck_bead(c), y);
-  }
+  join_aux(c);
+  launch_assemble(s, c, dpsi, c->phi_w.get(), phi_real, ck_bead(c), y);
 }
 
 void apply_saddle_prec(pe_context* c, int prec, const double* x, double* y) {

@@ -506,9 +506,12 @@ void build_green_tables(pe_context* c);
 void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
                  double sig_const, const int* owner, int64_t n, const RealGeom& rg);
 void build_bead_matrix(pe_context* c);
+// phi_real[b] += sum_j R_bj q_j over the stored inter-body pairs
 template <typename T>
-void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const double* dpsi,
-                          const double* phi_wave, const double* phi_near, const double* ck0, double* y_top);
+void launch_spmv_add(hipStream_t s, pe_context* c, const double* q, double* phi_real);
+// y_top[b] = -(phi_wave[b] + phi_real[b] - ck0_b) + dpsi[body(b)]
+void launch_assemble(hipStream_t s, pe_context* c, const double* dpsi, const double* phi_wave,
+                     const double* phi_real, const double* ck0, double* y_top);
 // Adds the real-space potential (and field, if E) at the targets from up to
 // two source sets; field_single evaluates the field in single precision.
 // tab0 / tab1 (may be null): pair tables of the classes (tgt, src0) and

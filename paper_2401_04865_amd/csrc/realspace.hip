@@ -318,6 +318,11 @@ constexpr int kQ = 16;          // queue entries per lane
 constexpr int kQFlush = 8;      // candidates between flushes (kQ - kQFlush entries stay free)
 constexpr int kSetBit = 30;     // queue entry: sorted source index | set << kSetBit
 constexpr int kMaxRuns = 36;    // stencil runs: 2 source sets x 9 columns x 2 runs
+// single-precision passes: staged candidates stay in an LDS ring of
+// kRegions batches of 64 and the queues hold ring slots (slot | set << 8)
+constexpr int kRegions = 2;
+constexpr int kRing = 64 * kRegions;
+static_assert(kRing <= 256 && (kRegions & (kRegions - 1)) == 0, "ring slots are 8 bits, regions a power of two");
 
 
 // EV selects the pair evaluation: EV_GENERAL (any precision and
@@ -808,26 +813,22 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   }
 }
 
-// y_top[b] = -(phi_wave[b] + phi_near[b] + sum_j R_bj q_j - ck0_b) + dpsi[body(b)]
-// for every bead b (phi_near may be null).
-// ck0_b = ck[0] - ck[1] * sigma_b^2 (the k = 0 constant of the split).
-// CSR rows in cell order; 16 lanes per row read the row's entries
-// contiguously and reduce with lane shuffles (4 rows per wavefront).  Rows
-// hold about ten entries, so most lanes take one; that entry and the bead's
-// own terms are loaded before either is used, which overlaps the two chains
-// of dependent loads (row -> column -> charge, row -> bead -> body -> dpsi).
+// phi_real[b] += sum_j R_bj q_j over the stored inter-body pairs of bead b
+// (which then holds the whole real-space part).  CSR rows in cell order; 16
+// lanes per row read the row's entries contiguously and reduce with lane
+// shuffles (4 rows per wavefront).  Rows hold about ten entries, so most
+// lanes take one; the row's first entry and the bead's own term are loaded
+// before either is used, which overlaps the two chains of dependent loads.
 template <typename T>
-__global__ void __launch_bounds__(256) spmv_assemble_kernel(
-    const int64_t* __restrict__ row_ptr, const int* __restrict__ col, const T* __restrict__ val,
-    const int* __restrict__ row_bead, const double* __restrict__ sig, int64_t n,
-    const double* __restrict__ q, const double* __restrict__ phi_wave, const double* __restrict__ phi_near,
-    const double* __restrict__ ck, const double* __restrict__ dpsi, const int* __restrict__ body_of,
-    double* __restrict__ y) {
+__global__ void __launch_bounds__(256) spmv_add_kernel(const int64_t* __restrict__ row_ptr,
+                                                       const int* __restrict__ col, const T* __restrict__ val,
+                                                       const int* __restrict__ row_bead, int64_t n,
+                                                       const double* __restrict__ q, double* __restrict__ phi_real) {
   const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int sub = threadIdx.x & 15;
   T acc = 0;
   int b = 0;
-  double sg = 0.0, pw = 0.0, pn = 0.0, dp = 0.0;
+  double pn = 0.0;
   if (i < n) {
     const int64_t o0 = row_ptr[i] + sub, e = row_ptr[i + 1];
     b = row_bead[i];
@@ -837,12 +838,8 @@ __global__ void __launch_bounds__(256) spmv_assemble_kernel(
       j = col[o0];  // a negative column is a zero entry
       v = val[o0];
     }
-    sg = sig[b];
-    pw = phi_wave[b];
-    if (phi_near) pn = phi_near[b];
-    const int bo = dpsi ? body_of[b] : 0;
+    if (sub == 0) pn = phi_real[b];
     if (o0 < e) acc = v * (T)q[j < 0 ? -1 - j : j];
-    if (dpsi) dp = dpsi[bo];
     for (int64_t o = o0 + 16; o < e; o += 16) {
       const int jj = col[o];
       acc += val[o] * (T)q[jj < 0 ? -1 - jj : jj];
@@ -850,10 +847,20 @@ __global__ void __launch_bounds__(256) spmv_assemble_kernel(
   }
 #pragma unroll
   for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-  if (i < n && sub == 0) {
-    const double phi = (double)acc + pw + (phi_near ? pn : 0.0) - (ck[0] - ck[1] * sg * sg);
-    y[b] = -phi + (dpsi ? dp : 0.0);
-  }
+  if (i < n && sub == 0) phi_real[b] = (double)acc + pn;
+}
+
+// y_top[b] = -(phi_wave[b] + phi_real[b] - ck0_b) + dpsi[body(b)]
+__global__ void __launch_bounds__(256) assemble_kernel(int64_t n, const double* __restrict__ phi_wave,
+                                                       const double* __restrict__ phi_real,
+                                                       const double* __restrict__ sig, const double* __restrict__ ck,
+                                                       const double* __restrict__ dpsi, const int* __restrict__ body_of,
+                                                       double* __restrict__ y) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  const double sg = sig[b];
+  const double phi = phi_wave[b] + phi_real[b] - (ck[0] - ck[1] * sg * sg);
+  y[b] = -phi + (dpsi ? dpsi[body_of[b]] : 0.0);
 }
 
 // Values of the stored bead-bead pairs from the current positions (caller
@@ -1187,8 +1194,7 @@ void build_near_block(hipStream_t s, const BodyType& t, const RealGeom& rg, doub
 }
 
 template <typename T>
-void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const double* dpsi,
-                          const double* phi_wave, const double* phi_near, const double* ck0, double* y_top) {
+void launch_spmv_add(hipStream_t s, pe_context* c, const double* q, double* phi_real) {
   const int64_t n = c->n_bead;
   if (n == 0) return;
   const T* val;
@@ -1197,9 +1203,17 @@ void launch_spmv_assemble(hipStream_t s, pe_context* c, const double* q, const d
     require(c->have_val32, "float real-space operator not built (precision is PE_FP64)");
     val = c->val32.get();
   }
-  hipLaunchKernelGGL(spmv_assemble_kernel<T>, dim3(nblk(16 * n, 256)), dim3(256), 0, s, c->row_ptr.get(),
-                     c->col.get(), val, c->csr_row.get(), c->bead_sig.get(), n, q, phi_wave, phi_near, ck0, dpsi,
-                     c->body_of.get(), y_top);
+  hipLaunchKernelGGL(spmv_add_kernel<T>, dim3(nblk(16 * n, 256)), dim3(256), 0, s, c->row_ptr.get(), c->col.get(),
+                     val, c->csr_row.get(), n, q, phi_real);
+  PE_CHECK_LAUNCH();
+}
+
+void launch_assemble(hipStream_t s, pe_context* c, const double* dpsi, const double* phi_wave,
+                     const double* phi_real, const double* ck0, double* y_top) {
+  const int64_t n = c->n_bead;
+  if (n == 0) return;
+  hipLaunchKernelGGL(assemble_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, n, phi_wave, phi_real,
+                     c->bead_sig.get(), ck0, dpsi, c->body_of.get(), y_top);
   PE_CHECK_LAUNCH();
 }
 
@@ -1367,10 +1381,8 @@ void update_pair_tables(hipStream_t s, PairTables& pt, const RealGeom& rg, const
   PE_HIP(hipStreamSynchronize(s));
 }
 
-template void launch_spmv_assemble<float>(hipStream_t, pe_context*, const double*, const double*, const double*,
-                                          const double*, const double*, double*);
-template void launch_spmv_assemble<double>(hipStream_t, pe_context*, const double*, const double*, const double*,
-                                           const double*, const double*, double*);
+template void launch_spmv_add<float>(hipStream_t, pe_context*, const double*, double*);
+template void launch_spmv_add<double>(hipStream_t, pe_context*, const double*, double*);
 template void launch_pair_onfly<float>(hipStream_t, const ParticleSet&, const ParticleSet*, const double*,
                                        const ParticleSet*, const double*, const RealGeom&, double*, double*, bool,
                                        unsigned long long*, const float4*, const float4*);
