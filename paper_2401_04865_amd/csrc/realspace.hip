@@ -35,6 +35,7 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <type_traits>
 
 #include "pe_internal.hpp"
 #include "vector.hpp"
@@ -332,7 +333,7 @@ static_assert(kRing <= 256 && (kRegions & (kRegions - 1)) == 0, "ring slots are 
 enum { EV_GENERAL = 0, EV_ERFCX = 1, EV_TABLE = 2 };
 
 template <int MODE, typename T, typename TF, int EV>
-__global__ void __launch_bounds__(256) pair_queue_kernel(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == EV_TABLE ? 6 : 1))) pair_queue_kernel(
     const double4* __restrict__ tpos, const int* __restrict__ tidx, const int* __restrict__ tstart,
     const int4* __restrict__ chunks, int nchunk, SrcSet s0, SrcSet s1, int nsrc, RealGeom g, float rc2f,
     PairOut out) {
@@ -340,8 +341,16 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
                 "table evaluations are single-precision potential / field passes");
   constexpr bool kOwn = MODE == MODE_COUNT || MODE == MODE_FILL;
   constexpr int kTabF4 = EV == EV_TABLE ? 4 * kPairTabPieces : (EV == EV_ERFCX ? 2 * kErfcxPieces : 1);
-  __shared__ int qbuf[kWaves][kQ][64];
-  __shared__ float4 cbuf[kWaves][64];
+  // Single-precision passes keep every staged candidate (position in the
+  // target frame, charge, width) in an LDS ring and queue ring slots, so a
+  // pair's evaluation reads LDS only; the general pass queues source indices
+  // and reads the double records from global memory.
+  constexpr bool kRingQ = EV != EV_GENERAL;
+  using QE = typename std::conditional<kRingQ, unsigned short, int>::type;
+  __shared__ QE qbuf[kWaves][kQ][64];
+  __shared__ float4 cbuf[kWaves][kRingQ ? kRing : 64];  // ring: x, y, z; w: slot | set << 8
+  __shared__ float cq[kRingQ ? kWaves : 1][kRingQ ? kRing : 1];                // ring: charge
+  __shared__ float cw[EV == EV_ERFCX ? kWaves : 1][EV == EV_ERFCX ? kRing : 1];  // ring: width
   __shared__ float4 etab[kTabF4];
   __shared__ int cownb[kOwn ? kWaves : 1][64];  // owner tags of the staged candidates (count / fill)
   __shared__ int rstart[kWaves][kMaxRuns + 1];
@@ -376,7 +385,7 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   const int rx = nc0 >= 3 ? 1 : 0, ry = nc1 >= 3 ? 1 : 0, rz = nc2 >= 3 ? 1 : 0;
   const float Lf0 = (float)g.L[0], Lf1 = (float)g.L[1], Lf2 = (float)g.L[2];
   const double a0 = g.L[0] / nc0, a1 = g.L[1] / nc1;
-  int (*qb)[64] = qbuf[wv];
+  QE (*qb)[64] = qbuf[wv];
   int pushed = 0, popped = 0;
 
   // per-target results
@@ -463,42 +472,18 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     }
   };
 
-  // single precision throughout once the minimum-image difference is formed
-  // in double (float coordinates of a large box would cost digits of r)
+  // Single-precision evaluations: the candidate's position was staged in the
+  // target frame (differences formed in double once per candidate, so the
+  // float coordinates stay within about two cells of the origin), and a
+  // lane's queued pair is evaluated from the ring alone.
   const float pw2 = (float)p.w * (float)p.w;
   const float rc2e = (float)g.rc2;
   const float xif = (float)g.xi, cf = (float)(kInv4Pi / g.eps);
-  // Single-precision evaluations are split into a fetch (the source's
-  // position, width and charge) and the arithmetic: the drain takes two
-  // queued sources of a lane per round, issuing both fetches before the
-  // first evaluation, so the second source's loads overlap the first's
-  // arithmetic.
-  struct Src {
-    double x, y, z, w;  // sorted position and width
-    double q;           // charge
-    int set;
-  };
-  auto fetch = [&](int e) {
-    Src o;
-    o.set = e >> kSetBit;
-    const int sidx = e & ((1 << kSetBit) - 1);
-    const double4 qp = o.set ? s1.pos[sidx] : s0.pos[sidx];
-    o.x = qp.x;
-    o.y = qp.y;
-    o.z = qp.z;
-    o.w = qp.w;
-    o.q = o.set ? s1.q[sidx] : s0.q[sidx];
-    return o;
-  };
-  auto evaluate_fast = [&](const Src& sc) {
-    const float dx = (float)min_img(p.x - sc.x, g.L[0], g.inv_L[0]);
-    const float dy = (float)min_img(p.y - sc.y, g.L[1], g.inv_L[1]);
-    const float dz = (float)min_img(p.z - sc.z, g.L[2], g.inv_L[2]);
+  const float iL0 = (float)g.inv_L[0], iL1 = (float)g.inv_L[1], iL2 = (float)g.inv_L[2];
+  auto evaluate_fast = [&](float dx, float dy, float dz, float qf, float sw) {
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     if (!(r2 < rc2e)) return;
     ++nev;
-    const float qf = (float)sc.q;
-    const float sw = (float)sc.w;
     const float s2 = fmaf(sw, sw, pw2);
     float R, F = 0.0f;
     if (r2 == 0.0f) R = self_value<float>(s2, g);
@@ -516,22 +501,19 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   // point and gets no field (inv_r = 0)
   const float tab_w = (float)(kPairTabPieces / sqrt(g.rc2));  // pieces per unit length
   const float tab_d = -2.0f * tab_w;                          // -dt/dr
-  // branch-free: every lane runs the arithmetic and a lane whose source is
-  // not a pair (none queued, or outside r_c in double) adds nothing, so the
-  // loads of both sources of a pass are needed, and issued, up front
-  auto evaluate_tab = [&](const Src& sc, bool valid) {
-    const float dx = (float)min_img(p.x - sc.x, g.L[0], g.inv_L[0]);
-    const float dy = (float)min_img(p.y - sc.y, g.L[1], g.inv_L[1]);
-    const float dz = (float)min_img(p.z - sc.z, g.L[2], g.inv_L[2]);
+  // branch-free: every lane runs the arithmetic and a lane whose entry is
+  // not a pair (none queued) adds nothing, so both ring reads of a pass are
+  // issued up front
+  auto evaluate_tab = [&](float dx, float dy, float dz, float q, int set, bool valid) {
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const bool ok = valid && r2 < rc2e;
     nev += ok ? 1 : 0;
-    const float qf = ok ? (float)sc.q : 0.0f;
+    const float qf = ok ? q : 0.0f;
     const float inv_r = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
     const float w = r2 * inv_r * tab_w;
     const int k = min((int)w, kPairTabPieces - 1);
     const float t = fmaf(2.0f, w - (float)k, -1.0f);
-    const float4* tb = etab + 2 * (sc.set * kPairTabPieces + k);
+    const float4* tb = etab + 2 * (set * kPairTabPieces + k);
     const float4 lo = tb[0], hi = tb[1];
     // value v and slope d = dv/dt in one Horner pass
     float v = hi.w, d = hi.w;
@@ -550,10 +532,12 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     v = fmaf(v, t, lo.x);
     acc += ok ? v * qf : 0.0f;
     if constexpr (MODE == MODE_FIELD) {
-      const float fq = ok ? d * tab_d * inv_r * qf : 0.0f;  // -R'(r) / r q
-      ex += fq * dx;
-      ey += fq * dy;
-      ez += fq * dz;
+      // an entry that is not a pair may hold a padding point (NaN): select,
+      // never multiply by zero
+      const float fq = d * tab_d * inv_r * qf;  // -R'(r) / r q
+      ex += ok ? fq * dx : 0.0f;
+      ey += ok ? fq * dy : 0.0f;
+      ez += ok ? fq * dz : 0.0f;
     }
   };
 
@@ -566,13 +550,15 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   // stream samples all stencil cells evenly: each target then finds its
   // pairs at a steady rate and the queues of all lanes fill alike (a
   // cell-by-cell order feeds the targets near one face first and leaves the
-  // others idle).  Candidates are staged 64 at a time in LDS, relative to
-  // the target column's origin (x, y) and in the target's image (z), and
-  // tested in unrolled groups of kQFlush (the batch is padded with NaN
-  // points, which never hit).  After every group the queues are drained: as
-  // many rounds as keep every lane busy, and at least enough that kQFlush
-  // more pushes cannot overflow any queue; after the last group, everything
-  // left.  (One drain site, so the pair evaluation is emitted once.)
+  // others idle).  Candidates are staged 64 at a time in LDS, in the
+  // frame of the target chunk, and tested in unrolled groups of kQFlush (the
+  // batch is padded with NaN points, which never hit).  After every group
+  // the queues are drained: as many rounds as keep every lane busy, and at
+  // least enough that kQFlush more pushes cannot overflow any queue; after
+  // the last group, everything left.  (One drain site, so the pair
+  // evaluation is emitted once.)  Single-precision passes stage each batch
+  // into the next of the ring's kRegions regions; before a region is staged
+  // again, the drain also empties every queue entry that points into it.
   float4* cb = cbuf[wv];
   int* cown = cownb[kOwn ? wv : 0];
   int* rs = rstart[wv];
@@ -635,10 +621,18 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // target relative to its column's origin (x, y); z as is.  A source's
-  // float x, y are relative to its own column's origin, which lies ox a0,
-  // oy a1 from the target column's origin in the target's image.
-  const float px = (float)(p.x - cx * a0), py = (float)(p.y - cy * a1), pz = (float)p.z;
+  // The target frame.  General passes: x, y relative to the target
+  // column's origin, z as is (a source's float x, y are relative to its own
+  // column's origin, which lies ox a0, oy a1 from the target column's origin
+  // in the target's image).  Single-precision passes: relative to the centre
+  // of the chunk's cells, every coordinate formed in double and rounded once
+  // (a source in the same image subtracts the same double origin, so the
+  // self pair has r = 0 exactly).
+  const double a2 = g.L[2] / nc2;
+  const double fx0 = kRingQ ? (cx + 0.5) * a0 : cx * a0;
+  const double fy0 = kRingQ ? (cy + 0.5) * a1 : cy * a1;
+  const double fz0 = kRingQ ? (cz + 0.5 * nz) * a2 : 0.0;
+  const float px = (float)(p.x - fx0), py = (float)(p.y - fy0), pz = (float)(p.z - fz0);
   const float a0f = (float)a0, a1f = (float)a1, Lz = Lf2;
   // bounding box of the wavefront's targets (same frame as the candidates)
   float bx0 = active ? px : INFINITY, bx1 = active ? px : -INFINITY;
@@ -663,12 +657,17 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
   bz1 = uniform_f(bz1);
   int next = 0, pbase = 0;  // next stream position to stage and (next S) mod M
   int nbat = 0, k0 = 0;
+  int batch = 0;  // batches staged
+  const float4* cnd_base = cb;  // the batch under test
+  // ring: pushed at the end of each of the last kRegions - 1 batches, newest first
+  int ends[kRegions > 1 ? kRegions - 1 : 1] = {};
   const float nanf_ = __int_as_float(0x7fc00000);
   for (;;) {
     bool finished = false;
     if (k0 >= nbat) {
       if (next < M) {
         float4 v = make_float4(nanf_, nanf_, nanf_, nanf_);
+        float vq = 0.0f, vw = 0.0f;  // ring: charge and width
         int own = -1;
         bool keep = false;
         if (next + lane < M) {
@@ -687,9 +686,22 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
           const int zimg = code >> 5;
           const float ofz = zimg == 1 ? -Lz : (zimg == 2 ? Lz : 0.0f);
           const int sidx = rb[lo] + (pos - rs[lo]);
-          const float4 sp = (set ? s1.posf : s0.posf)[sidx];
-          v = make_float4(sp.x + ofx, sp.y + ofy, sp.z + ofz, __int_as_float(sidx | set << kSetBit));
-          own = __float_as_int(sp.w);
+          if constexpr (kRingQ) {
+            // the run's column and z image in the target frame, in double
+            const int ox = ((code >> 1) & 3) - 1, oy = ((code >> 3) & 3) - 1;
+            const double shx = cx + ox < 0 ? -g.L[0] : (cx + ox >= nc0 ? g.L[0] : 0.0);
+            const double shy = cy + oy < 0 ? -g.L[1] : (cy + oy >= nc1 ? g.L[1] : 0.0);
+            const double shz = zimg == 1 ? -g.L[2] : (zimg == 2 ? g.L[2] : 0.0);
+            const double4 sp = (set ? s1.pos : s0.pos)[sidx];
+            v = make_float4((float)(sp.x - (fx0 - shx)), (float)(sp.y - (fy0 - shy)), (float)(sp.z - (fz0 - shz)),
+                            __int_as_float(set << 8));
+            vq = (float)(set ? s1.q : s0.q)[sidx];
+            vw = (float)sp.w;
+          } else {
+            const float4 sp = (set ? s1.posf : s0.posf)[sidx];
+            v = make_float4(sp.x + ofx, sp.y + ofy, sp.z + ofz, __int_as_float(sidx | set << kSetBit));
+            own = __float_as_int(sp.w);
+          }
           keep = true;
           if (!per_pair_image) {
             // farther than the cutoff from the targets' bounding box: no lane can hit it
@@ -702,12 +714,21 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
         // the kept candidates first, in stream order; NaN points after them
         const unsigned long long km = __ballot(keep);
         const int nkeep = __popcll(km);
+        const int region = kRingQ ? (batch & (kRegions - 1)) * 64 : 0;
+        float4* dst = cb + region;
         if (keep) {
           const int slot = __popcll(km & ((1ull << lane) - 1ull));
-          cb[slot] = v;
+          if constexpr (kRingQ) {
+            v.w = __int_as_float(__float_as_int(v.w) | (region + slot));
+            cq[wv][region + slot] = vq;
+            if constexpr (EV == EV_ERFCX) cw[wv][region + slot] = vw;
+          }
+          dst[slot] = v;
           if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) cown[slot] = own;
         }
-        if (lane >= nkeep) cb[lane] = make_float4(nanf_, nanf_, nanf_, nanf_);  // slots past the kept ones
+        if (lane >= nkeep) dst[lane] = make_float4(nanf_, nanf_, nanf_, nanf_);  // slots past the kept ones
+        cnd_base = dst;
+        ++batch;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -723,23 +744,31 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
     if (!finished) {
 #pragma unroll
       for (int kk = 0; kk < kQFlush; ++kk) {
-        const float4 cnd = cb[k0 + kk];
+        const float4 cnd = cnd_base[k0 + kk];
         float dx = px - cnd.x;
         float dy = py - cnd.y;
         float dz = pz - cnd.z;
         if (per_pair_image) {
-          dx -= Lf0 * rintf(dx / Lf0);
-          dy -= Lf1 * rintf(dy / Lf1);
-          dz -= Lf2 * rintf(dz / Lf2);
+          if constexpr (kRingQ) {  // as the evaluation forms them
+            dx -= Lf0 * rintf(dx * iL0);
+            dy -= Lf1 * rintf(dy * iL1);
+            dz -= Lf2 * rintf(dz * iL2);
+          } else {
+            dx -= Lf0 * rintf(dx / Lf0);
+            dy -= Lf1 * rintf(dy / Lf1);
+            dz -= Lf2 * rintf(dz / Lf2);
+          }
         }
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        bool hit = active && r2 < rc2f;
+        // (single-precision passes: the evaluation's own test, on the same
+        // float differences)
+        const float r2 = kRingQ ? fmaf(dx, dx, fmaf(dy, dy, dz * dz)) : dx * dx + dy * dy + dz * dz;
+        bool hit = active && r2 < (kRingQ ? rc2e : rc2f);
         if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) {
           // pairs inside a body with a dense intra-body block are not listed
           hit = hit && (own_body < 0 || cown[k0 + kk] != own_body);
         }
         // the slot at pushed is free (at most kQ - 1 entries pending)
-        qb[pushed & (kQ - 1)][lane] = __float_as_int(cnd.w);
+        qb[pushed & (kQ - 1)][lane] = (QE)__float_as_int(cnd.w);
         pushed += hit ? 1 : 0;
       }
       k0 += kQFlush;
@@ -751,7 +780,20 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
       mn = min(mn, __shfl_xor(mn, off, 64));
       mx = max(mx, __shfl_xor(mx, off, 64));
     }
-    const int rounds = finished ? mx : max(mn, mx - (kQ - kQFlush));
+    int rounds = finished ? mx : max(mn, mx - (kQ - kQFlush));
+    if constexpr (kRingQ) {
+      if (!finished && k0 >= nbat) {
+        // the batch's last group: the next staging reuses the region of
+        // batch (this - kRegions + 1), whose entries are the first ends[last]
+        int old = kRegions > 1 ? ends[kRegions > 1 ? kRegions - 2 : 0] - popped : pend;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) old = max(old, __shfl_xor(old, off, 64));
+        rounds = max(rounds, old);
+#pragma unroll
+        for (int i = kRegions - 2; i > 0; --i) ends[i] = ends[i - 1];
+        ends[0] = pushed;
+      }
+    }
     if constexpr (EV == EV_GENERAL) {
       for (int r = 0; r < rounds; ++r) {
         if (popped < pushed) {
@@ -761,25 +803,33 @@ __global__ void __launch_bounds__(256) pair_queue_kernel(
         }
       }
     } else {
-      // two rounds per pass: both sources fetched first
-      for (int r = 0; r < rounds; r += 2) {
-        const int avail = min(pushed - popped, min(2, rounds - r));
-        // both fetches unconditional (a lane without a second source re-reads
-        // its first, or source 0 of set 0), so the loads are issued back to
-        // back and the first evaluation waits for its own loads only
-        const int ea = avail > 0 ? qb[popped & (kQ - 1)][lane] : 0;
-        const int eb = avail > 1 ? qb[(popped + 1) & (kQ - 1)][lane] : ea;
-        const Src a = fetch(ea);
-        const Src b = fetch(eb);
-        popped += max(avail, 0);
-        if constexpr (EV == EV_TABLE) {
-          evaluate_tab(a, avail > 0);
-          evaluate_tab(b, avail > 1);
-        } else {
-          if (avail > 0) evaluate_fast(a);
-          if (avail > 1) evaluate_fast(b);
+      // two rounds per pass, both ring entries read first (a lane without a
+      // second entry re-reads its first, or slot 0); the per-pair minimum
+      // image (boxes of one cell along an axis) is a separate copy of the loop
+      const float4* ring = cb;
+      auto drain = [&](auto img) {
+        constexpr bool kImg = decltype(img)::value;
+        auto diff = [&](float d, float Lf, float iL) { return kImg ? d - Lf * rintf(d * iL) : d; };
+        for (int r = 0; r < rounds; r += 2) {
+          const int avail = min(pushed - popped, min(2, rounds - r));
+          const int ea = avail > 0 ? (int)qb[popped & (kQ - 1)][lane] : 0;
+          const int eb = avail > 1 ? (int)qb[(popped + 1) & (kQ - 1)][lane] : ea;
+          const float4 a = ring[ea & 255], b = ring[eb & 255];
+          const float qa = cq[wv][ea & 255], qb2 = cq[wv][eb & 255];
+          popped += avail;
+          const float dxa = diff(px - a.x, Lf0, iL0), dya = diff(py - a.y, Lf1, iL1), dza = diff(pz - a.z, Lf2, iL2);
+          const float dxb = diff(px - b.x, Lf0, iL0), dyb = diff(py - b.y, Lf1, iL1), dzb = diff(pz - b.z, Lf2, iL2);
+          if constexpr (EV == EV_TABLE) {
+            evaluate_tab(dxa, dya, dza, qa, ea >> 8, avail > 0);
+            evaluate_tab(dxb, dyb, dzb, qb2, eb >> 8, avail > 1);
+          } else {
+            if (avail > 0) evaluate_fast(dxa, dya, dza, qa, cw[wv][ea & 255]);
+            if (avail > 1) evaluate_fast(dxb, dyb, dzb, qb2, cw[wv][eb & 255]);
+          }
         }
-      }
+      };
+      if (per_pair_image) drain(std::true_type{});
+      else drain(std::false_type{});
     }
     if (finished) break;
   }
