@@ -196,6 +196,7 @@ struct ParticleSet {
   DevBuf<int> cell_start;   // ncell + 1
   DevBuf<int> cell_count;   // ncell (scratch)
   DevBuf<int> cell_of;      // caller order (scratch)
+  DevBuf<int> zsub;         // caller order: z slab of the particle within its cell (scratch)
   DevBuf<double4> tmp;      // caller order wrapped positions (scratch)
   DevBuf<int4> chunks;      // pair-traversal work units: (first, end sorted slot, first cell, cells), <= 64 each
   DevBuf<double> qsorted;   // charges in sorted order for the pair passes (scratch)

@@ -223,9 +223,18 @@ __device__ __forceinline__ void pair_kernel_fast(float r2, float s2, float xi, f
 
 // ---------------------------------------------------------------- cell list
 
+// Order within a cell: by the particle's z slab (kZSlabs per cell), then by
+// caller index, packed in one sort key (slab << kSlabShift | index) while the
+// set has fewer than 2^kSlabShift particles (larger sets sort by index
+// only).  A traversal unit, a run of consecutive particles of one (x, y)
+// column, then spans a short stretch of z instead of whole cells, so its
+// bounding box, and the candidates it tests, shrink.
+constexpr int kSlabShift = 24;
+constexpr int kZSlabs = 128;
+
 __global__ void assign_cells_kernel(const double* __restrict__ pos, const double* __restrict__ sig,
                                     double sig_const, int64_t n, RealGeom g, double4* __restrict__ tmp,
-                                    int* __restrict__ cell_of, int* __restrict__ count,
+                                    int* __restrict__ cell_of, int* __restrict__ zsub, int* __restrict__ count,
                                     unsigned long long* __restrict__ sig_check) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // uniform widths: sig_check[1] = the first width; a wavefront that sees
@@ -248,6 +257,8 @@ __global__ void assign_cells_kernel(const double* __restrict__ pos, const double
     const int cz = cell_coord(z, g.cell_inv[2], g.nc[2]);
     const int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
     cell_of[i] = c;
+    const double fz = z * g.cell_inv[2] - cz;  // position within the cell along z, [0, 1)
+    zsub[i] = min(max((int)(fz * kZSlabs), 0), kZSlabs - 1);
     atomicAdd(&count[c], 1);
     differs = !(s == s_ref);
   }
@@ -255,27 +266,30 @@ __global__ void assign_cells_kernel(const double* __restrict__ pos, const double
   if (__ballot(differs) != 0ull && (threadIdx.x & 63) == 0) sig_check[0] = 1ull;
 }
 
-__global__ void scatter_cells_kernel(const int* __restrict__ cell_of, int64_t n,
-                                     int* __restrict__ cursor, int* __restrict__ idx) {
+// idx receives sort keys (see kSlabShift); gather_sorted_kernel strips them.
+__global__ void scatter_cells_kernel(const int* __restrict__ cell_of, const int* __restrict__ zsub, int64_t n,
+                                     int slabs, int* __restrict__ cursor, int* __restrict__ idx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int slot = atomicAdd(&cursor[cell_of[i]], 1);
-  idx[slot] = (int)i;
+  idx[slot] = slabs ? (int)i | zsub[i] << kSlabShift : (int)i;
 }
 
-__global__ void gather_sorted_kernel(const double4* __restrict__ tmp, const int* __restrict__ idx,
-                                     const int* __restrict__ owner, int64_t n, RealGeom g,
+__global__ void gather_sorted_kernel(const double4* __restrict__ tmp, int* __restrict__ idx,
+                                     const int* __restrict__ owner, int64_t n, int slabs, RealGeom g,
                                      double4* __restrict__ pos, float4* __restrict__ posf) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double4 p = tmp[idx[i]];
+  const int k = slabs ? idx[i] & ((1 << kSlabShift) - 1) : idx[i];
+  idx[i] = k;
+  const double4 p = tmp[k];
   pos[i] = p;
   // single-precision copy: x and y relative to the origin of the particle's
   // cell, z as is (cells of one (x, y) column are read as one run)
   const double ax = g.L[0] / g.nc[0], ay = g.L[1] / g.nc[1];
   const int cx = cell_coord(p.x, g.cell_inv[0], g.nc[0]);
   const int cy = cell_coord(p.y, g.cell_inv[1], g.nc[1]);
-  const int tag = owner ? owner[idx[i]] : -1;
+  const int tag = owner ? owner[k] : -1;
   posf[i] = make_float4((float)(p.x - cx * ax), (float)(p.y - cy * ay), (float)p.z, __int_as_float(tag));
 }
 
@@ -773,28 +787,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
       }
       k0 += kQFlush;
     }
-    const int pend = pushed - popped;
-    int mn = active ? pend : 1 << 30, mx = pend;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      mn = min(mn, __shfl_xor(mn, off, 64));
-      mx = max(mx, __shfl_xor(mx, off, 64));
-    }
-    int rounds = finished ? mx : max(mn, mx - (kQ - kQFlush));
-    if constexpr (kRingQ) {
-      if (!finished && k0 >= nbat) {
-        // the batch's last group: the next staging reuses the region of
-        // batch (this - kRegions + 1), whose entries are the first ends[last]
-        int old = kRegions > 1 ? ends[kRegions > 1 ? kRegions - 2 : 0] - popped : pend;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) old = max(old, __shfl_xor(old, off, 64));
-        rounds = max(rounds, old);
-#pragma unroll
-        for (int i = kRegions - 2; i > 0; --i) ends[i] = ends[i - 1];
-        ends[0] = pushed;
-      }
-    }
     if constexpr (EV == EV_GENERAL) {
+      const int pend = pushed - popped;
+      int mn = active ? pend : 1 << 30, mx = pend;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        mn = min(mn, __shfl_xor(mn, off, 64));
+        mx = max(mx, __shfl_xor(mx, off, 64));
+      }
+      const int rounds = finished ? mx : max(mn, mx - (kQ - kQFlush));
       for (int r = 0; r < rounds; ++r) {
         if (popped < pushed) {
           const int e = qb[popped & (kQ - 1)][lane];
@@ -803,6 +804,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
         }
       }
     } else {
+      // The same drain policy decided by ballots pass by pass: another round
+      // while some queue holds more than kQ - kQFlush entries, or every
+      // active lane has one, or (the batch's last group) some entry points
+      // into the region the next staging reuses, that of batch
+      // (this - kRegions + 1), whose entries are the first ends[last]; after
+      // the last group, while any entry is left.
+      const bool batch_end = !finished && k0 >= nbat;
+      const int old_end = kRegions > 1 ? ends[kRegions > 1 ? kRegions - 2 : 0] : pushed;
+      if (batch_end) {
+#pragma unroll
+        for (int i = kRegions - 2; i > 0; --i) ends[i] = ends[i - 1];
+        ends[0] = pushed;
+      }
+      auto rounds_wanted = [&]() {  // 0, 1 or 2 (or more) rounds still due
+        const int pend = pushed - popped;
+        auto due = [&](int r) {  // at least r more rounds
+          if (finished) return __ballot(pend >= r) != 0ull;
+          // (every active lane holding r entries: the chunk's first lane is active)
+          bool d = __ballot(pend > kQ - kQFlush + r - 1) != 0ull ||
+                   (__ballot(active && pend < r) == 0ull && __ballot(pend >= r) != 0ull);
+          if (batch_end) d = d || __ballot(old_end - popped >= r) != 0ull;
+          return d;
+        };
+        return due(2) ? 2 : (due(1) ? 1 : 0);
+      };
       // two rounds per pass, both ring entries read first (a lane without a
       // second entry re-reads its first, or slot 0); the per-pair minimum
       // image (boxes of one cell along an axis) is a separate copy of the loop
@@ -810,8 +836,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
       auto drain = [&](auto img) {
         constexpr bool kImg = decltype(img)::value;
         auto diff = [&](float d, float Lf, float iL) { return kImg ? d - Lf * rintf(d * iL) : d; };
-        for (int r = 0; r < rounds; r += 2) {
-          const int avail = min(pushed - popped, min(2, rounds - r));
+        for (;;) {
+          const int rw = rounds_wanted();
+          if (rw == 0) break;
+          const int avail = min(pushed - popped, rw);
           const int ea = avail > 0 ? (int)qb[popped & (kQ - 1)][lane] : 0;
           const int eb = avail > 1 ? (int)qb[(popped + 1) & (kQ - 1)][lane] : ea;
           const float4 a = ring[ea & 255], b = ring[eb & 255];
@@ -996,6 +1024,7 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   ps.idx.ensure(n);
   ps.tmp.ensure(n);
   ps.cell_of.ensure(n);
+  ps.zsub.ensure(n);
   ps.cell_start.ensure(ncell + 1);
   ps.cell_count.ensure(ncell);
   PE_HIP(hipMemsetAsync(ps.cell_count.get(), 0, sizeof(int) * ncell, s));
@@ -1003,7 +1032,7 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   PE_HIP(hipMemsetAsync(ps.sig_check.get(), 0, sizeof(unsigned long long), s));
   if (n > 0) {
     hipLaunchKernelGGL(assign_cells_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, pos_caller, sig_caller,
-                       sig_const, n, rg, ps.tmp.get(), ps.cell_of.get(), ps.cell_count.get(),
+                       sig_const, n, rg, ps.tmp.get(), ps.cell_of.get(), ps.zsub.get(), ps.cell_count.get(),
                        ps.sig_check.get());
     PE_CHECK_LAUNCH();
   }
@@ -1076,15 +1105,16 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   // cursor = start (reuse cell_count)
   PE_HIP(hipMemcpyAsync(ps.cell_count.get(), start.data(), sizeof(int) * ncell, hipMemcpyHostToDevice, s));
   if (n > 0) {
-    hipLaunchKernelGGL(scatter_cells_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.cell_of.get(), n,
-                       ps.cell_count.get(), ps.idx.get());
+    const int slabs = n < ((int64_t)1 << kSlabShift) ? 1 : 0;
+    hipLaunchKernelGGL(scatter_cells_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.cell_of.get(), ps.zsub.get(), n,
+                       slabs, ps.cell_count.get(), ps.idx.get());
     PE_CHECK_LAUNCH();
-    // sort each cell's slice by caller index so the order (and every sum over
-    // it) is the same on every run
+    // sort each cell's slice by z slab and caller index, so the order (and
+    // every sum over it) is the same on every run
     launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get(),
                         ncell ? *std::max_element(cnt.begin(), cnt.end()) : 0);
     hipLaunchKernelGGL(gather_sorted_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.tmp.get(),
-                       ps.idx.get(), owner, n, rg, ps.pos.get(), ps.posf.get());
+                       ps.idx.get(), owner, n, slabs, rg, ps.pos.get(), ps.posf.get());
     PE_CHECK_LAUNCH();
   }
   // the host arrays live in the set: no wait here
