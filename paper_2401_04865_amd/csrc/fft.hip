@@ -356,6 +356,9 @@ __global__ void __launch_bounds__(256) fft256_lines_kernel(typename C2<T>::type*
   C* twl = X + 16 * kF16Ld;               // 256 twiddles exp(-2 pi i m / 256)
   __shared__ int64_t lbase[kF16Lines];
   __shared__ T lfac[kF16Lines], lksq[kF16Lines];
+  // scaling: the x factors e_x and k_x^2 of the 256 points, staged once per
+  // block (read from LDS in the middle of the transform, not from memory)
+  __shared__ T xfac[SCALE ? 256 : 1], xksq[SCALE ? 256 : 1];
   const int64_t L0 = (int64_t)blockIdx.x * kF16Lines;
   if ((int)threadIdx.x < kF16Lines) {
     const int64_t L = L0 + threadIdx.x;
@@ -369,6 +372,10 @@ __global__ void __launch_bounds__(256) fft256_lines_kernel(typename C2<T>::type*
     }
   }
   twl[threadIdx.x] = tw[threadIdx.x];
+  if (SCALE) {
+    xfac[threadIdx.x] = (T)sa.ex[threadIdx.x];
+    xksq[threadIdx.x] = (T)sa.kx2[threadIdx.x];
+  }
   __syncthreads();
   const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int64_t lb = lbase[c];
@@ -399,8 +406,13 @@ __global__ void __launch_bounds__(256) fft256_lines_kernel(typename C2<T>::type*
 #pragma unroll
       for (int k2 = 0; k2 < 16; ++k2) {
         const int kx = g + 16 * k2;
-        const T k2s = (T)sa.kx2[kx] + lksq[c];
-        T gk = k2s > (T)0 ? (T)sa.ex[kx] * lfac[c] / k2s : (T)0;
+        const T k2s = xksq[kx] + lksq[c];
+        // single precision: the hardware reciprocal (1 ulp) instead of the
+        // correctly rounded division sequence
+        T inv;
+        if constexpr (sizeof(T) == 4) inv = __builtin_amdgcn_rcpf(k2s);
+        else inv = (T)1 / k2s;
+        T gk = k2s > (T)0 ? xfac[kx] * lfac[c] * inv : (T)0;
         if (sa.shell_a > 0.0) gk *= j0_squared<T>(k2s, (T)sa.shell_a);
         v[k2] = {v[k2].x * gk, v[k2].y * gk};
       }

@@ -557,11 +557,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     gidx[ax][l] = wrap_idx(kTile * u + l, g.N[ax]);
   }
   __syncthreads();
-  // region rows (lx, ly) of Hs contiguous z values, 16 threads per row;
-  // eight rows' loads are issued before their stores, so their latencies
-  // overlap
+  // region rows (lx, ly) of Hs contiguous z values, 16 threads per row (a
+  // second pass of 16 only where Hs > 16, which a compile-time P <= 9
+  // excludes); eight rows' loads are issued before their stores, so their
+  // latencies overlap
+  constexpr int kHalves = PP > 0 ? (kTile + PP - 1 + 15) / 16 : 2;
   for (int r0 = threadIdx.x >> 4; r0 < Hs2; r0 += 16 * 8) {
-    T v[8][2];
+    T v[8][kHalves];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int row = r0 + 16 * u;
@@ -569,7 +571,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       const int ly = row - lx * Hs;
       const int64_t rb = row < Hs2 ? ((int64_t)gidx[0][lx] * g.N[1] + gidx[1][ly]) * g.N[2] : 0;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kHalves; ++h) {
         const int lz = (threadIdx.x & 15) + 16 * h;
         v[u][h] = (row < Hs2 && lz < Hs) ? grid[rb + gidx[2][lz]] : (T)0;
       }
@@ -578,7 +580,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     for (int u = 0; u < 8; ++u) {
       const int row = r0 + 16 * u;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < kHalves; ++h) {
         const int lz = (threadIdx.x & 15) + 16 * h;
         if (row < Hs2 && lz < Hs) H[row * Hs + lz] = v[u][h];
       }
