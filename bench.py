@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=20)
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="mixed precision: tolerance of each inner float solve (0: the library default)")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="untimed steps with events around every kernel class (per-class breakdown)")
     args = ap.parse_args()
@@ -219,7 +221,8 @@ def main():
     def params(prec, learned=False, precond=1, rel_tol=1e-6, mesh=None, box=None, rhs64=False):
         return B.make_params(system.box if box is None else box, system.mesh if mesh is None else mesh, P=8,
                              split_tol=tol, rel_tol=rel_tol, precision=prec,
-                             use_learned_guess=1 if learned else 0, precond=precond, rhs_fp64=1 if rhs64 else 0)
+                             use_learned_guess=1 if learned else 0, precond=precond, rhs_fp64=1 if rhs64 else 0,
+                             inner_tol=args.inner_tol)
 
     def dev_of(s):
         f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")

@@ -109,7 +109,8 @@ typedef struct pe_params {
   int32_t gmres_restart;  /* Krylov basis size before a restart, default 100, at most 255 */
   int32_t max_iters;      /* total Krylov iterations, default 1000 */
   double rel_tol;         /* target ||b - A x|| / ||b|| with the double operator, default 1e-6 */
-  double inner_tol;       /* PE_MIXED: relative tolerance of each inner solve, default 1e-4 */
+  double inner_tol;       /* PE_MIXED: floor of each inner solve's relative tolerance, default 1e-7
+                             (each inner solve aims at half of rel_tol, see pe_solve_polarization) */
   int32_t max_refine;     /* PE_MIXED: max outer refinement steps, default 8 */
   int32_t use_learned_guess; /* 1: start from the network's prediction (needs a loaded model) */
   int32_t precond;        /* 1 (default): block-Jacobi preconditioner (inverse of each body's
@@ -228,7 +229,12 @@ pe_status pe_apply_potential(pe_context* ctx, const double* charges, double* psi
  * (precond = 0).  With PE_MIXED the inner solves use the float operator
  * inside a double iterative refinement whose residuals b - A x are formed
  * with the double operator (and, with rhs_fp64, a double b); convergence is
- * only ever declared on such a double residual, also for a warm start.
+ * only ever declared on such a double residual, also for a warm start.  Each
+ * inner solve starts from the current residual r (relative size rel) and
+ * stops when the float residual estimate has fallen by
+ * max(inner_tol, 0.5 rel_tol / rel), at most 0.5: it aims at half the target,
+ * so one double residual usually confirms convergence, and the floor keeps it
+ * from chasing the float operator's rounding.
  *   q_init   dev n_bead or NULL (zero guess, or the network's when enabled)
  *   q_out    dev n_bead;  dpsi_out dev n_body;  dipole_out dev n_body x 3 or NULL
  *            (S_i = sum_j r_ij q_ij, eq. "rigid_dipole")

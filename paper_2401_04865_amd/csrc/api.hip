@@ -358,20 +358,21 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
   ProfScope ps_all(c->prof, s, PE_PROF_MATVEC, sizeof(T) == 8, (double)nb);
   const double* q = x;
   const double* dpsi = x + nb;
-  launch_moments(s, q, c->bead_sig.get(), 0.0, nb, ck_coef(c), c->red.get(), ck_bead(c), nullptr);
-  launch_seg_sum(s, c->off.get(), c->n_body, q, y + nb);
   T* gA = grid_real<T>(c->gridA);
   T* gB = grid_real<T>(c->gridB);
   const bool dbl = sizeof(T) == 8;
   // the real-space part on the auxiliary stream, into its own buffer, while
   // the mesh part (spread, FFT, contraction) runs on the caller's: the dense
   // intra-body blocks per shape, then the sparse inter-body pairs added;
-  // the assembly after the join
+  // also the charge moments (the k = 0 term) and the body net charges; the
+  // assembly after the join
   c->phi_near.ensure((size_t)std::max<int64_t>(nb, 1));
   double* phi_real = c->phi_near.get();
   fork_aux(c);
   {
     hipStream_t sa = c->aux;
+    launch_moments(sa, q, c->bead_sig.get(), 0.0, nb, ck_coef(c), c->red.get(), ck_bead(c), nullptr);
+    launch_seg_sum(sa, c->off.get(), c->n_body, q, y + nb);
     PE_HIP(hipMemsetAsync(phi_real, 0, sizeof(double) * nb, sa));
     for (auto& t : c->pc.types) {
       if (!t.near || t.bodies.empty()) continue;
@@ -896,7 +897,7 @@ pe_status pe_default_params(pe_params* p) {
   p->gmres_restart = 100;
   p->max_iters = 1000;
   p->rel_tol = 1e-6;
-  p->inner_tol = 1e-4;
+  p->inner_tol = 1e-7;
   p->max_refine = 8;
   p->use_learned_guess = 0;
   p->precond = 1;
@@ -933,7 +934,7 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
   require(p.rel_tol > 0, "rel_tol must be positive");
   c = new pe_context();
   c->p = p;
-  if (c->p.inner_tol <= 0) c->p.inner_tol = 1e-4;
+  if (c->p.inner_tol <= 0) c->p.inner_tol = 1e-7;
   if (c->p.max_refine <= 0) c->p.max_refine = 8;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   PE_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
