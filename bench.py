@@ -50,16 +50,34 @@ TRAIN_DEFAULT = {"cfg2": 0, "cfg3": 0, "cfg4": 2000, "cfg5": 200}
 
 # HBM bytes per launch (profiler scope) of a kernel class on the default
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes over a short
-# run of this script (the class's dispatches of five steps, averaged;
-# FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the ratios a plain 256 MiB
-# device copy reads on those counters).  Each entry records the source files
-# of the kernels and of their launches with their sha1 at measurement; once
-# one changes the figure is stale and `traffic` is reported null, as it is on
-# any other workload.
+# run of this script (the class's dispatches of five steps and the isolated
+# products, averaged; FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the
+# ratios a plain 256 MiB device copy reads on those counters), and what the
+# SQ counter passes of that run show bounds the class.  Each entry records
+# the source files of the kernels and of their launches with their sha1 at
+# measurement; once one changes the figures are stale and `traffic` is
+# reported null, as it is on any other workload.
 TRAFFIC = {
-    "pair_f32": {"workload": "cfg5", "bytes_per_launch": 1.375e9,
-                 "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "83ae5a528fd52d9ce40bfb5e8fe773457299762d",
-                             "paper_2401_04865_amd/csrc/api.hip": "db2cf28a122a3411da773082a60831037809cb40"}},
+    "spread_f32": {"workload": "cfg5", "bytes_per_launch": 1.079e8,
+                   "limiter": ("vector ALU issue: 0.63 (beads) and 0.69 (ions) VALU instructions per CU-cycle "
+                               "of at most 1 (SQ_INSTS_VALU); LDS 0.09-0.12 instructions per CU-cycle"),
+                   "sources": {"paper_2401_04865_amd/csrc/grid.hip": "dbc03333d6e50d9815017f6d44e93b0779234aa9",
+                               "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
+    "fft_z_r2c_f32": {"workload": "cfg5", "bytes_per_launch": 1.365e8,
+                      "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
+                                  "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
+    "fft_y_fwd_f32": {"workload": "cfg5", "bytes_per_launch": 1.449e8,
+                      "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
+                                  "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
+    "fft_x_scale_f32": {"workload": "cfg5", "bytes_per_launch": 1.453e8,
+                        "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
+                                    "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
+    "fft_y_inv_f32": {"workload": "cfg5", "bytes_per_launch": 1.449e8,
+                      "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
+                                  "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
+    "fft_z_c2r_f32": {"workload": "cfg5", "bytes_per_launch": 1.428e8,
+                      "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
+                                  "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
 }
 
 
@@ -456,13 +474,16 @@ def main():
         key = f"{name}_{'f64' if dbl else 'f32'}"
         tr = TRAFFIC.get(key)
         # a figure holds only for the workload it was counted on
-        traffic = (tr["bytes_per_launch"] if tr and tr["workload"] == args.workload and traffic_current(tr)
-                   else None)
+        current = bool(tr) and tr["workload"] == args.workload and traffic_current(tr)
+        traffic = tr["bytes_per_launch"] if current else None
         share = per_class[(name, dbl)][1] / total_ms
-        return {"kernel": key, "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "avg_launch_us": round(1e3 * ms / cnt, 2), "launches": int(cnt),
-                "algorithmic_per_launch": amount / cnt, "share_of_kernel_time": round(share, 3)}
+        out = {"kernel": key, "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+               "frac": round(achieved / peak, 4), "traffic": traffic,
+               "avg_launch_us": round(1e3 * ms / cnt, 2), "launches": int(cnt),
+               "algorithmic_per_launch": amount / cnt, "share_of_kernel_time": round(share, 3)}
+        if current and "limiter" in tr:
+            out["limiter"] = tr["limiter"]
+        return out
 
     roofs = [r for r in (roofline(n, db) for n, db in modeled) if r is not None]
     roof = None
