@@ -40,6 +40,14 @@ __device__ __forceinline__ int support_start(double x, double inv_h, int P, doub
   return (int)m0;
 }
 
+// The value of axis ax (per lane) among three uniform ones, by selects: an
+// index into the by-value geometry struct would read the kernel arguments
+// from memory at every use.
+template <typename V>
+__device__ __forceinline__ V sel3(int ax, V a, V b, V c) {
+  return ax == 0 ? a : (ax == 1 ? b : c);
+}
+
 // m in [-N, 2N) -> [0, N)
 __device__ __forceinline__ int wrap_idx(int m, int N) {
   m = m < 0 ? m + N : m;
@@ -49,7 +57,7 @@ __device__ __forceinline__ int wrap_idx(int m, int N) {
 // Window factor w(d_j) = wnorm exp(-wexp d_j^2) of support point j.
 template <typename T>
 __device__ __forceinline__ T window(const GridGeom& g, int ax, int j, double delta) {
-  const double dj = ((double)j + delta) * g.h[ax];
+  const double dj = ((double)j + delta) * sel3(ax, g.h[0], g.h[1], g.h[2]);
   return (T)g.wnorm * exp((T)(-g.wexp * dj * dj));
 }
 
@@ -62,10 +70,10 @@ __device__ __forceinline__ void window_setup(const double4 p, const GridGeom& g,
     const int j = lane - ax * P;
     const double x = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
     double delta;
-    const int m0 = support_start(x, g.inv_h[ax], P, delta);
+    const int m0 = support_start(x, sel3(ax, g.inv_h[0], g.inv_h[1], g.inv_h[2]), P, delta);
     w_s[lane] = window<T>(g, ax, j, delta);
-    i_s[lane] = wrap_idx(m0 + j, g.N[ax]);
-    if (d_s) d_s[lane] = (T)(((double)j + delta) * g.h[ax]);
+    i_s[lane] = wrap_idx(m0 + j, sel3(ax, g.N[0], g.N[1], g.N[2]));
+    if (d_s) d_s[lane] = (T)(((double)j + delta) * sel3(ax, g.h[0], g.h[1], g.h[2]));
   }
 }
 
@@ -275,7 +283,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     // ahead, so their latency overlaps the current round's work.
     const int c3 = lane / 3, ax3 = lane - 3 * (lane / 3);
     const bool stager = lane < 3 * kWaveChunk;
-    const int N = g.N[ax3];
+    const int N = sel3(ax3, g.N[0], g.N[1], g.N[2]);
+    const double ih3 = sel3(ax3, g.inv_h[0], g.inv_h[1], g.inv_h[2]);
+    const double h3 = sel3(ax3, g.h[0], g.h[1], g.h[2]);
     const int u = ax3 == 0 ? ux : (ax3 == 1 ? uy : uz);
     // (called with every lane of the wavefront active)
     auto entry_at = [&](int c0) {
@@ -308,7 +318,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       }
       if (i1 >= 0) {
         double delta;
-        const int m0 = support_start(x1, g.inv_h[ax3], P, delta);
+        const int m0 = support_start(x1, ih3, P, delta);
         // tile-local position of support point 0, taken in [1 - P, kTile - 1]
         int s0 = wrap_idx(m0, N) - kTile * u;
         if (s0 > kTile - 1) s0 -= N;
@@ -317,7 +327,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
           // single precision once the support is placed: the displacement
           // (j + delta) h is below P h, so float keeps it to rounding and the
           // exponential to a few ulp
-          const float hf = (float)g.h[ax3], df = (float)delta, we = (float)g.wexp;
+          const float hf = (float)h3, df = (float)delta, we = (float)g.wexp;
           const float wn = (float)g.wnorm * (float)q1;
 #pragma unroll
           for (int loc = 0; loc < kTile; ++loc) {
@@ -330,7 +340,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
           for (int loc = 0; loc < kTile; ++loc) {
             const int j = loc - s0;
-            const double d = ((double)j + delta) * g.h[ax3];
+            const double d = ((double)j + delta) * h3;
             fw[c3][ax3][loc] = (j >= 0 && j < P) ? (T)(wn * exp(-g.wexp * d * d)) : (T)0;
           }
         }
@@ -413,8 +423,8 @@ __global__ void __launch_bounds__(256) spread_block_kernel(const double4* __rest
       const int i = entries[c0 + c];
       const double x = reinterpret_cast<const double*>(pos + i)[ax];
       double delta;
-      const int m0 = support_start(x, g.inv_h[ax], P, delta);
-      const int N = g.N[ax];
+      const int m0 = support_start(x, sel3(ax, g.inv_h[0], g.inv_h[1], g.inv_h[2]), P, delta);
+      const int N = sel3(ax, g.N[0], g.N[1], g.N[2]);
       const int u = ax == 0 ? ux : (ax == 1 ? uy : uz);
       // tile-local position of support point 0, taken in [1 - P, kTile - 1]
       int s0 = wrap_idx(m0, N) - kTile * u;
@@ -554,7 +564,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   if ((int)threadIdx.x < 3 * Hs) {
     const int ax = threadIdx.x / Hs, l = threadIdx.x - ax * Hs;
     const int u = ax == 0 ? ux : (ax == 1 ? uy : uz);
-    gidx[ax][l] = wrap_idx(kTile * u + l, g.N[ax]);
+    gidx[ax][l] = wrap_idx(kTile * u + l, sel3(ax, g.N[0], g.N[1], g.N[2]));
   }
   __syncthreads();
   // region rows (lx, ly) of Hs contiguous z values, 16 threads per row (a
@@ -572,8 +582,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       const int64_t rb = row < Hs2 ? ((int64_t)gidx[0][lx] * g.N[1] + gidx[1][ly]) * g.N[2] : 0;
 #pragma unroll
       for (int h = 0; h < kHalves; ++h) {
+        // every load issued (a point outside the region reads grid[0]), so
+        // no branch separates them
         const int lz = (threadIdx.x & 15) + 16 * h;
-        v[u][h] = (row < Hs2 && lz < Hs) ? grid[rb + gidx[2][lz]] : (T)0;
+        const bool ok = row < Hs2 && lz < Hs;
+        const T val = grid[ok ? rb + gidx[2][lz] : 0];
+        v[u][h] = ok ? val : (T)0;
       }
     }
 #pragma unroll
@@ -591,11 +605,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   const int sub = lane >> 4, s = lane & 15;
   const int slot = 4 * wv + sub;
   const int e0 = home_start[tile], e1 = home_start[tile + 1];
+  // the particle of the next round (entry and position) is loaded while
+  // this round's is contracted (not in the single-precision field variant,
+  // whose registers that would spill at eight wavefronts per SIMD)
+  constexpr bool kAhead = !(FIELD && sizeof(T) == 4);
+  int i_next = home_entries[min(e0 + slot, e1 - 1)];
+  double4 p_next = pos[i_next];
   for (int base = e0; base < e1; base += 16) {
     const int e = base + slot;
     const bool valid = e < e1;
-    const int i = home_entries[valid ? e : e1 - 1];
-    const double4 p = pos[i];
+    const int i = kAhead ? i_next : home_entries[valid ? e : e1 - 1];
+    const double4 p = kAhead ? p_next : pos[i];
+    if (kAhead && base + 16 < e1) {
+      i_next = home_entries[min(e + 16, e1 - 1)];
+      p_next = pos[i_next];
+    }
     // support of the three axes (placed in double), then the window factors
     // and displacements; in single precision the factors are formed in
     // float, the displacement (j + delta) h being below P h
@@ -603,18 +627,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     const int mx = support_start(p.x, g.inv_h[0], P, dlx);
     const int my = support_start(p.y, g.inv_h[1], P, dly);
     const int mz = support_start(p.z, g.inv_h[2], P, dlz);
-    for (int k = s; k < 3 * P; k += 16) {
+    auto factor = [&](int k) {
       const int ax = k / P;
       const int j = k - ax * P;
-      const double delta = ax == 0 ? dlx : (ax == 1 ? dly : dlz);
+      const double delta = sel3(ax, dlx, dly, dlz);
+      const double h = sel3(ax, g.h[0], g.h[1], g.h[2]);
       if constexpr (sizeof(T) == 4) {
-        const float d = ((float)j + (float)delta) * (float)g.h[ax];
+        const float d = ((float)j + (float)delta) * (float)h;
         w_s[slot][k] = (float)g.wnorm * __expf(-(float)g.wexp * d * d);
         if (FIELD) d_s[slot][k] = d;
       } else {
-        w_s[slot][k] = window<T>(g, ax, j, delta);
-        if (FIELD) d_s[slot][k] = (T)(((double)j + delta) * g.h[ax]);
+        const double d = ((double)j + delta) * h;
+        w_s[slot][k] = (T)(g.wnorm * exp(-g.wexp * d * d));
+        if (FIELD) d_s[slot][k] = (T)d;
       }
+    };
+    if constexpr (PP > 0 && kAhead) {
+#pragma unroll
+      for (int it = 0; it < (3 * PP + 15) / 16; ++it)
+        if (s + 16 * it < 3 * PP) factor(s + 16 * it);
+    } else {
+      for (int k = s; k < 3 * P; k += 16) factor(k);
     }
     // first support point relative to the region origin, per axis
     const int ox = wrap_idx(mx, g.N[0]) - kTile * ux;
