@@ -365,10 +365,15 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
   // the mesh part (spread, FFT, contraction) runs on the caller's: the dense
   // intra-body blocks per shape, then the sparse inter-body pairs added;
   // also the charge moments (the k = 0 term) and the body net charges; the
-  // assembly after the join
+  // assembly after the join.  The mesh part is the longer chain, so its
+  // launches are enqueued first: the caller's stream must not idle while
+  // the host enqueues the auxiliary work.
   c->phi_near.ensure((size_t)std::max<int64_t>(nb, 1));
   double* phi_real = c->phi_near.get();
   fork_aux(c);
+  { ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)nb); launch_spread<T>(s, c->B, q, gA, c->gg, false); }
+  launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
+  { ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
   {
     hipStream_t sa = c->aux;
     launch_moments(sa, q, c->bead_sig.get(), 0.0, nb, ck_coef(c), c->red.get(), ck_bead(c), nullptr);
@@ -386,9 +391,6 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
     ProfScope ps(c->prof, sa, PE_PROF_SPMV, dbl, (double)c->nnz);
     launch_spmv_add<T>(sa, c, q, phi_real);
   }
-  { ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)nb); launch_spread<T>(s, c->B, q, gA, c->gg, false); }
-  launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
-  { ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
   join_aux(c);
   launch_assemble(s, c, dpsi, c->phi_w.get(), phi_real, ck_bead(c), y);
 }
@@ -688,17 +690,22 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
     int jend = 0;
     double last_est = beta;
     const bool pre = c->p.precond != 0 && !c->pc.types.empty();
+    // z_j = M^-1 v_j
+    auto precond = [&](int j) {
+      ProfScope ps(c->prof, s, PE_PROF_PRECOND, prec != PE_MIXED, precond_madds(c));
+      double* vj = k.V + (size_t)j * n;
+      double* zj = k.Z + (size_t)j * n;
+      if (prec == PE_MIXED) precond_apply<float>(s, c, vj, zj);
+      else precond_apply<double>(s, c, vj, zj);
+    };
+    bool z_ahead = false;  // z_j already enqueued while the host read step j-1's estimate
     for (int j = 0; j < m; ++j) {
       double* vj = k.V + (size_t)j * n;
       if (pre) {
-        double* zj = k.Z + (size_t)j * n;
-        {
-          ProfScope ps(c->prof, s, PE_PROF_PRECOND, prec != PE_MIXED, precond_madds(c));
-          if (prec == PE_MIXED) precond_apply<float>(s, c, vj, zj);
-          else precond_apply<double>(s, c, vj, zj);
-        }
-        vj = zj;
+        if (!z_ahead) precond(j);
+        vj = k.Z + (size_t)j * n;
       }
+      z_ahead = false;
       apply_saddle_prec(c, prec, vj, k.w);
       (prec == PE_MIXED ? *mv32 : *mv64) += 1;
       {
@@ -711,7 +718,16 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
         launch_scale(s, k.w, k.nrm, k.V + (size_t)(j + 1) * n, n);
         launch_givens(s, k.h1, k.h2, k.nrm, k.st, m, j, k.res);
       }
-      const double est = fetch(c, k.res);
+      // the estimate travels to the host while the next step's
+      // preconditioner runs (unused if this step ends the solve)
+      PE_HIP(hipMemcpyAsync(c->pinned, k.res, sizeof(double), hipMemcpyDeviceToHost, s));
+      PE_HIP(hipEventRecord(c->ev_est, s));
+      if (pre && j + 1 < m && out.iters + 1 < max_iters) {
+        precond(j + 1);
+        z_ahead = true;
+      }
+      PE_HIP(hipEventSynchronize(c->ev_est));
+      const double est = c->pinned[0];
       out.iters += 1;
       if (info && info->n_hist < 1024) info->hist[info->n_hist++] = est / bnorm;
       jend = j + 1;
@@ -940,6 +956,7 @@ pe_status pe_create(const pe_params* params, void* hip_stream, pe_context** out)
   PE_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
   PE_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   PE_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  PE_HIP(hipEventCreateWithFlags(&c->ev_est, hipEventDisableTiming));
   {
     int dev = 0, lds = 0;
     PE_HIP(hipGetDevice(&dev));
@@ -972,6 +989,7 @@ pe_status pe_destroy(pe_context* ctx) {
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_est) (void)hipEventDestroy(ctx->ev_est);
   delete ctx;
   return PE_OK;
 }

@@ -380,6 +380,7 @@ struct pe_context {
   // so they overlap the spread / FFT / gather of the same pass
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_est = nullptr;  // a Krylov step's residual estimate has reached the host
   pe::DevBuf<double> phi_pair, E_pair;  // the pair passes' own outputs (summed after the join)
   pe::DevBuf<double> phi_near;          // the near-field blocks' output of a Krylov product
   std::string err;
