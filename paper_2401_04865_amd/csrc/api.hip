@@ -1064,16 +1064,24 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
   c->n_body = n_body;
   c->n_bead = nb;
   c->n_ion = n_ion;
+  // the body structure (offsets, bead -> body) is uploaded again only when
+  // it changed (a Brownian run keeps it from step to step)
+  const bool same_bodies = c->bodies_uploaded && c->h_off == off;
   c->h_off = off;
   for (int d = 0; d < 3; ++d) c->E0[d] = E0[d];
   // copies
   c->off.ensure(n_body + 1);
-  PE_HIP(hipMemcpyAsync(c->off.get(), off.data(), sizeof(int64_t) * (n_body + 1), hipMemcpyHostToDevice, s));
-  std::vector<int> bof(nb);
-  for (int64_t i = 0; i < n_body; ++i)
-    for (int64_t j = off[i]; j < off[i + 1]; ++j) bof[j] = (int)i;
   c->body_of.ensure(nb);
-  if (nb) PE_HIP(hipMemcpyAsync(c->body_of.get(), bof.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+  if (!same_bodies) {
+    c->bodies_uploaded = false;
+    PE_HIP(hipMemcpyAsync(c->off.get(), off.data(), sizeof(int64_t) * (n_body + 1), hipMemcpyHostToDevice, s));
+    std::vector<int> bof(nb);
+    for (int64_t i = 0; i < n_body; ++i)
+      for (int64_t j = off[i]; j < off[i + 1]; ++j) bof[j] = (int)i;
+    if (nb) PE_HIP(hipMemcpyAsync(c->body_of.get(), bof.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+    PE_HIP(hipStreamSynchronize(s));  // (the host arrays end with this scope)
+    c->bodies_uploaded = true;
+  }
   c->bead_x.ensure(3 * nb);
   c->bead_sig.ensure(nb);
   c->rel.ensure(3 * nb);

@@ -757,23 +757,21 @@ void build_tile_lists(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
                        (int*)nullptr);
     PE_CHECK_LAUNCH();
   }
-  std::vector<int>& cnt = ps.h_tcnt;
-  cnt.resize(nt);
-  PE_HIP(hipMemcpyAsync(cnt.data(), tcount, sizeof(int) * nt, hipMemcpyDeviceToHost, s));
+  int* cnt = ps.h_tcnt.get<int>(nt);
+  PE_HIP(hipMemcpyAsync(cnt, tcount, sizeof(int) * nt, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
-  std::vector<int>& start = ps.h_tstart;
-  start.assign(nt + 1, 0);
+  int* start = ps.h_tstart.get<int>((size_t)nt + 1);
+  start[0] = 0;
   for (int t = 0; t < nt; ++t) start[t + 1] = start[t] + cnt[t];
   ps.n_entries = start[nt];
   ps.tile_entries.ensure(std::max<int64_t>(ps.n_entries, 1));
-  PE_HIP(hipMemcpyAsync(ps.tile_start.get(), start.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
-  PE_HIP(hipMemcpyAsync(tcount, start.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(ps.tile_start.get(), start, sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(tcount, start, sizeof(int) * nt, hipMemcpyHostToDevice, s));
   if (ps.n > 0) {
     hipLaunchKernelGGL(tile_list_kernel<true>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, tcount,
                        ps.tile_entries.get());
     PE_CHECK_LAUNCH();
-    launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get(),
-                        nt ? *std::max_element(cnt.begin(), cnt.end()) : 0);
+    launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get(), nt ? *std::max_element(cnt, cnt + nt) : 0);
   }
   ps.have_tile_lists = true;
 }
@@ -803,28 +801,26 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g, bool spread_
     hipLaunchKernelGGL(home_count_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, hcount);
     PE_CHECK_LAUNCH();
   }
-  std::vector<int>& cnt = ps.h_hcnt;
-  cnt.resize(nt);
-  PE_HIP(hipMemcpyAsync(cnt.data(), hcount, sizeof(int) * nt, hipMemcpyDeviceToHost, s));
+  int* cnt = ps.h_hcnt.get<int>(nt);
+  PE_HIP(hipMemcpyAsync(cnt, hcount, sizeof(int) * nt, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
-  std::vector<int>& hstart = ps.h_hstart;
-  std::vector<int>& htiles = ps.h_htiles;
-  hstart.assign(nt + 1, 0);
-  htiles.clear();
+  int* hstart = ps.h_hstart.get<int>((size_t)nt + 1);
+  int* htiles = ps.h_htiles.get<int>(nt);
+  int nht = 0;
+  hstart[0] = 0;
   int hmax = 0;
   for (int t = 0; t < nt; ++t) {
     hstart[t + 1] = hstart[t] + cnt[t];
     hmax = std::max(hmax, cnt[t]);
-    if (cnt[t]) htiles.push_back(t);
+    if (cnt[t]) htiles[nht++] = t;
   }
   ps.home_start.ensure(nt + 1);
   ps.home_entries.ensure(std::max<int64_t>(ps.n, 1));
-  ps.n_home_tiles = (int)htiles.size();
-  ps.home_tiles.ensure(std::max<size_t>(htiles.size(), 1));
-  PE_HIP(hipMemcpyAsync(ps.home_start.get(), hstart.data(), sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
-  PE_HIP(hipMemcpyAsync(hcount, hstart.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
-  if (!htiles.empty())
-    PE_HIP(hipMemcpyAsync(ps.home_tiles.get(), htiles.data(), sizeof(int) * htiles.size(), hipMemcpyHostToDevice, s));
+  ps.n_home_tiles = nht;
+  ps.home_tiles.ensure(std::max(nht, 1));
+  PE_HIP(hipMemcpyAsync(ps.home_start.get(), hstart, sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(hcount, hstart, sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  if (nht) PE_HIP(hipMemcpyAsync(ps.home_tiles.get(), htiles, sizeof(int) * nht, hipMemcpyHostToDevice, s));
   if (ps.n > 0) {
     hipLaunchKernelGGL(home_fill_kernel, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, hcount,
                        ps.home_entries.get());

@@ -81,6 +81,35 @@ struct ArenaScope {
   ~ArenaScope() { tl_arena = prev; }
 };
 
+// Page-locked host memory for the set-up's transfers of counts and offsets
+// (a pageable end makes each copy a blocking, staged one).  Grown on demand;
+// each buffer carries one transfer per set-up call, and every set-up call
+// ends with a stream synchronization, so no buffer is reallocated or
+// rewritten under a copy in flight.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  template <typename T>
+  T* get(size_t n) {
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (bytes > cap) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess || !p)
+        throw Error(PE_ERR_NOMEM, "page-locked host staging buffer");
+      cap = bytes;
+    }
+    return static_cast<T*>(p);
+  }
+};
+
 // A buffer in the context's workspace; grows on demand, never shrinks.
 template <typename T>
 struct DevBuf {
@@ -207,10 +236,9 @@ struct ParticleSet {
   DevBuf<int> tile_count;   // 2 ntile (scratch: counts and cursors of both list kinds)
   // host copies of the counts and offsets (kept so the copies to the device
   // need no wait before the builders return)
-  std::vector<int> h_tcnt, h_tstart, h_hcnt, h_hstart, h_htiles, h_ccnt, h_cstart;
+  PinnedBuf h_tcnt, h_tstart, h_hcnt, h_hstart, h_htiles, h_ccnt, h_cstart, h_chunks;
   bool have_tile_lists = false;   // tile lists built for the current configuration
   bool spread_by_home = false;    // single-precision spreading walks the sorted home lists
-  std::vector<int4> h_chunks;
   std::vector<int4> h_colchunks;             // traversal units in column order (scratch)
   std::vector<int> h_colfirst, h_colcursor;  // per column: first unit, and a cursor (scratch)
   DevBuf<int> tile_entries; // sorted-particle indices, grouped by tile
@@ -224,7 +252,6 @@ struct ParticleSet {
   // width check of the set: [0] nonzero if the widths differ, [1] the first
   // width's bits; sig_uniform is the width when all are equal, else 0
   DevBuf<unsigned long long> sig_check;
-  unsigned long long h_sig_check[2] = {0, 0};
   double sig_uniform = 0.0;
 };
 
@@ -381,6 +408,7 @@ struct pe_context {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_est = nullptr;  // a Krylov step's residual estimate has reached the host
+  bool bodies_uploaded = false; // off and body_of hold the body structure h_off describes
   pe::DevBuf<double> phi_pair, E_pair;  // the pair passes' own outputs (summed after the join)
   pe::DevBuf<double> phi_near;          // the near-field blocks' output of a Krylov product
   std::string err;

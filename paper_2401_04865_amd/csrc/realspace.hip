@@ -1036,19 +1036,21 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
                        ps.sig_check.get());
     PE_CHECK_LAUNCH();
   }
-  std::vector<int>& cnt = ps.h_ccnt;
-  std::vector<int>& start = ps.h_cstart;
-  cnt.resize(ncell);
-  start.assign(ncell + 1, 0);
-  PE_HIP(hipMemcpyAsync(cnt.data(), ps.cell_count.get(), sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
-  if (n > 0)
-    PE_HIP(hipMemcpyAsync(ps.h_sig_check, ps.sig_check.get(), sizeof(ps.h_sig_check), hipMemcpyDeviceToHost, s));
+  // counts and, 8-byte aligned after them, the width check in one
+  // page-locked buffer
+  const size_t sig_at = ((size_t)ncell + 1) & ~(size_t)1;  // ints
+  int* cnt = ps.h_ccnt.get<int>(sig_at + 4);
+  unsigned long long* sig = reinterpret_cast<unsigned long long*>(cnt + sig_at);
+  int* start = ps.h_cstart.get<int>((size_t)ncell + 1);
+  PE_HIP(hipMemcpyAsync(cnt, ps.cell_count.get(), sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
+  if (n > 0) PE_HIP(hipMemcpyAsync(sig, ps.sig_check.get(), 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
   {
-    double w;
-    std::memcpy(&w, &ps.h_sig_check[1], sizeof(double));
-    ps.sig_uniform = n > 0 && ps.h_sig_check[0] == 0 && w > 0 && w < INFINITY ? w : 0.0;
+    double w = 0;
+    if (n > 0) std::memcpy(&w, &sig[1], sizeof(double));
+    ps.sig_uniform = n > 0 && sig[0] == 0 && w > 0 && w < INFINITY ? w : 0.0;
   }
+  start[0] = 0;
   for (int c = 0; c < ncell; ++c) start[c + 1] = start[c] + cnt[c];
   // traversal work units: runs of up to 64 consecutive particles of one
   // (x, y) column, so a wavefront's lanes are all busy however the cells are
@@ -1084,8 +1086,8 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   // (a contiguous range, see xcd_remap) read their sources from a compact
   // region that its L2 can hold, rather than from a slab of whole planes
   constexpr int kBrick = 8;
-  std::vector<int4>& chunks = ps.h_chunks;
-  chunks.clear();
+  int4* chunks = ps.h_chunks.get<int4>(colchunks.size());
+  int nch = 0;
   std::vector<int>& cursor = ps.h_colcursor;
   cursor.assign(col_first.begin(), col_first.end() - 1);
   for (int bx = 0; bx < nc0; bx += kBrick)
@@ -1095,15 +1097,15 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
           for (int y = by; y < std::min(by + kBrick, nc1); ++y) {
             const int col = x * nc1 + y;
             while (cursor[col] < col_first[col + 1] && colchunks[cursor[col]].z % nc2 < bz + kBrick)
-              chunks.push_back(colchunks[cursor[col]++]);
+              chunks[nch++] = colchunks[cursor[col]++];
           }
-  ps.n_chunks = (int)chunks.size();
+  ps.n_chunks = nch;
   ps.chunks.ensure(std::max<int64_t>(ps.n_chunks, 1));
   if (ps.n_chunks)
-    PE_HIP(hipMemcpyAsync(ps.chunks.get(), chunks.data(), sizeof(int4) * ps.n_chunks, hipMemcpyHostToDevice, s));
-  PE_HIP(hipMemcpyAsync(ps.cell_start.get(), start.data(), sizeof(int) * (ncell + 1), hipMemcpyHostToDevice, s));
+    PE_HIP(hipMemcpyAsync(ps.chunks.get(), chunks, sizeof(int4) * ps.n_chunks, hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(ps.cell_start.get(), start, sizeof(int) * (ncell + 1), hipMemcpyHostToDevice, s));
   // cursor = start (reuse cell_count)
-  PE_HIP(hipMemcpyAsync(ps.cell_count.get(), start.data(), sizeof(int) * ncell, hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(ps.cell_count.get(), start, sizeof(int) * ncell, hipMemcpyHostToDevice, s));
   if (n > 0) {
     const int slabs = n < ((int64_t)1 << kSlabShift) ? 1 : 0;
     hipLaunchKernelGGL(scatter_cells_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.cell_of.get(), ps.zsub.get(), n,
@@ -1111,8 +1113,7 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
     PE_CHECK_LAUNCH();
     // sort each cell's slice by z slab and caller index, so the order (and
     // every sum over it) is the same on every run
-    launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get(),
-                        ncell ? *std::max_element(cnt.begin(), cnt.end()) : 0);
+    launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get(), ncell ? *std::max_element(cnt, cnt + ncell) : 0);
     hipLaunchKernelGGL(gather_sorted_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.tmp.get(),
                        ps.idx.get(), owner, n, slabs, rg, ps.pos.get(), ps.posf.get());
     PE_CHECK_LAUNCH();
