@@ -710,18 +710,14 @@ GmresOut gmres(pe_context* c, int prec, const double* b, double* x, bool x_zero,
       (prec == PE_MIXED ? *mv32 : *mv64) += 1;
       {
         ProfScope ps(c->prof, s, PE_PROF_KRYLOV, true);
-        launch_mdot(s, k.V, n, j + 1, k.w, n, partial, k.h1, false);
-        launch_maxpy(s, k.V, n, j + 1, k.h1, k.w, n, 1.0);
-        launch_mdot(s, k.V, n, j + 1, k.w, n, partial, k.h2, false);
-        launch_maxpy(s, k.V, n, j + 1, k.h2, k.w, n, 1.0);
-        launch_mdot(s, k.w, n, 1, k.w, n, partial, k.nrm, true);
-        launch_scale(s, k.w, k.nrm, k.V + (size_t)(j + 1) * n, n);
-        launch_givens(s, k.h1, k.h2, k.nrm, k.st, m, j, k.res);
+        // CGS2, the next basis vector and the Givens step in four launches;
+        // the residual estimate goes straight to page-locked host memory
+        launch_cgs_step(s, k.V, n, j + 1, k.w, n, partial, k.h1, k.h2, k.nrm, k.V + (size_t)(j + 1) * n, k.st, m,
+                        j, k.res, c->pinned);
+        PE_HIP(hipEventRecord(c->ev_est, s));
       }
-      // the estimate travels to the host while the next step's
-      // preconditioner runs (unused if this step ends the solve)
-      PE_HIP(hipMemcpyAsync(c->pinned, k.res, sizeof(double), hipMemcpyDeviceToHost, s));
-      PE_HIP(hipEventRecord(c->ev_est, s));
+      // the host reads the estimate while the next step's preconditioner
+      // runs (unused if this step ends the solve)
       if (pre && j + 1 < m && out.iters + 1 < max_iters) {
         precond(j + 1);
         z_ahead = true;
@@ -806,7 +802,7 @@ void prepare_constants(pe_context* c) {
   build_erfcx_table(c->stream, c->erfcx_tab);
   c->rg.erfcx = c->erfcx_tab.get();
   c->sums.ensure(64);
-  c->red.ensure((size_t)kMaxK * 1024 + 8192);
+  c->red.ensure((size_t)2 * kMaxK * 1024 + 8192);
   c->consts_ready = true;
 }
 
@@ -828,7 +824,7 @@ size_t estimate_workspace(const pe_context* c, int64_t nb, int64_t nbody, int64_
   size_t b = 0;
   // parameter tables and reduction buffers
   b += up(24.0 * (Nx + Ny + Nz)) * 2 + up(16.0 * (Nx + Ny + Nz)) + up(64 * 1024);
-  b += up(8.0 * (64 + nbody)) + up(8.0 * ((double)kMaxK * 1024 + 8192));
+  b += up(8.0 * (64 + nbody)) + up(8.0 * (2.0 * kMaxK * 1024 + 8192));
   // grids: two real double grids, the half spectrum, the kept float ion grid
   b += 2 * up(8 * G) + up(16 * Gc) + up(4 * G);
   // the system's copies

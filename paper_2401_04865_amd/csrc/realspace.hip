@@ -892,39 +892,47 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
 }
 
 // phi_real[b] += sum_j R_bj q_j over the stored inter-body pairs of bead b
-// (which then holds the whole real-space part).  CSR rows in cell order; 16
-// lanes per row read the row's entries contiguously and reduce with lane
-// shuffles (4 rows per wavefront).  Rows hold about ten entries, so most
-// lanes take one; the row's first entry and the bead's own term are loaded
-// before either is used, which overlaps the two chains of dependent loads.
+// (which then holds the whole real-space part).  CSR rows in cell order;
+// kSpmvLanes lanes per row read the row's entries contiguously and reduce
+// with lane shuffles.  Rows hold about ten entries, so a lane takes one or
+// two: each lane loads its first two entries and the bead's own term before
+// using any of them, which overlaps the chains of dependent loads.
+constexpr int kSpmvLanes = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(256) spmv_add_kernel(const int64_t* __restrict__ row_ptr,
                                                        const int* __restrict__ col, const T* __restrict__ val,
                                                        const int* __restrict__ row_bead, int64_t n,
                                                        const double* __restrict__ q, double* __restrict__ phi_real) {
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-  const int sub = threadIdx.x & 15;
+  constexpr int L = kSpmvLanes;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
+  const int sub = threadIdx.x % L;
   T acc = 0;
   int b = 0;
   double pn = 0.0;
   if (i < n) {
     const int64_t o0 = row_ptr[i] + sub, e = row_ptr[i + 1];
     b = row_bead[i];
-    int j = 0;
-    T v = 0;
+    int j0 = 0, j1 = 0;  // a negative column is a zero entry
+    T v0 = 0, v1 = 0;
     if (o0 < e) {
-      j = col[o0];  // a negative column is a zero entry
-      v = val[o0];
+      j0 = col[o0];
+      v0 = val[o0];
+    }
+    if (o0 + L < e) {
+      j1 = col[o0 + L];
+      v1 = val[o0 + L];
     }
     if (sub == 0) pn = phi_real[b];
-    if (o0 < e) acc = v * (T)q[j < 0 ? -1 - j : j];
-    for (int64_t o = o0 + 16; o < e; o += 16) {
+    if (o0 < e) acc = v0 * (T)q[j0 < 0 ? -1 - j0 : j0];
+    if (o0 + L < e) acc += v1 * (T)q[j1 < 0 ? -1 - j1 : j1];
+    for (int64_t o = o0 + 2 * L; o < e; o += L) {
       const int jj = col[o];
       acc += val[o] * (T)q[jj < 0 ? -1 - jj : jj];
     }
   }
 #pragma unroll
-  for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+  for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
   if (i < n && sub == 0) phi_real[b] = (double)acc + pn;
 }
 
@@ -1284,8 +1292,8 @@ void launch_spmv_add(hipStream_t s, pe_context* c, const double* q, double* phi_
     require(c->have_val32, "float real-space operator not built (precision is PE_FP64)");
     val = c->val32.get();
   }
-  hipLaunchKernelGGL(spmv_add_kernel<T>, dim3(nblk(16 * n, 256)), dim3(256), 0, s, c->row_ptr.get(), c->col.get(),
-                     val, c->csr_row.get(), n, q, phi_real);
+  hipLaunchKernelGGL(spmv_add_kernel<T>, dim3(nblk(kSpmvLanes * n, 256)), dim3(256), 0, s, c->row_ptr.get(),
+                     c->col.get(), val, c->csr_row.get(), n, q, phi_real);
   PE_CHECK_LAUNCH();
 }
 

@@ -202,19 +202,17 @@ __global__ void sub_kernel(const double* __restrict__ x, const double* __restric
 }
 
 // Arnoldi column j: h = h1 + h2 (two Gram-Schmidt passes), subdiagonal = norm.
-// Apply the previous rotations, form the new one, update g; store |g[j+1]|.
+// Apply the previous rotations, form the new one, update g; return |g[j+1]|.
 // Layout of st (double): H[(m+1) x m] column-major at 0, cs[m], sn[m], g[m+1].
-__global__ void givens_kernel(const double* __restrict__ h1, const double* __restrict__ h2,
-                              const double* __restrict__ nrm, double* __restrict__ st, int m, int j,
-                              double* __restrict__ res) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ double givens_step(const double* __restrict__ h1, const double* __restrict__ h2, double nrm,
+                              double* __restrict__ st, int m, int j) {
   double* H = st;
   double* cs = st + (m + 1) * m;
   double* sn = cs + m;
   double* g = sn + m;
   double* col = H + (int64_t)j * (m + 1);
   for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  col[j + 1] = *nrm;
+  col[j + 1] = nrm;
   for (int i = 0; i < j; ++i) {
     const double a = col[i], b = col[i + 1];
     col[i] = cs[i] * a + sn[i] * b;
@@ -231,7 +229,115 @@ __global__ void givens_kernel(const double* __restrict__ h1, const double* __res
   const double gj = g[j];
   g[j] = c * gj;
   g[j + 1] = -s * gj;
-  *res = fabs(g[j + 1]);
+  return fabs(g[j + 1]);
+}
+
+__global__ void givens_kernel(const double* __restrict__ h1, const double* __restrict__ h2,
+                              const double* __restrict__ nrm, double* __restrict__ st, int m, int j,
+                              double* __restrict__ res) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  *res = givens_step(h1, h2, *nrm, st, m, j);
+}
+
+// One Arnoldi step in four launches instead of a reduction kernel per pass:
+// each kernel below starts by finishing the previous kernel's reduction
+// itself (every workgroup sums the same partials in the same fixed order, so
+// all of them hold the same values bit for bit), then updates its chunk of w
+// and writes its own partial sums for the next one.  No workgroup waits on
+// another inside a kernel.
+
+// out[k] = sum of the nb partials of output k (partial[k * nb + i]): lane l
+// takes i = l, l + 64, ..., then the wavefront tree; wavefront q of the
+// workgroup takes k = q, q + 4, ...
+__device__ void final_sums(const double* __restrict__ partial, int nb, int K, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int k = wv; k < K; k += nw) {
+    double s = 0;
+    for (int i = lane; i < nb; i += 64) s += partial[(int64_t)k * nb + i];
+    s = wsum(s);
+    if (lane == 0) out[k] = s;
+  }
+}
+
+// Gram-Schmidt pass: h = the previous pass's dot products (from pin, nb
+// partials each; workgroup 0 also stores them in hout), w -= V h over the
+// workgroup's chunk, then the partial sums for the next reduction: V_k . w,
+// k < K, or (NORM) w . w.
+template <bool NORM>
+__global__ void __launch_bounds__(kBS) cgs_pass_kernel(const double* __restrict__ V, int64_t ldv, int K,
+                                                       const double* __restrict__ pin, double* __restrict__ hout,
+                                                       double* __restrict__ w, int64_t n, int64_t chunk,
+                                                       double* __restrict__ pout) {
+  __shared__ double hs[kMaxK];
+  final_sums(pin, (int)gridDim.x, K, hs);
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < K; k += blockDim.x) hout[k] = hs[k];
+  const int64_t b = (int64_t)blockIdx.x * chunk;
+  const int64_t e = b + chunk < n ? b + chunk : n;
+  if constexpr (NORM) {
+    double acc[1] = {0};
+    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+      double s = 0;
+      for (int k = 0; k < K; ++k) s += hs[k] * V[k * ldv + i];
+      const double wi = w[i] - s;
+      w[i] = wi;
+      acc[0] += wi * wi;
+    }
+    __shared__ double o[1];
+    block_sum<1>(acc, o);
+    if (threadIdx.x == 0) pout[blockIdx.x] = o[0];
+  } else {
+    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+      double s = 0;
+      for (int k = 0; k < K; ++k) s += hs[k] * V[k * ldv + i];
+      w[i] -= s;
+    }
+    // each thread reads back only the elements it wrote
+    __shared__ double red[kMaxK][kBS / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < K; ++k) {
+      double t = 0;
+      for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) t += V[k * ldv + i] * w[i];
+      t = wsum(t);
+      if (lane == 0) red[k][wv] = t;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      double p = 0;
+      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) p += red[k][q];
+      pout[(int64_t)k * gridDim.x + blockIdx.x] = p;
+    }
+  }
+}
+
+// End of the step: ||w|| from the norm partials, vout = w / ||w|| over the
+// workgroup's chunk; workgroup 0 stores the norm and takes the Givens step of
+// column j (h1 + h2, ||w||), writing the residual estimate to *res and, when
+// given, to page-locked host memory (read by the host after the stream
+// reaches an event recorded behind this kernel).
+__global__ void __launch_bounds__(kBS) cgs_finish_kernel(const double* __restrict__ w, int64_t n, int64_t chunk,
+                                                         const double* __restrict__ pnorm,
+                                                         const double* __restrict__ h1,
+                                                         const double* __restrict__ h2, double* __restrict__ nrm,
+                                                         double* __restrict__ vout, double* __restrict__ st, int m,
+                                                         int j, double* __restrict__ res, double* res_host) {
+  __shared__ double ss[1];
+  final_sums(pnorm, (int)gridDim.x, 1, ss);
+  __syncthreads();
+  const double d = sqrt(ss[0]);
+  const int64_t b = (int64_t)blockIdx.x * chunk;
+  const int64_t e = b + chunk < n ? b + chunk : n;
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) vout[i] = d > 0 ? w[i] / d : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *nrm = d;
+    const double r = givens_step(h1, h2, d, st, m, j);
+    *res = r;
+    if (res_host) {
+      *res_host = r;
+      __threadfence_system();
+    }
+  }
 }
 
 // g = [beta, 0, ...]
@@ -428,6 +534,36 @@ void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y,
 void launch_sub(hipStream_t s, const double* x, const double* y, double* z, int64_t n) {
   if (n == 0) return;
   hipLaunchKernelGGL(sub_kernel, dim3(nblk(n, kBS)), dim3(kBS), 0, s, x, y, z, n);
+  PE_CHECK_LAUNCH();
+}
+
+namespace {
+// chunks of the Krylov reductions: 1024 elements, or n / 1024 when that is
+// larger, so there are at most 1024 partials per output
+int64_t kchunk(int64_t n) {
+  int64_t chunk = 1024;
+  if ((n + chunk - 1) / chunk > 1024) chunk = (n + 1023) / 1024;
+  return chunk;
+}
+unsigned kchunks(int64_t n, int64_t chunk) { return (unsigned)std::max<int64_t>(1, (n + chunk - 1) / chunk); }
+}  // namespace
+
+void launch_cgs_step(hipStream_t s, const double* V, int64_t ldv, int K, double* w, int64_t n, double* partial,
+                     double* h1, double* h2, double* nrm, double* vout, double* st, int m, int j, double* res,
+                     double* res_host) {
+  require(K >= 1 && K <= kMaxK, "Gram-Schmidt: too many vectors");
+  const int64_t chunk = kchunk(n);
+  const unsigned nb = kchunks(n, chunk);
+  double* p1 = partial;
+  double* p2 = partial + (size_t)kMaxK * 1024;
+  hipLaunchKernelGGL(mdot_partial_kernel, dim3(nb, K), dim3(kBS), 0, s, V, ldv, w, n, chunk, p1);
+  PE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cgs_pass_kernel<false>, dim3(nb), dim3(kBS), 0, s, V, ldv, K, p1, h1, w, n, chunk, p2);
+  PE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cgs_pass_kernel<true>, dim3(nb), dim3(kBS), 0, s, V, ldv, K, p2, h2, w, n, chunk, p1);
+  PE_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cgs_finish_kernel, dim3(nb), dim3(kBS), 0, s, w, n, chunk, p1, h1, h2, nrm, vout, st, m, j,
+                     res, res_host);
   PE_CHECK_LAUNCH();
 }
 

@@ -29,6 +29,14 @@ void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y,
 void launch_sub(hipStream_t s, const double* x, const double* y, double* z, int64_t n);
 void launch_givens(hipStream_t s, const double* h1, const double* h2, const double* nrm, double* st, int m,
                    int j, double* res);
+// One classical Gram-Schmidt (CGS2) Arnoldi step of column j in four
+// launches: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, *nrm = ||w||,
+// vout = w / ||w||, then the Givens step (h1 + h2, ||w||) with the residual
+// estimate in *res and, when res_host is given, in page-locked host memory.
+// V holds K vectors of n (stride ldv); partial holds 2 kMaxK 1024 doubles.
+void launch_cgs_step(hipStream_t s, const double* V, int64_t ldv, int K, double* w, int64_t n, double* partial,
+                     double* h1, double* h2, double* nrm, double* vout, double* st, int m, int j, double* res,
+                     double* res_host);
 void launch_init_g(hipStream_t s, double* st, int m, const double* beta);
 void launch_backsolve(hipStream_t s, const double* st, int m, int k, double* y);
 
