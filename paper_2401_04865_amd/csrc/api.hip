@@ -365,32 +365,36 @@ void apply_saddle(pe_context* c, const double* x, double* y) {
   // the mesh part (spread, FFT, contraction) runs on the caller's: the dense
   // intra-body blocks per shape, then the sparse inter-body pairs added;
   // also the charge moments (the k = 0 term) and the body net charges; the
-  // assembly after the join.  The mesh part is the longer chain, so its
-  // launches are enqueued first: the caller's stream must not idle while
-  // the host enqueues the auxiliary work.
+  // assembly after the join.  The spread is enqueued first, then the
+  // auxiliary work (enqueued while the spread runs, and run beside the
+  // spread, which is instruction-bound, rather than beside the FFT passes,
+  // which are bandwidth-bound), then the rest of the mesh part.
   c->phi_near.ensure((size_t)std::max<int64_t>(nb, 1));
   double* phi_real = c->phi_near.get();
   fork_aux(c);
   { ProfScope ps(c->prof, s, PE_PROF_SPREAD, dbl, (double)nb); launch_spread<T>(s, c->B, q, gA, c->gg, false); }
-  launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
-  { ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
   {
     hipStream_t sa = c->aux;
     launch_moments(sa, q, c->bead_sig.get(), 0.0, nb, ck_coef(c), c->red.get(), ck_bead(c), nullptr);
     launch_seg_sum(sa, c->off.get(), c->n_body, q, y + nb);
-    PE_HIP(hipMemsetAsync(phi_real, 0, sizeof(double) * nb, sa));
+    // every bead segment belongs to one body: when all bodies have a dense
+    // block, the block products write every entry and nothing is cleared
+    const bool all_near = c->pc.near_beads == nb;
+    if (!all_near) PE_HIP(hipMemsetAsync(phi_real, 0, sizeof(double) * nb, sa));
     for (auto& t : c->pc.types) {
       if (!t.near || t.bodies.empty()) continue;
       const T* R;
       if constexpr (sizeof(T) == 8) R = t.R64.get();
       else R = t.R32.get();
       ProfScope ps(c->prof, sa, PE_PROF_NEAR, dbl, (double)t.N * t.N * (double)t.bodies.size());
-      launch_body_gemm<T>(sa, R, t.N, false, true, t.dbodies.get(), (int)t.bodies.size(), c->off.get(), nb,
+      launch_body_gemm<T>(sa, R, t.N, false, !all_near, t.dbodies.get(), (int)t.bodies.size(), c->off.get(), nb,
                           q, phi_real, c->pc.gemm_ws.get());
     }
     ProfScope ps(c->prof, sa, PE_PROF_SPMV, dbl, (double)c->nnz);
     launch_spmv_add<T>(sa, c, q, phi_real);
   }
+  launch_wave_pipeline<T>(s, c, gA, gB, c->gridC.get());
+  { ProfScope ps(c->prof, s, PE_PROF_GATHER, dbl, (double)nb); launch_gather<T>(s, c->B, gB, c->gg, c->phi_w.get(), nullptr, false); }
   join_aux(c);
   launch_assemble(s, c, dpsi, c->phi_w.get(), phi_real, ck_bead(c), y);
 }

@@ -206,30 +206,94 @@ __global__ void sorted_charges_kernel(const int* __restrict__ idx, const double*
 // q f_x[a] f_y[b] f_z[c] into the z-pencil (a, b, 0..7) it holds in
 // registers.  No workgroup barrier inside the loop.  At the end the four
 // tiles meet in LDS and the column is written once, 32 values of z per row
-// (whole 128-byte lines in single precision), with no atomics; every tile is
-// written (empty ones with zeros), so the grid needs no clearing between
-// products.  The lists are sorted, so the result is the same bit for bit on
-// every run.
+// (whole 128-byte lines in single precision, 16-byte stores where the mesh
+// allows), with no atomics; every tile is written (empty ones with zeros), so
+// the grid needs no clearing between products.  The lists are sorted, so the
+// result is the same bit for bit on every run.
 constexpr int kWaveChunk = 21;
+
+// Single-precision window factors of a particle set, once per configuration
+// (positions fixed, charges not), for supports of at most 8 points on meshes
+// of whole tiles (every N a multiple of 8).  Such a support covers a tile
+// from slot m mod 8 on (m: wrapped index of support point 0, the home tile)
+// and, when it does not start on slot 0, the next tile up to slot m mod 8
+// (exclusive).  Both are the eight factors rotated by m mod 8,
+// rot[loc] = f[(loc - m) mod 8], masked: so rot is stored, per particle
+// (sorted order) and axis, with m.  f[j] = wnorm exp(-wexp ((j + delta) h)^2)
+// for j < P (zero up to 8), in the float arithmetic the spreading kernel
+// applies.  Planar layout: wf[(2 ax + h) n + i] holds slots 4h..4h+3 of
+// particle i, so consecutive threads store consecutive vectors.
+__global__ void __launch_bounds__(256) window_factors_kernel(const double4* __restrict__ pos, int64_t n, GridGeom g,
+                                                             float4* __restrict__ wf, int4* __restrict__ ws) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = pos[i];
+  const float we = (float)g.wexp, wn = (float)g.wnorm;
+  int m[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const double x = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
+    double delta;
+    m[ax] = wrap_idx(support_start(x, g.inv_h[ax], g.P, delta), g.N[ax]);
+    const float hf = (float)g.h[ax], df = (float)delta;
+    float f[kTile];
+#pragma unroll
+    for (int loc = 0; loc < kTile; ++loc) {
+      const int j = (loc - m[ax]) & (kTile - 1);
+      const float d = ((float)j + df) * hf;
+      f[loc] = j < g.P ? wn * __expf(-we * d * d) : 0.0f;
+    }
+    wf[(2 * ax) * n + i] = make_float4(f[0], f[1], f[2], f[3]);
+    wf[(2 * ax + 1) * n + i] = make_float4(f[4], f[5], f[6], f[7]);
+  }
+  ws[i] = make_int4(m[0], m[1], m[2], 0);
+}
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+  using type = float4;
+  static __device__ __forceinline__ type add(type a, type b) {
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+  }
+};
+template <> struct Vec16<double> {
+  using type = double2;
+  static __device__ __forceinline__ type add(type a, type b) { return make_double2(a.x + b.x, a.y + b.y); }
+};
 
 // HOME: the particle list of a tile is the concatenation of the sorted home
 // lists of the tiles (ux - dx, uy - dy, uz - dz), d in {0, 1}^3 (tile_start /
 // entries are then the home lists); particles whose support misses the tile
 // get zero factors.  Eight wavefronts per SIMD (at most 64 VGPRs, no spills;
-// 14 KB of LDS per workgroup leaves room for eight workgroups per CU): the
+// at most 16 KB of LDS per workgroup leaves room for eight workgroups per CU): the
 // loop waits on its list and position loads, and more resident wavefronts hide
 // them (bead spread 198 -> 189 us on the 256^3 mesh).
+// PRE (single precision, P <= 8, N a multiple of 8 on every axis; nset
+// particles in the set): the factors come rotated from window_factors_kernel; a staging lane keeps slot
+// loc where loc >= s0 in the home tile (s0 >= 0, the tile-local position of
+// support point 0) or loc < s0 + 8 in the next one, times the charge (x
+// axis): eight selects instead of eight exponentials (staging drops from
+// about 120 vector instructions per round to about 30).  Its rows are 12
+// floats, which spreads the row stores of a wavefront over more LDS banks.
 // Double precision (used for the ions' home lists when a double pass spreads
 // them) takes the window factors in double and holds four wavefronts per
 // SIMD (the z-pencil is twice as wide in registers).
-template <typename T, bool HOME>
+template <typename T, bool HOME, bool PRE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) spread_tile_kernel(const double4* __restrict__ pos,
                                                           const double* __restrict__ qs,
                                                           const int* __restrict__ tile_start,
                                                           const int* __restrict__ entries,
+                                                          const float4* __restrict__ wfac,
+                                                          const int* __restrict__ wsta, int64_t nset,
                                                           T* __restrict__ grid, GridGeom g, int accumulate) {
-  __shared__ T f_s[kWaves][kWaveChunk][3][kTile];
-  __shared__ T col[kTile][kTile][kWaves * kTile];  // (a, b, z of the column)
+  static_assert(!PRE || sizeof(T) == 4, "precomputed factors are single precision");
+  constexpr int kRow = PRE ? 12 : kTile;  // LDS slots per staged (particle, axis)
+  constexpr int kSlice = kWaveChunk * 3 * kRow;
+  constexpr int kStage = kWaves * kSlice;
+  constexpr int kColLen = kWaves * kTile;                  // z values of the column
+  constexpr int kCol = kTile * kTile * kColLen;
+  // staged rows during the loop, the column (a, b, z) after it
+  __shared__ __align__(16) T smem[kStage > kCol ? kStage : kCol];
   const int nbz = (g.ntile[2] + kWaves - 1) / kWaves;
   const int bz = blockIdx.x % nbz;
   const int uy = (blockIdx.x / nbz) % g.ntile[1];
@@ -277,16 +341,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       e0 = tile_start[tid];
       e1 = tile_start[tid + 1];
     }
-    T (*fw)[3][kTile] = f_s[wv];
+    T* fw = smem + wv * kSlice;  // row (c, ax) at fw + (3 c + ax) kRow
     // staging lane: particle c3 of the round, axis ax3.  Loads run ahead of
-    // use: the entries two rounds ahead, the coordinate and charge one round
-    // ahead, so their latency overlaps the current round's work.
+    // use: the entries two rounds ahead, the coordinate (or the factors) and
+    // charge one round ahead, so their latency overlaps the current round's
+    // work.
     const int c3 = lane / 3, ax3 = lane - 3 * (lane / 3);
     const bool stager = lane < 3 * kWaveChunk;
     const int N = sel3(ax3, g.N[0], g.N[1], g.N[2]);
     const double ih3 = sel3(ax3, g.inv_h[0], g.inv_h[1], g.inv_h[2]);
     const double h3 = sel3(ax3, g.h[0], g.h[1], g.h[2]);
     const int u = ax3 == 0 ? ux : (ax3 == 1 ? uy : uz);
+    T* const srow = fw + (3 * c3 + ax3) * kRow;
     // (called with every lane of the wavefront active)
     auto entry_at = [&](int c0) {
       const int k = c0 + c3;
@@ -302,46 +368,72 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         return entries[k];
       }
     };
+    // what a staging lane reads per round
+    struct Stage {
+      double x = 0, q = 1;                        // coordinate, charge
+      float4 fa = {0, 0, 0, 0}, fb = {0, 0, 0, 0};  // PRE: factors 0..7
+      int mw = 0;                                 // PRE: wrapped index of support point 0
+    };
+    auto fetch = [&](int i, Stage& st) {
+      if (i < 0) return;
+      if constexpr (PRE) {
+        st.fa = wfac[(2 * ax3) * nset + i];
+        st.fb = wfac[(2 * ax3 + 1) * nset + i];
+        st.mw = wsta[4 * i + ax3];
+      } else {
+        st.x = reinterpret_cast<const double*>(pos + i)[ax3];
+      }
+      if (ax3 == 0) st.q = qs[i];
+    };
     int i1 = entry_at(e0), i2 = entry_at(e0 + kWaveChunk);
-    double x1 = 0, q1 = 1;
-    if (i1 >= 0) {
-      x1 = reinterpret_cast<const double*>(pos + i1)[ax3];
-      if (ax3 == 0) q1 = qs[i1];
-    }
+    Stage st1;
+    fetch(i1, st1);
     for (int c0 = e0; c0 < e1; c0 += kWaveChunk) {
       const int nc = min(kWaveChunk, e1 - c0);
       const int i3 = entry_at(c0 + 2 * kWaveChunk);
-      double x2 = 0, q2 = 1;
-      if (i2 >= 0) {
-        x2 = reinterpret_cast<const double*>(pos + i2)[ax3];
-        if (ax3 == 0) q2 = qs[i2];
-      }
+      Stage st2;
+      fetch(i2, st2);
       if (i1 >= 0) {
-        double delta;
-        const int m0 = support_start(x1, ih3, P, delta);
-        // tile-local position of support point 0, taken in [1 - P, kTile - 1]
-        int s0 = wrap_idx(m0, N) - kTile * u;
-        if (s0 > kTile - 1) s0 -= N;
-        if (s0 < 1 - P) s0 += N;
-        if constexpr (sizeof(T) == 4) {
-          // single precision once the support is placed: the displacement
-          // (j + delta) h is below P h, so float keeps it to rounding and the
-          // exponential to a few ulp
-          const float hf = (float)h3, df = (float)delta, we = (float)g.wexp;
-          const float wn = (float)g.wnorm * (float)q1;
+        if constexpr (PRE) {
+          int s0 = st1.mw - kTile * u;
+          if (s0 > kTile - 1) s0 -= N;
+          if (s0 < 1 - P) s0 += N;
+          // s0 outside [1 - P, 7]: a neighbour's home particle whose support
+          // stops short of this tile (all zero)
+          const bool seen = s0 >= 1 - P && s0 <= kTile - 1;
+          const int mr = s0 & (kTile - 1);
+          const bool home = s0 >= 0;
+          const float qf = seen ? (float)st1.q : 0.0f;
+          const float f[kTile] = {st1.fa.x, st1.fa.y, st1.fa.z, st1.fa.w, st1.fb.x, st1.fb.y, st1.fb.z, st1.fb.w};
 #pragma unroll
-          for (int loc = 0; loc < kTile; ++loc) {
-            const int j = loc - s0;
-            const float d = ((float)j + df) * hf;
-            fw[c3][ax3][loc] = (j >= 0 && j < P) ? (T)(wn * __expf(-we * d * d)) : (T)0;
-          }
+          for (int loc = 0; loc < kTile; ++loc) srow[loc] = (loc >= mr) == home ? f[loc] * qf : 0.0f;
         } else {
-          const double wn = g.wnorm * q1;
+          double delta;
+          const int m0 = support_start(st1.x, ih3, P, delta);
+          // tile-local position of support point 0, taken in [1 - P, kTile - 1]
+          int s0 = wrap_idx(m0, N) - kTile * u;
+          if (s0 > kTile - 1) s0 -= N;
+          if (s0 < 1 - P) s0 += N;
+          if constexpr (sizeof(T) == 4) {
+            // single precision once the support is placed: the displacement
+            // (j + delta) h is below P h, so float keeps it to rounding and the
+            // exponential to a few ulp
+            const float hf = (float)h3, df = (float)delta, we = (float)g.wexp;
+            const float wn = (float)g.wnorm * (float)st1.q;
 #pragma unroll
-          for (int loc = 0; loc < kTile; ++loc) {
-            const int j = loc - s0;
-            const double d = ((double)j + delta) * h3;
-            fw[c3][ax3][loc] = (j >= 0 && j < P) ? (T)(wn * exp(-g.wexp * d * d)) : (T)0;
+            for (int loc = 0; loc < kTile; ++loc) {
+              const int j = loc - s0;
+              const float d = ((float)j + df) * hf;
+              srow[loc] = (j >= 0 && j < P) ? (T)(wn * __expf(-we * d * d)) : (T)0;
+            }
+          } else {
+            const double wn = g.wnorm * st1.q;
+#pragma unroll
+            for (int loc = 0; loc < kTile; ++loc) {
+              const int j = loc - s0;
+              const double d = ((double)j + delta) * h3;
+              srow[loc] = (j >= 0 && j < P) ? (T)(wn * exp(-g.wexp * d * d)) : (T)0;
+            }
           }
         }
       }
@@ -349,9 +441,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int c = 0; c < nc; ++c) {
-        const T coef = fw[c][0][pa] * fw[c][1][pb];
+        const T* r = fw + 3 * c * kRow;
+        const T coef = r[pa] * r[kRow + pb];
 #pragma unroll
-        for (int z = 0; z < kTile; ++z) acc[z] += coef * fw[c][2][z];
+        for (int z = 0; z < kTile; ++z) acc[z] += coef * r[2 * kRow + z];
       }
       // the slice is restaged next round
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -359,24 +452,45 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       i1 = i2;
       i2 = i3;
-      x1 = x2;
-      q1 = q2;
+      st1 = st2;
     }
   }
+  __syncthreads();  // every wavefront is done with its staged rows
+  T* col = smem;    // (a, b, z of the column)
 #pragma unroll
-  for (int z = 0; z < kTile; ++z) col[pa][pb][kTile * wv + z] = acc[z];
+  for (int z = 0; z < kTile; ++z) col[(pa * kTile + pb) * kColLen + kTile * wv + z] = acc[z];
   __syncthreads();
-  // rows (a, b) of up to 32 z values: 8 threads per row, 4 values each
-  const int zlen = min(kWaves * kTile, g.N[2] - kWaves * kTile * bz);
-  for (int k = threadIdx.x; k < kTile * kTile * kWaves * kTile; k += blockDim.x) {
-    const int zz = k % (kWaves * kTile);
-    const int row = k / (kWaves * kTile);
-    const int a = row / kTile, b = row % kTile;
-    const int gx = kTile * ux + a, gy = kTile * uy + b, gz = kWaves * kTile * bz + zz;
-    if (gx < g.N[0] && gy < g.N[1] && zz < zlen) {
-      const int64_t o = ((int64_t)gx * g.N[1] + gy) * g.N[2] + gz;
-      const T v = col[a][b][zz];
-      grid[o] = accumulate ? grid[o] + v : v;
+  const int zlen = min(kColLen, g.N[2] - kColLen * bz);
+  constexpr int kV = 16 / (int)sizeof(T);
+  if (g.N[2] % kV == 0) {
+    // rows (a, b) of up to 32 z values in 16-byte vectors (zlen and every
+    // offset are multiples of kV)
+    using V = typename Vec16<T>::type;
+    for (int k = threadIdx.x; k < kCol / kV; k += blockDim.x) {
+      const int zz = (k % (kColLen / kV)) * kV;
+      const int row = k / (kColLen / kV);
+      const int a = row / kTile, b = row % kTile;
+      const int gx = kTile * ux + a, gy = kTile * uy + b, gz = kColLen * bz + zz;
+      if (gx < g.N[0] && gy < g.N[1] && zz < zlen) {
+        const int64_t o = ((int64_t)gx * g.N[1] + gy) * g.N[2] + gz;
+        V v = *reinterpret_cast<const V*>(col + row * kColLen + zz);
+        V* dst = reinterpret_cast<V*>(grid + o);
+        if (accumulate) v = Vec16<T>::add(*dst, v);
+        *dst = v;
+      }
+    }
+  } else {
+    // rows (a, b) of up to 32 z values: 8 threads per row, 4 values each
+    for (int k = threadIdx.x; k < kCol; k += blockDim.x) {
+      const int zz = k % kColLen;
+      const int row = k / kColLen;
+      const int a = row / kTile, b = row % kTile;
+      const int gx = kTile * ux + a, gy = kTile * uy + b, gz = kColLen * bz + zz;
+      if (gx < g.N[0] && gy < g.N[1] && zz < zlen) {
+        const int64_t o = ((int64_t)gx * g.N[1] + gy) * g.N[2] + gz;
+        const T v = col[row * kColLen + zz];
+        grid[o] = accumulate ? grid[o] + v : v;
+      }
     }
   }
 }
@@ -791,6 +905,7 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g, bool spread_
   spread_by_home = spread_by_home && g.P <= kTile && g.N[0] % kTile == 0 && g.N[1] % kTile == 0 &&
                    g.N[2] % kTile == 0;
   ps.have_tile_lists = false;
+  ps.wfac_valid = false;
   ps.spread_by_home = spread_by_home;
   if (!spread_by_home) build_tile_lists(s, ps, g);
   ps.tile_count.ensure(2 * (size_t)nt);
@@ -829,6 +944,22 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g, bool spread_
   }
 }
 
+bool window_factors_apply(const GridGeom& g) {
+  return g.P <= kTile && g.N[0] % kTile == 0 && g.N[1] % kTile == 0 && g.N[2] % kTile == 0;
+}
+
+void prepare_window_factors(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
+  if (ps.wfac_valid || !window_factors_apply(g)) return;
+  ps.wfac.ensure(6 * (size_t)std::max<int64_t>(ps.n, 1));
+  ps.wsta.ensure((size_t)std::max<int64_t>(ps.n, 1));
+  if (ps.n > 0) {
+    hipLaunchKernelGGL(window_factors_kernel, dim3((unsigned)((ps.n + 255) / 256)), dim3(256), 0, s, ps.pos.get(),
+                       ps.n, g, ps.wfac.get(), ps.wsta.get());
+    PE_CHECK_LAUNCH();
+  }
+  ps.wfac_valid = true;
+}
+
 template <typename T>
 void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* grid, const GridGeom& g,
                    bool accumulate) {
@@ -844,12 +975,22 @@ void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* gri
     }
     const int nbz = (g.ntile[2] + kWaves - 1) / kWaves;
     const int nt = g.ntile[0] * g.ntile[1] * nbz;
-    if (ps.spread_by_home)
-      hipLaunchKernelGGL((spread_tile_kernel<T, true>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
-                         m.qspread.get(), ps.home_start.get(), ps.home_entries.get(), grid, g, accumulate ? 1 : 0);
-    else
-      hipLaunchKernelGGL((spread_tile_kernel<T, false>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
-                         m.qspread.get(), ps.tile_start.get(), ps.tile_entries.get(), grid, g, accumulate ? 1 : 0);
+    const int* start = ps.spread_by_home ? ps.home_start.get() : ps.tile_start.get();
+    const int* entries = ps.spread_by_home ? ps.home_entries.get() : ps.tile_entries.get();
+    // the tile lists of a set spread by every Krylov product (supports of at
+    // most one tile on whole tiles): factors computed once per configuration
+    if (!ps.spread_by_home && window_factors_apply(g)) {
+      prepare_window_factors(s, m, g);
+      hipLaunchKernelGGL((spread_tile_kernel<T, false, true>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
+                         m.qspread.get(), start, entries, ps.wfac.get(), reinterpret_cast<const int*>(ps.wsta.get()),
+                         ps.n, grid, g, accumulate ? 1 : 0);
+    } else if (ps.spread_by_home) {
+      hipLaunchKernelGGL((spread_tile_kernel<T, true, false>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
+                         m.qspread.get(), start, entries, nullptr, nullptr, ps.n, grid, g, accumulate ? 1 : 0);
+    } else {
+      hipLaunchKernelGGL((spread_tile_kernel<T, false, false>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
+                         m.qspread.get(), start, entries, nullptr, nullptr, ps.n, grid, g, accumulate ? 1 : 0);
+    }
   } else if (ps.spread_by_home) {
     // a set spread from its sorted home lists (the ions in mixed precision,
     // whose double pass forms the right-hand side): no tile lists needed
@@ -861,8 +1002,9 @@ void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* gri
     }
     const int nbz = (g.ntile[2] + kWaves - 1) / kWaves;
     const int nt = g.ntile[0] * g.ntile[1] * nbz;
-    hipLaunchKernelGGL((spread_tile_kernel<T, true>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
-                       m.qspread.get(), ps.home_start.get(), ps.home_entries.get(), grid, g, accumulate ? 1 : 0);
+    hipLaunchKernelGGL((spread_tile_kernel<T, true, false>), dim3((unsigned)nt), dim3(256), 0, s, ps.pos.get(),
+                       m.qspread.get(), ps.home_start.get(), ps.home_entries.get(), nullptr, nullptr, ps.n, grid, g,
+                       accumulate ? 1 : 0);
   } else {
     if (!ps.have_tile_lists) build_tile_lists(s, m, g);
     // double: the window exponentials dominate, and spreading them over the

@@ -230,6 +230,9 @@ struct ParticleSet {
   DevBuf<int4> chunks;      // pair-traversal work units: (first, end sorted slot, first cell, cells), <= 64 each
   DevBuf<double> qsorted;   // charges in sorted order for the pair passes (scratch)
   DevBuf<double> qspread;   // charges in sorted order for spreading (scratch)
+  DevBuf<float4> wfac;      // sorted: single-precision window factors, 8 per axis, rotated (support <= 8)
+  DevBuf<int4> wsta;        // sorted: wrapped mesh index of support point 0 per axis
+  bool wfac_valid = false;  // window factors of the current configuration
   int n_chunks = 0;
   // grid tiles overlapped by each particle's support (spreading lists)
   DevBuf<int> tile_start;   // ntile + 1
@@ -388,6 +391,7 @@ struct Precond {
   DevBuf<int> assigned;            // per body: type index
   DevBuf<unsigned char> dense;     // per body: intra-body pairs held by a dense block
   std::vector<unsigned char> dense_h;  // host copy
+  int64_t near_beads = 0;          // beads of bodies with a dense block
   DevBuf<double> gemm_ws;          // partial tiles of the split per-shape products
 };
 
@@ -515,6 +519,12 @@ namespace pe {
 
 // grid: spread charges q (indexed by caller index through idx) into grid (accumulate)
 void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g, bool spread_by_home);
+// single-precision window factors of the set's configuration (supports of at
+// most 8 points on meshes of whole 8-point tiles): computed by the first
+// single-precision spread of the set's tile lists after the configuration
+// changed, used by every later one
+bool window_factors_apply(const GridGeom& g);
+void prepare_window_factors(hipStream_t s, ParticleSet& ps, const GridGeom& g);
 template <typename T>
 void launch_spread(hipStream_t s, const ParticleSet& ps, const double* q, T* grid, const GridGeom& g,
                    bool accumulate);

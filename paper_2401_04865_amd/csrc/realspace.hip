@@ -1026,6 +1026,7 @@ float candidate_rc2(const RealGeom& g) {
 void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
                  double sig_const, const int* owner, int64_t n, const RealGeom& rg) {
   ps.n = n;
+  ps.wfac_valid = false;
   const int ncell = rg.nc[0] * rg.nc[1] * rg.nc[2];
   ps.pos.ensure(n);
   ps.posf.ensure(n);

@@ -278,6 +278,7 @@ void shape_setup(pe_context* c) {
   Precond& pc = c->pc;
   hipStream_t s = c->stream;
   for (auto& t : pc.types) t.bodies.clear();
+  pc.near_beads = 0;
   const int64_t nbody = c->n_body;
   if (nbody == 0) return;
   pc.assigned.ensure(nbody);
@@ -330,6 +331,9 @@ void shape_setup(pe_context* c) {
     if (t.near)
       for (int b : t.bodies) dense[b] = 1;
   }
+  pc.near_beads = 0;
+  for (auto& t : pc.types)
+    if (t.near) pc.near_beads += (int64_t)t.N * (int64_t)t.bodies.size();
   // workspace of the split products (in doubles; float partials use half)
   size_t ws = 1;
   for (auto& t : pc.types)
