@@ -649,6 +649,7 @@ __global__ void __launch_bounds__(256) gather_kernel(const double4* __restrict__
 // (the common support): the lines are unrolled, their P loads issued
 // together, and the x factors held in registers.
 constexpr int kGatherLDS = 48 * 1024;
+constexpr int kGatherRow = 16;  // LDS row of the region with a compile-time support (P = 8)
 
 // Single precision is held to 64 VGPRs (the field variant needs 65 unforced),
 // eight wavefronts per SIMD; its LDS region of 15^3 floats still lets eight
@@ -675,18 +676,51 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   const int P = PP > 0 ? PP : g.P;
   const int Hs = kTile + P - 1;
   const int Hs2 = Hs * Hs;
+  // LDS row (lx, ly) of the region: Hs z values, padded to 16 with a
+  // compile-time support (16-byte aligned rows)
+  const int Hrow = PP > 0 ? kGatherRow : Hs;
+  const int Hx = Hs * Hrow;  // stride of lx
+  static_assert(PP == 0 || kTile + PP - 1 <= kGatherRow, "region rows fit the padded LDS rows");
   if ((int)threadIdx.x < 3 * Hs) {
     const int ax = threadIdx.x / Hs, l = threadIdx.x - ax * Hs;
     const int u = ax == 0 ? ux : (ax == 1 ? uy : uz);
     gidx[ax][l] = wrap_idx(kTile * u + l, sel3(ax, g.N[0], g.N[1], g.N[2]));
   }
   __syncthreads();
-  // region rows (lx, ly) of Hs contiguous z values, 16 threads per row (a
-  // second pass of 16 only where Hs > 16, which a compile-time P <= 9
+  // single precision, a compile-time support, a region that does not wrap in
+  // z and 16-byte aligned grid rows: four lanes per region row, each loading
+  // four consecutive z values as one 16-byte vector (the 16th value of a row
+  // is read and not used); all of a thread's loads are issued before its
+  // stores
+  constexpr int kVecPasses = PP > 0 ? (((kTile + PP - 1) * (kTile + PP - 1)) + 63) / 64 : 1;
+  const bool vec_rows = sizeof(T) == 4 && PP > 0 && g.N[2] % 4 == 0 && kTile * uz + kGatherRow <= g.N[2];
+  if constexpr (sizeof(T) == 4 && PP > 0) {
+    if (vec_rows) {
+      const int q4 = threadIdx.x & 3;
+      float4 v[kVecPasses];
+#pragma unroll
+      for (int u = 0; u < kVecPasses; ++u) {
+        const int row = (threadIdx.x >> 2) + 64 * u;
+        const int lx = row / Hs;
+        const int ly = row - lx * Hs;
+        const int64_t o = row < Hs2
+                              ? ((int64_t)gidx[0][lx] * g.N[1] + gidx[1][ly]) * g.N[2] + kTile * uz + 4 * q4
+                              : 0;
+        v[u] = *reinterpret_cast<const float4*>(grid + o);
+      }
+#pragma unroll
+      for (int u = 0; u < kVecPasses; ++u) {
+        const int row = (threadIdx.x >> 2) + 64 * u;
+        if (row < Hs2) *reinterpret_cast<float4*>(H + row * Hrow + 4 * q4) = v[u];
+      }
+    }
+  }
+  // otherwise region rows (lx, ly) of Hs contiguous z values, 16 threads per
+  // row (a second pass of 16 only where Hs > 16, which a compile-time P <= 9
   // excludes); eight rows' loads are issued before their stores, so their
   // latencies overlap
   constexpr int kHalves = PP > 0 ? (kTile + PP - 1 + 15) / 16 : 2;
-  for (int r0 = threadIdx.x >> 4; r0 < Hs2; r0 += 16 * 8) {
+  for (int r0 = threadIdx.x >> 4; r0 < (vec_rows ? 0 : Hs2); r0 += 16 * 8) {
     T v[8][kHalves];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -710,7 +744,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
       for (int h = 0; h < kHalves; ++h) {
         const int lz = (threadIdx.x & 15) + 16 * h;
-        if (row < Hs2 && lz < Hs) H[row * Hs + lz] = v[u][h];
+        if (row < Hs2 && lz < Hs) H[row * Hrow + lz] = v[u][h];
       }
     }
   }
@@ -786,10 +820,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const int jy = t / PP;
         const int jz = t - jy * PP;
         const T wyz = wsl[PP + jy] * wsl[2 * PP + jz];
-        const T* col = H + (ox * Hs + oy + jy) * Hs + oz + jz;
+        const T* col = H + (ox * Hs + oy + jy) * Hrow + oz + jz;
         T v[PP];
 #pragma unroll
-        for (int jx = 0; jx < PP; ++jx) v[jx] = col[jx * Hs2];
+        for (int jx = 0; jx < PP; ++jx) v[jx] = col[jx * Hx];
         T lacc = 0, lx = 0;
 #pragma unroll
         for (int jx = 0; jx < PP; ++jx) {
@@ -809,10 +843,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       const int jy = t / P;
       const int jz = t - jy * P;
       const T wyz = wsl[P + jy] * wsl[2 * P + jz];
-      const T* col = H + (ox * Hs + oy + jy) * Hs + oz + jz;
+      const T* col = H + (ox * Hs + oy + jy) * Hrow + oz + jz;
       T lacc = 0, lx = 0;
       for (int jx = 0; jx < P; ++jx) {
-        const T v = col[jx * Hs2] * wsl[jx];
+        const T v = col[jx * Hx] * wsl[jx];
         lacc += v;
         if (FIELD) lx += v * dsl[jx];
       }
@@ -1022,7 +1056,7 @@ void launch_gather(hipStream_t s, const ParticleSet& ps, const T* grid, const Gr
   if (ps.n == 0) return;
   require(g.P <= kMaxP, "support P must be <= 16");
   const int Hs = kTile + g.P - 1;
-  const size_t region = (size_t)Hs * Hs * Hs * sizeof(T);
+  const size_t region = (size_t)Hs * Hs * (g.P == 8 ? kGatherRow : Hs) * sizeof(T);
   // tile-staged in single precision, and in double for P = 8 (the unrolled
   // contraction: 187 -> 148 us per bead pass at cfg5); double with other
   // supports per particle (its region halves the workgroups an LDS holds)
