@@ -34,6 +34,11 @@ struct Error : std::runtime_error {
 inline void require(bool ok, const std::string& msg) {
   if (!ok) throw Error(PE_ERR_ARG, msg);
 }
+// a literal message builds no string unless the check fails (checks on hot
+// host paths allocate nothing)
+inline void require(bool ok, const char* msg) {
+  if (!ok) throw Error(PE_ERR_ARG, msg);
+}
 
 // -------------------------------------------------------- device workspace
 
@@ -242,8 +247,8 @@ struct ParticleSet {
   PinnedBuf h_tcnt, h_tstart, h_hcnt, h_hstart, h_htiles, h_ccnt, h_cstart, h_chunks;
   bool have_tile_lists = false;   // tile lists built for the current configuration
   bool spread_by_home = false;    // single-precision spreading walks the sorted home lists
-  std::vector<int4> h_colchunks;             // traversal units in column order (scratch)
-  std::vector<int> h_colfirst, h_colcursor;  // per column: first unit, and a cursor (scratch)
+  std::vector<int> h_colcur, h_colz;         // per column: next particle and its cell (scratch of the unit build)
+  std::vector<int> h_start;                  // cell offsets on the host (scratch of the unit build)
   DevBuf<int> tile_entries; // sorted-particle indices, grouped by tile
   int64_t n_entries = 0;
   // home tile of each particle (the tile holding its first support point):

@@ -1050,7 +1050,7 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   const size_t sig_at = ((size_t)ncell + 1) & ~(size_t)1;  // ints
   int* cnt = ps.h_ccnt.get<int>(sig_at + 4);
   unsigned long long* sig = reinterpret_cast<unsigned long long*>(cnt + sig_at);
-  int* start = ps.h_cstart.get<int>((size_t)ncell + 1);
+  int* start_pinned = ps.h_cstart.get<int>((size_t)ncell + 1);
   PE_HIP(hipMemcpyAsync(cnt, ps.cell_count.get(), sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
   if (n > 0) PE_HIP(hipMemcpyAsync(sig, ps.sig_check.get(), 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
@@ -1059,8 +1059,18 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
     if (n > 0) std::memcpy(&w, &sig[1], sizeof(double));
     ps.sig_uniform = n > 0 && sig[0] == 0 && w > 0 && w < INFINITY ? w : 0.0;
   }
-  start[0] = 0;
-  for (int c = 0; c < ncell; ++c) start[c + 1] = start[c] + cnt[c];
+  // offsets in ordinary host memory (the walk below reads them many times;
+  // the page-locked copy only carries the upload), the counts read once
+  std::vector<int>& start_v = ps.h_start;
+  start_v.resize((size_t)ncell + 1);
+  int cmax = 0;
+  start_v[0] = 0;
+  for (int c = 0; c < ncell; ++c) {
+    const int k = cnt[c];
+    start_v[c + 1] = start_v[c] + k;
+    cmax = std::max(cmax, k);
+  }
+  const int* start = start_v.data();
   // traversal work units: runs of up to 64 consecutive particles of one
   // (x, y) column, so a wavefront's lanes are all busy however the cells are
   // filled; a unit spans at most nz_max cells along z (the stencil reaches
@@ -1069,52 +1079,56 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   const int nc0 = rg.nc[0], nc1 = rg.nc[1], nc2 = rg.nc[2];
   const int nz_max = nc2 >= 3 ? std::min(nc2 - 2, 2) : 1;
   const int ncol = nc0 * nc1;
-  std::vector<int4>& colchunks = ps.h_colchunks;
-  std::vector<int>& col_first = ps.h_colfirst;
-  colchunks.clear();
-  col_first.assign(ncol + 1, 0);
-  for (int col = 0; col < ncol; ++col) {
-    col_first[col] = (int)colchunks.size();
-    const int c0 = col * nc2;
-    int cur = start[c0];
-    const int col_end = start[c0 + nc2];
-    int z = 0;
-    while (cur < col_end) {
-      while (start[c0 + z + 1] <= cur) ++z;  // cell of the unit's first particle
-      int end = std::min(cur + 64, col_end);
-      const int zlim = std::min(z + nz_max, nc2);
-      end = std::min(end, start[c0 + zlim]);
-      int zl = z;
-      while (start[c0 + zl + 1] < end) ++zl;  // cell of the unit's last particle
-      colchunks.push_back(make_int4(cur, end, c0 + z, zl - z + 1));
-      cur = end;
-    }
-  }
-  col_first[ncol] = (int)colchunks.size();
   // work order: bricks of kBrick^3 cells, so the units in flight on one XCD
   // (a contiguous range, see xcd_remap) read their sources from a compact
-  // region that its L2 can hold, rather than from a slab of whole planes
+  // region that its L2 can hold, rather than from a slab of whole planes.
+  // One pass: the bricks in order, and in each the columns' units that start
+  // in the brick, every column walked on from where its previous brick left
+  // it (per column the next particle and its cell).
   constexpr int kBrick = 8;
-  int4* chunks = ps.h_chunks.get<int4>(colchunks.size());
+  // at most n/64 full units, and per column one unit per nz_max cells ended
+  // by the z limit and one ended by the column's end
+  const int64_t bound = n / 64 + 1 + (int64_t)ncol * ((nc2 + nz_max - 1) / nz_max + 1);
+  int4* chunks = ps.h_chunks.get<int4>((size_t)bound);
+  std::vector<int>& ccur = ps.h_colcur;
+  std::vector<int>& cz = ps.h_colz;
+  ccur.resize(ncol);
+  cz.assign(ncol, 0);
+  for (int col = 0; col < ncol; ++col) ccur[col] = start[col * nc2];
   int nch = 0;
-  std::vector<int>& cursor = ps.h_colcursor;
-  cursor.assign(col_first.begin(), col_first.end() - 1);
   for (int bx = 0; bx < nc0; bx += kBrick)
     for (int by = 0; by < nc1; by += kBrick)
-      for (int bz = 0; bz < nc2; bz += kBrick)
+      for (int bz = 0; bz < nc2; bz += kBrick) {
+        const int zb = std::min(bz + kBrick, nc2);
         for (int x = bx; x < std::min(bx + kBrick, nc0); ++x)
           for (int y = by; y < std::min(by + kBrick, nc1); ++y) {
-            const int col = x * nc1 + y;
-            while (cursor[col] < col_first[col + 1] && colchunks[cursor[col]].z % nc2 < bz + kBrick)
-              chunks[nch++] = colchunks[cursor[col]++];
+            const int col = x * nc1 + y, c0 = col * nc2;
+            const int* st = start + c0;
+            int cur = ccur[col], z = cz[col];
+            const int col_end = st[nc2];
+            while (cur < col_end) {
+              while (st[z + 1] <= cur) ++z;  // cell of the unit's first particle
+              if (z >= zb) break;            // the unit starts in a later brick
+              int end = std::min(cur + 64, col_end);
+              end = std::min(end, st[std::min(z + nz_max, nc2)]);
+              int zl = z;
+              while (st[zl + 1] < end) ++zl;  // cell of the unit's last particle
+              require(nch < bound, "traversal work units exceed their bound");
+              chunks[nch++] = make_int4(cur, end, c0 + z, zl - z + 1);
+              cur = end;
+            }
+            ccur[col] = cur;
+            cz[col] = z;
           }
+      }
   ps.n_chunks = nch;
   ps.chunks.ensure(std::max<int64_t>(ps.n_chunks, 1));
   if (ps.n_chunks)
     PE_HIP(hipMemcpyAsync(ps.chunks.get(), chunks, sizeof(int4) * ps.n_chunks, hipMemcpyHostToDevice, s));
-  PE_HIP(hipMemcpyAsync(ps.cell_start.get(), start, sizeof(int) * (ncell + 1), hipMemcpyHostToDevice, s));
+  std::memcpy(start_pinned, start, sizeof(int) * ((size_t)ncell + 1));
+  PE_HIP(hipMemcpyAsync(ps.cell_start.get(), start_pinned, sizeof(int) * (ncell + 1), hipMemcpyHostToDevice, s));
   // cursor = start (reuse cell_count)
-  PE_HIP(hipMemcpyAsync(ps.cell_count.get(), start, sizeof(int) * ncell, hipMemcpyHostToDevice, s));
+  PE_HIP(hipMemcpyAsync(ps.cell_count.get(), start_pinned, sizeof(int) * ncell, hipMemcpyHostToDevice, s));
   if (n > 0) {
     const int slabs = n < ((int64_t)1 << kSlabShift) ? 1 : 0;
     hipLaunchKernelGGL(scatter_cells_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.cell_of.get(), ps.zsub.get(), n,
@@ -1122,7 +1136,7 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
     PE_CHECK_LAUNCH();
     // sort each cell's slice by z slab and caller index, so the order (and
     // every sum over it) is the same on every run
-    launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get(), ncell ? *std::max_element(cnt, cnt + ncell) : 0);
+    launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get(), cmax);
     hipLaunchKernelGGL(gather_sorted_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.tmp.get(),
                        ps.idx.get(), owner, n, slabs, rg, ps.pos.get(), ps.posf.get());
     PE_CHECK_LAUNCH();
