@@ -893,35 +893,54 @@ namespace {
 
 // Spreading lists of a set (particles overlapping each tile), sorted within
 // each tile so the accumulation order is the same on every run.
-void build_tile_lists(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
+// Tile lists in two halves around one wait: the counts (and their copy to
+// the host), then the offsets on the host, their upload and the fill.
+void tile_lists_count(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
   const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];
   ps.tile_start.ensure(nt + 1);
   ps.tile_count.ensure(2 * (size_t)nt);
   int* tcount = ps.tile_count.get();
   PE_HIP(hipMemsetAsync(tcount, 0, sizeof(int) * nt, s));
-  const unsigned nb = (unsigned)((ps.n + 255) / 256);
   if (ps.n > 0) {
-    hipLaunchKernelGGL(tile_list_kernel<false>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, tcount,
-                       (int*)nullptr);
+    hipLaunchKernelGGL(tile_list_kernel<false>, dim3((unsigned)((ps.n + 255) / 256)), dim3(256), 0, s, ps.pos.get(),
+                       ps.n, g, tcount, (int*)nullptr);
     PE_CHECK_LAUNCH();
   }
   int* cnt = ps.h_tcnt.get<int>(nt);
   PE_HIP(hipMemcpyAsync(cnt, tcount, sizeof(int) * nt, hipMemcpyDeviceToHost, s));
-  PE_HIP(hipStreamSynchronize(s));
+}
+
+// (the counts' copy has completed)
+void tile_lists_finish(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
+  const int nt = g.ntile[0] * g.ntile[1] * g.ntile[2];
+  int* tcount = ps.tile_count.get();
+  const int* cnt = ps.h_tcnt.get<int>(nt);
   int* start = ps.h_tstart.get<int>((size_t)nt + 1);
+  int run = 0, cmax = 0;
   start[0] = 0;
-  for (int t = 0; t < nt; ++t) start[t + 1] = start[t] + cnt[t];
-  ps.n_entries = start[nt];
+  for (int t = 0; t < nt; ++t) {
+    const int k = cnt[t];
+    run += k;
+    cmax = std::max(cmax, k);
+    start[t + 1] = run;
+  }
+  ps.n_entries = run;
   ps.tile_entries.ensure(std::max<int64_t>(ps.n_entries, 1));
   PE_HIP(hipMemcpyAsync(ps.tile_start.get(), start, sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
   PE_HIP(hipMemcpyAsync(tcount, start, sizeof(int) * nt, hipMemcpyHostToDevice, s));
   if (ps.n > 0) {
-    hipLaunchKernelGGL(tile_list_kernel<true>, dim3(nb), dim3(256), 0, s, ps.pos.get(), ps.n, g, tcount,
-                       ps.tile_entries.get());
+    hipLaunchKernelGGL(tile_list_kernel<true>, dim3((unsigned)((ps.n + 255) / 256)), dim3(256), 0, s, ps.pos.get(),
+                       ps.n, g, tcount, ps.tile_entries.get());
     PE_CHECK_LAUNCH();
-    launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get(), nt ? *std::max_element(cnt, cnt + nt) : 0);
+    launch_segment_sort(s, ps.tile_start.get(), nt, ps.tile_entries.get(), cmax);
   }
   ps.have_tile_lists = true;
+}
+
+void build_tile_lists(hipStream_t s, ParticleSet& ps, const GridGeom& g) {
+  tile_lists_count(s, ps, g);
+  PE_HIP(hipStreamSynchronize(s));
+  tile_lists_finish(s, ps, g);
 }
 
 }  // namespace
@@ -941,7 +960,8 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g, bool spread_
   ps.have_tile_lists = false;
   ps.wfac_valid = false;
   ps.spread_by_home = spread_by_home;
-  if (!spread_by_home) build_tile_lists(s, ps, g);
+  // the tile lists' counts and the home lists' counts behind one wait
+  if (!spread_by_home) tile_lists_count(s, ps, g);
   ps.tile_count.ensure(2 * (size_t)nt);
   int* hcount = ps.tile_count.get() + nt;
   PE_HIP(hipMemsetAsync(hcount, 0, sizeof(int) * nt, s));
@@ -953,15 +973,17 @@ void build_tiles(hipStream_t s, ParticleSet& ps, const GridGeom& g, bool spread_
   int* cnt = ps.h_hcnt.get<int>(nt);
   PE_HIP(hipMemcpyAsync(cnt, hcount, sizeof(int) * nt, hipMemcpyDeviceToHost, s));
   PE_HIP(hipStreamSynchronize(s));
+  if (!spread_by_home) tile_lists_finish(s, ps, g);
   int* hstart = ps.h_hstart.get<int>((size_t)nt + 1);
   int* htiles = ps.h_htiles.get<int>(nt);
-  int nht = 0;
+  int nht = 0, run = 0, hmax = 0;
   hstart[0] = 0;
-  int hmax = 0;
   for (int t = 0; t < nt; ++t) {
-    hstart[t + 1] = hstart[t] + cnt[t];
-    hmax = std::max(hmax, cnt[t]);
-    if (cnt[t]) htiles[nht++] = t;
+    const int k = cnt[t];
+    run += k;
+    hstart[t + 1] = run;
+    hmax = std::max(hmax, k);
+    if (k) htiles[nht++] = t;
   }
   ps.home_start.ensure(nt + 1);
   ps.home_entries.ensure(std::max<int64_t>(ps.n, 1));
