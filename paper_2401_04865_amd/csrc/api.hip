@@ -1163,10 +1163,17 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
                        c->body_of.get(), nb, c->rel.get());
   PE_CHECK_LAUNCH();
   // the two sets' cells and lists: ions on the auxiliary stream, so their
-  // kernels run while the host waits on the beads' counts and vice versa
+  // kernels run while the host works on the beads' counts and vice versa
+  // (both sets' counts are launched before the first wait)
   fork_aux(c);
-  build_cells(s, c->B, c->bead_x.get(), c->bead_sig.get(), 0.0, c->body_of.get(), nb, rg);
-  build_cells(c->aux, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, nullptr, n_ion, rg);
+  cells_count(s, c->B, c->bead_x.get(), c->bead_sig.get(), 0.0, nb, rg);
+  cells_count(c->aux, c->I, c->ion_x.get(), c->ion_sig.get(), 0.0, n_ion, rg);
+  PE_HIP(hipStreamSynchronize(s));
+  cells_finish(s, c->B, c->body_of.get(), rg);
+  PE_HIP(hipStreamSynchronize(c->aux));
+  cells_finish(c->aux, c->I, nullptr, rg);
+  // the bodies' shape matches behind the same wait as the beads' tile counts
+  shape_match_launch(c);
   // beads are spread by every Krylov product: tile lists; ions once per
   // configuration in single precision: their sorted home lists serve
   build_tiles(s, c->B, c->gg, false);

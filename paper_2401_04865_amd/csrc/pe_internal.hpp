@@ -396,6 +396,7 @@ struct Precond {
   DevBuf<int> assigned;            // per body: type index
   DevBuf<unsigned char> dense;     // per body: intra-body pairs held by a dense block
   std::vector<unsigned char> dense_h;  // host copy
+  PinnedBuf h_asg;                 // per body: type index, on the host
   int64_t near_beads = 0;          // beads of bodies with a dense block
   DevBuf<double> gemm_ws;          // partial tiles of the split per-shape products
 };
@@ -550,6 +551,11 @@ void build_green_tables(pe_context* c);
 // the single-precision copy
 void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
                  double sig_const, const int* owner, int64_t n, const RealGeom& rg);
+// the same in two halves around the caller's wait on s: the cell counts (and
+// their copy to the host), then the offsets, work units and sorted records
+void cells_count(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
+                 double sig_const, int64_t n, const RealGeom& rg);
+void cells_finish(hipStream_t s, ParticleSet& ps, const int* owner, const RealGeom& rg);
 void build_bead_matrix(pe_context* c);
 // phi_real[b] += sum_j R_bj q_j over the stored inter-body pairs
 template <typename T>
@@ -575,6 +581,9 @@ void update_pair_tables(hipStream_t s, PairTables& pt, const RealGeom& rg, const
 // body shapes (shapes.hip): group bodies into shape types (device-side
 // matching, types cached across configurations), build the per-shape blocks
 void shape_setup(pe_context* c);
+// the first half of shape_setup, launched earlier: the known shapes' matches
+// and their copy to the host (shape_setup runs after a wait on the stream)
+void shape_match_launch(pe_context* c);
 // y[:, b] (+)= A x[:, b] for the bodies b of one shape: column b is the
 // body's bead segment of x (plus its dPsi entry when bordered, A then
 // (N+1) x (N+1)); accumulate adds into y.

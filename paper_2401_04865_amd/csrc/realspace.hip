@@ -1023,8 +1023,8 @@ float candidate_rc2(const RealGeom& g) {
   return (float)(rcf * rcf);
 }
 
-void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
-                 double sig_const, const int* owner, int64_t n, const RealGeom& rg) {
+void cells_count(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
+                 double sig_const, int64_t n, const RealGeom& rg) {
   ps.n = n;
   ps.wfac_valid = false;
   const int ncell = rg.nc[0] * rg.nc[1] * rg.nc[2];
@@ -1050,10 +1050,17 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   const size_t sig_at = ((size_t)ncell + 1) & ~(size_t)1;  // ints
   int* cnt = ps.h_ccnt.get<int>(sig_at + 4);
   unsigned long long* sig = reinterpret_cast<unsigned long long*>(cnt + sig_at);
-  int* start_pinned = ps.h_cstart.get<int>((size_t)ncell + 1);
   PE_HIP(hipMemcpyAsync(cnt, ps.cell_count.get(), sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
   if (n > 0) PE_HIP(hipMemcpyAsync(sig, ps.sig_check.get(), 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  PE_HIP(hipStreamSynchronize(s));
+}
+
+void cells_finish(hipStream_t s, ParticleSet& ps, const int* owner, const RealGeom& rg) {
+  const int64_t n = ps.n;
+  const int ncell = rg.nc[0] * rg.nc[1] * rg.nc[2];
+  const size_t sig_at = ((size_t)ncell + 1) & ~(size_t)1;  // ints
+  const int* cnt = ps.h_ccnt.get<int>(sig_at + 4);
+  const unsigned long long* sig = reinterpret_cast<const unsigned long long*>(cnt + sig_at);
+  int* start_pinned = ps.h_cstart.get<int>((size_t)ncell + 1);
   {
     double w = 0;
     if (n > 0) std::memcpy(&w, &sig[1], sizeof(double));
@@ -1142,6 +1149,13 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
     PE_CHECK_LAUNCH();
   }
   // the host arrays live in the set: no wait here
+}
+
+void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const double* sig_caller,
+                 double sig_const, const int* owner, int64_t n, const RealGeom& rg) {
+  cells_count(s, ps, pos_caller, sig_caller, sig_const, n, rg);
+  PE_HIP(hipStreamSynchronize(s));
+  cells_finish(s, ps, owner, rg);
 }
 
 namespace {

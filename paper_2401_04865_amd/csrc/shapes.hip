@@ -274,6 +274,19 @@ void launch_match(pe_context* c, const BodyType& t, int type_id) {
 
 }  // namespace
 
+void shape_match_launch(pe_context* c) {
+  Precond& pc = c->pc;
+  hipStream_t s = c->stream;
+  const int64_t nbody = c->n_body;
+  if (nbody == 0) return;
+  pc.assigned.ensure(nbody);
+  pc.dense.ensure(nbody);
+  PE_HIP(hipMemsetAsync(pc.assigned.get(), 0xFF, sizeof(int) * nbody, s));  // -1: unassigned
+  for (size_t ti = 0; ti < pc.types.size(); ++ti) launch_match(c, pc.types[ti], (int)ti);
+  int* asg = pc.h_asg.get<int>(nbody);
+  PE_HIP(hipMemcpyAsync(asg, pc.assigned.get(), sizeof(int) * nbody, hipMemcpyDeviceToHost, s));
+}
+
 void shape_setup(pe_context* c) {
   Precond& pc = c->pc;
   hipStream_t s = c->stream;
@@ -281,16 +294,13 @@ void shape_setup(pe_context* c) {
   pc.near_beads = 0;
   const int64_t nbody = c->n_body;
   if (nbody == 0) return;
-  pc.assigned.ensure(nbody);
-  pc.dense.ensure(nbody);
-  PE_HIP(hipMemsetAsync(pc.assigned.get(), 0xFF, sizeof(int) * nbody, s));  // -1: unassigned
-  for (size_t ti = 0; ti < pc.types.size(); ++ti) launch_match(c, pc.types[ti], (int)ti);
-  std::vector<int> asg(nbody);
+  // the known shapes' matches, launched by shape_match_launch, have reached
+  // the host
+  int* asg = pc.h_asg.get<int>(nbody);
   auto fetch_assigned = [&]() {
-    PE_HIP(hipMemcpyAsync(asg.data(), pc.assigned.get(), sizeof(int) * nbody, hipMemcpyDeviceToHost, s));
+    PE_HIP(hipMemcpyAsync(asg, pc.assigned.get(), sizeof(int) * nbody, hipMemcpyDeviceToHost, s));
     PE_HIP(hipStreamSynchronize(s));
   };
-  fetch_assigned();
   for (int64_t first = 0;;) {
     while (first < nbody && asg[first] >= 0) ++first;
     if (first == nbody) break;
@@ -341,9 +351,9 @@ void shape_setup(pe_context* c) {
       ws = std::max({ws, body_gemm_workspace(t.N, (int)t.bodies.size(), true),
                      body_gemm_workspace(t.N, (int)t.bodies.size(), false)});
   pc.gemm_ws.ensure(ws);
-  PE_HIP(hipMemcpyAsync(pc.dense.get(), dense.data(), nbody, hipMemcpyHostToDevice, s));
-  PE_HIP(hipStreamSynchronize(s));
+  // from the kept host copy, which outlives the copy (no wait)
   pc.dense_h = dense;
+  PE_HIP(hipMemcpyAsync(pc.dense.get(), pc.dense_h.data(), nbody, hipMemcpyHostToDevice, s));
 }
 
 int body_gemm_splits(int N, int nbt, bool bordered) {
