@@ -294,8 +294,8 @@ std::vector<Stats> array_stats(pe_context* c, const std::vector<StatReq>& reqs) 
   }
   if (slot == 0) return out;
   require(3 * slot <= c->red.cap, "reduction buffer too small for the input checks");
-  std::vector<double> h(3 * slot);
-  PE_HIP(hipMemcpyAsync(h.data(), c->red.get(), sizeof(double) * 3 * slot, hipMemcpyDeviceToHost, c->stream));
+  double* h = c->h_stats.get<double>(3 * slot);
+  PE_HIP(hipMemcpyAsync(h, c->red.get(), sizeof(double) * 3 * slot, hipMemcpyDeviceToHost, c->stream));
   PE_HIP(hipStreamSynchronize(c->stream));
   size_t o = 0;
   for (size_t r = 0; r < reqs.size(); ++r) {
@@ -1103,6 +1103,8 @@ pe_status pe_set_system(pe_context* c, int64_t n_body, const int64_t* body_offse
     if (n_body) PE_HIP(hipMemcpyAsync(c->quat.get(), qi.data(), sizeof(double) * 4 * n_body, hipMemcpyHostToDevice, s));
     PE_HIP(hipStreamSynchronize(s));
   }
+  // the pair structure's displacement check behind the input checks' wait
+  launch_max_disp_early(c);
   // validation on the device
   double sig_max = 0, sig_min = INFINITY;
   {

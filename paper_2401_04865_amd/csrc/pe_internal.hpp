@@ -469,6 +469,10 @@ struct pe_context {
   std::vector<int64_t> csr_off;
   std::vector<unsigned char> csr_dense;
   pe::DevBuf<double> csr_x0;       // bead positions (caller order) at the build
+  pe::PinnedBuf h_disp;             // per-block largest squared displacement since the build, on the host
+  bool disp_pending = false;        // h_disp filled by launch_max_disp_early for this configuration
+  unsigned disp_nbk = 0;
+  pe::PinnedBuf h_stats;            // partials of the input checks, on the host
   pe::DevBuf<int> csr_row;         // caller bead index of every row
   pe::DevBuf<double> csr_part;     // displacement reduction partials
   pe::DevBuf<int> cnt;
@@ -557,6 +561,10 @@ void cells_count(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
                  double sig_const, int64_t n, const RealGeom& rg);
 void cells_finish(hipStream_t s, ParticleSet& ps, const int* owner, const RealGeom& rg);
 void build_bead_matrix(pe_context* c);
+// the beads' largest displacement since the stored pair structure was built,
+// launched early with its copy to the host (build_bead_matrix reads it after
+// a later wait on the stream); only when a structure for the same bodies exists
+void launch_max_disp_early(pe_context* c);
 // phi_real[b] += sum_j R_bj q_j over the stored inter-body pairs
 template <typename T>
 void launch_spmv_add(hipStream_t s, pe_context* c, const double* q, double* phi_real);

@@ -1190,6 +1190,21 @@ void launch_queue(hipStream_t s, const ParticleSet& tgt, const SrcSet& s0, const
 
 }  // namespace
 
+void launch_max_disp_early(pe_context* c) {
+  c->disp_pending = false;
+  const int64_t n = c->n_bead;
+  if (!(c->csr_valid && n > 0 && c->csr_off == c->h_off)) return;
+  const unsigned nbk = std::min<unsigned>(256, nblk(n, 256));
+  c->csr_part.ensure(256);
+  hipLaunchKernelGGL(max_disp_kernel, dim3(nbk), dim3(256), 0, c->stream, c->bead_x.get(), c->csr_x0.get(), n,
+                     c->csr_part.get());
+  PE_CHECK_LAUNCH();
+  PE_HIP(hipMemcpyAsync(c->h_disp.get<double>(256), c->csr_part.get(), sizeof(double) * nbk, hipMemcpyDeviceToHost,
+                        c->stream));
+  c->disp_pending = true;
+  c->disp_nbk = nbk;
+}
+
 void build_bead_matrix(pe_context* c) {
   hipStream_t s = c->stream;
   const int64_t n = c->n_bead;
@@ -1209,17 +1224,27 @@ void build_bead_matrix(pe_context* c) {
   bool rebuild = !(c->csr_valid && skin > 0 && c->csr_skin == skin && c->csr_rc == rc && c->csr_off == c->h_off &&
                    c->csr_dense == c->pc.dense_h);
   if (!rebuild && n > 0) {
-    const unsigned nbk = std::min<unsigned>(256, nblk(n, 256));
-    c->csr_part.ensure(256);
-    hipLaunchKernelGGL(max_disp_kernel, dim3(nbk), dim3(256), 0, s, c->bead_x.get(), c->csr_x0.get(), n,
-                       c->csr_part.get());
-    PE_CHECK_LAUNCH();
-    PE_HIP(hipMemcpyAsync(c->pinned, c->csr_part.get(), sizeof(double) * nbk, hipMemcpyDeviceToHost, s));
-    PE_HIP(hipStreamSynchronize(s));
+    const double* part;
+    unsigned nbk;
+    if (c->disp_pending) {
+      // launched by launch_max_disp_early; the stream has been waited on since
+      part = c->h_disp.get<double>(256);
+      nbk = c->disp_nbk;
+    } else {
+      nbk = std::min<unsigned>(256, nblk(n, 256));
+      c->csr_part.ensure(256);
+      hipLaunchKernelGGL(max_disp_kernel, dim3(nbk), dim3(256), 0, s, c->bead_x.get(), c->csr_x0.get(), n,
+                         c->csr_part.get());
+      PE_CHECK_LAUNCH();
+      PE_HIP(hipMemcpyAsync(c->pinned, c->csr_part.get(), sizeof(double) * nbk, hipMemcpyDeviceToHost, s));
+      PE_HIP(hipStreamSynchronize(s));
+      part = c->pinned;
+    }
     double mx = 0;
-    for (unsigned k = 0; k < nbk; ++k) mx = (c->pinned[k] > mx || c->pinned[k] != c->pinned[k]) ? c->pinned[k] : mx;
+    for (unsigned k = 0; k < nbk; ++k) mx = (part[k] > mx || part[k] != part[k]) ? part[k] : mx;
     rebuild = !(mx <= 0.25 * skin * skin);
   }
+  c->disp_pending = false;
   if (rebuild) {
     c->cnt.ensure(n);
     RealGeom rgb = c->rg;
