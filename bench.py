@@ -58,26 +58,26 @@ TRAIN_DEFAULT = {"cfg2": 0, "cfg3": 0, "cfg4": 2000, "cfg5": 200}
 # measurement; once one changes the figures are stale and `traffic` is
 # reported null, as it is on any other workload.
 TRAFFIC = {
-    "spread_f32": {"workload": "cfg5", "bytes_per_launch": 1.079e8,
-                   "limiter": ("vector ALU issue: 0.63 (beads) and 0.69 (ions) VALU instructions per CU-cycle "
-                               "of at most 1 (SQ_INSTS_VALU); LDS 0.09-0.12 instructions per CU-cycle"),
-                   "sources": {"paper_2401_04865_amd/csrc/grid.hip": "dbc03333d6e50d9815017f6d44e93b0779234aa9",
-                               "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
-    "fft_z_r2c_f32": {"workload": "cfg5", "bytes_per_launch": 1.365e8,
+    "spread_f32": {"workload": "cfg5", "bytes_per_launch": 1.429e+08,
+                   "limiter": ("vector ALU issue: 0.53 (beads) and 0.68 (ions) VALU instructions per CU-cycle "
+                               "of at most 1 (SQ_INSTS_VALU); LDS 0.10-0.12 instructions per CU-cycle"),
+                   "sources": {"paper_2401_04865_amd/csrc/grid.hip": "3672ce91f3b84b5236c3bdf7f8e1cb6aac51564c",
+                               "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+    "fft_z_r2c_f32": {"workload": "cfg5", "bytes_per_launch": 1.364e+08,
                       "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                  "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
-    "fft_y_fwd_f32": {"workload": "cfg5", "bytes_per_launch": 1.449e8,
+                                  "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+    "fft_y_fwd_f32": {"workload": "cfg5", "bytes_per_launch": 1.448e+08,
                       "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                  "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
-    "fft_x_scale_f32": {"workload": "cfg5", "bytes_per_launch": 1.453e8,
+                                  "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+    "fft_x_scale_f32": {"workload": "cfg5", "bytes_per_launch": 1.453e+08,
                         "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                    "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
-    "fft_y_inv_f32": {"workload": "cfg5", "bytes_per_launch": 1.449e8,
+                                    "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+    "fft_y_inv_f32": {"workload": "cfg5", "bytes_per_launch": 1.448e+08,
                       "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                  "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
-    "fft_z_c2r_f32": {"workload": "cfg5", "bytes_per_launch": 1.428e8,
+                                  "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+    "fft_z_c2r_f32": {"workload": "cfg5", "bytes_per_launch": 1.427e+08,
                       "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                  "paper_2401_04865_amd/csrc/api.hip": "da273294a6d4752116dfe3edc354e708183f23fa"}},
+                                  "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
 }
 
 
