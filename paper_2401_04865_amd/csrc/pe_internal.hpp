@@ -210,14 +210,14 @@ void build_erfcx_table(hipStream_t s, DevBuf<float>& tab);
 // Single-precision table of the Gaussian-regularized real-space kernel R(r)
 // for one class of pairs (one value of s2 = sigma_t^2 + sigma_s^2): r in
 // [0, r_c] cut into kPairTabPieces pieces of width h; on piece k,
-// R(r) = sum_j a_j t^j with t = 2 (r - (k + 1/2) h) / h in [-1, 1], degree 7
-// (8 floats per piece, interpolation at the Chebyshev points of the piece).
-// dR/dr = (2 / h) sum_j j a_j t^(j-1) comes from the same coefficients.
-// build_pair_table fits the pieces in double, rounds them to float and checks
-// value and slope against the closed form at 18 points per piece; it returns
-// false (and the caller keeps the general kernel) if either misses by more
-// than 1e-7 of its largest magnitude on [0, r_c].
-constexpr int kPairTabPieces = 32;
+// R(r) = sum_j a_j t^j with t = 2 (r - (k + 1/2) h) / h in [-1, 1], degree 6
+// (interpolation at the 7 Chebyshev points of the piece; 8 floats per piece,
+// the last zero).  dR/dr = (2 / h) sum_j j a_j t^(j-1) comes from the same
+// coefficients.  build_pair_table fits the pieces in double, rounds them to
+// float and checks value and slope against the closed form at 18 points per
+// piece; it returns false (and the caller keeps the general kernel) if
+// either misses by more than 1e-7 of its largest magnitude on [0, r_c].
+constexpr int kPairTabPieces = 64;
 constexpr int kPairTabFloats = 8 * kPairTabPieces;
 bool build_pair_table(const RealGeom& rg, double s2, float* out);
 

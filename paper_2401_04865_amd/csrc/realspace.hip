@@ -334,10 +334,14 @@ constexpr int kQFlush = 8;      // candidates between flushes (kQ - kQFlush entr
 constexpr int kSetBit = 30;     // queue entry: sorted source index | set << kSetBit
 constexpr int kMaxRuns = 36;    // stencil runs: 2 source sets x 9 columns x 2 runs
 // single-precision passes: staged candidates stay in an LDS ring of
-// kRegions batches of 64 and the queues hold ring slots (slot | set << 8)
+// kRegions batches of 64 and the queues hold ring slots (slot | set <<
+// kRingSetShift); one more slot, kRing, is a placeholder (at the origin,
+// charge zero) that a lane with no queued pair evaluates
 constexpr int kRegions = 2;
 constexpr int kRing = 64 * kRegions;
-static_assert(kRing <= 256 && (kRegions & (kRegions - 1)) == 0, "ring slots are 8 bits, regions a power of two");
+constexpr int kRingSetShift = 11;  // the set's offset in the class tables in LDS, in bytes
+static_assert(kRing < 256 && (kRegions & (kRegions - 1)) == 0, "ring slots are 8 bits, regions a power of two");
+static_assert(2 * kPairTabPieces * 16 == 1 << kRingSetShift, "one set's class table: two float4 per piece");
 
 
 // EV selects the pair evaluation: EV_GENERAL (any precision and
@@ -362,9 +366,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
   constexpr bool kRingQ = EV != EV_GENERAL;
   using QE = typename std::conditional<kRingQ, unsigned short, int>::type;
   __shared__ QE qbuf[kWaves][kQ][64];
-  __shared__ float4 cbuf[kWaves][kRingQ ? kRing : 64];  // ring: x, y, z; w: slot | set << 8
-  __shared__ float cq[kRingQ ? kWaves : 1][kRingQ ? kRing : 1];                // ring: charge
-  __shared__ float cw[EV == EV_ERFCX ? kWaves : 1][EV == EV_ERFCX ? kRing : 1];  // ring: width
+  __shared__ float4 cbuf[kWaves][kRingQ ? kRing + 1 : 64];  // ring: x, y, z; w: slot | set << kRingSetShift
+  __shared__ float cq[kRingQ ? kWaves : 1][kRingQ ? kRing + 1 : 1];                // ring: charge
+  __shared__ float cw[EV == EV_ERFCX ? kWaves : 1][EV == EV_ERFCX ? kRing + 1 : 1];  // ring: width
   __shared__ float4 etab[kTabF4];
   __shared__ int cownb[kOwn ? kWaves : 1][64];  // owner tags of the staged candidates (count / fill)
   __shared__ int rstart[kWaves][kMaxRuns + 1];
@@ -511,28 +515,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
     }
   };
 
-  // class tables: r = 0 (the self pair) reads R(0) at the table's first
-  // point and gets no field (inv_r = 0)
-  const float tab_w = (float)(kPairTabPieces / sqrt(g.rc2));  // pieces per unit length
-  const float tab_d = -2.0f * tab_w;                          // -dt/dr
-  // branch-free: every lane runs the arithmetic and a lane whose entry is
-  // not a pair (none queued) adds nothing, so both ring reads of a pass are
-  // issued up front
-  auto evaluate_tab = [&](float dx, float dy, float dz, float q, int set, bool valid) {
+  // Class tables: piece k = floor(w) of w = r / h (h = r_c / kPairTabPieces)
+  // at t = 2 frac(w) - 1, so t stays in [-1, 1) and the polynomial finite.
+  // Branch- and select-free: a lane with no queued pair evaluates the ring's
+  // placeholder slot (charge zero) and adds exact zeros; w is clamped to the
+  // last piece, which keeps the placeholder's (and a NaN difference's) table
+  // read in range.  The self pair (r = 0) reads R(0) at the first piece's
+  // first point; its field term vanishes with dx = dy = dz = 0.  The field
+  // sums collect d u q x with u = 1 / (h r); -R'(r) / r = -2 d u, and the
+  // factor -2 is applied once per target.
+  const float tab_w = (float)(kPairTabPieces / sqrt(g.rc2));  // 1 / h
+  const float tab_top = (float)kPairTabPieces - 0.5f;
+  auto evaluate_tab = [&](float dx, float dy, float dz, float q, int e) {
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const bool ok = valid && r2 < rc2e;
-    nev += ok ? 1 : 0;
-    const float qf = ok ? q : 0.0f;
-    const float inv_r = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
-    const float w = r2 * inv_r * tab_w;
-    const int k = min((int)w, kPairTabPieces - 1);
-    const float t = fmaf(2.0f, w - (float)k, -1.0f);
-    const float4* tb = etab + 2 * (set * kPairTabPieces + k);
+    const float u = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f)) * tab_w;
+    const float w = fminf(r2 * u, tab_top);
+    const float t = fmaf(2.0f, __builtin_amdgcn_fractf(w), -1.0f);
+    const float4* tb =
+        reinterpret_cast<const float4*>(reinterpret_cast<const char*>(etab) + (e & (1 << kRingSetShift))) +
+        2 * (int)w;
     const float4 lo = tb[0], hi = tb[1];
-    // value v and slope d = dv/dt in one Horner pass
-    float v = hi.w, d = hi.w;
-    v = fmaf(v, t, hi.z);
-    d = fmaf(d, t, v);
+    // degree 6: value v and slope d = dv/dt in one Horner pass
+    float v = hi.z, d = hi.z;
     v = fmaf(v, t, hi.y);
     d = fmaf(d, t, v);
     v = fmaf(v, t, hi.x);
@@ -544,14 +548,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
     v = fmaf(v, t, lo.y);
     d = fmaf(d, t, v);
     v = fmaf(v, t, lo.x);
-    acc += ok ? v * qf : 0.0f;
+    acc = fmaf(v, q, acc);
     if constexpr (MODE == MODE_FIELD) {
-      // an entry that is not a pair may hold a padding point (NaN): select,
-      // never multiply by zero
-      const float fq = d * tab_d * inv_r * qf;  // -R'(r) / r q
-      ex += ok ? fq * dx : 0.0f;
-      ey += ok ? fq * dy : 0.0f;
-      ez += ok ? fq * dz : 0.0f;
+      const float fq = d * u * q;
+      ex = fmaf(fq, dx, ex);
+      ey = fmaf(fq, dy, ey);
+      ez = fmaf(fq, dz, ez);
     }
   };
 
@@ -617,6 +619,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
   }
   if (lane < n_open) rs[lane + 1] = incl;
   if (lane == 0) rs[0] = 0;
+  if constexpr (kRingQ) {
+    if (lane == 0) {  // the placeholder slot
+      cb[kRing] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(kRing));
+      cq[wv][kRing] = 0.0f;
+    }
+  }
   const int M = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
   // stride: near M / golden ratio, coprime to M (a permutation of 0 .. M-1)
   int stride = 1;
@@ -646,7 +654,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
   const double fx0 = kRingQ ? (cx + 0.5) * a0 : cx * a0;
   const double fy0 = kRingQ ? (cy + 0.5) * a1 : cy * a1;
   const double fz0 = kRingQ ? (cz + 0.5 * nz) * a2 : 0.0;
-  const float px = (float)(p.x - fx0), py = (float)(p.y - fy0), pz = (float)(p.z - fz0);
+  float px = (float)(p.x - fx0), py = (float)(p.y - fy0), pz = (float)(p.z - fz0);
   const float a0f = (float)a0, a1f = (float)a1, Lz = Lf2;
   // bounding box of the wavefront's targets (same frame as the candidates)
   float bx0 = active ? px : INFINITY, bx1 = active ? px : -INFINITY;
@@ -669,13 +677,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
   by1 = uniform_f(by1);
   bz0 = uniform_f(bz0);
   bz1 = uniform_f(bz1);
+  const float nanf_ = __int_as_float(0x7fc00000);
+  if (kRingQ && !active) px = py = pz = nanf_;  // no candidate test hits
   int next = 0, pbase = 0;  // next stream position to stage and (next S) mod M
   int nbat = 0, k0 = 0;
   int batch = 0;  // batches staged
   const float4* cnd_base = cb;  // the batch under test
   // ring: pushed at the end of each of the last kRegions - 1 batches, newest first
   int ends[kRegions > 1 ? kRegions - 1 : 1] = {};
-  const float nanf_ = __int_as_float(0x7fc00000);
   for (;;) {
     bool finished = false;
     if (k0 >= nbat) {
@@ -708,7 +717,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
             const double shz = zimg == 1 ? -g.L[2] : (zimg == 2 ? g.L[2] : 0.0);
             const double4 sp = (set ? s1.pos : s0.pos)[sidx];
             v = make_float4((float)(sp.x - (fx0 - shx)), (float)(sp.y - (fy0 - shy)), (float)(sp.z - (fz0 - shz)),
-                            __int_as_float(set << 8));
+                            __int_as_float(set << kRingSetShift));
             vq = (float)(set ? s1.q : s0.q)[sidx];
             vw = (float)sp.w;
           } else {
@@ -776,7 +785,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
         // (single-precision passes: the evaluation's own test, on the same
         // float differences)
         const float r2 = kRingQ ? fmaf(dx, dx, fmaf(dy, dy, dz * dz)) : dx * dx + dy * dy + dz * dz;
-        bool hit = active && r2 < (kRingQ ? rc2e : rc2f);
+        bool hit = (kRingQ || active) && r2 < (kRingQ ? rc2e : rc2f);
         if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) {
           // pairs inside a body with a dense intra-body block are not listed
           hit = hit && (own_body < 0 || cown[k0 + kk] != own_body);
@@ -829,9 +838,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
         };
         return due(2) ? 2 : (due(1) ? 1 : 0);
       };
-      // two rounds per pass, both ring entries read first (a lane without a
-      // second entry re-reads its first, or slot 0); the per-pair minimum
-      // image (boxes of one cell along an axis) is a separate copy of the loop
+      // two rounds per pass, both ring entries read first (a lane without an
+      // entry reads the placeholder slot); the per-pair minimum image (boxes
+      // of one cell along an axis) is a separate copy of the loop
       const float4* ring = cb;
       auto drain = [&](auto img) {
         constexpr bool kImg = decltype(img)::value;
@@ -840,16 +849,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
           const int rw = rounds_wanted();
           if (rw == 0) break;
           const int avail = min(pushed - popped, rw);
-          const int ea = avail > 0 ? (int)qb[popped & (kQ - 1)][lane] : 0;
-          const int eb = avail > 1 ? (int)qb[(popped + 1) & (kQ - 1)][lane] : ea;
+          const int ea = avail > 0 ? (int)qb[popped & (kQ - 1)][lane] : kRing;
+          const int eb = avail > 1 ? (int)qb[(popped + 1) & (kQ - 1)][lane] : kRing;
           const float4 a = ring[ea & 255], b = ring[eb & 255];
           const float qa = cq[wv][ea & 255], qb2 = cq[wv][eb & 255];
           popped += avail;
           const float dxa = diff(px - a.x, Lf0, iL0), dya = diff(py - a.y, Lf1, iL1), dza = diff(pz - a.z, Lf2, iL2);
           const float dxb = diff(px - b.x, Lf0, iL0), dyb = diff(py - b.y, Lf1, iL1), dzb = diff(pz - b.z, Lf2, iL2);
           if constexpr (EV == EV_TABLE) {
-            evaluate_tab(dxa, dya, dza, qa, ea >> 8, avail > 0);
-            evaluate_tab(dxb, dyb, dzb, qb2, eb >> 8, avail > 1);
+            evaluate_tab(dxa, dya, dza, qa, ea);
+            evaluate_tab(dxb, dyb, dzb, qb2, eb);
           } else {
             if (avail > 0) evaluate_fast(dxa, dya, dza, qa, cw[wv][ea & 255]);
             if (avail > 1) evaluate_fast(dxb, dyb, dzb, qb2, cw[wv][eb & 255]);
@@ -862,7 +871,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
     if (finished) break;
   }
   if (out.npairs) {
-    unsigned long long v = (unsigned long long)nev;
+    // (table passes evaluate every queued entry, each inside the cutoff)
+    unsigned long long v = (unsigned long long)(EV == EV_TABLE ? pushed : nev);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0) atomicAdd(out.npairs, v);
@@ -884,9 +894,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
     const int oi = tidx[t];
     out.phi[oi] += (double)acc;
     if (MODE == MODE_FIELD) {
-      out.E[3 * oi] += (double)ex;
-      out.E[3 * oi + 1] += (double)ey;
-      out.E[3 * oi + 2] += (double)ez;
+      const TF fs = EV == EV_TABLE ? (TF)-2 : (TF)1;  // see evaluate_tab
+      out.E[3 * oi] += (double)(fs * ex);
+      out.E[3 * oi + 1] += (double)(fs * ey);
+      out.E[3 * oi + 2] += (double)(fs * ez);
     }
   }
 }
@@ -1439,7 +1450,7 @@ void gauss_pair(double r, double b, double xi, double c, double& R, double& dR) 
 
 bool build_pair_table(const RealGeom& rg, double s2, float* out) {
   if (rg.reg != PE_REG_GAUSSIAN || !(s2 > 0.0) || !(rg.rc2 > 0.0)) return false;
-  constexpr int K = kPairTabPieces, N = 8;
+  constexpr int K = kPairTabPieces, N = 7;  // N coefficients of 8 stored
   const double rc = std::sqrt(rg.rc2), h = rc / K;
   const double b = 1.0 / std::sqrt(2.0 * s2), xi = rg.xi, c = kInv4Pi / rg.eps;
   double err_v = 0.0, err_d = 0.0, max_v = 0.0, max_d = 0.0;
@@ -1470,8 +1481,8 @@ bool build_pair_table(const RealGeom& rg, double s2, float* out) {
         Tc[j] = Tn[j];
       }
     }
-    float* o = out + (size_t)N * k;
-    for (int j = 0; j < N; ++j) o[j] = (float)mono[j];
+    float* o = out + (size_t)8 * k;
+    for (int j = 0; j < 8; ++j) o[j] = j < N ? (float)mono[j] : 0.0f;
     // the rounded coefficients against the closed form, ends of the piece included
     for (int i = 0; i <= 17; ++i) {
       const double t = -1.0 + 2.0 * i / 17.0;
