@@ -841,7 +841,7 @@ size_t estimate_workspace(const pe_context* c, int64_t nb, int64_t nbody, int64_
   for (int d = 0; d < 3; ++d) ncell *= rc_min > 0 ? std::min(512.0, std::max(1.0, std::floor(p.box[d] / rc_min))) : 1;
   const double ntile = std::ceil(Nx / 8) * std::ceil(Ny / 8) * std::ceil(Nz / 8);
   for (double m : {(double)nb, (double)ni})
-    b += up(160.0 * m + 1) + up(12.0 * (ncell + 1)) + up(16.0 * (ntile + 1)) + 4 * Arena::kAlign;
+    b += up(180.0 * m + 1) + up(12.0 * (ncell + 1)) + up(16.0 * (ntile + 1)) + 4 * Arena::kAlign;
   // per-particle outputs and scratch in caller order
   b += up(8 * na) * 3 + up(24 * na) * 3 + up(8 * std::max(n, na)) + up(8 * std::max(3 * na, n)) + up(8 * n) * 2 +
        up(8.0 * nb) * 2 + up(24.0 * nb) * 2 + up(8 * std::max(3 * n, 2 * na)) + up(72.0 * nbody) * 2;

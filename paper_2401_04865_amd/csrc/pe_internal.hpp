@@ -226,6 +226,7 @@ struct ParticleSet {
   int64_t n = 0;
   DevBuf<double4> pos;      // sorted: wrapped x,y,z and sigma in w
   DevBuf<float4> posf;      // sorted: x, y relative to the cell origin, z (single precision); owner body as int bits
+  DevBuf<uint4> posx;       // sorted: x, y, z in fixed point (2^32 units per box length); sigma as float bits
   DevBuf<int> idx;          // sorted slot -> caller index within the set
   DevBuf<int> cell_start;   // ncell + 1
   DevBuf<int> cell_count;   // ncell (scratch)
@@ -234,6 +235,7 @@ struct ParticleSet {
   DevBuf<double4> tmp;      // caller order wrapped positions (scratch)
   DevBuf<int4> chunks;      // pair-traversal work units: (first, end sorted slot, first cell, cells), <= 64 each
   DevBuf<double> qsorted;   // charges in sorted order for the pair passes (scratch)
+  DevBuf<float> qsortedf;   // the same in single precision (scratch)
   DevBuf<double> qspread;   // charges in sorted order for spreading (scratch)
   DevBuf<float4> wfac;      // sorted: single-precision window factors, 8 per axis, rotated (support <= 8)
   DevBuf<int4> wsta;        // sorted: wrapped mesh index of support point 0 per axis

@@ -277,7 +277,7 @@ __global__ void scatter_cells_kernel(const int* __restrict__ cell_of, const int*
 
 __global__ void gather_sorted_kernel(const double4* __restrict__ tmp, int* __restrict__ idx,
                                      const int* __restrict__ owner, int64_t n, int slabs, RealGeom g,
-                                     double4* __restrict__ pos, float4* __restrict__ posf) {
+                                     double4* __restrict__ pos, float4* __restrict__ posf, uint4* __restrict__ posx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int k = slabs ? idx[i] & ((1 << kSlabShift) - 1) : idx[i];
@@ -291,14 +291,22 @@ __global__ void gather_sorted_kernel(const double4* __restrict__ tmp, int* __res
   const int cy = cell_coord(p.y, g.cell_inv[1], g.nc[1]);
   const int tag = owner ? owner[k] : -1;
   posf[i] = make_float4((float)(p.x - cx * ax), (float)(p.y - cy * ay), (float)p.z, __int_as_float(tag));
+  // fixed point: the box maps onto 2^32 units per axis, so the 32-bit
+  // difference of two records is exact and already the minimum image
+  auto fix = [](double x, double inv_L) { return (unsigned)(long long)rint(x * inv_L * 4294967296.0); };
+  posx[i] = make_uint4(fix(p.x, g.inv_L[0]), fix(p.y, g.inv_L[1]), fix(p.z, g.inv_L[2]), __float_as_uint((float)p.w));
 }
 
 // Charges of a set in its sorted (cell) order, so the pair kernels read them
 // without the index indirection.
 __global__ void sort_charges_kernel(const int* __restrict__ idx, const double* __restrict__ q, int64_t n,
-                                    double* __restrict__ qs) {
+                                    double* __restrict__ qs, float* __restrict__ qsf) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) qs[i] = q[idx[i]];
+  if (i < n) {
+    const double v = q[idx[i]];
+    qs[i] = v;
+    qsf[i] = (float)v;
+  }
 }
 
 // ------------------------------------------------------------ pair traversal
@@ -307,9 +315,11 @@ __global__ void sort_charges_kernel(const int* __restrict__ idx, const double* _
 struct SrcSet {
   const double4* pos;   // sorted by cell: wrapped x, y, z, sigma
   const float4* posf;   // single precision: x, y relative to the cell origin, z; w: owner tag
+  const uint4* posx;    // fixed point (2^32 units per box length): x, y, z; w: sigma as float bits
   const int* idx;       // sorted slot -> caller index
   const int* start;     // cell_start
   const double* q;      // charges in sorted order (potential passes)
+  const float* qf;      // the same in single precision
   const float4* tab;    // pair table of the class (targets, this set), or null
 };
 
@@ -352,9 +362,9 @@ enum { EV_GENERAL = 0, EV_ERFCX = 1, EV_TABLE = 2 };
 
 template <int MODE, typename T, typename TF, int EV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == EV_TABLE ? 6 : 1))) pair_queue_kernel(
-    const double4* __restrict__ tpos, const int* __restrict__ tidx, const int* __restrict__ tstart,
-    const int4* __restrict__ chunks, int nchunk, SrcSet s0, SrcSet s1, int nsrc, RealGeom g, float rc2f,
-    PairOut out) {
+    const double4* __restrict__ tpos, const uint4* __restrict__ tposx, const int* __restrict__ tidx,
+    const int* __restrict__ tstart, const int4* __restrict__ chunks, int nchunk, SrcSet s0, SrcSet s1, int nsrc,
+    RealGeom g, float rc2f, PairOut out) {
   static_assert(EV == EV_GENERAL || (sizeof(T) == 4 && sizeof(TF) == 4 && (MODE == MODE_POT || MODE == MODE_FIELD)),
                 "table evaluations are single-precision potential / field passes");
   constexpr bool kOwn = MODE == MODE_COUNT || MODE == MODE_FILL;
@@ -647,14 +657,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
   // column's origin, z as is (a source's float x, y are relative to its own
   // column's origin, which lies ox a0, oy a1 from the target column's origin
   // in the target's image).  Single-precision passes: relative to the centre
-  // of the chunk's cells, every coordinate formed in double and rounded once
-  // (a source in the same image subtracts the same double origin, so the
-  // self pair has r = 0 exactly).
+  // of the chunk's cells, from the fixed-point records: the 32-bit
+  // difference to the centre is exact and the minimum image, rounded to
+  // float once and scaled (the same operations for a target and a source,
+  // so the self pair has r = 0 exactly).  With the stencil's cells distinct
+  // (three columns per axis, a unit at most nc_z - 2 cells long) every
+  // source within r_c of a target is that image; boxes of one cell along an
+  // axis take the per-pair minimum image as well.
   const double a2 = g.L[2] / nc2;
-  const double fx0 = kRingQ ? (cx + 0.5) * a0 : cx * a0;
-  const double fy0 = kRingQ ? (cy + 0.5) * a1 : cy * a1;
-  const double fz0 = kRingQ ? (cz + 0.5 * nz) * a2 : 0.0;
-  float px = (float)(p.x - fx0), py = (float)(p.y - fy0), pz = (float)(p.z - fz0);
+  const double fx0 = cx * a0, fy0 = cy * a1;
+  const double sfix = 4294967296.0;
+  const unsigned fcx = (unsigned)(long long)rint((cx + 0.5) * a0 * g.inv_L[0] * sfix);
+  const unsigned fcy = (unsigned)(long long)rint((cy + 0.5) * a1 * g.inv_L[1] * sfix);
+  const unsigned fcz = (unsigned)(long long)rint((cz + 0.5 * nz) * a2 * g.inv_L[2] * sfix);
+  const float fsc0 = (float)(g.L[0] / sfix), fsc1 = (float)(g.L[1] / sfix), fsc2 = (float)(g.L[2] / sfix);
+  auto fix_off = [](unsigned a, unsigned c, float sc) { return (float)(int)(a - c) * sc; };
+  float px, py, pz;
+  if constexpr (kRingQ) {
+    const uint4 tp = tposx[active ? t : begin];
+    px = fix_off(tp.x, fcx, fsc0);
+    py = fix_off(tp.y, fcy, fsc1);
+    pz = fix_off(tp.z, fcz, fsc2);
+  } else {
+    px = (float)(p.x - fx0);
+    py = (float)(p.y - fy0);
+    pz = (float)p.z;
+  }
   const float a0f = (float)a0, a1f = (float)a1, Lz = Lf2;
   // bounding box of the wavefront's targets (same frame as the candidates)
   float bx0 = active ? px : INFINITY, bx1 = active ? px : -INFINITY;
@@ -704,23 +732,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
           }
           const int code = rc[lo];
           const int set = code & 1;
-          const float ofx = (float)(((code >> 1) & 3) - 1) * a0f;
-          const float ofy = (float)(((code >> 3) & 3) - 1) * a1f;
-          const int zimg = code >> 5;
-          const float ofz = zimg == 1 ? -Lz : (zimg == 2 ? Lz : 0.0f);
           const int sidx = rb[lo] + (pos - rs[lo]);
           if constexpr (kRingQ) {
-            // the run's column and z image in the target frame, in double
-            const int ox = ((code >> 1) & 3) - 1, oy = ((code >> 3) & 3) - 1;
-            const double shx = cx + ox < 0 ? -g.L[0] : (cx + ox >= nc0 ? g.L[0] : 0.0);
-            const double shy = cy + oy < 0 ? -g.L[1] : (cy + oy >= nc1 ? g.L[1] : 0.0);
-            const double shz = zimg == 1 ? -g.L[2] : (zimg == 2 ? g.L[2] : 0.0);
-            const double4 sp = (set ? s1.pos : s0.pos)[sidx];
-            v = make_float4((float)(sp.x - (fx0 - shx)), (float)(sp.y - (fy0 - shy)), (float)(sp.z - (fz0 - shz)),
+            const uint4 sp = (set ? s1.posx : s0.posx)[sidx];
+            v = make_float4(fix_off(sp.x, fcx, fsc0), fix_off(sp.y, fcy, fsc1), fix_off(sp.z, fcz, fsc2),
                             __int_as_float(set << kRingSetShift));
-            vq = (float)(set ? s1.q : s0.q)[sidx];
-            vw = (float)sp.w;
+            vq = (set ? s1.qf : s0.qf)[sidx];
+            vw = __uint_as_float(sp.w);
           } else {
+            // the run's column and z image
+            const float ofx = (float)(((code >> 1) & 3) - 1) * a0f;
+            const float ofy = (float)(((code >> 3) & 3) - 1) * a1f;
+            const int zimg = code >> 5;
+            const float ofz = zimg == 1 ? -Lz : (zimg == 2 ? Lz : 0.0f);
             const float4 sp = (set ? s1.posf : s0.posf)[sidx];
             v = make_float4(sp.x + ofx, sp.y + ofy, sp.z + ofz, __int_as_float(sidx | set << kSetBit));
             own = __float_as_int(sp.w);
@@ -1041,6 +1065,7 @@ void cells_count(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
   const int ncell = rg.nc[0] * rg.nc[1] * rg.nc[2];
   ps.pos.ensure(n);
   ps.posf.ensure(n);
+  ps.posx.ensure(n);
   ps.idx.ensure(n);
   ps.tmp.ensure(n);
   ps.cell_of.ensure(n);
@@ -1156,7 +1181,7 @@ void cells_finish(hipStream_t s, ParticleSet& ps, const int* owner, const RealGe
     // every sum over it) is the same on every run
     launch_segment_sort(s, ps.cell_start.get(), ncell, ps.idx.get(), cmax);
     hipLaunchKernelGGL(gather_sorted_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, ps.tmp.get(),
-                       ps.idx.get(), owner, n, slabs, rg, ps.pos.get(), ps.posf.get());
+                       ps.idx.get(), owner, n, slabs, rg, ps.pos.get(), ps.posf.get(), ps.posx.get());
     PE_CHECK_LAUNCH();
   }
   // the host arrays live in the set: no wait here
@@ -1171,15 +1196,17 @@ void build_cells(hipStream_t s, ParticleSet& ps, const double* pos_caller, const
 
 namespace {
 
-SrcSet src_of(const ParticleSet& ps, const double* qsorted, const float4* tab = nullptr) {
-  return SrcSet{ps.pos.get(), ps.posf.get(), ps.idx.get(), ps.cell_start.get(), qsorted, tab};
+SrcSet src_of(const ParticleSet& ps, const double* qsorted, const float* qsortedf = nullptr,
+              const float4* tab = nullptr) {
+  return SrcSet{ps.pos.get(), ps.posf.get(), ps.posx.get(), ps.idx.get(), ps.cell_start.get(), qsorted, qsortedf, tab};
 }
 
 template <int MODE, typename T, typename TF, int EV>
 void launch_queue_ev(hipStream_t s, const ParticleSet& tgt, const SrcSet& s0, const SrcSet& s1, int nsrc,
                      const RealGeom& rg, const PairOut& out) {
   hipLaunchKernelGGL((pair_queue_kernel<MODE, T, TF, EV>), dim3(nblk(tgt.n_chunks, kWaves)), dim3(64 * kWaves), 0,
-                     s, tgt.pos.get(), tgt.idx.get(), tgt.cell_start.get(), tgt.chunks.get(), tgt.n_chunks, s0, s1,
+                     s, tgt.pos.get(), tgt.posx.get(), tgt.idx.get(), tgt.cell_start.get(), tgt.chunks.get(),
+                     tgt.n_chunks, s0, s1,
                      nsrc, rg, candidate_rc2(rg), out);
   PE_CHECK_LAUNCH();
 }
@@ -1386,16 +1413,17 @@ void launch_pair_onfly(hipStream_t s, const ParticleSet& tgt, const ParticleSet*
   if (!src0) return;
   require(src0->n < (int64_t(1) << kSetBit) && (!src1 || src1->n < (int64_t(1) << kSetBit)),
           "too many particles in one set for the pair traversal");
-  auto sorted_q = [&](const ParticleSet& ps, const double* q) {
+  auto sorted_q = [&](const ParticleSet& ps, const double* q, const float4* tab) {
     ParticleSet& m = const_cast<ParticleSet&>(ps);
     m.qsorted.ensure(std::max<int64_t>(ps.n, 1));
+    m.qsortedf.ensure(std::max<int64_t>(ps.n, 1));
     hipLaunchKernelGGL(sort_charges_kernel, dim3(nblk(ps.n, 256)), dim3(256), 0, s, ps.idx.get(), q, ps.n,
-                       m.qsorted.get());
+                       m.qsorted.get(), m.qsortedf.get());
     PE_CHECK_LAUNCH();
-    return m.qsorted.get();
+    return src_of(ps, m.qsorted.get(), m.qsortedf.get(), tab);
   };
-  const SrcSet a = src_of(*src0, sorted_q(*src0, q0), tab0);
-  const SrcSet b = src1 ? src_of(*src1, sorted_q(*src1, q1), tab1) : a;
+  const SrcSet a = sorted_q(*src0, q0, tab0);
+  const SrcSet b = src1 ? sorted_q(*src1, q1, tab1) : a;
   const int nsrc = src1 ? 2 : 1;
   PairOut out{};
   out.phi = phi;
