@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
   constexpr bool kRingQ = EV != EV_GENERAL;
   using QE = typename std::conditional<kRingQ, unsigned short, int>::type;
   __shared__ QE qbuf[kWaves][kQ][64];
-  __shared__ float4 cbuf[kWaves][kRingQ ? kRing + 1 : 64];  // ring: x, y, z; w: slot | set << kRingSetShift
+  __shared__ float4 cbuf[kWaves][kRingQ ? kRing + 1 : 64];  // ring: -2 x, -2 y, -2 z, |c|^2; else x, y, z, entry
   __shared__ float cq[kRingQ ? kWaves : 1][kRingQ ? kRing + 1 : 1];                // ring: charge
   __shared__ float cw[EV == EV_ERFCX ? kWaves : 1][EV == EV_ERFCX ? kRing + 1 : 1];  // ring: width
   __shared__ float4 etab[kTabF4];
@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
   // sums collect d u q x with u = 1 / (h r); -R'(r) / r = -2 d u, and the
   // factor -2 is applied once per target.
   const float tab_w = (float)(kPairTabPieces / sqrt(g.rc2));  // 1 / h
-  const float tab_top = (float)kPairTabPieces - 0.5f;
+  const float tab_top = (float)kPairTabPieces - 0.0625f;
   auto evaluate_tab = [&](float dx, float dy, float dz, float q, int e) {
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const float u = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f)) * tab_w;
@@ -631,7 +631,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
   if (lane == 0) rs[0] = 0;
   if constexpr (kRingQ) {
     if (lane == 0) {  // the placeholder slot
-      cb[kRing] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(kRing));
+      cb[kRing] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       cq[wv][kRing] = 0.0f;
     }
   }
@@ -707,10 +707,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
   bz1 = uniform_f(bz1);
   const float nanf_ = __int_as_float(0x7fc00000);
   if (kRingQ && !active) px = py = pz = nanf_;  // no candidate test hits
+  // single-precision candidate test: |t - c|^2 < r_c^2 as
+  // |c|^2 - 2 t.c < r_c^2 - |t|^2, three multiply-adds on the staged
+  // (-2c, |c|^2) (rounding moves the test by about 1e-6 of r_c^2, where the
+  // pair's value is at the split's tolerance; a queued pair just beyond r_c
+  // is evaluated on the last piece of the table)
+  const float thr = rc2e - fmaf(px, px, fmaf(py, py, pz * pz));
   int next = 0, pbase = 0;  // next stream position to stage and (next S) mod M
   int nbat = 0, k0 = 0;
   int batch = 0;  // batches staged
   const float4* cnd_base = cb;  // the batch under test
+  int creg = 0, cn0 = 0;        // its ring region and its number of set-0 candidates (set 1 follows)
   // ring: pushed at the end of each of the last kRegions - 1 batches, newest first
   int ends[kRegions > 1 ? kRegions - 1 : 1] = {};
   for (;;) {
@@ -758,23 +765,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
             keep = ex * ex + ey * ey + ez * ez < rc2f;
           }
         }
-        // the kept candidates first, in stream order; NaN points after them
+        // the kept candidates first, in stream order (single-precision
+        // passes: those of set 0, then those of set 1); NaN points after them
+        const unsigned long long lt = (1ull << lane) - 1ull;
         const unsigned long long km = __ballot(keep);
         const int nkeep = __popcll(km);
         const int region = kRingQ ? (batch & (kRegions - 1)) * 64 : 0;
         float4* dst = cb + region;
-        if (keep) {
-          const int slot = __popcll(km & ((1ull << lane) - 1ull));
-          if constexpr (kRingQ) {
-            v.w = __int_as_float(__float_as_int(v.w) | (region + slot));
+        int n0 = nkeep;
+        if constexpr (kRingQ) {
+          const unsigned long long k1 = __ballot(keep && (__float_as_int(v.w) >> kRingSetShift) != 0);
+          n0 = nkeep - __popcll(k1);
+          if (keep) {
+            const int slot = (k1 >> lane) & 1ull ? n0 + __popcll(k1 & lt) : __popcll(km & ~k1 & lt);
             cq[wv][region + slot] = vq;
             if constexpr (EV == EV_ERFCX) cw[wv][region + slot] = vw;
+            dst[slot] = make_float4(-2.0f * v.x, -2.0f * v.y, -2.0f * v.z, fmaf(v.x, v.x, fmaf(v.y, v.y, v.z * v.z)));
           }
+        } else if (keep) {
+          const int slot = __popcll(km & lt);
           dst[slot] = v;
           if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) cown[slot] = own;
         }
         if (lane >= nkeep) dst[lane] = make_float4(nanf_, nanf_, nanf_, nanf_);  // slots past the kept ones
         cnd_base = dst;
+        creg = __builtin_amdgcn_readfirstlane(region);
+        cn0 = __builtin_amdgcn_readfirstlane(n0);
         ++batch;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -788,7 +804,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
         finished = true;
       }
     }
-    if (!finished) {
+    if (!finished && kRingQ) {
+      // (the per-pair minimum image is a separate copy of the loop)
+      auto test_group = [&](auto img) {
+#pragma unroll
+        for (int kk = 0; kk < kQFlush; ++kk) {
+          const float4 cnd = cnd_base[k0 + kk];
+          bool hit;
+          if constexpr (decltype(img)::value) {  // the differences as the evaluation forms them
+            float dx = fmaf(0.5f, cnd.x, px), dy = fmaf(0.5f, cnd.y, py), dz = fmaf(0.5f, cnd.z, pz);
+            dx -= Lf0 * rintf(dx * iL0);
+            dy -= Lf1 * rintf(dy * iL1);
+            dz -= Lf2 * rintf(dz * iL2);
+            hit = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rc2e;
+          } else {
+            hit = fmaf(px, cnd.x, fmaf(py, cnd.y, fmaf(pz, cnd.z, cnd.w))) < thr;
+          }
+          // the slot at pushed is free (at most kQ - 1 entries pending)
+          const int kc = k0 + kk;
+          qb[pushed & (kQ - 1)][lane] = (QE)((creg + kc) | (kc >= cn0 ? 1 << kRingSetShift : 0));
+          pushed += hit ? 1 : 0;
+        }
+      };
+      if (per_pair_image) test_group(std::true_type{});
+      else test_group(std::false_type{});
+      k0 += kQFlush;
+    } else if (!finished) {
 #pragma unroll
       for (int kk = 0; kk < kQFlush; ++kk) {
         const float4 cnd = cnd_base[k0 + kk];
@@ -796,20 +837,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
         float dy = py - cnd.y;
         float dz = pz - cnd.z;
         if (per_pair_image) {
-          if constexpr (kRingQ) {  // as the evaluation forms them
-            dx -= Lf0 * rintf(dx * iL0);
-            dy -= Lf1 * rintf(dy * iL1);
-            dz -= Lf2 * rintf(dz * iL2);
-          } else {
-            dx -= Lf0 * rintf(dx / Lf0);
-            dy -= Lf1 * rintf(dy / Lf1);
-            dz -= Lf2 * rintf(dz / Lf2);
-          }
+          dx -= Lf0 * rintf(dx / Lf0);
+          dy -= Lf1 * rintf(dy / Lf1);
+          dz -= Lf2 * rintf(dz / Lf2);
         }
-        // (single-precision passes: the evaluation's own test, on the same
-        // float differences)
-        const float r2 = kRingQ ? fmaf(dx, dx, fmaf(dy, dy, dz * dz)) : dx * dx + dy * dy + dz * dz;
-        bool hit = (kRingQ || active) && r2 < (kRingQ ? rc2e : rc2f);
+        bool hit = active && dx * dx + dy * dy + dz * dz < rc2f;
         if constexpr (MODE == MODE_COUNT || MODE == MODE_FILL) {
           // pairs inside a body with a dense intra-body block are not listed
           hit = hit && (own_body < 0 || cown[k0 + kk] != own_body);
@@ -878,8 +910,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
           const float4 a = ring[ea & 255], b = ring[eb & 255];
           const float qa = cq[wv][ea & 255], qb2 = cq[wv][eb & 255];
           popped += avail;
-          const float dxa = diff(px - a.x, Lf0, iL0), dya = diff(py - a.y, Lf1, iL1), dza = diff(pz - a.z, Lf2, iL2);
-          const float dxb = diff(px - b.x, Lf0, iL0), dyb = diff(py - b.y, Lf1, iL1), dzb = diff(pz - b.z, Lf2, iL2);
+          // (the ring holds -2c: t - c = t + c' / 2, exact as a subtraction)
+          const float dxa = diff(fmaf(0.5f, a.x, px), Lf0, iL0), dya = diff(fmaf(0.5f, a.y, py), Lf1, iL1),
+                      dza = diff(fmaf(0.5f, a.z, pz), Lf2, iL2);
+          const float dxb = diff(fmaf(0.5f, b.x, px), Lf0, iL0), dyb = diff(fmaf(0.5f, b.y, py), Lf1, iL1),
+                      dzb = diff(fmaf(0.5f, b.z, pz), Lf2, iL2);
           if constexpr (EV == EV_TABLE) {
             evaluate_tab(dxa, dya, dza, qa, ea);
             evaluate_tab(dxb, dyb, dzb, qb2, eb);
