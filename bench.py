@@ -58,26 +58,33 @@ TRAIN_DEFAULT = {"cfg2": 0, "cfg3": 0, "cfg4": 2000, "cfg5": 200}
 # measurement; once one changes the figures are stale and `traffic` is
 # reported null, as it is on any other workload.
 TRAFFIC = {
-    "spread_f32": {"workload": "cfg5", "bytes_per_launch": 1.429e+08,
+    # one launch at the ion targets (426 MB) and one at the beads (79 MB) per step
+    "pair_f32": {"workload": "cfg5", "bytes_per_launch": 2.522e+08,
+                 "limiter": ("vector ALU issue 0.77-0.84 VALU instructions per CU-cycle of at most 1 (SQ_INSTS_VALU) "
+                             "at the ion targets, with the latency of the drain's dependent LDS reads; "
+                             "LDS bank conflicts 0.27-0.30 cycles per CU-cycle"),
+                 "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "68e887466fb4de7cc1b2a2a36038c36c05ef14bb",
+                             "paper_2401_04865_amd/csrc/api.hip": "c534fd0c4fbf9294bd0c55a617f1930ea64a886f"}},
+    "spread_f32": {"workload": "cfg5", "bytes_per_launch": 1.399e+08,
                    "limiter": ("vector ALU issue: 0.53 (beads) and 0.68 (ions) VALU instructions per CU-cycle "
                                "of at most 1 (SQ_INSTS_VALU); LDS 0.10-0.12 instructions per CU-cycle"),
                    "sources": {"paper_2401_04865_amd/csrc/grid.hip": "3672ce91f3b84b5236c3bdf7f8e1cb6aac51564c",
-                               "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+                               "paper_2401_04865_amd/csrc/api.hip": "c534fd0c4fbf9294bd0c55a617f1930ea64a886f"}},
     "fft_z_r2c_f32": {"workload": "cfg5", "bytes_per_launch": 1.364e+08,
                       "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                  "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+                                  "paper_2401_04865_amd/csrc/api.hip": "c534fd0c4fbf9294bd0c55a617f1930ea64a886f"}},
     "fft_y_fwd_f32": {"workload": "cfg5", "bytes_per_launch": 1.448e+08,
                       "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                  "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+                                  "paper_2401_04865_amd/csrc/api.hip": "c534fd0c4fbf9294bd0c55a617f1930ea64a886f"}},
     "fft_x_scale_f32": {"workload": "cfg5", "bytes_per_launch": 1.453e+08,
                         "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                    "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+                                    "paper_2401_04865_amd/csrc/api.hip": "c534fd0c4fbf9294bd0c55a617f1930ea64a886f"}},
     "fft_y_inv_f32": {"workload": "cfg5", "bytes_per_launch": 1.448e+08,
                       "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                  "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+                                  "paper_2401_04865_amd/csrc/api.hip": "c534fd0c4fbf9294bd0c55a617f1930ea64a886f"}},
     "fft_z_c2r_f32": {"workload": "cfg5", "bytes_per_launch": 1.427e+08,
                       "sources": {"paper_2401_04865_amd/csrc/fft.hip": "5047d66b62c368381a9e409fbdaa23ab99502cc4",
-                                  "paper_2401_04865_amd/csrc/api.hip": "104db8bcd3d74a75ca343baf47db49c33502447e"}},
+                                  "paper_2401_04865_amd/csrc/api.hip": "c534fd0c4fbf9294bd0c55a617f1930ea64a886f"}},
 }
 
 
