@@ -882,7 +882,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
         for (int i = kRegions - 2; i > 0; --i) ends[i] = ends[i - 1];
         ends[0] = pushed;
       }
-      auto rounds_wanted = [&]() {  // 0, 1 or 2 (or more) rounds still due
+      // rounds per drain pass: with more, the lanes whose queues hold fewer
+      // entries than the pass takes evaluate the placeholder
+      constexpr int kPass = 1;
+      auto rounds_wanted = [&]() {  // 0 .. kPass (or more) rounds still due
         const int pend = pushed - popped;
         auto due = [&](int r) {  // at least r more rounds
           if (finished) return __ballot(pend >= r) != 0ull;
@@ -892,9 +895,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
           if (batch_end) d = d || __ballot(old_end - popped >= r) != 0ull;
           return d;
         };
-        return due(2) ? 2 : (due(1) ? 1 : 0);
+#pragma unroll
+        for (int r = kPass; r > 0; --r)
+          if (due(r)) return r;
+        return 0;
       };
-      // two rounds per pass, both ring entries read first (a lane without an
+      // kPass rounds per pass, all ring entries read first (a lane without an
       // entry reads the placeholder slot); the per-pair minimum image (boxes
       // of one cell along an axis) is a separate copy of the loop
       const float4* ring = cb;
@@ -905,22 +911,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EV == 
           const int rw = rounds_wanted();
           if (rw == 0) break;
           const int avail = min(pushed - popped, rw);
-          const int ea = avail > 0 ? (int)qb[popped & (kQ - 1)][lane] : kRing;
-          const int eb = avail > 1 ? (int)qb[(popped + 1) & (kQ - 1)][lane] : kRing;
-          const float4 a = ring[ea & 255], b = ring[eb & 255];
-          const float qa = cq[wv][ea & 255], qb2 = cq[wv][eb & 255];
+          int e[kPass];
+          float4 cv[kPass];
+          float qv[kPass];
+#pragma unroll
+          for (int i = 0; i < kPass; ++i) e[i] = avail > i ? (int)qb[(popped + i) & (kQ - 1)][lane] : kRing;
+#pragma unroll
+          for (int i = 0; i < kPass; ++i) {
+            cv[i] = ring[e[i] & 255];
+            qv[i] = cq[wv][e[i] & 255];
+          }
           popped += avail;
-          // (the ring holds -2c: t - c = t + c' / 2, exact as a subtraction)
-          const float dxa = diff(fmaf(0.5f, a.x, px), Lf0, iL0), dya = diff(fmaf(0.5f, a.y, py), Lf1, iL1),
-                      dza = diff(fmaf(0.5f, a.z, pz), Lf2, iL2);
-          const float dxb = diff(fmaf(0.5f, b.x, px), Lf0, iL0), dyb = diff(fmaf(0.5f, b.y, py), Lf1, iL1),
-                      dzb = diff(fmaf(0.5f, b.z, pz), Lf2, iL2);
-          if constexpr (EV == EV_TABLE) {
-            evaluate_tab(dxa, dya, dza, qa, ea);
-            evaluate_tab(dxb, dyb, dzb, qb2, eb);
-          } else {
-            if (avail > 0) evaluate_fast(dxa, dya, dza, qa, cw[wv][ea & 255]);
-            if (avail > 1) evaluate_fast(dxb, dyb, dzb, qb2, cw[wv][eb & 255]);
+#pragma unroll
+          for (int i = 0; i < kPass; ++i) {
+            // (the ring holds -2c: t - c = t + c' / 2, exact as a subtraction)
+            const float dx = diff(fmaf(0.5f, cv[i].x, px), Lf0, iL0), dy = diff(fmaf(0.5f, cv[i].y, py), Lf1, iL1),
+                        dz = diff(fmaf(0.5f, cv[i].z, pz), Lf2, iL2);
+            if constexpr (EV == EV_TABLE) evaluate_tab(dx, dy, dz, qv[i], e[i]);
+            else if (avail > i) evaluate_fast(dx, dy, dz, qv[i], cw[wv][e[i] & 255]);
           }
         }
       };
