@@ -58,12 +58,12 @@ TRAIN_DEFAULT = {"cfg2": 0, "cfg3": 0, "cfg4": 2000, "cfg5": 200}
 # measurement; once one changes the figures are stale and `traffic` is
 # reported null, as it is on any other workload.
 TRAFFIC = {
-    # one launch at the ion targets (426 MB) and one at the beads (79 MB) per step
-    "pair_f32": {"workload": "cfg5", "bytes_per_launch": 2.522e+08,
-                 "limiter": ("vector ALU issue 0.77-0.84 VALU instructions per CU-cycle of at most 1 (SQ_INSTS_VALU) "
+    # one launch at the ion targets (425 MB) and one at the beads (78 MB) per step
+    "pair_f32": {"workload": "cfg5", "bytes_per_launch": 2.517e+08,
+                 "limiter": ("vector ALU issue 0.72-0.78 VALU instructions per CU-cycle of at most 1 (SQ_INSTS_VALU) "
                              "at the ion targets, with the latency of the drain's dependent LDS reads; "
-                             "LDS bank conflicts 0.27-0.30 cycles per CU-cycle"),
-                 "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "68e887466fb4de7cc1b2a2a36038c36c05ef14bb",
+                             "LDS bank conflicts 0.25-0.27 cycles per CU-cycle"),
+                 "sources": {"paper_2401_04865_amd/csrc/realspace.hip": "c32609c619e6d7183752007d1375fd611d29a813",
                              "paper_2401_04865_amd/csrc/api.hip": "c534fd0c4fbf9294bd0c55a617f1930ea64a886f"}},
     "spread_f32": {"workload": "cfg5", "bytes_per_launch": 1.399e+08,
                    "limiter": ("vector ALU issue: 0.53 (beads) and 0.68 (ions) VALU instructions per CU-cycle "
